@@ -1,0 +1,493 @@
+/*
+ * CPU oracle for degree-separated, direction-optimized BFS.
+ *
+ * TEST INFRASTRUCTURE ONLY. Nothing in the product path may include, link,
+ * load or call this file; only the tests, the smoke check and the CPU-baseline
+ * leg of the benchmark use it. It shares no code with the GPU library: it
+ * builds its own adjacency, runs its own search and computes its own
+ * statistics from the paper's definitions, written plainly and slowly.
+ *
+ * What it computes, and the passage each part follows:
+ *  - G: the simple symmetric graph of an edge list. The paper assumes a
+ *    symmetric graph (Section II-A, "graph") built by edge doubling
+ *    (Section VI-A, "Reporting"); self-loops and duplicate edges are dropped
+ *    (the paper is silent on both; simple-graph reading).
+ *  - BFS depth = hop distance from the source (Section VI-A: the
+ *    implementation outputs hop distances), found by a serial FIFO search.
+ *    Direction optimization only changes the work, never the result
+ *    (Section IV-B), so every GPU mode must reproduce exactly these depths.
+ *  - parent: any neighbour one level shallower is valid; results are checked
+ *    by invariants, not by equality (several trees are correct).
+ *  - Degree separation (Section II-A "delegates"/"normal vertices",
+ *    Section III-A): a vertex is a delegate iff its out-degree exceeds TH;
+ *    delegates are renumbered 0..d-1 in ascending vertex ID (Fig. 2 caption).
+ *  - The four edge classes nn, nd, dn, dd (Section II-A, Section IV) and the
+ *    source list / masks used by the backward kernels (Section IV-B).
+ *  - The direction decision of Section IV-B: forward workload FV (sum of
+ *    neighbour-list lengths of the frontier), backward workload
+ *    BV = |U|(q+s)/q, switch forward->backward when FV > factor0*BV and
+ *    backward->forward when FV < factor1*BV, replayed level by level from
+ *    the oracle's own depths.
+ *  - Brute-force all-pairs shortest paths (Floyd-Warshall) and union-find
+ *    components, built straight from the edge list, to pin the search.
+ *
+ * Parity status: every function here is pinned by tests against closed
+ * forms, brute force or hand-derived values, except the bv_exact option,
+ * which is pinned only by the geometric-series identity.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+typedef struct or_graph {
+  int32_t n;
+  int64_t m;   /* directed edges (each undirected edge counted twice) */
+  int64_t *off;
+  int32_t *col;
+} or_graph;
+
+enum { OR_OK = 0, OR_EINVAL = -1, OR_ENOMEM = -2 };
+
+static int cmp_i32(const void *a, const void *b) {
+  int32_t x = *(const int32_t *)a, y = *(const int32_t *)b;
+  return (x > y) - (x < y);
+}
+
+/*
+ * Adjacency of the simple symmetric graph: both directions of every pair with
+ * u != v, rows sorted ascending, duplicates removed. Returns OR_OK or an error
+ * (endpoint outside [0, n), allocation failure).
+ */
+int or_graph_build(const int32_t *src, const int32_t *dst, int64_t g, int32_t n,
+                   or_graph **out) {
+  if (!out || n < 1 || g < 0 || (g > 0 && (!src || !dst))) return OR_EINVAL;
+  *out = NULL;
+  for (int64_t e = 0; e < g; ++e)
+    if (src[e] < 0 || src[e] >= n || dst[e] < 0 || dst[e] >= n) return OR_EINVAL;
+
+  int64_t *cnt = (int64_t *)calloc((size_t)n + 1, sizeof(int64_t));
+  if (!cnt) return OR_ENOMEM;
+#pragma omp parallel for schedule(static)
+  for (int64_t e = 0; e < g; ++e) {
+    if (src[e] == dst[e]) continue;
+    __atomic_fetch_add(&cnt[src[e]], 1, __ATOMIC_RELAXED);
+    __atomic_fetch_add(&cnt[dst[e]], 1, __ATOMIC_RELAXED);
+  }
+  int64_t *start = (int64_t *)malloc(((size_t)n + 1) * sizeof(int64_t));
+  if (!start) { free(cnt); return OR_ENOMEM; }
+  start[0] = 0;
+  for (int32_t v = 0; v < n; ++v) start[v + 1] = start[v] + cnt[v];
+  int64_t total = start[n];
+  int32_t *tmp = (int32_t *)malloc((size_t)(total > 0 ? total : 1) * sizeof(int32_t));
+  if (!tmp) { free(cnt); free(start); return OR_ENOMEM; }
+  memset(cnt, 0, ((size_t)n + 1) * sizeof(int64_t));
+#pragma omp parallel for schedule(static)
+  for (int64_t e = 0; e < g; ++e) {
+    int32_t u = src[e], v = dst[e];
+    if (u == v) continue;
+    int64_t pu = __atomic_fetch_add(&cnt[u], 1, __ATOMIC_RELAXED);
+    int64_t pv = __atomic_fetch_add(&cnt[v], 1, __ATOMIC_RELAXED);
+    tmp[start[u] + pu] = v;
+    tmp[start[v] + pv] = u;
+  }
+  /* sort and de-duplicate each row in place; cnt[v] becomes the unique degree */
+#pragma omp parallel for schedule(dynamic, 1024)
+  for (int32_t v = 0; v < n; ++v) {
+    int32_t *row = tmp + start[v];
+    int64_t len = start[v + 1] - start[v];
+    if (len > 1) qsort(row, (size_t)len, sizeof(int32_t), cmp_i32);
+    int64_t k = 0;
+    for (int64_t i = 0; i < len; ++i)
+      if (k == 0 || row[i] != row[k - 1]) row[k++] = row[i];
+    cnt[v] = k;
+  }
+  or_graph *G = (or_graph *)calloc(1, sizeof(or_graph));
+  int64_t *off = (int64_t *)malloc(((size_t)n + 1) * sizeof(int64_t));
+  if (!G || !off) { free(G); free(off); free(cnt); free(start); free(tmp); return OR_ENOMEM; }
+  off[0] = 0;
+  for (int32_t v = 0; v < n; ++v) off[v + 1] = off[v] + cnt[v];
+  int64_t m = off[n];
+  int32_t *col = (int32_t *)malloc((size_t)(m > 0 ? m : 1) * sizeof(int32_t));
+  if (!col) { free(G); free(off); free(cnt); free(start); free(tmp); return OR_ENOMEM; }
+#pragma omp parallel for schedule(dynamic, 1024)
+  for (int32_t v = 0; v < n; ++v)
+    memcpy(col + off[v], tmp + start[v], (size_t)cnt[v] * sizeof(int32_t));
+  free(cnt); free(start); free(tmp);
+  G->n = n; G->m = m; G->off = off; G->col = col;
+  *out = G;
+  return OR_OK;
+}
+
+void or_graph_free(or_graph *G) {
+  if (!G) return;
+  free(G->off); free(G->col); free(G);
+}
+int32_t or_graph_n(const or_graph *G) { return G->n; }
+int64_t or_graph_m(const or_graph *G) { return G->m; }
+const int64_t *or_graph_off(const or_graph *G) { return G->off; }
+const int32_t *or_graph_col(const or_graph *G) { return G->col; }
+
+/*
+ * Serial FIFO BFS from s: depth = hop distance (-1 if unreachable),
+ * parent = the vertex that first discovered it (s for s, -1 if unreachable).
+ * parent may be NULL.
+ */
+int or_bfs(const or_graph *G, int32_t s, int32_t *depth, int32_t *parent) {
+  if (!G || !depth || s < 0 || s >= G->n) return OR_EINVAL;
+  const int32_t n = G->n;
+  int32_t *queue = (int32_t *)malloc((size_t)n * sizeof(int32_t));
+  if (!queue) return OR_ENOMEM;
+  for (int32_t v = 0; v < n; ++v) depth[v] = -1;
+  if (parent)
+    for (int32_t v = 0; v < n; ++v) parent[v] = -1;
+  int64_t head = 0, tail = 0;
+  depth[s] = 0;
+  if (parent) parent[s] = s;
+  queue[tail++] = s;
+  while (head < tail) {
+    int32_t u = queue[head++];
+    for (int64_t i = G->off[u]; i < G->off[u + 1]; ++i) {
+      int32_t v = G->col[i];
+      if (depth[v] < 0) {
+        depth[v] = depth[u] + 1;
+        if (parent) parent[v] = u;
+        queue[tail++] = v;
+      }
+    }
+  }
+  free(queue);
+  return OR_OK;
+}
+
+/*
+ * Brute force: Floyd-Warshall all-pairs hop distances on the simple symmetric
+ * graph of the raw pairs, built straight from the edge list (no CSR), for
+ * n <= 1024. dist is n*n row-major, -1 where unreachable.
+ */
+int or_apsp(int32_t n, const int32_t *src, const int32_t *dst, int64_t g, int32_t *dist) {
+  if (n < 1 || n > 1024 || !dist || g < 0) return OR_EINVAL;
+  const int32_t INF = 1 << 29;
+  for (int64_t i = 0; i < (int64_t)n * n; ++i) dist[i] = INF;
+  for (int32_t i = 0; i < n; ++i) dist[(int64_t)i * n + i] = 0;
+  for (int64_t e = 0; e < g; ++e) {
+    int32_t u = src[e], v = dst[e];
+    if (u < 0 || v < 0 || u >= n || v >= n) return OR_EINVAL;
+    if (u == v) continue;
+    dist[(int64_t)u * n + v] = 1;
+    dist[(int64_t)v * n + u] = 1;
+  }
+  for (int32_t k = 0; k < n; ++k)
+    for (int32_t i = 0; i < n; ++i) {
+      int32_t dik = dist[(int64_t)i * n + k];
+      if (dik >= INF) continue;
+      for (int32_t j = 0; j < n; ++j) {
+        int32_t c = dik + dist[(int64_t)k * n + j];
+        if (c < dist[(int64_t)i * n + j]) dist[(int64_t)i * n + j] = c;
+      }
+    }
+  for (int64_t i = 0; i < (int64_t)n * n; ++i)
+    if (dist[i] >= INF) dist[i] = -1;
+  return OR_OK;
+}
+
+static int32_t uf_find(int32_t *p, int32_t x) {
+  while (p[x] != x) { p[x] = p[p[x]]; x = p[x]; }
+  return x;
+}
+
+/*
+ * Connected components by union-find over the raw pairs (no CSR).
+ * label[v] = smallest vertex ID in v's component.
+ */
+int or_components(int32_t n, const int32_t *src, const int32_t *dst, int64_t g, int32_t *label) {
+  if (n < 1 || !label || g < 0) return OR_EINVAL;
+  int32_t *p = (int32_t *)malloc((size_t)n * sizeof(int32_t));
+  if (!p) return OR_ENOMEM;
+  for (int32_t v = 0; v < n; ++v) p[v] = v;
+  for (int64_t e = 0; e < g; ++e) {
+    int32_t u = src[e], v = dst[e];
+    if (u < 0 || v < 0 || u >= n || v >= n) { free(p); return OR_EINVAL; }
+    int32_t a = uf_find(p, u), b = uf_find(p, v);
+    if (a == b) continue;
+    if (a < b) p[b] = a; else p[a] = b;   /* root is always the smaller ID */
+  }
+  for (int32_t v = 0; v < n; ++v) label[v] = uf_find(p, v);
+  free(p);
+  return OR_OK;
+}
+
+static int has_edge(const or_graph *G, int32_t u, int32_t v) {
+  int64_t lo = G->off[u], hi = G->off[u + 1];
+  while (lo < hi) {
+    int64_t mid = lo + (hi - lo) / 2;
+    if (G->col[mid] < v) lo = mid + 1; else hi = mid;
+  }
+  return lo < G->off[u + 1] && G->col[lo] == v;
+}
+
+/*
+ * Invariants of a BFS result from s (checked on every run):
+ *  1  depth[s] == 0 (and parent[s] == s when parents are given);
+ *  2  every reached v != s has {parent[v], v} in E and
+ *     depth[parent[v]] == depth[v] - 1;
+ *  3  every edge {u, v} has both ends unreached or |depth[u]-depth[v]| <= 1;
+ *  4  the reached set equals the component of s (label from or_components);
+ *  5  unreached vertices carry depth -1 and parent -1; no depth below -1.
+ * 1-4 together force depth[v] == dist(s, v). Returns 0 when all hold, else
+ * the number of the first failed invariant; *bad gets the offending vertex.
+ * parent and label may be NULL (their checks are skipped).
+ */
+int or_check_bfs(const or_graph *G, int32_t s, const int32_t *depth, const int32_t *parent,
+                 const int32_t *label, int64_t *bad) {
+  const int32_t n = G->n;
+  int64_t dummy;
+  if (!bad) bad = &dummy;
+  *bad = -1;
+  if (s < 0 || s >= n || !depth) return OR_EINVAL;
+  if (depth[s] != 0 || (parent && parent[s] != s)) { *bad = s; return 1; }
+  if (parent) {
+    for (int32_t v = 0; v < n; ++v) {
+      if (v == s || depth[v] < 0) continue;
+      int32_t p = parent[v];
+      if (p < 0 || p >= n || !has_edge(G, p, v) || depth[p] != depth[v] - 1) {
+        *bad = v;
+        return 2;
+      }
+    }
+  }
+  for (int32_t u = 0; u < n; ++u) {
+    for (int64_t i = G->off[u]; i < G->off[u + 1]; ++i) {
+      int32_t v = G->col[i];
+      int32_t du = depth[u], dv = depth[v];
+      if (du < 0 && dv < 0) continue;
+      if (du < 0 || dv < 0 || du - dv > 1 || dv - du > 1) { *bad = u; return 3; }
+    }
+  }
+  if (label) {
+    for (int32_t v = 0; v < n; ++v) {
+      int same = label[v] == label[s];
+      if (same != (depth[v] >= 0)) { *bad = v; return 4; }
+    }
+  }
+  for (int32_t v = 0; v < n; ++v) {
+    if (depth[v] < -1) { *bad = v; return 5; }
+    if (depth[v] == -1 && parent && parent[v] != -1) { *bad = v; return 5; }
+  }
+  return 0;
+}
+
+/* ---------------------------------------------------------------------- */
+/* Degree separation (Section II-A, Section III-A, Fig. 2 caption).        */
+/* ---------------------------------------------------------------------- */
+
+static inline int64_t or_deg(const or_graph *G, int32_t v) { return G->off[v + 1] - G->off[v]; }
+
+typedef struct {
+  int64_t n, m, d;
+  int64_t e_nn, e_nd, e_dn, e_dd;
+  int64_t n_ndsrc, n_ddsrc, n_dnsrc;
+  int64_t max_deg;
+} or_split_stats_t;
+
+/*
+ * Counts of the degree-separated layout at threshold TH: d = #{v: deg v > TH};
+ * e_xy = directed edges u->v with class(u) = x, class(v) = y (n = normal,
+ * d = delegate); ndsrc = normals with >= 1 delegate neighbour; ddsrc /
+ * dnsrc = delegates with >= 1 delegate / normal neighbour (Section IV-B).
+ */
+int or_split_stats(const or_graph *G, int64_t TH, or_split_stats_t *st) {
+  if (!G || !st) return OR_EINVAL;
+  memset(st, 0, sizeof(*st));
+  st->n = G->n;
+  st->m = G->m;
+  for (int32_t u = 0; u < G->n; ++u) {
+    int64_t du = or_deg(G, u);
+    if (du > st->max_deg) st->max_deg = du;
+    int u_del = du > TH;
+    if (u_del) st->d++;
+    int64_t to_del = 0, to_norm = 0;
+    for (int64_t i = G->off[u]; i < G->off[u + 1]; ++i) {
+      int v_del = or_deg(G, G->col[i]) > TH;
+      if (v_del) to_del++; else to_norm++;
+    }
+    if (u_del) {
+      st->e_dd += to_del; st->e_dn += to_norm;
+      if (to_del) st->n_ddsrc++;
+      if (to_norm) st->n_dnsrc++;
+    } else {
+      st->e_nd += to_del; st->e_nn += to_norm;
+      if (to_del) st->n_ndsrc++;
+    }
+  }
+  return OR_OK;
+}
+
+/* Delegate IDs: did[v] = rank of v among delegates in ascending ID, else -1. */
+int or_delegate_ids(const or_graph *G, int64_t TH, int32_t *did) {
+  if (!G || !did) return OR_EINVAL;
+  int32_t next = 0;
+  for (int32_t v = 0; v < G->n; ++v) did[v] = or_deg(G, v) > TH ? next++ : -1;
+  return OR_OK;
+}
+
+/*
+ * The four subgraphs as separate CSRs, rows in ascending neighbour order:
+ *   nn: rows 0..n-1 (empty for delegates), columns = vertex IDs of normals
+ *   nd: rows 0..n-1 (empty for delegates), columns = delegate IDs
+ *   dn: rows 0..d-1 (delegate IDs), columns = vertex IDs of normals
+ *   dd: rows 0..d-1, columns = delegate IDs
+ * Offsets arrays have n+1 or d+1 entries; column arrays are sized by the
+ * e_xy counts of or_split_stats.
+ */
+int or_split_rows(const or_graph *G, int64_t TH, const int32_t *did,
+                  int64_t *nn_off, int32_t *nn_col, int64_t *nd_off, int32_t *nd_col,
+                  int64_t *dn_off, int32_t *dn_col, int64_t *dd_off, int32_t *dd_col) {
+  if (!G || !did) return OR_EINVAL;
+  int64_t a = 0, b = 0, c = 0, e = 0;
+  int32_t k = 0;
+  nn_off[0] = nd_off[0] = 0;
+  dn_off[0] = dd_off[0] = 0;
+  for (int32_t u = 0; u < G->n; ++u) {
+    int u_del = or_deg(G, u) > TH;
+    for (int64_t i = G->off[u]; i < G->off[u + 1]; ++i) {
+      int32_t v = G->col[i];
+      int v_del = or_deg(G, v) > TH;
+      if (!u_del && !v_del) nn_col[a++] = v;
+      else if (!u_del && v_del) nd_col[b++] = did[v];
+      else if (u_del && !v_del) dn_col[c++] = v;
+      else dd_col[e++] = did[v];
+    }
+    nn_off[u + 1] = a;
+    nd_off[u + 1] = b;
+    if (u_del) { dn_off[k + 1] = c; dd_off[k + 1] = e; ++k; }
+  }
+  return OR_OK;
+}
+
+/* ---------------------------------------------------------------------- */
+/* Direction decision replay (Section IV-B).                               */
+/* ---------------------------------------------------------------------- */
+
+/*
+ * One term of the backward workload: the expected number of parents checked
+ * before the first visited one, when each of od potential parents is visited
+ * with probability a, i.e. the sum over i < od of (1-a)^i, in closed form
+ * (1 - (1-a)^od) / a.
+ */
+double or_bv_term(double a, int64_t od) {
+  if (od <= 0) return 0.0;
+  if (a >= 1.0) return 1.0;
+  return (1.0 - pow(1.0 - a, (double)od)) / a;
+}
+
+/* The paper's approximation of BV for large od: |U| (q + s) / q. */
+double or_bv_approx(int64_t U, int64_t q, int64_t s) {
+  if (q <= 0 || U <= 0) return 0.0;
+  return (double)U * ((double)q + (double)s) / (double)q;
+}
+
+enum { K_DD = 0, K_DN = 1, K_ND = 2 };
+
+typedef struct {
+  int64_t q[3], s[3], U[3], FV[3];   /* per DO kernel dd, dn, nd */
+  double BV[3];
+  int32_t dir[3];                    /* direction used at this level: 0 fwd, 1 bwd */
+  int64_t FV_nn, q_nn;               /* nn is always forward */
+  int64_t frontier_normal, frontier_delegate;
+} or_level_t;
+
+/*
+ * Replays the direction schedule of one search from the oracle's own depths.
+ * At level L (frontier = vertices at depth L; visited = depth in [0, L]):
+ *   dd: FV = sum of dd degrees of frontier delegates, q = frontier delegates
+ *       with a dd edge, U = ddsrc minus visited, s = |U|;
+ *   dn: FV = sum of dn degrees of frontier delegates, q = frontier delegates
+ *       with a dn edge, U = ndsrc minus visited, s = |dnsrc minus visited|;
+ *   nd: FV = sum of nd degrees of frontier normals, q = frontier normals
+ *       with an nd edge, U = dnsrc minus visited, s = |ndsrc minus visited|.
+ * If q == 0 the kernel has nothing to do and keeps its direction; otherwise
+ * forward switches to backward when FV > factor0*BV and backward switches to
+ * forward when FV < factor1*BV. BV is |U|(q+s)/q (bv_exact == 0) or the sum
+ * of or_bv_term over U with od = the degree in the reversed subgraph
+ * (bv_exact == 1). Writes at most max_levels records; returns the number of
+ * levels with a non-empty frontier, or a negative error.
+ */
+int or_do_replay(const or_graph *G, int64_t TH, const int32_t *depth, const double *factor0,
+                 const double *factor1, int bv_exact, or_level_t *out, int max_levels) {
+  if (!G || !depth || !factor0 || !factor1) return OR_EINVAL;
+  const int32_t n = G->n;
+  int32_t maxd = -1;
+  for (int32_t v = 0; v < n; ++v) if (depth[v] > maxd) maxd = depth[v];
+  int32_t dir[3] = {0, 0, 0};
+  int levels = maxd + 1;
+  for (int32_t L = 0; L <= maxd; ++L) {
+    or_level_t r;
+    memset(&r, 0, sizeof(r));
+    double bvx[3] = {0, 0, 0};
+    for (int32_t v = 0; v < n; ++v) {
+      int64_t dv = or_deg(G, v);
+      int del = dv > TH;
+      int64_t to_del = 0, to_norm = 0;
+      for (int64_t i = G->off[v]; i < G->off[v + 1]; ++i) {
+        if (or_deg(G, G->col[i]) > TH) to_del++; else to_norm++;
+      }
+      int in_frontier = depth[v] == L;
+      int unvisited = depth[v] < 0 || depth[v] > L;
+      if (del) {
+        if (in_frontier) {
+          r.frontier_delegate++;
+          r.FV[K_DD] += to_del;
+          r.FV[K_DN] += to_norm;
+          if (to_del) r.q[K_DD]++;
+          if (to_norm) r.q[K_DN]++;
+        }
+        if (unvisited) {
+          if (to_del) { r.U[K_DD]++; r.s[K_DD]++; }
+          if (to_norm) { r.U[K_ND]++; r.s[K_DN]++; }
+        }
+      } else {
+        if (in_frontier) {
+          r.frontier_normal++;
+          r.FV[K_ND] += to_del;
+          r.FV_nn += to_norm;
+          if (to_del) r.q[K_ND]++;
+          if (to_norm) r.q_nn++;
+        }
+        if (unvisited && to_del) { r.U[K_DN]++; r.s[K_ND]++; }
+      }
+    }
+    if (bv_exact) {
+      for (int k = 0; k < 3; ++k) {
+        if (r.q[k] == 0) continue;
+        double a = (double)r.q[k] / ((double)r.q[k] + (double)r.s[k]);
+        for (int32_t v = 0; v < n; ++v) {
+          int64_t dv = or_deg(G, v);
+          int del = dv > TH;
+          if (!(depth[v] < 0 || depth[v] > L)) continue;
+          int64_t to_del = 0, to_norm = 0;
+          for (int64_t i = G->off[v]; i < G->off[v + 1]; ++i) {
+            if (or_deg(G, G->col[i]) > TH) to_del++; else to_norm++;
+          }
+          /* od(u) = degree of u in the reversed subgraph the backward kernel scans */
+          if (k == K_DD && del && to_del) bvx[k] += or_bv_term(a, to_del);
+          if (k == K_DN && !del && to_del) bvx[k] += or_bv_term(a, to_del);
+          if (k == K_ND && del && to_norm) bvx[k] += or_bv_term(a, to_norm);
+        }
+      }
+    }
+    for (int k = 0; k < 3; ++k) {
+      r.BV[k] = bv_exact ? bvx[k] : or_bv_approx(r.U[k], r.q[k], r.s[k]);
+      if (r.q[k] > 0) {
+        if (dir[k] == 0 && (double)r.FV[k] > factor0[k] * r.BV[k]) dir[k] = 1;
+        else if (dir[k] == 1 && (double)r.FV[k] < factor1[k] * r.BV[k]) dir[k] = 0;
+      }
+      r.dir[k] = dir[k];
+    }
+    if (out && L < max_levels) out[L] = r;
+  }
+  return levels;
+}

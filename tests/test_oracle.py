@@ -1,0 +1,313 @@
+"""Pins of the CPU oracle against things other than itself: closed forms,
+brute-force all-pairs shortest paths, hand-derived values from the paper's
+definitions, and a textbook identity. None of these needs a GPU."""
+import os
+
+import numpy as np
+import pytest
+
+from closed_forms import all_closed_forms, complete, cycle, grid, path, star
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _graph(oracle_mod, n, src, dst):
+    return oracle_mod.Graph(src, dst, n)
+
+
+@pytest.mark.parametrize("case", all_closed_forms(), ids=lambda c: c[0])
+def test_closed_form_depths(oracle_mod, case):
+    name, n, src, dst, dist, sources = case
+    G = _graph(oracle_mod, n, src, dst)
+    label = G.components()
+    for s in sources:
+        depth, parent = G.bfs(s)
+        np.testing.assert_array_equal(depth, dist(s), err_msg=f"{name} s={s}")
+        assert G.check(s, depth, parent, label) == (0, -1)
+
+
+def test_apsp_matches_closed_forms(oracle_mod):
+    for n, src, dst, dist in (path(30), cycle(31), grid(5, 7), complete(9)):
+        D = oracle_mod.apsp(n, src, dst)
+        for s in range(n):
+            np.testing.assert_array_equal(D[s], dist(s))
+
+
+def _random_pairs(rng, n, k, loops=True):
+    src = rng.integers(0, n, size=k).astype(np.int32)
+    dst = rng.integers(0, n, size=k).astype(np.int32)
+    if loops:
+        src[: k // 20] = dst[: k // 20]          # some self-loops
+    dup = rng.integers(0, k, size=k // 10)
+    src = np.concatenate([src, dst[dup]])      # some reversed duplicates
+    dst = np.concatenate([dst, src[dup]])
+    return src, dst
+
+
+@pytest.mark.parametrize("n,k,seed", [(60, 40, 1), (100, 150, 2), (128, 400, 3), (90, 900, 4)])
+def test_bfs_equals_brute_force_random(oracle_mod, n, k, seed):
+    rng = np.random.default_rng(seed)
+    src, dst = _random_pairs(rng, n, k)
+    D = oracle_mod.apsp(n, src, dst)
+    G = _graph(oracle_mod, n, src, dst)
+    label = G.components()
+    for s in range(n):
+        depth, parent = G.bfs(s)
+        np.testing.assert_array_equal(depth, D[s])
+        assert G.check(s, depth, parent, label)[0] == 0
+
+
+@pytest.mark.parametrize("scale", [5, 6, 7])
+def test_bfs_equals_brute_force_tiny_rmat(oracle_mod, inputs_mod, scale):
+    src, dst = inputs_mod.rmat_edges(scale)
+    n = 1 << scale
+    D = oracle_mod.apsp(n, src, dst)
+    G = _graph(oracle_mod, n, src, dst)
+    for s in range(0, n, 3):
+        depth, _ = G.bfs(s, want_parent=False)
+        np.testing.assert_array_equal(depth, D[s])
+
+
+def test_csr_is_the_simple_symmetric_graph(oracle_mod):
+    rng = np.random.default_rng(7)
+    n = 70
+    src, dst = _random_pairs(rng, n, 500)
+    G = _graph(oracle_mod, n, src, dst)
+    adj = [set() for _ in range(n)]
+    for u, v in zip(src.tolist(), dst.tolist()):
+        if u != v:
+            adj[u].add(v)
+            adj[v].add(u)
+    off, col = G.off, G.col
+    assert G.m == sum(len(a) for a in adj)
+    for v in range(n):
+        assert col[off[v]:off[v + 1]].tolist() == sorted(adj[v])
+
+
+def test_csr_rejects_out_of_range(oracle_mod):
+    with pytest.raises(ValueError):
+        oracle_mod.Graph(np.array([0, 5], np.int32), np.array([1, 1], np.int32), 5)
+
+
+def test_components_closed_form(oracle_mod):
+    from closed_forms import disjoint_paths
+    n, src, dst, _ = disjoint_paths(6, 4)
+    lab = _graph(oracle_mod, n, src, dst).components()
+    assert lab.tolist() == [0] * 6 + [6] * 4
+
+
+def test_checker_flags_planted_mistakes(oracle_mod):
+    """Every invariant fires on a result broken in the way it guards against."""
+    n, src, dst, dist = grid(6, 6)
+    G = _graph(oracle_mod, n, src, dst)
+    label = G.components()
+    depth, parent = G.bfs(0)
+    assert G.check(0, depth, parent, label)[0] == 0
+
+    d, p = depth.copy(), parent.copy()
+    p[0] = 1                                     # source is not its own parent
+    assert G.check(0, d, p, label)[0] == 1
+
+    d, p = depth.copy(), parent.copy()
+    p[35] = 0                                    # parent that is not a neighbour
+    assert G.check(0, d, p, label) == (2, 35)
+
+    d, p = depth.copy(), parent.copy()
+    d[35] += 2                                   # depth off by two: parent level wrong
+    assert G.check(0, d, p, label)[0] == 2
+
+    d = depth.copy()
+    d[35] += 2                                   # same, without parents: edge rule fires
+    assert G.check(0, d, None, label)[0] == 3
+
+    n2, s2, t2, _ = path(5)
+    src2 = np.concatenate([s2, [5]]).astype(np.int32)   # edge 5-6: a second component
+    dst2 = np.concatenate([t2, [6]]).astype(np.int32)
+    G2 = _graph(oracle_mod, 7, src2, dst2)
+    lab2 = G2.components()
+    d2, p2 = G2.bfs(0)
+    assert G2.check(0, d2, p2, lab2)[0] == 0
+    d2b = d2.copy()
+    d2b[5], d2b[6] = 9, 10                      # reached outside the component
+    assert G2.check(0, d2b, None, lab2)[0] == 4
+    d2c = d2.copy()
+    d2c[6] = -3
+    assert G2.check(0, d2c, None, None)[0] == 5
+
+
+def test_split_star(oracle_mod):
+    k = 20
+    n, src, dst, _ = star(k)
+    G = _graph(oracle_mod, n, src, dst)
+    for TH in (1, 5, 19):
+        st = G.split_stats(TH)
+        assert st["d"] == 1
+        assert (st["e_nn"], st["e_nd"], st["e_dn"], st["e_dd"]) == (0, k, k, 0)
+        assert (st["n_ndsrc"], st["n_ddsrc"], st["n_dnsrc"]) == (k, 0, 1)
+    st = G.split_stats(k)                       # strict '>': degree == TH stays normal
+    assert st["d"] == 0 and st["e_nn"] == 2 * k
+
+
+def test_split_threshold_edge_cases(oracle_mod, inputs_mod):
+    src, dst = inputs_mod.rmat_edges(9)
+    G = _graph(oracle_mod, 512, src, dst)
+    deg = G.degrees()
+    st = G.split_stats(int(deg.max()))
+    assert st["d"] == 0 and st["e_nn"] == G.m and st["e_nd"] == st["e_dn"] == st["e_dd"] == 0
+    st = G.split_stats(0)                       # every non-isolated vertex is a delegate
+    assert st["d"] == int((deg > 0).sum())
+    assert st["e_nn"] == st["e_nd"] == st["e_dn"] == 0 and st["e_dd"] == G.m
+    n, s, t, _ = complete(8)
+    st = _graph(oracle_mod, n, s, t).split_stats(6)
+    assert st["d"] == 8 and st["e_dd"] == 56
+
+
+def test_split_path_th1(oracle_mod):
+    # path 0-1-2-3-4: interior vertices have degree 2 > 1 -> delegates 0,1,2
+    n, src, dst, _ = path(5)
+    G = _graph(oracle_mod, n, src, dst)
+    r = G.split_rows(1)
+    assert r["did"].tolist() == [-1, 0, 1, 2, -1]
+    assert r["nd_col"].tolist() == [0, 2]       # 0->1 (delegate 0), 4->3 (delegate 2)
+    assert r["nd_off"].tolist() == [0, 1, 1, 1, 1, 2]
+    assert r["dn_off"].tolist() == [0, 1, 1, 2] and r["dn_col"].tolist() == [0, 4]
+    assert r["dd_off"].tolist() == [0, 1, 3, 4] and r["dd_col"].tolist() == [1, 0, 2, 1]
+    assert r["nn_col"].size == 0
+
+
+def _csr_to_pairs(off, col):
+    rows = np.repeat(np.arange(len(off) - 1), np.diff(off))
+    return set(zip(rows.tolist(), col.tolist()))
+
+
+@pytest.mark.parametrize("TH", [0, 2, 8, 16, 32, 10**6])
+def test_split_identities_rmat(oracle_mod, inputs_mod, TH):
+    src, dst = inputs_mod.rmat_edges(10)
+    G = _graph(oracle_mod, 1024, src, dst)
+    st = G.split_stats(TH)
+    r = G.split_rows(TH)
+    assert st["e_nn"] + st["e_nd"] + st["e_dn"] + st["e_dd"] == G.m
+    assert st["e_nd"] == st["e_dn"]
+    assert st["d"] == int((G.degrees() > TH).sum())
+    dd = _csr_to_pairs(r["dd_off"], r["dd_col"])
+    assert dd == {(b, a) for a, b in dd}                     # dd symmetric
+    nd = _csr_to_pairs(r["nd_off"], r["nd_col"])             # (normal, delegate id)
+    dn = _csr_to_pairs(r["dn_off"], r["dn_col"])             # (delegate id, normal)
+    assert nd == {(b, a) for a, b in dn}                     # nd is dn reversed
+    nn = _csr_to_pairs(r["nn_off"], r["nn_col"])
+    assert nn == {(b, a) for a, b in nn}                     # nn symmetric at one GPU
+
+
+def test_fig2_renumbering(oracle_mod):
+    """Fig. 2 caption: TH = 5, vertices 7 and 8 become delegates 0 and 1."""
+    fix = {}
+    with open(os.path.join(GOLD, "fig2_renumbering.txt")) as f:
+        for line in f:
+            if line.startswith("#") or not line.strip():
+                continue
+            t = line.split()
+            if t[0] == "threshold":
+                TH = int(t[1])
+            else:
+                fix[int(t[1])] = int(t[2])
+    # a graph on 0..12 in which only 7 and 8 have degree > 5 (7: 6, 8: 7)
+    pairs = [(7, x) for x in (0, 1, 2, 3, 4, 8)] + [(8, x) for x in (5, 6, 9, 10, 11, 12)]
+    pairs += [(0, 1), (2, 3)]
+    src = np.array([a for a, _ in pairs], np.int32)
+    dst = np.array([b for _, b in pairs], np.int32)
+    G = _graph(oracle_mod, 13, src, dst)
+    assert (G.degrees() > TH).sum() == len(fix)
+    did = G.delegate_ids(TH)
+    for v, want in fix.items():
+        assert did[v] == want
+    assert (did[[v for v in range(13) if v not in fix]] == -1).all()
+
+
+def test_bv_closed_form_is_geometric_sum(oracle_mod):
+    for a in (1e-3, 0.01, 0.1, 0.37, 0.5, 0.9, 1.0):
+        for k in (1, 2, 3, 7, 16, 33, 64):
+            direct = sum((1 - a) ** i for i in range(k))
+            assert oracle_mod.bv_term(a, k) == pytest.approx(direct, rel=1e-12)
+            # the first line of the printed equation sums to exactly 1 for every
+            # od, which is why it is read as garbled (see the reading list)
+            printed = (1 - a) ** k + sum(a * (1 - a) ** i for i in range(k))
+            assert printed == pytest.approx(1.0, rel=1e-12)
+    # large od: the term tends to 1/a, so sum over U tends to |U|/a = |U|(q+s)/q
+    assert oracle_mod.bv_term(0.25, 10**6) == pytest.approx(4.0)
+    assert oracle_mod.bv_approx(10, 2, 6) == pytest.approx(10 * 8 / 2)
+    assert oracle_mod.bv_approx(0, 2, 6) == 0.0 and oracle_mod.bv_approx(5, 0, 6) == 0.0
+
+
+def _factors():
+    f0, f1 = {}, {}
+    with open(os.path.join(GOLD, "do_factors.txt")) as f:
+        for line in f:
+            if line.startswith("#") or not line.strip():
+                continue
+            kind, k, v = line.split()
+            (f0 if kind == "factor0" else f1)[k] = float(v)
+    order = ("dd", "dn", "nd")
+    return tuple(f0[k] for k in order), tuple(f1[k] for k in order)
+
+
+def test_do_replay_star_hand_derived(oracle_mod):
+    """Star with hub 0 (the only delegate) and k leaves, searched from leaf 1.
+    Level 0: frontier {1}: nd has q=1, FV=1, U = {hub}, s = k-1 unvisited
+    leaves, BV = 1*(1+k-1)/1 = k; FV = 1 > 1e-7*k so nd goes backward.
+    Level 1: frontier {hub}: dn has q=1, FV=k, U = k-1 leaves, s = 0, BV = k-1;
+    k > 0.05(k-1) so dn goes backward. nd has no frontier and stays backward.
+    Level 2: frontier = k-1 leaves: nd q=k-1, FV=k-1, U = {}, BV = 0."""
+    k = 12
+    n, src, dst, _ = star(k)
+    G = _graph(oracle_mod, n, src, dst)
+    f0, f1 = _factors()
+    depth, _ = G.bfs(1)
+    L = G.do_replay(2, depth, f0, f1)
+    assert len(L) == 3
+    assert L[0]["q"] == [0, 0, 1] and L[0]["FV"] == [0, 0, 1]
+    assert L[0]["U"] == [0, k - 1, 1] and L[0]["s"] == [0, 1, k - 1]
+    assert L[0]["BV"][2] == pytest.approx(k) and L[0]["dir"] == [0, 0, 1]
+    assert L[1]["q"] == [0, 1, 0] and L[1]["FV"] == [0, k, 0]
+    assert L[1]["U"] == [0, k - 1, 0] and L[1]["s"] == [0, 0, k - 1]
+    assert L[1]["BV"][1] == pytest.approx(k - 1) and L[1]["dir"] == [0, 1, 1]
+    assert L[2]["q"] == [0, 0, k - 1] and L[2]["FV"] == [0, 0, k - 1]
+    assert L[2]["U"] == [0, 0, 0] and L[2]["BV"] == [0.0, 0.0, 0.0]
+    assert L[2]["dir"] == [0, 1, 1]
+    assert [x["frontier_normal"] for x in L] == [1, 0, k - 1]
+    assert [x["frontier_delegate"] for x in L] == [0, 1, 0]
+
+
+def test_do_replay_two_hubs_strict_comparison(oracle_mod):
+    """Hubs A=0 and B=1 joined, each with k leaves; TH=2, source A.
+    Level 0: dd: q=1, FV=1, U={B}, s=1 -> BV = 1*(1+1)/1 = 2 and
+    FV = 1 is not > 0.5*2 = 1, so dd stays forward (strict comparison).
+    dn: q=1, FV=k, U = all 2k leaves, s = |{B}| = 1 -> BV = 2k*(1+1)/1 = 4k,
+    and FV = k > 0.05*4k = 0.2k, so dn goes backward."""
+    k = 10
+    pairs = [(0, 1)] + [(0, 2 + i) for i in range(k)] + [(1, 2 + k + i) for i in range(k)]
+    src = np.array([a for a, _ in pairs], np.int32)
+    dst = np.array([b for _, b in pairs], np.int32)
+    G = _graph(oracle_mod, 2 + 2 * k, src, dst)
+    f0, f1 = _factors()
+    depth, _ = G.bfs(0)
+    L = G.do_replay(2, depth, f0, f1)
+    assert L[0]["q"][:2] == [1, 1] and L[0]["FV"][:2] == [1, k]
+    assert L[0]["U"][:2] == [1, 2 * k] and L[0]["s"][:2] == [1, 1]
+    assert L[0]["BV"][0] == pytest.approx(2.0) and L[0]["BV"][1] == pytest.approx(4 * k)
+    assert L[0]["dir"] == [0, 1, 0]
+    # factor1 > FV/BV at a backward kernel switches it back to forward
+    L2 = G.do_replay(2, depth, f0, (0.0, 10.0, 0.0))
+    assert L2[0]["dir"][1] == 1
+    assert L2[1]["dir"][1] == (0 if L2[1]["q"][1] > 0 else 1)
+
+
+def test_table1_totals():
+    """Table I: per-subgraph rows summed over p GPUs give 8n + 8dp + 4m + 4|E_nn|."""
+    with open(os.path.join(GOLD, "table1_memory.txt")) as f:
+        rows = [list(map(int, l.split())) for l in f if l.strip() and not l.startswith("#")]
+    for p, n, d, e_nn, e_nd, e_dn, e_dd, want in rows:
+        per_gpu = (n / p * 4 + e_nn / p * 8) + (n / p * 4 + e_nd / p * 4) \
+            + (d * 4 + e_dn / p * 4) + (d * 4 + e_dd / p * 4)
+        assert per_gpu * p == want
+        m = e_nn + e_nd + e_dn + e_dd
+        assert 8 * n + 8 * d * p + 4 * m + 4 * e_nn == want
