@@ -1,0 +1,285 @@
+/*
+ * dsbfs: degree-separated, direction-optimized breadth-first search for one
+ * AMD Instinct MI355X (gfx950).
+ *
+ * The method is that of Pan, Pearce and Owens, "Scalable Breadth-First Search
+ * on a GPU Cluster" (arXiv 1803.03922), for one GPU's share of the graph:
+ * vertices are separated by degree into delegates (degree > TH) and normal
+ * vertices (Section III-A), edges are stored as four subgraphs nn, nd, dn, dd
+ * with 32-bit local IDs (Section III-C, Table I), and each BFS level chooses
+ * top-down or bottom-up traversal per subgraph from a workload comparison
+ * (Section IV-B). On top of it: bit-parallel multi-source BFS (64 sources per
+ * batch as lanes of a 64-bit mask per vertex) and a continuous-batching query
+ * server.
+ *
+ * Conventions for every function below:
+ *  - Every function returns a dsbfs_status: 0 on success, a negative code on
+ *    failure. No function throws or aborts across this boundary. The message
+ *    of the last failure on the calling thread is dsbfs_last_error().
+ *  - Vertex IDs are int32 in [0, n) with n <= 2^31 - 1; edge counts are int64.
+ *  - "stream" is a hipStream_t passed as void* (NULL = the legacy default
+ *    stream). Device work of a call is ordered on that stream. Calls that
+ *    return results on the host synchronize the stream before returning.
+ *  - Device pointers are plain device (HBM) addresses, host pointers are
+ *    plain host addresses; no framework types cross this boundary.
+ *  - A graph is immutable after creation: concurrent searches on one graph
+ *    with distinct workspaces and streams are safe. A workspace is used by
+ *    one call at a time.
+ */
+#ifndef DSBFS_H
+#define DSBFS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t dsbfs_status;
+
+enum {
+  DSBFS_OK = 0,
+  DSBFS_ERR_INVALID_ARG = -1,   /* bad pointer, size, vertex ID or option */
+  DSBFS_ERR_RANGE = -2,         /* a size does not fit the layout's integer widths */
+  DSBFS_ERR_OUT_OF_MEMORY = -3, /* the allocator returned NULL */
+  DSBFS_ERR_BUDGET = -4,        /* server admission refused: HBM budget exhausted */
+  DSBFS_ERR_HIP = -5,           /* a HIP runtime call failed (message kept) */
+  DSBFS_ERR_NOT_READY = -6,     /* server wait timed out */
+  DSBFS_ERR_DEVICE = -7         /* a kernel reported an internal failure */
+};
+
+/*
+ * Device memory provider. alloc returns a device pointer of at least `bytes`
+ * bytes usable on `stream`, or NULL; free releases one. Passing NULL for the
+ * allocator everywhere below means hipMalloc / hipFree. The library keeps the
+ * pointer it was given for the lifetime of the objects created with it.
+ */
+typedef struct dsbfs_allocator {
+  void *ctx;
+  void *(*alloc)(void *ctx, size_t bytes, void *stream);
+  void (*free)(void *ctx, void *ptr, void *stream);
+} dsbfs_allocator;
+
+/* Options of graph construction. */
+typedef struct dsbfs_build_opts {
+  int32_t threshold;       /* TH >= 0: a vertex is a delegate iff degree > TH
+                              (Section II-A, "delegates"; Section III-A) */
+  int32_t edges_on_device; /* 1: src/dst are device pointers; 0: host pointers */
+  int32_t keep_plain_csr;  /* 1: keep the plain CSR too (needed by mode 0 and by
+                              multi-source BFS); 0: free it after the split */
+  int32_t reserved;
+} dsbfs_build_opts;
+
+/* Sizes of a built graph. Degrees are counted after symmetrization,
+   self-loop removal and de-duplication. */
+typedef struct dsbfs_graph_stats {
+  int64_t n;          /* vertices */
+  int64_t m_dir;      /* directed edges (twice the undirected simple edges) */
+  int64_t d;          /* delegates */
+  int64_t e_nn, e_nd, e_dn, e_dd; /* directed edges per class (Section II-A) */
+  int64_t n_ndsrc;    /* normal vertices with a delegate neighbour (Section IV-B) */
+  int64_t n_ddsrc;    /* delegates with a delegate neighbour */
+  int64_t n_dnsrc;    /* delegates with a normal neighbour */
+  int64_t max_degree;
+  int64_t bytes_layout; /* device bytes of the degree-separated layout */
+  int64_t bytes_plain;  /* device bytes of the plain CSR (0 if not kept) */
+  int32_t threshold;
+  int32_t reserved;
+} dsbfs_graph_stats;
+
+/* Per-search options. */
+typedef struct dsbfs_run_opts {
+  int32_t mode;         /* 0: plain top-down BFS on the plain CSR;
+                           1: degree-separated direction-optimized BFS */
+  int32_t want_parent;  /* 1: write parent[] as well as depth[] */
+  double factor0[3];    /* forward->backward switch factors for dd, dn, nd
+                           (Section IV-B); defaults 0.5, 0.05, 1e-7 (Section VI-B) */
+  double factor1[3];    /* backward->forward switch factors; default 0 */
+  int32_t forced;       /* direction schedule: 0 heuristic (Section IV-B);
+                           1 always forward; 2 backward wherever possible from
+                           level 1 on; 3 seeded random per level and kernel.
+                           Depths never depend on it (Section IV-B). */
+  int32_t reserved;
+  uint64_t forced_seed; /* seed of schedule 3 */
+} dsbfs_run_opts;
+
+/* Fills *o with the defaults listed above (mode 1, parents on). */
+dsbfs_status dsbfs_run_opts_default(dsbfs_run_opts *o);
+
+/* One BFS level of a mode-1 search: the inputs of the direction decision
+   (Section IV-B) for the three kernels with direction optimization, indexed
+   dd = 0, dn = 1, nd = 2, and the work the level's kernels did. */
+typedef struct dsbfs_level_stats {
+  int64_t q[3];      /* frontier vertices with an edge in that subgraph */
+  int64_t s[3];      /* unvisited sources in the forward subgraph */
+  int64_t U[3];      /* unvisited sources of the reversed subgraph */
+  int64_t FV[3];     /* forward workload: frontier neighbour-list lengths */
+  double BV[3];      /* backward workload |U|(q+s)/q */
+  int32_t dir[3];    /* direction taken: 0 forward, 1 backward */
+  int32_t reserved;
+  int64_t FV_nn, q_nn;               /* nn is always forward */
+  int64_t frontier_normal, frontier_delegate;
+} dsbfs_level_stats;
+
+/* Summary of one search. levels[] is caller memory of `capacity` records;
+   the first min(num_levels, capacity) are filled (mode 1 only). */
+typedef struct dsbfs_run_stats {
+  int32_t num_levels;   /* levels with a non-empty frontier */
+  int32_t capacity;
+  dsbfs_level_stats *levels;
+  int64_t reached;      /* vertices with depth >= 0 */
+  int64_t edges_cc;     /* undirected simple edges in the source's component */
+} dsbfs_run_stats;
+
+typedef struct dsbfs_graph dsbfs_graph;
+typedef struct dsbfs_workspace dsbfs_workspace;
+typedef struct dsbfs_server dsbfs_server;
+
+/*
+ * Builds the graph on the device from an edge list of num_edges pairs
+ * (src[i], dst[i]): the simple symmetric graph on [0, num_vertices) (the
+ * paper assumes a symmetric graph made by edge doubling, Section II-A and
+ * Section VI-A; self-loops and duplicates are dropped), then the degree
+ * separation at opts->threshold: delegate IDs in ascending vertex ID
+ * (Fig. 2 caption), the four subgraphs nn/nd/dn/dd (Section III-C), the nd
+ * source list and the dd/dn source masks (Section IV-B).
+ * Ownership: the caller keeps src/dst (copied); the graph owns its device
+ * memory, taken from `alloc` (NULL = hipMalloc). Synchronizes `stream`.
+ * Errors: INVALID_ARG (null pointer, num_vertices < 1, num_edges < 0, an
+ * endpoint outside [0, n), threshold < 0), RANGE (a row too long for the
+ * packed offsets), OUT_OF_MEMORY, HIP.
+ */
+dsbfs_status dsbfs_graph_create(const int32_t *src, const int32_t *dst, int64_t num_edges,
+                                int32_t num_vertices, const dsbfs_build_opts *opts,
+                                const dsbfs_allocator *alloc, void *stream, dsbfs_graph **out);
+
+/* Sizes of a graph (host struct). */
+dsbfs_status dsbfs_graph_stats_get(const dsbfs_graph *g, dsbfs_graph_stats *out);
+
+/*
+ * Copies one array of the device layout to host memory, for inspection and
+ * tests. `which`: 0 degree int32[n]; 1 delegate ID int32[n] (-1 for normal);
+ * 2 vertex of each delegate int32[d]; 3 normal row offsets uint64[n+1];
+ * 4 normal columns int32[]; 5 delegate row offsets uint64[d+1]; 6 delegate
+ * columns int32[]; 7 nd source list int32[n_ndsrc]; 8 dd source mask
+ * uint32[ceil(d/32)]; 9 dn source mask uint32[ceil(d/32)]; 10 plain CSR
+ * offsets int64[n+1]; 11 plain CSR columns int32[m_dir].
+ * Row offsets are packed: bits 0..39 = start of the row, bits 40..63 = length
+ * of its first part (nn for normal rows, dd for delegate rows); the row ends
+ * at the start of the next row. Normal row v holds nn neighbours (vertex IDs)
+ * then nd neighbours (delegate IDs); delegate row k holds dd neighbours
+ * (delegate IDs) then dn neighbours (vertex IDs); each part ascending.
+ * *bytes receives the array size; nothing is copied if capacity is smaller.
+ * Synchronizes the graph's stream.
+ */
+dsbfs_status dsbfs_graph_export(const dsbfs_graph *g, int32_t which, void *host_out,
+                                int64_t capacity_bytes, int64_t *bytes);
+
+/* Frees the graph's device memory. NULL is accepted. */
+dsbfs_status dsbfs_graph_destroy(dsbfs_graph *g);
+
+/*
+ * Per-call scratch for searches on graph g: bitmaps, queues and counters of
+ * single-source search, and lane state for up to max_lanes (0 or 64)
+ * simultaneous multi-source lanes. Memory from the graph's allocator.
+ */
+dsbfs_status dsbfs_workspace_create(const dsbfs_graph *g, int32_t max_lanes,
+                                    dsbfs_workspace **out);
+dsbfs_status dsbfs_workspace_destroy(dsbfs_workspace *ws);
+
+/*
+ * Single-source BFS from `source`. depth (device int32[n], required) gets the
+ * hop distance of every vertex (-1 unreachable); parent (device int32[n], or
+ * NULL when opts->want_parent is 0) gets a BFS-tree parent (source: itself;
+ * unreachable: -1). Both indexed by original vertex ID. Mode 1 follows
+ * Section IV: per level, previsit of the normal queue and of the delegate
+ * frontier mask, the direction decision of Section IV-B for dd, dn and nd
+ * (nn always forward), then the visits. opts NULL = defaults. stats may be
+ * NULL; when given, the call synchronizes the stream and fills it.
+ * Errors: INVALID_ARG (source outside [0, n), null depth, mode 0 without a
+ * plain CSR, parent NULL while want_parent), HIP, DEVICE.
+ */
+dsbfs_status dsbfs_bfs(const dsbfs_graph *g, dsbfs_workspace *ws, int32_t source,
+                       const dsbfs_run_opts *opts, int32_t *depth, int32_t *parent,
+                       dsbfs_run_stats *stats, void *stream);
+
+/* Tile and schedule parameters of multi-source BFS (chosen by the tuner). */
+typedef struct dsbfs_ms_opts {
+  int32_t block;          /* threads per workgroup: 64, 128, 256, 512 or 1024 */
+  int32_t blocks_per_cu;  /* workgroups per compute unit of the persistent grid */
+  int32_t bu_permille;    /* bottom-up when active frontier vertices exceed this
+                             many per mille of n (0..1000) */
+  int32_t use_graph;      /* 1: capture the launch in a hipGraph and replay it */
+} dsbfs_ms_opts;
+
+/*
+ * Multi-source BFS from k sources (host int32[k], each in [0, n)), bit-parallel
+ * in batches of 64 lanes, all batches in one persistent launch. depth is a
+ * device int32[k][n] array: row i gets the hop distances from sources[i]
+ * (-1 unreachable), exactly as k single-source searches would. Uses the plain
+ * CSR (graph built with keep_plain_csr = 1). opts NULL = tuned/cached
+ * defaults. Errors: INVALID_ARG, HIP, DEVICE (persistent-grid barrier failure).
+ */
+dsbfs_status dsbfs_msbfs(const dsbfs_graph *g, dsbfs_workspace *ws, const int32_t *sources,
+                         int32_t k, const dsbfs_ms_opts *opts, int32_t *depth, void *stream);
+
+/*
+ * Autotuner of multi-source BFS: times every candidate tile/schedule setting on
+ * graph g with the given sources and writes the fastest to *best. If
+ * cache_path is not NULL the result is read from / stored in that JSON file,
+ * keyed by the graph's n, m_dir and the device name.
+ */
+dsbfs_status dsbfs_msbfs_tune(const dsbfs_graph *g, dsbfs_workspace *ws, const int32_t *sources,
+                              int32_t k, const char *cache_path, dsbfs_ms_opts *best,
+                              void *stream);
+
+/* Per-query record of the server, times in host steady-clock nanoseconds. */
+typedef struct dsbfs_query_stats {
+  int64_t arrival_ns, admit_ns, start_ns, done_ns;
+  int32_t graph_id, source, levels, batched; /* batched: 1 = ran as a lane */
+} dsbfs_query_stats;
+
+/* Server configuration. */
+typedef struct dsbfs_server_opts {
+  size_t hbm_budget_bytes; /* cap on graphs + lane state + result buffers */
+  int32_t max_lanes;       /* lanes per running batch, 1..64 */
+  int32_t batched;         /* 1: continuous batching into multi-source lanes;
+                              0: one query at a time with single-source BFS */
+  dsbfs_ms_opts ms;        /* kernel parameters of the batched path */
+} dsbfs_server_opts;
+
+/*
+ * Query server (continuous batching). create starts one scheduler thread on
+ * the current device; add_graph moves a graph under the server (admitted only
+ * if it fits the budget: else BUDGET and the caller keeps it); submit queues a
+ * single-source query (arrival_ns: caller's steady-clock timestamp, 0 = now)
+ * and returns a ticket; wait blocks until that query's depth array is on the
+ * device (timeout_ns < 0: forever; NOT_READY on timeout) and returns its
+ * device pointer (int32[n_graph], owned by the server until release);
+ * release returns the result buffer to the budget. Results stay device
+ * resident. destroy stops the thread and frees everything.
+ */
+dsbfs_status dsbfs_server_create(const dsbfs_server_opts *opts, const dsbfs_allocator *alloc,
+                                 dsbfs_server **out);
+dsbfs_status dsbfs_server_add_graph(dsbfs_server *s, dsbfs_graph *g, int32_t *graph_id);
+dsbfs_status dsbfs_server_submit(dsbfs_server *s, int32_t graph_id, int32_t source,
+                                 int64_t arrival_ns, int64_t *ticket);
+dsbfs_status dsbfs_server_wait(dsbfs_server *s, int64_t ticket, int64_t timeout_ns,
+                               const int32_t **depth_dev, dsbfs_query_stats *stats);
+dsbfs_status dsbfs_server_release(dsbfs_server *s, int64_t ticket);
+dsbfs_status dsbfs_server_destroy(dsbfs_server *s);
+
+/* Host steady-clock now, in nanoseconds (the server's time base). */
+int64_t dsbfs_now_ns(void);
+
+/* Static text of a status code. */
+const char *dsbfs_status_str(dsbfs_status st);
+/* Message of the last failure on the calling thread ("" if none). */
+const char *dsbfs_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DSBFS_H */

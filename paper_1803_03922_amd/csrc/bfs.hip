@@ -1,0 +1,768 @@
+// Single-source BFS on one GPU.
+//
+// Mode 1 is the paper's degree-separated direction-optimized BFS at p = 1
+// (Section IV): the normal frontier is a compacted queue, the delegate
+// frontier a bitmask (Section IV-A). Each level runs
+//   previsit  - normal queue: nn/nd workloads, normal frontier bitmap;
+//               delegate mask: frontier list, dd/dn workloads, bottom-up
+//               candidate list (Section IV, "previsit");
+//   decision  - per kernel dd, dn, nd: FV vs BV = |U|(q+s)/q with factor0 /
+//               factor1 (Section IV-B); nn is always top-down;
+//   visits    - top-down: normal queue over nn (+nd), delegate list over dd
+//               and/or dn with merge-path style load balance over the
+//               frontier's prefix sum; bottom-up: dn via the nd rows of the nd
+//               source list, dd and nd via the delegate rows of unvisited
+//               delegates, each stopping at the first frontier parent;
+//   close     - Vd |= Nd, Fd = Nd, Nd = 0, clear the normal frontier bitmap.
+// Exactly-once discovery comes from atomic test-and-set on the visited
+// bitmaps (normals: Vn; delegates: Nd, checked against Vd), so queues hold no
+// duplicates and depth/parent are written once per vertex.
+//
+// Mode 0 is plain top-down BFS over the plain CSR (the paper's "BFS" beside
+// "DOBFS", Section VI-C), with the same load-balanced expansion.
+#include <cmath>
+
+#include "internal.hpp"
+
+namespace dsbfs {
+
+Workspace::~Workspace() {
+  if (hctr) (void)hipHostFree(hctr);
+}
+
+namespace {
+
+constexpr int kBS = 256;
+constexpr int kNW = kBS / kWave;
+
+// ---------------------------------------------------------------------------
+// init
+// ---------------------------------------------------------------------------
+__global__ void k_init(int32_t *depth, int32_t *parent, int32_t n, uint32_t *Vn, uint32_t *Fn,
+                       int32_t nwords, uint32_t *Vd, uint32_t *Fd, uint32_t *Nd, int32_t dwords) {
+  const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+  const int64_t t0 = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  for (int64_t v = t0; v < n; v += stride) {
+    depth[v] = -1;
+    if (parent) parent[v] = -1;
+  }
+  for (int64_t w = t0; w < nwords; w += stride) {
+    Vn[w] = 0;
+    Fn[w] = 0;
+  }
+  for (int64_t w = t0; w < dwords; w += stride) {
+    Vd[w] = 0;
+    Fd[w] = 0;
+    Nd[w] = 0;
+  }
+}
+
+// Seeds the source: a delegate enters the delegate frontier mask, a normal
+// vertex the normal queue. prev->qn_next becomes the level-0 queue length.
+__global__ void k_seed(int32_t s, const int32_t *did, int32_t *depth, int32_t *parent,
+                       uint32_t *Vn, uint32_t *Vd, uint32_t *Fd, int32_t *Q, LevelCtr *prev,
+                       int mode) {
+  depth[s] = 0;
+  if (parent) parent[s] = s;
+  const int32_t k = mode == 1 ? did[s] : -1;
+  if (k >= 0) {
+    Vd[k >> 5] |= 1u << (k & 31);
+    Fd[k >> 5] |= 1u << (k & 31);
+    prev->qn_next = 0;
+  } else {
+    Vn[s >> 5] |= 1u << (s & 31);
+    Q[0] = s;
+    prev->qn_next = 1;
+  }
+  prev->nc_next = 0;
+}
+
+// ---------------------------------------------------------------------------
+// previsit
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kBS) k_prev_normal(const int32_t *Q, const LevelCtr *prev,
+                                                     const uint64_t *noff, uint32_t *Fn,
+                                                     LevelCtr *cur) {
+  const int64_t qn = int64_t(prev->qn_next);
+  unsigned long long fv_nn = 0, q_nn = 0, fv_nd = 0, q_nd = 0;
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < qn;
+       i += int64_t(gridDim.x) * blockDim.x) {
+    const int32_t u = Q[i];
+    const uint64_t w0 = noff[u], w1 = noff[u + 1];
+    const int64_t nn = row_first(w0), nd = row_start(w1) - row_start(w0) - nn;
+    fv_nn += nn;
+    q_nn += nn > 0;
+    fv_nd += nd;
+    q_nd += nd > 0;
+    atomicOr(&Fn[u >> 5], 1u << (u & 31));
+  }
+  fv_nn = wave_sum(fv_nn);
+  q_nn = wave_sum(q_nn);
+  fv_nd = wave_sum(fv_nd);
+  q_nd = wave_sum(q_nd);
+  if (lane_id() == 0) {
+    if (fv_nn) atomicAdd(&cur->fv_nn, fv_nn);
+    if (q_nn) atomicAdd(&cur->q_nn, q_nn);
+    if (fv_nd) atomicAdd(&cur->fv_nd, fv_nd);
+    if (q_nd) atomicAdd(&cur->q_nd, q_nd);
+  }
+}
+
+// One thread per mask word: frontier delegates -> dlist (+ dd/dn workloads),
+// unvisited delegates with a dd or dn edge -> dcand.
+__global__ void __launch_bounds__(kBS) k_prev_deleg(const uint32_t *Fd, const uint32_t *Vd,
+                                                    const uint32_t *ddm, const uint32_t *dnm,
+                                                    int32_t dwords, const uint64_t *doff,
+                                                    int32_t *dlist, int32_t *dcand,
+                                                    LevelCtr *cur) {
+  unsigned long long fv_dd = 0, q_dd = 0, fv_dn = 0, q_dn = 0;
+  for (int64_t w = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; w < dwords;
+       w += int64_t(gridDim.x) * blockDim.x) {
+    uint32_t f = Fd[w];
+    uint32_t c = ~Vd[w] & (ddm[w] | dnm[w]);
+    if (f) {
+      unsigned long long pos = atomicAdd(&cur->nd_list, (unsigned long long)__popc(f));
+      while (f) {
+        const int b = __ffs(f) - 1;
+        f &= f - 1;
+        const int32_t k = int32_t(w * 32 + b);
+        dlist[pos++] = k;
+        const uint64_t w0 = doff[k], w1 = doff[k + 1];
+        const int64_t dd = row_first(w0), dn = row_start(w1) - row_start(w0) - dd;
+        fv_dd += dd;
+        q_dd += dd > 0;
+        fv_dn += dn;
+        q_dn += dn > 0;
+      }
+    }
+    if (c) {
+      unsigned long long pos = atomicAdd(&cur->nd_cand, (unsigned long long)__popc(c));
+      while (c) {
+        const int b = __ffs(c) - 1;
+        c &= c - 1;
+        dcand[pos++] = int32_t(w * 32 + b);
+      }
+    }
+  }
+  fv_dd = wave_sum(fv_dd);
+  q_dd = wave_sum(q_dd);
+  fv_dn = wave_sum(fv_dn);
+  q_dn = wave_sum(q_dn);
+  if (lane_id() == 0) {
+    if (fv_dd) atomicAdd(&cur->fv_dd, fv_dd);
+    if (q_dd) atomicAdd(&cur->q_dd, q_dd);
+    if (fv_dn) atomicAdd(&cur->fv_dn, fv_dn);
+    if (q_dn) atomicAdd(&cur->q_dn, q_dn);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// visits
+// ---------------------------------------------------------------------------
+struct Out {
+  int32_t *depth;
+  int32_t *parent;
+  int32_t level1;  // depth written by this level (L + 1)
+  __device__ __forceinline__ void put(int32_t v, int32_t p) const {
+    depth[v] = level1;
+    if (parent) parent[v] = p;
+  }
+};
+
+__device__ __forceinline__ void flush_work(LevelCtr *cur, unsigned long long tdv,
+                                           unsigned long long tde, unsigned long long buc,
+                                           unsigned long long bue, unsigned long long cl) {
+  tdv = wave_sum(tdv);
+  tde = wave_sum(tde);
+  buc = wave_sum(buc);
+  bue = wave_sum(bue);
+  cl = wave_sum(cl);
+  if (lane_id() == 0) {
+    if (tdv) atomicAdd(&cur->td_vertices, tdv);
+    if (tde) atomicAdd(&cur->td_edges, tde);
+    if (buc) atomicAdd(&cur->bu_candidates, buc);
+    if (bue) atomicAdd(&cur->bu_edges, bue);
+    if (cl) atomicAdd(&cur->claimed, cl);
+  }
+}
+
+// Top-down from the normal queue over nn (always) and nd (if nd_td). Each
+// wave owns 64 queue entries; their row lengths are prefix-summed across the
+// wave and the wave walks the concatenated edge range 64 edges at a time, so
+// lanes stay busy whatever the mix of degrees (all are <= TH).
+__global__ void __launch_bounds__(kBS) k_td_normal(const int32_t *Q, int64_t qn,
+                                                   const uint64_t *noff, const int32_t *ncol,
+                                                   const int32_t *vid_of, int nd_td, Out out,
+                                                   uint32_t *Vn, const uint32_t *Vd, uint32_t *Nd,
+                                                   int32_t *Qnext, LevelCtr *cur) {
+  __shared__ int32_t s_excl[kNW][kWave];
+  __shared__ int32_t s_u[kNW][kWave];
+  __shared__ int32_t s_nn[kNW][kWave];
+  __shared__ int64_t s_beg[kNW][kWave];
+  const int w = threadIdx.x / kWave, l = lane_id();
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  int32_t u = 0, nn = 0, len = 0;
+  int64_t beg = 0;
+  if (i < qn) {
+    u = Q[i];
+    const uint64_t w0 = noff[u], w1 = noff[u + 1];
+    beg = row_start(w0);
+    nn = int32_t(row_first(w0));
+    len = nd_td ? int32_t(row_start(w1) - beg) : nn;
+  }
+  const int32_t incl = wave_incl_scan(len);
+  const int32_t T = __shfl(incl, kWave - 1, kWave);
+  s_excl[w][l] = incl - len;
+  s_u[w][l] = u;
+  s_nn[w][l] = nn;
+  s_beg[w][l] = beg;
+  __syncthreads();
+  unsigned long long claimed = 0;
+  for (int32_t e0 = 0; e0 < T; e0 += kWave) {
+    const int32_t e = e0 + l;
+    bool won = false;
+    int32_t v = 0;
+    if (e < T) {
+      int lo = 0;
+#pragma unroll
+      for (int step = 32; step > 0; step >>= 1) {
+        const int c = lo + step;
+        if (c < kWave && s_excl[w][c] <= e) lo = c;
+      }
+      const int32_t j = e - s_excl[w][lo];
+      const int32_t src = s_u[w][lo];
+      v = ncol[s_beg[w][lo] + j];
+      if (j < s_nn[w][lo]) {
+        won = bit_claim(Vn, uint32_t(v));
+        if (won) out.put(v, src);
+      } else if (!bit_test(Vd, uint32_t(v)) && bit_claim(Nd, uint32_t(v))) {
+        out.put(vid_of[v], src);
+        ++claimed;
+      }
+    }
+    const int64_t pos = wave_append(won, &cur->qn_next);
+    if (won) {
+      Qnext[pos] = v;
+      ++claimed;
+    }
+  }
+  flush_work(cur, i < qn ? 1 : 0, l == 0 ? (unsigned long long)T : 0, 0, 0, claimed);
+}
+
+// Largest idx in [0, cnt) with pre[idx] <= e (pre non-decreasing, pre[0] = 0).
+__device__ __forceinline__ int64_t seg_search(const int64_t *pre, int64_t cnt, int64_t e) {
+  int64_t lo = 0, hi = cnt - 1;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi + 1) >> 1;
+    if (pre[mid] <= e) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+__global__ void k_dlen(const int32_t *dlist, const LevelCtr *cur, const uint64_t *doff, int dd_td,
+                       int dn_td, int32_t *dlen) {
+  const int64_t nd = int64_t(cur->nd_list);
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < nd;
+       i += int64_t(gridDim.x) * blockDim.x) {
+    const int32_t k = dlist[i];
+    const uint64_t w0 = doff[k], w1 = doff[k + 1];
+    const int64_t dd = row_first(w0), dn = row_start(w1) - row_start(w0) - dd;
+    dlen[i] = int32_t((dd_td ? dd : 0) + (dn_td ? dn : 0));
+  }
+}
+
+// Top-down from the delegate frontier over dd and/or dn. Delegate degrees span
+// a wide range, so the work is balanced over edges: every thread takes runs of
+// consecutive edges of the frontier's concatenated lists, located by a binary
+// search in the prefix sum of their lengths (merge-path style partitioning).
+constexpr int kRun = 4;
+
+__global__ void __launch_bounds__(kBS) k_td_deleg(const int32_t *dlist, const int64_t *dscan,
+                                                  const LevelCtr *curc, const uint64_t *doff,
+                                                  const int32_t *dcol, const int32_t *vid_of,
+                                                  int dd_td, int dn_td, Out out, uint32_t *Vn,
+                                                  const uint32_t *Vd, uint32_t *Nd,
+                                                  int32_t *Qnext, LevelCtr *cur) {
+  const int64_t nd = int64_t(curc->nd_list);
+  const int64_t E = dscan[nd];
+  const int64_t nruns = (E + kRun - 1) / kRun;
+  unsigned long long claimed = 0, edges = 0;
+  const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+  for (int64_t r0 = int64_t(blockIdx.x) * blockDim.x; r0 < nruns; r0 += stride) {
+    const int64_t r = r0 + threadIdx.x;
+    int64_t e = r * kRun;
+    const int64_t eend = min(e + kRun, E);
+    int64_t idx = r < nruns ? seg_search(dscan, nd, e) : 0;
+    for (int t = 0; t < kRun; ++t, ++e) {
+      bool won = false;
+      int32_t v = 0;
+      if (r < nruns && e < eend) {
+        while (dscan[idx + 1] <= e) ++idx;
+        const int32_t k = dlist[idx];
+        const int64_t j = e - dscan[idx];
+        const uint64_t w0 = doff[k];
+        const int64_t beg = row_start(w0), dd = row_first(w0);
+        const int64_t p = dd_td ? beg + j : beg + dd + j;
+        const bool is_dd = dd_td && j < dd;
+        const int32_t x = dcol[p];
+        ++edges;
+        if (is_dd) {
+          if (!bit_test(Vd, uint32_t(x)) && bit_claim(Nd, uint32_t(x))) {
+            out.put(vid_of[x], vid_of[k]);
+            ++claimed;
+          }
+        } else {
+          won = bit_claim(Vn, uint32_t(x));
+          if (won) {
+            v = x;
+            out.put(x, vid_of[k]);
+            ++claimed;
+          }
+        }
+      }
+      const int64_t pos = wave_append(won, &cur->qn_next);
+      if (won) Qnext[pos] = v;
+    }
+  }
+  flush_work(cur, 0, edges, 0, 0, claimed);
+}
+
+// Bottom-up dn (destination: normal vertices): every unvisited vertex of the
+// nd source list scans its nd part for a delegate in the frontier mask Fd and
+// stops at the first. Candidates still unvisited are compacted for the next
+// bottom-up level.
+__global__ void __launch_bounds__(kBS) k_bu_normal(const int32_t *cin, int64_t nc,
+                                                   const uint64_t *noff, const int32_t *ncol,
+                                                   const uint32_t *Fd, const int32_t *vid_of,
+                                                   Out out, uint32_t *Vn, int32_t *Qnext,
+                                                   int32_t *cout, LevelCtr *cur) {
+  unsigned long long cands = 0, edges = 0, claimed = 0;
+  const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+  for (int64_t i0 = int64_t(blockIdx.x) * blockDim.x; i0 < nc; i0 += stride) {
+    const int64_t i = i0 + threadIdx.x;
+    int32_t v = 0;
+    bool visited = true;
+    int32_t found = -1;
+    if (i < nc) {
+      v = cin[i];
+      visited = bit_test(Vn, uint32_t(v));
+      if (!visited) {
+        ++cands;
+        const uint64_t w0 = noff[v], w1 = noff[v + 1];
+        const int64_t b = row_start(w0) + row_first(w0), e = row_start(w1);
+        for (int64_t p = b; p < e; ++p) {
+          const int32_t k = ncol[p];
+          ++edges;
+          if (bit_test(Fd, uint32_t(k))) {
+            found = k;
+            break;
+          }
+        }
+      }
+    }
+    const bool won = found >= 0 && bit_claim(Vn, uint32_t(v));
+    if (won) {
+      out.put(v, vid_of[found]);
+      ++claimed;
+    }
+    const int64_t pos = wave_append(won, &cur->qn_next);
+    if (won) Qnext[pos] = v;
+    const bool keep = !visited && found < 0;
+    const int64_t cpos = wave_append(keep, &cur->nc_next);
+    if (keep) cout[cpos] = v;
+  }
+  flush_work(cur, 0, 0, cands, edges, claimed);
+}
+
+// Bottom-up dd and/or nd (destination: delegates): one wave per unvisited
+// delegate; the wave reads 64 row entries per step (dd part against Fd, dn
+// part against the normal frontier bitmap Fn) and stops at the first hit.
+__global__ void __launch_bounds__(kBS) k_bu_deleg(const int32_t *dcand, const LevelCtr *curc,
+                                                  const uint64_t *doff, const int32_t *dcol,
+                                                  const uint32_t *Fd, const uint32_t *Fn,
+                                                  const int32_t *vid_of, int dd_bu, int nd_bu,
+                                                  Out out, uint32_t *Nd, LevelCtr *cur) {
+  const int64_t nc = int64_t(curc->nd_cand);
+  const int l = lane_id();
+  const int64_t wid = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) / kWave;
+  const int64_t nw = int64_t(gridDim.x) * blockDim.x / kWave;
+  unsigned long long cands = 0, edges = 0, claimed = 0;
+  for (int64_t ci = wid; ci < nc; ci += nw) {
+    const int32_t k = dcand[ci];
+    const uint64_t w0 = doff[k], w1 = doff[k + 1];
+    const int64_t beg = row_start(w0), mid = beg + row_first(w0), end = row_start(w1);
+    const int64_t lo = dd_bu ? beg : mid, hi = nd_bu ? end : mid;
+    if (lo >= hi) continue;
+    if (l == 0) ++cands;
+    for (int64_t p0 = lo; p0 < hi; p0 += kWave) {
+      const int64_t p = p0 + l;
+      bool hit = false;
+      int32_t x = 0;
+      if (p < hi) {
+        x = dcol[p];
+        hit = p < mid ? bit_test(Fd, uint32_t(x)) : bit_test(Fn, uint32_t(x));
+      }
+      const uint64_t m = __ballot(hit);
+      if (m) {
+        const int f = __ffsll(static_cast<long long>(m)) - 1;
+        if (l == 0) edges += uint64_t(f + 1);
+        if (l == f && bit_claim(Nd, uint32_t(k))) {
+          out.put(vid_of[k], p < mid ? vid_of[x] : x);
+          ++claimed;
+        }
+        break;
+      }
+      if (l == 0) edges += uint64_t(min<int64_t>(kWave, hi - p0));
+    }
+  }
+  flush_work(cur, 0, 0, cands, edges, claimed);
+}
+
+// Level close: Vd |= Nd; Fd = Nd; Nd = 0; clear the normal frontier bitmap
+// (only words holding bits of this level's queue can be non-zero).
+__global__ void k_close(uint32_t *Vd, uint32_t *Fd, uint32_t *Nd, int32_t dwords,
+                        uint32_t *Fn, const int32_t *Q, const LevelCtr *prev) {
+  const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+  const int64_t t0 = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  for (int64_t w = t0; w < dwords; w += stride) {
+    const uint32_t x = Nd[w];
+    Vd[w] |= x;
+    Fd[w] = x;
+    Nd[w] = 0;
+  }
+  const int64_t qn = int64_t(prev->qn_next);
+  for (int64_t i = t0; i < qn; i += stride) Fn[Q[i] >> 5] = 0;
+}
+
+// ---------------------------------------------------------------------------
+// plain top-down (mode 0)
+// ---------------------------------------------------------------------------
+__global__ void k_plain_len(const int32_t *Q, const LevelCtr *prev, const int64_t *poff,
+                            int32_t *len) {
+  const int64_t qn = int64_t(prev->qn_next);
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < qn;
+       i += int64_t(gridDim.x) * blockDim.x) {
+    const int32_t u = Q[i];
+    len[i] = int32_t(poff[u + 1] - poff[u]);
+  }
+}
+
+__global__ void __launch_bounds__(kBS) k_plain_expand(const int32_t *Q, const LevelCtr *prev,
+                                                      const int64_t *scan, const int64_t *poff,
+                                                      const int32_t *pcol, Out out, uint32_t *Vn,
+                                                      int32_t *Qnext, LevelCtr *cur) {
+  const int64_t qn = int64_t(prev->qn_next);
+  const int64_t E = scan[qn];
+  const int64_t nruns = (E + kRun - 1) / kRun;
+  unsigned long long claimed = 0;
+  const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+  for (int64_t r0 = int64_t(blockIdx.x) * blockDim.x; r0 < nruns; r0 += stride) {
+    const int64_t r = r0 + threadIdx.x;
+    int64_t e = r * kRun;
+    const int64_t eend = min(e + kRun, E);
+    int64_t idx = r < nruns ? seg_search(scan, qn, e) : 0;
+    for (int t = 0; t < kRun; ++t, ++e) {
+      bool won = false;
+      int32_t v = 0;
+      if (r < nruns && e < eend) {
+        while (scan[idx + 1] <= e) ++idx;
+        const int32_t u = Q[idx];
+        v = pcol[poff[u] + (e - scan[idx])];
+        won = bit_claim(Vn, uint32_t(v));
+        if (won) {
+          out.put(v, u);
+          ++claimed;
+        }
+      }
+      const int64_t pos = wave_append(won, &cur->qn_next);
+      if (won) Qnext[pos] = v;
+    }
+  }
+  unsigned long long edges = 0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) edges = (unsigned long long)E;
+  flush_work(cur, 0, edges, 0, 0, claimed);
+}
+
+// reached vertices and the sum of their degrees (twice the component's edges)
+__global__ void k_reach_stats(const int32_t *depth, const int32_t *deg, int32_t n,
+                              unsigned long long *out) {
+  unsigned long long r = 0, s = 0;
+  for (int64_t v = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; v < n;
+       v += int64_t(gridDim.x) * blockDim.x)
+    if (depth[v] >= 0) {
+      ++r;
+      s += unsigned(deg[v]);
+    }
+  r = wave_sum(r);
+  s = wave_sum(s);
+  if (lane_id() == 0) {
+    if (r) atomicAdd(&out[0], r);
+    if (s) atomicAdd(&out[1], s);
+  }
+}
+
+uint64_t mix64(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+  return z ^ (z >> 31);
+}
+
+// Number of resident waves worth of blocks for grid-stride kernels.
+int stride_grid() { return 256 * 8; }
+
+}  // namespace
+
+Workspace *workspace_create(const Graph *g, int32_t max_lanes) {
+  if (max_lanes != 0 && max_lanes != 64)
+    fail(DSBFS_ERR_INVALID_ARG, "max_lanes must be 0 or 64");
+  Workspace *ws = new Workspace();
+  try {
+    ws->g = g;
+    ws->max_lanes = max_lanes;
+    const Alloc *al = &g->al;
+    hipStream_t s = g->stream;
+    const int64_t n = g->n, d = g->d;
+    ws->Vn.alloc(al, size_t(g->nwords()) * 4, s);
+    ws->Fn.alloc(al, size_t(g->nwords()) * 4, s);
+    ws->Vd.alloc(al, size_t(g->dwords()) * 4, s);
+    ws->Fd.alloc(al, size_t(g->dwords()) * 4, s);
+    ws->Nd.alloc(al, size_t(g->dwords()) * 4, s);
+    ws->q0.alloc(al, size_t(n) * 4, s);
+    ws->q1.alloc(al, size_t(n) * 4, s);
+    ws->dlist.alloc(al, size_t(d) * 4, s);
+    ws->dcand.alloc(al, size_t(d) * 4, s);
+    ws->dlen.alloc(al, size_t(std::max(n, d)) * 4, s);
+    ws->dscan.alloc(al, size_t(std::max(n, d) + 1) * 8, s);
+    ws->c0.alloc(al, size_t(g->st.n_ndsrc) * 4, s);
+    ws->c1.alloc(al, size_t(g->st.n_ndsrc) * 4, s);
+    ws->ctr.alloc(al, 2 * sizeof(LevelCtr), s);
+    ws->scan_tmp.alloc(al, scan_tmp_bytes(std::max(n, d)), s);
+    HIPCHK(hipHostMalloc(reinterpret_cast<void **>(&ws->hctr), 2 * sizeof(LevelCtr),
+                         hipHostMallocDefault));
+    if (max_lanes == 64) {
+      ws->ms_seen.alloc(al, size_t(n) * 8, s);
+      ws->ms_front.alloc(al, size_t(n) * 8, s);
+      ws->ms_next.alloc(al, size_t(n) * 8, s);
+    }
+    return ws;
+  } catch (...) {
+    delete ws;
+    throw;
+  }
+}
+
+void workspace_destroy(Workspace *ws) { delete ws; }
+
+static dsbfs_run_opts default_opts() {
+  dsbfs_run_opts o{};
+  o.mode = 1;
+  o.want_parent = 1;
+  o.factor0[0] = 0.5;
+  o.factor0[1] = 0.05;
+  o.factor0[2] = 1e-7;
+  o.factor1[0] = o.factor1[1] = o.factor1[2] = 0.0;
+  o.forced = 0;
+  o.forced_seed = 0;
+  return o;
+}
+
+void run_opts_default(dsbfs_run_opts *o) { *o = default_opts(); }
+
+// Backward workload estimate |U|(q+s)/q (Section IV-B), 0 when q or |U| is 0.
+static double bv_estimate(int64_t U, int64_t q, int64_t s) {
+  if (q <= 0 || U <= 0) return 0.0;
+  return double(U) * (double(q) + double(s)) / double(q);
+}
+
+void bfs_run(const Graph *g, Workspace *ws, int32_t source, const dsbfs_run_opts *opts_in,
+             int32_t *depth, int32_t *parent, dsbfs_run_stats *stats, hipStream_t s) {
+  if (!ws || ws->g != g) fail(DSBFS_ERR_INVALID_ARG, "workspace does not belong to this graph");
+  if (source < 0 || source >= g->n) fail(DSBFS_ERR_INVALID_ARG, "source outside [0, n)");
+  if (!depth) fail(DSBFS_ERR_INVALID_ARG, "depth must not be NULL");
+  const dsbfs_run_opts o = opts_in ? *opts_in : default_opts();
+  if (o.mode != 0 && o.mode != 1) fail(DSBFS_ERR_INVALID_ARG, "mode must be 0 or 1");
+  if (o.want_parent && !parent) fail(DSBFS_ERR_INVALID_ARG, "parent is NULL but want_parent");
+  if (o.mode == 0 && !g->pcol.p && g->m > 0)
+    fail(DSBFS_ERR_INVALID_ARG, "mode 0 needs the plain CSR (keep_plain_csr)");
+  if (o.forced < 0 || o.forced > 3) fail(DSBFS_ERR_INVALID_ARG, "forced must be 0..3");
+  int32_t *par = o.want_parent ? parent : nullptr;
+
+  const int32_t n = g->n, d = g->d;
+  uint32_t *Vn = ws->Vn.as<uint32_t>(), *Fn = ws->Fn.as<uint32_t>();
+  uint32_t *Vd = ws->Vd.as<uint32_t>(), *Fd = ws->Fd.as<uint32_t>(), *Nd = ws->Nd.as<uint32_t>();
+  int32_t *Q[2] = {ws->q0.as<int32_t>(), ws->q1.as<int32_t>()};
+  LevelCtr *ctr = ws->ctr.as<LevelCtr>();
+  LevelCtr *h = ws->hctr;
+  const int SG = stride_grid();
+
+  hipLaunchKernelGGL(k_init, dim3(grid_for(std::max(n, 1), kBS, 4096)), dim3(kBS), 0, s, depth,
+                     par, n, Vn, Fn, g->nwords(), Vd, Fd, Nd, g->dwords());
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipMemsetAsync(ctr, 0, 2 * sizeof(LevelCtr), s));
+  // level L uses ctr[L & 1]; the seed plays the part of "level -1" (ctr[1]).
+  hipLaunchKernelGGL(k_seed, dim3(1), dim3(1), 0, s, source, g->did.as<int32_t>(), depth, par,
+                     Vn, Vd, Fd, Q[0], ctr + 1, o.mode);
+  HIPCHK(hipGetLastError());
+
+  std::vector<dsbfs_level_stats> rec;
+  int qi = 0;  // Q[qi] is the current queue
+  Out out{depth, par, 0};
+
+  if (o.mode == 0) {
+    for (int32_t L = 0;; ++L) {
+      LevelCtr *cur = ctr + (L & 1), *prev = ctr + ((L + 1) & 1);
+      // the previous level's queue length is the only input of this level
+      HIPCHK(hipMemcpyAsync(h, prev, sizeof(LevelCtr), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      const int64_t qn = int64_t(h->qn_next);
+      if (qn == 0) break;
+      HIPCHK(hipMemsetAsync(cur, 0, sizeof(LevelCtr), s));
+      out.level1 = L + 1;
+      hipLaunchKernelGGL(k_plain_len, dim3(grid_for(qn, kBS, 8192)), dim3(kBS), 0, s, Q[qi], prev,
+                         g->poff.as<int64_t>(), ws->dlen.as<int32_t>());
+      HIPCHK(hipGetLastError());
+      scan_excl_i32_to_i64(ws->dlen.as<int32_t>(), ws->dscan.as<int64_t>(), qn, ws->scan_tmp.p, s);
+      hipLaunchKernelGGL(k_plain_expand, dim3(SG), dim3(kBS), 0, s, Q[qi], prev,
+                         ws->dscan.as<int64_t>(), g->poff.as<int64_t>(), g->pcol.as<int32_t>(),
+                         out, Vn, Q[qi ^ 1], cur);
+      HIPCHK(hipGetLastError());
+      qi ^= 1;
+      dsbfs_level_stats r{};
+      r.frontier_normal = qn;
+      rec.push_back(r);
+    }
+  } else {
+    int64_t rem_dd = g->st.n_ddsrc, rem_dn = g->st.n_dnsrc, rem_nd = g->st.n_ndsrc;
+    int dir[3] = {0, 0, 0};
+    int cand_state = -1;  // -1: candidates = nd source list; else ws->c[cand_state]
+    int64_t nc = g->st.n_ndsrc;
+    bool nc_pending = false;
+    int32_t *C[2] = {ws->c0.as<int32_t>(), ws->c1.as<int32_t>()};
+    for (int32_t L = 0;; ++L) {
+      LevelCtr *cur = ctr + (L & 1), *prev = ctr + ((L + 1) & 1);
+      HIPCHK(hipMemsetAsync(cur, 0, sizeof(LevelCtr), s));
+      hipLaunchKernelGGL(k_prev_normal, dim3(SG), dim3(kBS), 0, s, Q[qi], prev,
+                         g->noff.as<uint64_t>(), Fn, cur);
+      HIPCHK(hipGetLastError());
+      if (d > 0) {
+        hipLaunchKernelGGL(k_prev_deleg, dim3(grid_for(g->dwords(), kBS, 4096)), dim3(kBS), 0, s,
+                           Fd, Vd, g->ddsrc_mask.as<uint32_t>(), g->dnsrc_mask.as<uint32_t>(),
+                           g->dwords(), g->doff.as<uint64_t>(), ws->dlist.as<int32_t>(),
+                           ws->dcand.as<int32_t>(), cur);
+        HIPCHK(hipGetLastError());
+      }
+      HIPCHK(hipMemcpyAsync(h, ctr, 2 * sizeof(LevelCtr), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      const LevelCtr &hc = h[L & 1], &hp = h[(L + 1) & 1];
+      const int64_t qn = int64_t(hp.qn_next);
+      const int64_t fdn = int64_t(hc.nd_list);
+      if (nc_pending) {
+        // length of the candidate list the previous level's bottom-up normal
+        // kernel compacted
+        nc = int64_t(hp.nc_next);
+        nc_pending = false;
+      }
+      if (qn == 0 && fdn == 0) break;
+
+      // Direction decision (Section IV-B), indices dd = 0, dn = 1, nd = 2.
+      const int64_t q[3] = {int64_t(hc.q_dd), int64_t(hc.q_dn), int64_t(hc.q_nd)};
+      const int64_t FV[3] = {int64_t(hc.fv_dd), int64_t(hc.fv_dn), int64_t(hc.fv_nd)};
+      rem_dd -= q[0];
+      rem_dn -= q[1];
+      rem_nd -= q[2];
+      const int64_t U[3] = {rem_dd, rem_nd, rem_dn};
+      const int64_t S[3] = {rem_dd, rem_dn, rem_nd};
+      double BV[3];
+      for (int k = 0; k < 3; ++k) {
+        BV[k] = bv_estimate(U[k], q[k], S[k]);
+        if (o.forced == 1) dir[k] = 0;
+        else if (o.forced == 2) dir[k] = L >= 1 ? 1 : 0;
+        else if (o.forced == 3) dir[k] = int(mix64(o.forced_seed + uint64_t(L) * 3 + k) & 1);
+        else if (q[k] > 0) {
+          if (dir[k] == 0 && double(FV[k]) > o.factor0[k] * BV[k]) dir[k] = 1;
+          else if (dir[k] == 1 && double(FV[k]) < o.factor1[k] * BV[k]) dir[k] = 0;
+        }
+      }
+      dsbfs_level_stats r{};
+      for (int k = 0; k < 3; ++k) {
+        r.q[k] = q[k];
+        r.s[k] = S[k];
+        r.U[k] = U[k];
+        r.FV[k] = FV[k];
+        r.BV[k] = BV[k];
+        r.dir[k] = dir[k];
+      }
+      r.FV_nn = int64_t(hc.fv_nn);
+      r.q_nn = int64_t(hc.q_nn);
+      r.frontier_normal = qn;
+      r.frontier_delegate = fdn;
+      rec.push_back(r);
+
+      out.level1 = L + 1;
+      const bool dd_td = dir[0] == 0 && q[0] > 0, dn_td = dir[1] == 0 && q[1] > 0;
+      const bool nd_td = dir[2] == 0 && q[2] > 0;
+      const bool dd_bu = dir[0] == 1 && q[0] > 0, dn_bu = dir[1] == 1 && q[1] > 0;
+      const bool nd_bu = dir[2] == 1 && q[2] > 0;
+      if (qn > 0) {
+        hipLaunchKernelGGL(k_td_normal, dim3(grid_for(qn, kBS, 1 << 30)), dim3(kBS), 0, s, Q[qi],
+                           qn, g->noff.as<uint64_t>(), g->ncol.as<int32_t>(),
+                           g->vid_of.as<int32_t>(), int(nd_td), out, Vn, Vd, Nd, Q[qi ^ 1], cur);
+        HIPCHK(hipGetLastError());
+      }
+      if (dd_td || dn_td) {
+        hipLaunchKernelGGL(k_dlen, dim3(grid_for(fdn, kBS, 4096)), dim3(kBS), 0, s,
+                           ws->dlist.as<int32_t>(), cur, g->doff.as<uint64_t>(), int(dd_td),
+                           int(dn_td), ws->dlen.as<int32_t>());
+        HIPCHK(hipGetLastError());
+        scan_excl_i32_to_i64(ws->dlen.as<int32_t>(), ws->dscan.as<int64_t>(), fdn,
+                             ws->scan_tmp.p, s);
+        hipLaunchKernelGGL(k_td_deleg, dim3(SG), dim3(kBS), 0, s, ws->dlist.as<int32_t>(),
+                           ws->dscan.as<int64_t>(), cur, g->doff.as<uint64_t>(),
+                           g->dcol.as<int32_t>(), g->vid_of.as<int32_t>(), int(dd_td), int(dn_td),
+                           out, Vn, Vd, Nd, Q[qi ^ 1], cur);
+        HIPCHK(hipGetLastError());
+      }
+      if (dn_bu && nc > 0) {
+        const int32_t *cin = cand_state < 0 ? g->ndsrc.as<int32_t>() : C[cand_state];
+        const int nxt = cand_state < 0 ? 0 : (cand_state ^ 1);
+        hipLaunchKernelGGL(k_bu_normal, dim3(grid_for(nc, kBS, 1 << 30)), dim3(kBS), 0, s, cin, nc,
+                           g->noff.as<uint64_t>(), g->ncol.as<int32_t>(), Fd,
+                           g->vid_of.as<int32_t>(), out, Vn, Q[qi ^ 1], C[nxt], cur);
+        HIPCHK(hipGetLastError());
+        cand_state = nxt;
+        nc_pending = true;
+      }
+      if ((dd_bu || nd_bu) && hc.nd_cand > 0) {
+        hipLaunchKernelGGL(k_bu_deleg, dim3(grid_for(int64_t(hc.nd_cand) * kWave, kBS, 8192)),
+                           dim3(kBS), 0, s, ws->dcand.as<int32_t>(), cur, g->doff.as<uint64_t>(),
+                           g->dcol.as<int32_t>(), Fd, Fn, g->vid_of.as<int32_t>(), int(dd_bu),
+                           int(nd_bu), out, Nd, cur);
+        HIPCHK(hipGetLastError());
+      }
+      hipLaunchKernelGGL(k_close, dim3(grid_for(std::max<int64_t>(qn, g->dwords()), kBS, 4096)),
+                         dim3(kBS), 0, s, Vd, Fd, Nd, g->dwords(), Fn, Q[qi], prev);
+      HIPCHK(hipGetLastError());
+      qi ^= 1;
+    }
+  }
+
+  if (stats) {
+    HIPCHK(hipStreamSynchronize(s));
+    stats->num_levels = int32_t(rec.size());
+    for (int32_t i = 0; i < stats->num_levels && i < stats->capacity && stats->levels; ++i)
+      stats->levels[i] = rec[i];
+    unsigned long long *tmp = reinterpret_cast<unsigned long long *>(ws->dscan.p);
+    HIPCHK(hipMemsetAsync(tmp, 0, 2 * sizeof(unsigned long long), s));
+    hipLaunchKernelGGL(k_reach_stats, dim3(grid_for(n, kBS, 2048)), dim3(kBS), 0, s, depth,
+                       g->deg.as<int32_t>(), n, tmp);
+    HIPCHK(hipGetLastError());
+    unsigned long long hr[2];
+    HIPCHK(hipMemcpyAsync(hr, tmp, sizeof(hr), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    stats->reached = int64_t(hr[0]);
+    stats->edges_cc = int64_t(hr[1] / 2);
+  }
+}
+
+}  // namespace dsbfs

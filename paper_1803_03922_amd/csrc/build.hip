@@ -1,0 +1,542 @@
+// Graph construction on the device.
+//
+// Edge list -> simple symmetric graph (edge doubling, Section VI-A; symmetric
+// graph assumption, Section II-A; self-loops and duplicates dropped) ->
+// plain CSR -> degree separation at TH (Section III-A: delegate iff degree >
+// TH; delegates renumbered in ascending vertex ID, Fig. 2 caption) -> the
+// four subgraphs (Section III-C) stored as two row sets with packed offsets:
+//   normal row v   = [nn neighbours (vertex IDs) | nd neighbours (delegate IDs)]
+//   delegate row k = [dd neighbours (delegate IDs) | dn neighbours (vertex IDs)]
+// and the source list of nd plus the source masks of dd and dn (Section IV-B).
+//
+// At one GPU every vertex is local, so nn columns are 32-bit vertex IDs too
+// (the paper keeps them 64-bit only because they may be remote), and the
+// offsets are 64-bit because one GPU holds more than 2^32 edges at scale 26.
+#include <algorithm>
+
+#include "internal.hpp"
+
+namespace dsbfs {
+
+namespace {
+
+constexpr int kBS = 256;
+
+__global__ void k_validate(const int32_t *src, const int32_t *dst, int64_t g, int32_t n,
+                           unsigned long long *ctr /* [0] bad, [1] non-loop */) {
+  unsigned long long bad = 0, keep = 0;
+  for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < g;
+       e += int64_t(gridDim.x) * blockDim.x) {
+    const int32_t u = src[e], v = dst[e];
+    if (u < 0 || u >= n || v < 0 || v >= n) ++bad;
+    else if (u != v) ++keep;
+  }
+  bad = wave_sum(bad);
+  keep = wave_sum(keep);
+  if (lane_id() == 0) {
+    if (bad) atomicAdd(&ctr[0], bad);
+    if (keep) atomicAdd(&ctr[1], keep);
+  }
+}
+
+// Both directions of every non-loop pair as 64-bit keys (u << B) | v.
+__global__ void k_pack(const int32_t *src, const int32_t *dst, int64_t g, int B, uint64_t *keys,
+                       unsigned long long *cursor) {
+  const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+  for (int64_t e0 = int64_t(blockIdx.x) * blockDim.x; e0 < g; e0 += stride) {
+    const int64_t e = e0 + threadIdx.x;
+    int32_t u = 0, v = 0;
+    bool keep = false;
+    if (e < g) {
+      u = src[e];
+      v = dst[e];
+      keep = u != v;
+    }
+    const int64_t pos = wave_append(keep, cursor);
+    if (keep) {
+      keys[2 * pos] = (uint64_t(uint32_t(u)) << B) | uint64_t(uint32_t(v));
+      keys[2 * pos + 1] = (uint64_t(uint32_t(v)) << B) | uint64_t(uint32_t(u));
+    }
+  }
+}
+
+// poff[x] = index of the first key with row >= x, for x in [0, n]: between
+// consecutive keys j-1 and j every row in (row[j-1], row[j]] starts at j.
+__global__ void k_row_offsets(const uint64_t *keys, int64_t m, int B, int32_t n, int64_t *poff) {
+  for (int64_t j = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; j <= m;
+       j += int64_t(gridDim.x) * blockDim.x) {
+    const int64_t prev = j > 0 ? int64_t(keys[j - 1] >> B) : -1;
+    const int64_t cur = j < m ? int64_t(keys[j] >> B) : int64_t(n);
+    for (int64_t x = prev + 1; x <= cur; ++x) poff[x] = j;
+  }
+}
+
+__global__ void k_cols_and_degree(const uint64_t *keys, int64_t m, uint64_t vmask,
+                                  const int64_t *poff, int32_t n, int32_t *pcol, int32_t *deg) {
+  const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+  for (int64_t j = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; j < m; j += stride)
+    pcol[j] = int32_t(keys[j] & vmask);
+  for (int64_t v = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; v < n; v += stride)
+    deg[v] = int32_t(poff[v + 1] - poff[v]);
+}
+
+__global__ void k_flag_gt(const int32_t *deg, int32_t n, int32_t th, uint8_t *flag) {
+  for (int64_t v = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; v < n;
+       v += int64_t(gridDim.x) * blockDim.x)
+    flag[v] = deg[v] > th;
+}
+
+__global__ void k_fill_i32(int32_t *p, int64_t N, int32_t val) {
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < N;
+       i += int64_t(gridDim.x) * blockDim.x)
+    p[i] = val;
+}
+
+__global__ void k_did_scatter(const int32_t *vid_of, int32_t d, int32_t *did) {
+  for (int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; k < d;
+       k += int64_t(gridDim.x) * blockDim.x)
+    did[vid_of[k]] = int32_t(k);
+}
+
+// cnt_del[u] = number of delegate neighbours of u. Edge-parallel over the
+// sorted keys; rows are contiguous, so a segmented wave scan by row folds a
+// hub's entries into one atomic per wave.
+__global__ void k_count_delegate_nbrs(const uint64_t *keys, int64_t m, int B, uint64_t vmask,
+                                      const int32_t *did, int32_t *cnt_del) {
+  const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+  const int l = lane_id();
+  for (int64_t j0 = int64_t(blockIdx.x) * blockDim.x; j0 < m; j0 += stride) {
+    const int64_t j = j0 + threadIdx.x;
+    int64_t u = -1 - l;  // distinct per inactive lane: never merges
+    int32_t c = 0;
+    if (j < m) {
+      const uint64_t k = keys[j];
+      u = int64_t(k >> B);
+      c = did[int32_t(k & vmask)] >= 0;
+    }
+    for (int o = 1; o < kWave; o <<= 1) {
+      const int64_t uo = __shfl_up(u, o, kWave);
+      const int32_t co = __shfl_up(c, o, kWave);
+      if (l >= o && uo == u) c += co;
+    }
+    const int64_t un = __shfl_down(u, 1, kWave);
+    const bool tail = (l == kWave - 1) || un != u;
+    if (j < m && tail && c) atomicAdd(&cnt_del[u], c);
+  }
+}
+
+__global__ void k_row_lengths(const int32_t *deg, const int32_t *did, const int32_t *vid_of,
+                              int32_t n, int32_t d, int32_t *nlen, int32_t *dlen) {
+  const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+  for (int64_t v = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; v < n; v += stride)
+    nlen[v] = did[v] < 0 ? deg[v] : 0;
+  for (int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; k < d; k += stride)
+    dlen[k] = deg[vid_of[k]];
+}
+
+__global__ void k_pack_offsets(const int64_t *nstart, const int64_t *dstart, const int32_t *deg,
+                               const int32_t *did, const int32_t *vid_of, const int32_t *cnt_del,
+                               int32_t n, int32_t d, uint64_t *noff, uint64_t *doff) {
+  const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+  for (int64_t v = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; v <= n; v += stride) {
+    uint64_t first = 0;
+    if (v < n && did[v] < 0) first = uint64_t(deg[v] - cnt_del[v]);  // nn part
+    noff[v] = uint64_t(nstart[v]) | (first << kOffShift);
+  }
+  for (int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; k <= d; k += stride) {
+    uint64_t first = k < d ? uint64_t(cnt_del[vid_of[k]]) : 0;      // dd part
+    doff[k] = uint64_t(dstart[k]) | (first << kOffShift);
+  }
+}
+
+// Destination of row u in the new layout: (row offsets, columns, is delegate).
+struct RowDst {
+  uint64_t w;
+  int32_t *col;
+  bool del;
+};
+
+__device__ __forceinline__ RowDst row_dst(int32_t u, const int32_t *did, const uint64_t *noff,
+                                          int32_t *ncol, const uint64_t *doff, int32_t *dcol) {
+  const int32_t k = did[u];
+  if (k >= 0) return RowDst{doff[k], dcol, true};
+  return RowDst{noff[u], ncol, false};
+}
+
+// Rows with at most kSmallRow entries: one thread walks the row in order.
+constexpr int kSmallRow = 64;
+
+__global__ void k_split_small(const int64_t *poff, const int32_t *pcol, const int32_t *did,
+                              int32_t n, const uint64_t *noff, int32_t *ncol,
+                              const uint64_t *doff, int32_t *dcol) {
+  for (int64_t u = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; u < n;
+       u += int64_t(gridDim.x) * blockDim.x) {
+    const int64_t b = poff[u], e = poff[u + 1];
+    if (e - b == 0 || e - b > kSmallRow) continue;
+    const RowDst r = row_dst(int32_t(u), did, noff, ncol, doff, dcol);
+    int64_t pa = row_start(r.w), pb = pa + row_first(r.w);
+    for (int64_t j = b; j < e; ++j) {
+      const int32_t v = pcol[j];
+      const int32_t kv = did[v];
+      const bool v_del = kv >= 0;
+      // first part: same class as the row for delegates (dd), opposite-of-delegate
+      // for normals (nn); columns of delegate neighbours are delegate IDs.
+      const bool first = r.del ? v_del : !v_del;
+      const int32_t val = v_del ? kv : v;
+      if (first) r.col[pa++] = val;
+      else r.col[pb++] = val;
+    }
+  }
+}
+
+// Rows with more than kSmallRow entries: one wave per row, 64 entries per step,
+// order kept by ballot ranks.
+__global__ void k_split_large(const int32_t *rows, const int64_t *nrows, const int64_t *poff,
+                              const int32_t *pcol, const int32_t *did, const uint64_t *noff,
+                              int32_t *ncol, const uint64_t *doff, int32_t *dcol) {
+  const int64_t R = *nrows;
+  const int l = lane_id();
+  const int64_t wid = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) / kWave;
+  const int64_t nw = int64_t(gridDim.x) * blockDim.x / kWave;
+  for (int64_t i = wid; i < R; i += nw) {
+    const int32_t u = rows[i];
+    const int64_t b = poff[u], e = poff[u + 1];
+    const RowDst r = row_dst(u, did, noff, ncol, doff, dcol);
+    int64_t pa = row_start(r.w), pb = pa + row_first(r.w);
+    for (int64_t j0 = b; j0 < e; j0 += kWave) {
+      const int64_t j = j0 + l;
+      const bool ok = j < e;
+      int32_t v = 0, kv = -1;
+      if (ok) {
+        v = pcol[j];
+        kv = did[v];
+      }
+      const bool v_del = kv >= 0;
+      const bool first = r.del ? v_del : !v_del;
+      const uint64_t ma = __ballot(ok && first), mb = __ballot(ok && !first);
+      const int32_t val = v_del ? kv : v;
+      if (ok && first) r.col[pa + lanes_below(ma)] = val;
+      if (ok && !first) r.col[pb + lanes_below(mb)] = val;
+      pa += __popcll(ma);
+      pb += __popcll(mb);
+    }
+  }
+}
+
+__global__ void k_flag_large(const int64_t *poff, int32_t n, uint8_t *flag) {
+  for (int64_t u = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; u < n;
+       u += int64_t(gridDim.x) * blockDim.x)
+    flag[u] = poff[u + 1] - poff[u] > kSmallRow;
+}
+
+__global__ void k_flag_ndsrc(const int32_t *did, const int32_t *cnt_del, int32_t n, uint8_t *flag) {
+  for (int64_t u = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; u < n;
+       u += int64_t(gridDim.x) * blockDim.x)
+    flag[u] = did[u] < 0 && cnt_del[u] > 0;
+}
+
+__global__ void k_source_masks(const int32_t *vid_of, const int32_t *deg, const int32_t *cnt_del,
+                               int32_t d, uint32_t *ddm, uint32_t *dnm) {
+  const int32_t W = (d + 31) / 32;
+  for (int64_t w = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; w < W;
+       w += int64_t(gridDim.x) * blockDim.x) {
+    uint32_t a = 0, b = 0;
+    for (int i = 0; i < 32; ++i) {
+      const int64_t k = w * 32 + i;
+      if (k >= d) break;
+      const int32_t u = vid_of[k];
+      if (cnt_del[u] > 0) a |= 1u << i;
+      if (deg[u] - cnt_del[u] > 0) b |= 1u << i;
+    }
+    ddm[w] = a;
+    dnm[w] = b;
+  }
+}
+
+// [0] e_nn [1] e_nd [2] e_dn [3] e_dd [4] n_ndsrc [5] n_ddsrc [6] n_dnsrc [7] max degree
+__global__ void k_stats(const int32_t *deg, const int32_t *did, const int32_t *cnt_del, int32_t n,
+                        unsigned long long *out) {
+  unsigned long long a[7] = {0, 0, 0, 0, 0, 0, 0};
+  unsigned long long mx = 0;
+  for (int64_t u = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; u < n;
+       u += int64_t(gridDim.x) * blockDim.x) {
+    const unsigned long long dg = deg[u], cd = cnt_del[u], cn = dg - cd;
+    if (did[u] < 0) {
+      a[0] += cn; a[1] += cd; a[4] += cd > 0;
+    } else {
+      a[2] += cn; a[3] += cd; a[5] += cd > 0; a[6] += cn > 0;
+    }
+    mx = dg > mx ? dg : mx;
+  }
+  for (int i = 0; i < 7; ++i) {
+    unsigned long long s = wave_sum(a[i]);
+    if (lane_id() == 0 && s) atomicAdd(&out[i], s);
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    unsigned long long t = __shfl_xor(mx, o, kWave);
+    mx = t > mx ? t : mx;
+  }
+  if (lane_id() == 0) atomicMax(&out[7], mx);
+}
+
+int bits_for(int64_t n) {
+  int B = 1;
+  while ((int64_t(1) << B) < n) ++B;
+  return B;
+}
+
+}  // namespace
+
+Graph *graph_create(const int32_t *src, const int32_t *dst, int64_t g, int32_t n,
+                    const dsbfs_build_opts *opts, const dsbfs_allocator *alloc, hipStream_t s) {
+  if (n < 1) fail(DSBFS_ERR_INVALID_ARG, "num_vertices must be >= 1");
+  if (g < 0) fail(DSBFS_ERR_INVALID_ARG, "num_edges must be >= 0");
+  if (g > 0 && (!src || !dst)) fail(DSBFS_ERR_INVALID_ARG, "src/dst must not be NULL");
+  dsbfs_build_opts o{};
+  o.threshold = 32;
+  o.keep_plain_csr = 1;
+  if (opts) o = *opts;
+  if (o.threshold < 0) fail(DSBFS_ERR_INVALID_ARG, "threshold must be >= 0");
+  if (g > (int64_t(1) << 38)) fail(DSBFS_ERR_RANGE, "too many edges for the packed offsets");
+
+  Graph *G = new Graph();
+  try {
+    if (alloc && alloc->alloc && alloc->free) {
+      G->al.a = *alloc;
+      G->al.custom = true;
+    }
+    HIPCHK(hipGetDevice(&G->device));
+    G->stream = s;
+    G->n = n;
+    G->TH = o.threshold;
+    const Alloc *al = &G->al;
+    const int B = bits_for(n);
+    const uint64_t vmask = (uint64_t(1) << B) - 1;
+
+    // 1. edges on the device, validated
+    DevBuf esrc, edst;
+    const int32_t *ds = src, *dd = dst;
+    if (!o.edges_on_device && g > 0) {
+      esrc.alloc(al, size_t(g) * 4, s);
+      edst.alloc(al, size_t(g) * 4, s);
+      HIPCHK(hipMemcpyAsync(esrc.p, src, size_t(g) * 4, hipMemcpyHostToDevice, s));
+      HIPCHK(hipMemcpyAsync(edst.p, dst, size_t(g) * 4, hipMemcpyHostToDevice, s));
+      ds = esrc.as<int32_t>();
+      dd = edst.as<int32_t>();
+    }
+    DevBuf ctr;
+    ctr.alloc(al, 8 * sizeof(unsigned long long), s);
+    HIPCHK(hipMemsetAsync(ctr.p, 0, 8 * sizeof(unsigned long long), s));
+    unsigned long long *c = ctr.as<unsigned long long>();
+    if (g > 0) {
+      hipLaunchKernelGGL(k_validate, dim3(grid_for(g, kBS, 8192)), dim3(kBS), 0, s, ds, dd, g, n,
+                         c);
+      HIPCHK(hipGetLastError());
+    }
+    unsigned long long hc[2];
+    HIPCHK(hipMemcpyAsync(hc, c, sizeof(hc), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (hc[0]) fail(DSBFS_ERR_INVALID_ARG, "edge endpoint outside [0, num_vertices)");
+    const int64_t M2 = 2 * int64_t(hc[1]);
+
+    // 2. symmetrize into keys, sort, de-duplicate
+    DevBuf keys, alt;
+    keys.alloc(al, size_t(M2) * 8, s);
+    alt.alloc(al, size_t(M2) * 8, s);
+    if (M2 > 0) {
+      HIPCHK(hipMemsetAsync(c, 0, sizeof(unsigned long long), s));
+      hipLaunchKernelGGL(k_pack, dim3(grid_for(g, kBS, 8192)), dim3(kBS), 0, s, ds, dd, g, B,
+                         keys.as<uint64_t>(), c);
+      HIPCHK(hipGetLastError());
+    }
+    esrc.reset();
+    edst.reset();
+    int64_t m = 0;
+    {
+      DevBuf tmp;
+      tmp.alloc(al, std::max(radix_tmp_bytes(M2), compact_tmp_bytes(M2)), s);
+      radix_sort_u64(keys.as<uint64_t>(), alt.as<uint64_t>(), M2, 2 * B, tmp.p, s);
+      int64_t *cnt = reinterpret_cast<int64_t *>(c + 2);
+      unique_sorted_u64(keys.as<uint64_t>(), M2, alt.as<uint64_t>(), cnt, tmp.p, s);
+      m = d2h_scalar(cnt, s);
+    }
+    keys.reset();
+    G->m = m;
+    const uint64_t *uk = alt.as<uint64_t>();
+
+    // 3. plain CSR and degrees
+    G->poff.alloc(al, size_t(n + 1) * 8, s);
+    G->pcol.alloc(al, size_t(m) * 4, s);
+    G->deg.alloc(al, size_t(n) * 4, s);
+    hipLaunchKernelGGL(k_row_offsets, dim3(grid_for(m + 1, kBS, 16384)), dim3(kBS), 0, s, uk, m, B,
+                       n, G->poff.as<int64_t>());
+    HIPCHK(hipGetLastError());
+    hipLaunchKernelGGL(k_cols_and_degree, dim3(grid_for(std::max<int64_t>(m, n), kBS, 16384)),
+                       dim3(kBS), 0, s, uk, m, vmask, G->poff.as<int64_t>(), n,
+                       G->pcol.as<int32_t>(), G->deg.as<int32_t>());
+    HIPCHK(hipGetLastError());
+
+    // 4. degree separation: delegate iff degree > TH, IDs in ascending vertex ID
+    DevBuf flag, tmp;
+    flag.alloc(al, size_t(n), s);
+    tmp.alloc(al, compact_tmp_bytes(n), s);
+    G->vid_of.alloc(al, size_t(n) * 4, s);  // shrunk below once d is known
+    G->did.alloc(al, size_t(n) * 4, s);
+    hipLaunchKernelGGL(k_flag_gt, dim3(grid_for(n, kBS, 8192)), dim3(kBS), 0, s,
+                       G->deg.as<int32_t>(), n, o.threshold, flag.as<uint8_t>());
+    HIPCHK(hipGetLastError());
+    int64_t *cnt = reinterpret_cast<int64_t *>(c + 2);
+    compact_flags_u8(flag.as<uint8_t>(), n, G->vid_of.as<int32_t>(), cnt, tmp.p, s);
+    const int64_t d = d2h_scalar(cnt, s);
+    G->d = int32_t(d);
+    {
+      DevBuf v2;
+      v2.alloc(al, size_t(d) * 4, s);
+      if (d > 0)
+        HIPCHK(hipMemcpyAsync(v2.p, G->vid_of.p, size_t(d) * 4, hipMemcpyDeviceToDevice, s));
+      G->vid_of = std::move(v2);
+    }
+    hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(n, kBS, 8192)), dim3(kBS), 0, s,
+                       G->did.as<int32_t>(), int64_t(n), -1);
+    HIPCHK(hipGetLastError());
+    if (d > 0) {
+      hipLaunchKernelGGL(k_did_scatter, dim3(grid_for(d, kBS, 8192)), dim3(kBS), 0, s,
+                         G->vid_of.as<int32_t>(), int32_t(d), G->did.as<int32_t>());
+      HIPCHK(hipGetLastError());
+    }
+
+    // 5. delegate neighbours per row
+    DevBuf cnt_del;
+    cnt_del.alloc(al, size_t(n) * 4, s);
+    HIPCHK(hipMemsetAsync(cnt_del.p, 0, size_t(n) * 4, s));
+    if (m > 0) {
+      hipLaunchKernelGGL(k_count_delegate_nbrs, dim3(grid_for(m, kBS, 16384)), dim3(kBS), 0, s,
+                         uk, m, B, vmask, G->did.as<int32_t>(), cnt_del.as<int32_t>());
+      HIPCHK(hipGetLastError());
+    }
+    alt.reset();
+
+    // 6. statistics (needed for sizes and the packed-offset range check)
+    HIPCHK(hipMemsetAsync(c, 0, 8 * sizeof(unsigned long long), s));
+    hipLaunchKernelGGL(k_stats, dim3(grid_for(n, kBS, 4096)), dim3(kBS), 0, s,
+                       G->deg.as<int32_t>(), G->did.as<int32_t>(), cnt_del.as<int32_t>(), n, c);
+    HIPCHK(hipGetLastError());
+    unsigned long long hs[8];
+    HIPCHK(hipMemcpyAsync(hs, c, sizeof(hs), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (int64_t(hs[7]) > kMaxFirstPart)
+      fail(DSBFS_ERR_RANGE, "a vertex degree exceeds the packed row-offset limit (2^24-1)");
+
+    // 7. row offsets of the two row sets
+    {
+      DevBuf nlen, dlen, nstart, dstart, stmp;
+      nlen.alloc(al, size_t(n) * 4, s);
+      dlen.alloc(al, size_t(d) * 4, s);
+      nstart.alloc(al, size_t(n + 1) * 8, s);
+      dstart.alloc(al, size_t(d + 1) * 8, s);
+      stmp.alloc(al, scan_tmp_bytes(std::max<int64_t>(n, d)), s);
+      hipLaunchKernelGGL(k_row_lengths, dim3(grid_for(n, kBS, 8192)), dim3(kBS), 0, s,
+                         G->deg.as<int32_t>(), G->did.as<int32_t>(), G->vid_of.as<int32_t>(), n,
+                         int32_t(d), nlen.as<int32_t>(), dlen.as<int32_t>());
+      HIPCHK(hipGetLastError());
+      scan_excl_i32_to_i64(nlen.as<int32_t>(), nstart.as<int64_t>(), n, stmp.p, s);
+      scan_excl_i32_to_i64(dlen.as<int32_t>(), dstart.as<int64_t>(), d, stmp.p, s);
+      G->noff.alloc(al, size_t(n + 1) * 8, s);
+      G->doff.alloc(al, size_t(d + 1) * 8, s);
+      hipLaunchKernelGGL(k_pack_offsets, dim3(grid_for(n + 1, kBS, 8192)), dim3(kBS), 0, s,
+                         nstart.as<int64_t>(), dstart.as<int64_t>(), G->deg.as<int32_t>(),
+                         G->did.as<int32_t>(), G->vid_of.as<int32_t>(), cnt_del.as<int32_t>(), n,
+                         int32_t(d), G->noff.as<uint64_t>(), G->doff.as<uint64_t>());
+      HIPCHK(hipGetLastError());
+    }
+    const int64_t e_nn = hs[0], e_nd = hs[1], e_dn = hs[2], e_dd = hs[3];
+    G->ncol.alloc(al, size_t(e_nn + e_nd) * 4, s);
+    G->dcol.alloc(al, size_t(e_dn + e_dd) * 4, s);
+
+    // 8. scatter columns into the split rows
+    hipLaunchKernelGGL(k_split_small, dim3(grid_for(n, kBS, 16384)), dim3(kBS), 0, s,
+                       G->poff.as<int64_t>(), G->pcol.as<int32_t>(), G->did.as<int32_t>(), n,
+                       G->noff.as<uint64_t>(), G->ncol.as<int32_t>(), G->doff.as<uint64_t>(),
+                       G->dcol.as<int32_t>());
+    HIPCHK(hipGetLastError());
+    {
+      DevBuf rows;
+      rows.alloc(al, size_t(n) * 4, s);
+      hipLaunchKernelGGL(k_flag_large, dim3(grid_for(n, kBS, 8192)), dim3(kBS), 0, s,
+                         G->poff.as<int64_t>(), n, flag.as<uint8_t>());
+      HIPCHK(hipGetLastError());
+      compact_flags_u8(flag.as<uint8_t>(), n, rows.as<int32_t>(), cnt, tmp.p, s);
+      hipLaunchKernelGGL(k_split_large, dim3(2048), dim3(kBS), 0, s, rows.as<int32_t>(), cnt,
+                         G->poff.as<int64_t>(), G->pcol.as<int32_t>(), G->did.as<int32_t>(),
+                         G->noff.as<uint64_t>(), G->ncol.as<int32_t>(), G->doff.as<uint64_t>(),
+                         G->dcol.as<int32_t>());
+      HIPCHK(hipGetLastError());
+      HIPCHK(hipStreamSynchronize(s));
+    }
+
+    // 9. source list of nd, source masks of dd and dn
+    hipLaunchKernelGGL(k_flag_ndsrc, dim3(grid_for(n, kBS, 8192)), dim3(kBS), 0, s,
+                       G->did.as<int32_t>(), cnt_del.as<int32_t>(), n, flag.as<uint8_t>());
+    HIPCHK(hipGetLastError());
+    G->ndsrc.alloc(al, size_t(hs[4]) * 4, s);
+    compact_flags_u8(flag.as<uint8_t>(), n, G->ndsrc.as<int32_t>(), cnt, tmp.p, s);
+    G->ddsrc_mask.alloc(al, size_t(G->dwords()) * 4, s);
+    G->dnsrc_mask.alloc(al, size_t(G->dwords()) * 4, s);
+    if (d > 0) {
+      hipLaunchKernelGGL(k_source_masks, dim3(grid_for(G->dwords(), kBS, 4096)), dim3(kBS), 0, s,
+                         G->vid_of.as<int32_t>(), G->deg.as<int32_t>(), cnt_del.as<int32_t>(),
+                         int32_t(d), G->ddsrc_mask.as<uint32_t>(), G->dnsrc_mask.as<uint32_t>());
+      HIPCHK(hipGetLastError());
+    }
+    if (!o.keep_plain_csr) {
+      G->poff.reset();
+      G->pcol.reset();
+    }
+    HIPCHK(hipStreamSynchronize(s));
+
+    dsbfs_graph_stats &st = G->st;
+    std::memset(&st, 0, sizeof(st));
+    st.n = n;
+    st.m_dir = m;
+    st.d = d;
+    st.e_nn = e_nn; st.e_nd = e_nd; st.e_dn = e_dn; st.e_dd = e_dd;
+    st.n_ndsrc = hs[4]; st.n_ddsrc = hs[5]; st.n_dnsrc = hs[6];
+    st.max_degree = hs[7];
+    st.threshold = o.threshold;
+    st.bytes_layout = int64_t(n + 1) * 8 + int64_t(d + 1) * 8 + 4 * m;
+    st.bytes_plain = o.keep_plain_csr ? int64_t(n + 1) * 8 + 4 * m : 0;
+    return G;
+  } catch (...) {
+    delete G;
+    throw;
+  }
+}
+
+void graph_destroy(Graph *G) { delete G; }
+
+void graph_export(const Graph *G, int32_t which, void *host_out, int64_t cap, int64_t *bytes) {
+  const DevBuf *b = nullptr;
+  int64_t nb = 0;
+  const int64_t n = G->n, d = G->d;
+  switch (which) {
+    case 0: b = &G->deg; nb = n * 4; break;
+    case 1: b = &G->did; nb = n * 4; break;
+    case 2: b = &G->vid_of; nb = d * 4; break;
+    case 3: b = &G->noff; nb = (n + 1) * 8; break;
+    case 4: b = &G->ncol; nb = (G->st.e_nn + G->st.e_nd) * 4; break;
+    case 5: b = &G->doff; nb = (d + 1) * 8; break;
+    case 6: b = &G->dcol; nb = (G->st.e_dn + G->st.e_dd) * 4; break;
+    case 7: b = &G->ndsrc; nb = G->st.n_ndsrc * 4; break;
+    case 8: b = &G->ddsrc_mask; nb = int64_t(G->dwords()) * 4; break;
+    case 9: b = &G->dnsrc_mask; nb = int64_t(G->dwords()) * 4; break;
+    case 10: b = &G->poff; nb = G->poff.p ? (n + 1) * 8 : 0; break;
+    case 11: b = &G->pcol; nb = G->pcol.p ? G->m * 4 : 0; break;
+    default: fail(DSBFS_ERR_INVALID_ARG, "unknown array index");
+  }
+  *bytes = nb;
+  if (!host_out || cap < nb || nb == 0) return;
+  HIPCHK(hipMemcpyAsync(host_out, b->p, size_t(nb), hipMemcpyDeviceToHost, G->stream));
+  HIPCHK(hipStreamSynchronize(G->stream));
+}
+
+}  // namespace dsbfs

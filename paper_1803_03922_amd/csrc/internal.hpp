@@ -1,0 +1,217 @@
+// Internal declarations of the dsbfs HIP library (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "dsbfs.h"
+
+namespace dsbfs {
+
+constexpr int kWave = 64;
+constexpr uint64_t kOffMask = (1ull << 40) - 1;  // packed row offset: start in bits 0..39
+constexpr int kOffShift = 40;                    // length of the first part in bits 40..63
+constexpr int64_t kMaxFirstPart = (1ll << 24) - 1;
+
+// ---------------------------------------------------------------------------
+// Errors: internal code throws dsbfs::Error; the C-ABI layer catches it.
+// ---------------------------------------------------------------------------
+struct Error {
+  dsbfs_status status;
+  std::string msg;
+};
+
+[[noreturn]] void fail(dsbfs_status st, const std::string &msg);
+void hip_check(hipError_t e, const char *what, const char *file, int line);
+#define HIPCHK(x) ::dsbfs::hip_check((x), #x, __FILE__, __LINE__)
+
+// ---------------------------------------------------------------------------
+// Device memory through the caller's allocator (or hipMalloc).
+// ---------------------------------------------------------------------------
+struct Alloc {
+  dsbfs_allocator a{};
+  bool custom = false;
+  void *get(size_t bytes, hipStream_t s) const;
+  void put(void *p, hipStream_t s) const;
+};
+
+// Owning device buffer bound to an allocator.
+struct DevBuf {
+  void *p = nullptr;
+  size_t bytes = 0;
+  const Alloc *al = nullptr;
+  hipStream_t s = nullptr;
+  DevBuf() = default;
+  DevBuf(const DevBuf &) = delete;
+  DevBuf &operator=(const DevBuf &) = delete;
+  DevBuf(DevBuf &&o) noexcept { *this = std::move(o); }
+  DevBuf &operator=(DevBuf &&o) noexcept {
+    if (this != &o) {
+      reset();
+      p = o.p; bytes = o.bytes; al = o.al; s = o.s;
+      o.p = nullptr; o.bytes = 0;
+    }
+    return *this;
+  }
+  ~DevBuf() { reset(); }
+  void alloc(const Alloc *a, size_t nbytes, hipStream_t st) {
+    reset();
+    al = a; s = st; bytes = nbytes;
+    p = a->get(nbytes < 256 ? 256 : nbytes, st);
+  }
+  void reset() {
+    if (p && al) al->put(p, s);
+    p = nullptr; bytes = 0;
+  }
+  template <class T> T *as() const { return static_cast<T *>(p); }
+};
+
+// ---------------------------------------------------------------------------
+// Graph: the degree-separated layout (Section III-C) plus the plain CSR.
+//   Normal rows  (n rows, indexed by vertex ID; empty for delegates):
+//     [ nn neighbours (vertex IDs) | nd neighbours (delegate IDs) ]
+//   Delegate rows (d rows, indexed by delegate ID):
+//     [ dd neighbours (delegate IDs) | dn neighbours (vertex IDs) ]
+//   noff/doff are packed: start (bits 0..39) | first-part length << 40.
+// ---------------------------------------------------------------------------
+struct Graph {
+  Alloc al;
+  hipStream_t stream = nullptr;
+  int device = 0;
+  int32_t n = 0, d = 0, TH = 0;
+  int64_t m = 0;
+  dsbfs_graph_stats st{};
+  DevBuf deg, did, vid_of, noff, ncol, doff, dcol, ndsrc, ddsrc_mask, dnsrc_mask;
+  DevBuf poff, pcol;  // plain CSR: int64 offsets [n+1], int32 columns [m]
+  int32_t dwords() const { return (d + 31) / 32; }
+  int32_t nwords() const { return (n + 31) / 32; }
+};
+
+// Per-level counters of a single-source search (device; accumulated with
+// wave-aggregated atomics). Two copies alternate between levels.
+struct LevelCtr {
+  unsigned long long qn_next;   // tail of the next normal queue (queue length of the next level)
+  unsigned long long nc_next;   // tail of the next bottom-up normal candidate list
+  unsigned long long nd_list;   // frontier delegates of this level (length of dlist)
+  unsigned long long nd_cand;   // unvisited delegates with a dd or dn edge (length of dcand)
+  unsigned long long fv_nn, q_nn, fv_nd, q_nd;  // normal previsit
+  unsigned long long fv_dd, q_dd, fv_dn, q_dn;  // delegate previsit
+  unsigned long long td_vertices, td_edges;      // top-down work of this level
+  unsigned long long bu_candidates, bu_edges;    // bottom-up work of this level
+  unsigned long long claimed;                    // vertices discovered by this level
+  unsigned long long pad[3];
+};
+
+// Scratch of one search at a time (single-source and multi-source).
+struct Workspace {
+  const Graph *g = nullptr;
+  int32_t max_lanes = 0;
+  DevBuf Vn, Fn, Vd, Fd, Nd;   // uint32 bitmaps: visited/frontier normals, delegates
+  DevBuf q0, q1;               // normal queues, int32[n]
+  DevBuf dlist, dcand, dlen;   // int32[d]
+  DevBuf dscan;                // int64[max(n, d) + 1]: prefix of top-down lengths
+  DevBuf c0, c1;               // bottom-up normal candidates, int32[n_ndsrc]
+  DevBuf ctr;                  // LevelCtr[2]
+  DevBuf scan_tmp;
+  LevelCtr *hctr = nullptr;    // pinned host copy of ctr
+  // multi-source lane state
+  DevBuf ms_seen, ms_front, ms_next;  // uint64[n]
+  DevBuf ms_misc;
+  ~Workspace();
+};
+
+// ---------------------------------------------------------------------------
+// Device helpers.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+// Number of set bits of mask in lanes below the calling lane.
+__device__ __forceinline__ uint32_t lanes_below(uint64_t mask) {
+  return __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(mask >> 32),
+                                   __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(mask), 0u));
+}
+
+template <class T> __device__ __forceinline__ T wave_sum(T v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+  return v;
+}
+
+// Inclusive prefix sum across the 64 lanes of a wave.
+template <class T> __device__ __forceinline__ T wave_incl_scan(T v) {
+  const int l = lane_id();
+  for (int o = 1; o < kWave; o <<= 1) {
+    T t = __shfl_up(v, o, kWave);
+    if (l >= o) v += t;
+  }
+  return v;
+}
+
+// Wave-aggregated append: every lane with `want` gets a distinct slot of
+// *counter (returned), one atomic per wave. Lanes without `want` get -1.
+__device__ __forceinline__ int64_t wave_append(bool want, unsigned long long *counter) {
+  uint64_t m = __ballot(want);
+  if (m == 0) return -1;
+  int leader = __ffsll(static_cast<long long>(m)) - 1;
+  unsigned long long base = 0;
+  if (lane_id() == leader) base = atomicAdd(counter, static_cast<unsigned long long>(__popcll(m)));
+  base = __shfl(base, leader, kWave);
+  return want ? static_cast<int64_t>(base + lanes_below(m)) : -1;
+}
+
+__device__ __forceinline__ bool bit_test(const uint32_t *bm, uint32_t v) {
+  return (bm[v >> 5] >> (v & 31)) & 1u;
+}
+// Test-and-set: true iff this call changed the bit from 0 to 1.
+__device__ __forceinline__ bool bit_claim(uint32_t *bm, uint32_t v) {
+  const uint32_t b = 1u << (v & 31);
+  if (__hip_atomic_load(&bm[v >> 5], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & b) return false;
+  return !(atomicOr(&bm[v >> 5], b) & b);
+}
+
+__device__ __forceinline__ int64_t row_start(uint64_t w) { return static_cast<int64_t>(w & kOffMask); }
+__device__ __forceinline__ int64_t row_first(uint64_t w) { return static_cast<int64_t>(w >> kOffShift); }
+
+inline int grid_for(int64_t items, int per_block, int cap = 65536) {
+  int64_t g = (items + per_block - 1) / per_block;
+  if (g < 1) g = 1;
+  if (g > cap) g = cap;
+  return static_cast<int>(g);
+}
+
+// ---------------------------------------------------------------------------
+// Device-wide primitives (prims.hip).
+// ---------------------------------------------------------------------------
+// out[i] = sum of in[0..i), i in [0, N]; out has N+1 entries. tmp is scratch
+// of scan_tmp_bytes(N) bytes.
+size_t scan_tmp_bytes(int64_t N);
+void scan_excl_i32_to_i64(const int32_t *in, int64_t *out, int64_t N, void *tmp, hipStream_t s);
+void scan_excl_i64(const int64_t *in, int64_t *out, int64_t N, void *tmp, hipStream_t s);
+
+// LSD radix sort of N uint64 keys over bits [0, key_bits). Result lands in
+// keys (alt is scratch of N keys). hist_tmp is radix_tmp_bytes(N) bytes.
+size_t radix_tmp_bytes(int64_t N);
+void radix_sort_u64(uint64_t *keys, uint64_t *alt, int64_t N, int key_bits, void *hist_tmp,
+                    hipStream_t s);
+
+// Order-preserving compaction of indices i in [0, N) with flag[i] != 0 into
+// out; *count (device) gets the number kept. tmp: compact_tmp_bytes(N).
+size_t compact_tmp_bytes(int64_t N);
+void compact_flags_u8(const uint8_t *flag, int64_t N, int32_t *out, int64_t *count, void *tmp,
+                      hipStream_t s);
+// Keeps keys[i] where i == 0 or keys[i] != keys[i-1] (sorted input -> unique).
+void unique_sorted_u64(const uint64_t *keys, int64_t N, uint64_t *out, int64_t *count, void *tmp,
+                       hipStream_t s);
+
+// Host helpers.
+template <class T> T d2h_scalar(const T *dptr, hipStream_t s) {
+  T v{};
+  HIPCHK(hipMemcpyAsync(&v, dptr, sizeof(T), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  return v;
+}
+
+}  // namespace dsbfs

@@ -1,0 +1,70 @@
+"""The C-ABI library loads, exports every symbol the header declares, and
+rejects bad arguments on the host side before touching a GPU."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "dsbfs.h")
+
+
+def _declared():
+    txt = open(HEADER).read()
+    return sorted(set(re.findall(r"\b(dsbfs_[a-z0-9_]+)\s*\(", txt)))
+
+
+def test_header_symbols_exported():
+    from paper_1803_03922_amd import dsbfs
+    lib = ctypes.CDLL(dsbfs.LIB_PATH)
+    names = _declared()
+    assert len(names) == 19
+    for name in names:
+        assert hasattr(lib, name), name
+    # and the binding wraps every one of them under the same name
+    for name in names:
+        assert name in dsbfs.EXPORTED, name
+
+
+def test_status_strings():
+    from paper_1803_03922_amd import dsbfs
+    assert dsbfs.dsbfs_status_str(0) == b"ok"
+    assert dsbfs.dsbfs_status_str(dsbfs.ERR_BUDGET) == b"HBM budget exhausted"
+    assert dsbfs.dsbfs_status_str(-99) == b"unknown status"
+
+
+def test_default_factors_match_paper():
+    """Defaults are the paper's tuned factors (Section VI-B) in dd, dn, nd order."""
+    from paper_1803_03922_amd import dsbfs
+    o = dsbfs.dsbfs_run_opts()
+    assert dsbfs.dsbfs_run_opts_default(ctypes.byref(o)) == 0
+    assert list(o.factor0) == [0.5, 0.05, 1e-7]
+    assert list(o.factor1) == [0.0, 0.0, 0.0]
+    assert o.mode == 1 and o.want_parent == 1 and o.forced == 0
+
+
+def test_host_side_argument_errors():
+    from paper_1803_03922_amd import dsbfs
+    h = ctypes.c_void_p()
+    st = dsbfs.dsbfs_graph_create(None, None, 0, 0, None, None, None, ctypes.byref(h))
+    assert st == dsbfs.ERR_INVALID_ARG
+    assert b"num_vertices" in dsbfs.dsbfs_last_error()
+    st = dsbfs.dsbfs_graph_create(None, None, 5, 10, None, None, None, ctypes.byref(h))
+    assert st == dsbfs.ERR_INVALID_ARG
+    bo = dsbfs.dsbfs_build_opts(-1, 0, 1, 0)
+    st = dsbfs.dsbfs_graph_create(None, None, 0, 10, ctypes.byref(bo), None, None, ctypes.byref(h))
+    assert st == dsbfs.ERR_INVALID_ARG and b"threshold" in dsbfs.dsbfs_last_error()
+    assert dsbfs.dsbfs_graph_create(None, None, 0, 1, None, None, None, None) == dsbfs.ERR_INVALID_ARG
+    assert dsbfs.dsbfs_bfs(None, None, 0, None, None, None, None, None) == dsbfs.ERR_INVALID_ARG
+    assert dsbfs.dsbfs_graph_destroy(None) == 0
+    assert dsbfs.dsbfs_workspace_destroy(None) == 0
+    assert dsbfs.dsbfs_server_destroy(None) == 0
+    assert dsbfs.dsbfs_server_create(None, None, None) == dsbfs.ERR_INVALID_ARG
+
+
+def test_now_is_monotonic():
+    from paper_1803_03922_amd import dsbfs
+    a = dsbfs.now_ns()
+    b = dsbfs.now_ns()
+    assert 0 < a <= b

@@ -1,0 +1,241 @@
+"""GPU parity of single-source BFS (plain top-down and degree-separated DOBFS)
+against the CPU oracle and closed forms, through the C-ABI library.
+
+Depths must match bit-exactly; parents are checked by the oracle's invariant
+checker (several trees are correct)."""
+import numpy as np
+import pytest
+
+from closed_forms import all_closed_forms
+from gpu_helpers import GpuGraph, lib, log
+
+pytestmark = pytest.mark.gpu
+
+TH_CLOSED = (0, 1, 2, 3, 8, 10**6)
+
+
+@pytest.mark.parametrize("case", all_closed_forms(), ids=lambda c: c[0])
+def test_closed_forms_all_modes(oracle_mod, case):
+    name, n, src, dst, dist, sources = case
+    O = oracle_mod.Graph(src, dst, n)
+    label = O.components()
+    for TH in TH_CLOSED:
+        log(f"closed form {name} n={n} TH={TH}")
+        G = GpuGraph(src, dst, n, threshold=TH)
+        for s in sources:
+            want = dist(s)
+            for mode, forced, seed in ((0, 0, 0), (1, 0, 0), (1, 1, 0), (1, 2, 0), (1, 3, 7),
+                                       (1, 3, 8)):
+                depth, parent, _ = G.bfs(s, mode=mode, forced=forced, seed=seed)
+                np.testing.assert_array_equal(depth, want,
+                                              err_msg=f"{name} TH={TH} s={s} mode={mode} f={forced}")
+                assert O.check(s, depth, parent, label)[0] == 0, (name, TH, s, mode, forced)
+        G.close()
+
+
+def _rmat(inputs_mod, oracle_mod, scale):
+    src, dst = inputs_mod.rmat_edges(scale)
+    n = 1 << scale
+    return n, src, dst, oracle_mod.Graph(src, dst, n)
+
+
+@pytest.mark.parametrize("scale,TH", [(10, 8), (12, 16), (14, 32), (16, 32), (16, 64)])
+def test_rmat_parity(inputs_mod, oracle_mod, scale, TH):
+    n, src, dst, O = _rmat(inputs_mod, oracle_mod, scale)
+    label = O.components()
+    deg = O.degrees()
+    G = GpuGraph(src, dst, n, threshold=TH)
+    sources = inputs_mod.pick_sources(src, dst, n, 24, seed=2000 + scale)
+    for s in sources.tolist():
+        want, _ = O.bfs(s, want_parent=False)
+        for mode in (0, 1):
+            depth, parent, st = G.bfs(s, mode=mode, want_stats=True)
+            log(f"rmat scale={scale} TH={TH} s={s} mode={mode} levels={st['num_levels']}")
+            np.testing.assert_array_equal(depth, want)
+            assert O.check(s, depth, parent, label)[0] == 0
+            reached = want >= 0
+            assert st["reached"] == int(reached.sum())
+            assert st["edges_cc"] == int(deg[reached].sum() // 2)
+    G.close()
+
+
+def test_config1_plain_scale16_64_sources(inputs_mod, oracle_mod):
+    """Plain top-down BFS, RMAT scale 16, 64 seeded sources with degree >= 1."""
+    n, src, dst, O = _rmat(inputs_mod, oracle_mod, 16)
+    label = O.components()
+    G = GpuGraph(src, dst, n, threshold=32)
+    sources = inputs_mod.pick_sources(src, dst, n, 64, seed=1001)
+    assert len(sources) == 64
+    for s in sources.tolist():
+        want, _ = O.bfs(s, want_parent=False)
+        depth, parent, _ = G.bfs(s, mode=0)
+        np.testing.assert_array_equal(depth, want)
+        assert O.check(s, depth, parent, label)[0] == 0
+    G.close()
+
+
+def test_config2_do_scale22(inputs_mod, oracle_mod):
+    """Degree-separated DOBFS, TH = 32, RMAT scale 22, seeded sources."""
+    n, src, dst, O = _rmat(inputs_mod, oracle_mod, 22)
+    log("scale 22 oracle graph built")
+    G = GpuGraph(src, dst, n, threshold=32)
+    st = O.split_stats(32)
+    for k in ("d", "e_nn", "e_nd", "e_dn", "e_dd", "n_ndsrc", "n_ddsrc", "n_dnsrc"):
+        assert G.stats[k] == st[k], k
+    assert G.stats["m_dir"] == O.m
+    sources = inputs_mod.pick_sources(src, dst, n, 64, seed=1002)
+    for i, s in enumerate(sources.tolist()[:16]):
+        want, _ = O.bfs(s, want_parent=False)
+        depth, parent, _ = G.bfs(s, mode=1)
+        log(f"scale 22 source {i} s={s}")
+        np.testing.assert_array_equal(depth, want)
+        assert O.check(s, depth, parent, None)[0] == 0
+    G.close()
+
+
+def test_schedule_and_threshold_invariance(inputs_mod, oracle_mod):
+    """Direction never changes depths (Section IV-B), nor does TH."""
+    n, src, dst, O = _rmat(inputs_mod, oracle_mod, 14)
+    maxdeg = int(O.degrees().max())
+    sources = inputs_mod.pick_sources(src, dst, n, 6, seed=77)
+    wants = {s: O.bfs(s, want_parent=False)[0] for s in sources.tolist()}
+    for TH in (0, 16, 32, 64, 128, maxdeg):
+        G = GpuGraph(src, dst, n, threshold=TH)
+        for s, want in wants.items():
+            for forced, seed in [(0, 0), (1, 0), (2, 0)] + [(3, k) for k in range(8)]:
+                depth, parent, _ = G.bfs(s, forced=forced, seed=seed)
+                np.testing.assert_array_equal(depth, want, err_msg=f"TH={TH} f={forced}/{seed}")
+                assert O.check(s, depth, parent, None)[0] == 0
+        G.close()
+
+
+@pytest.mark.parametrize("scale,TH", [(12, 8), (14, 16), (16, 32)])
+def test_direction_schedule_matches_oracle_replay(inputs_mod, oracle_mod, scale, TH):
+    """Per-level q, s, |U|, FV, BV and the chosen directions equal the oracle's
+    replay of Section IV-B from its own level sets."""
+    n, src, dst, O = _rmat(inputs_mod, oracle_mod, scale)
+    G = GpuGraph(src, dst, n, threshold=TH)
+    for f0 in ((0.5, 0.05, 1e-7), (10.0, 10.0, 10.0), (1e-3, 1e-3, 1e-3)):
+        for f1 in ((0.0, 0.0, 0.0), (0.2, 0.5, 2.0)):
+            for s in inputs_mod.pick_sources(src, dst, n, 4, seed=31 + scale).tolist():
+                want, _ = O.bfs(s, want_parent=False)
+                depth, _, st = G.bfs(s, want_stats=True, factor0=f0, factor1=f1)
+                np.testing.assert_array_equal(depth, want)
+                rep = O.do_replay(TH, want, f0, f1)
+                assert st["num_levels"] == len(rep)
+                for L, (a, b) in enumerate(zip(st["levels"], rep)):
+                    for k in ("q", "s", "U", "FV", "dir"):
+                        assert a[k] == b[k], (L, k, a[k], b[k])
+                    assert a["BV"] == b["BV"], (L, a["BV"], b["BV"])
+                    assert a["FV_nn"] == b["FV_nn"] and a["q_nn"] == b["q_nn"]
+                    assert a["frontier_normal"] == b["frontier_normal"]
+                    assert a["frontier_delegate"] == b["frontier_delegate"]
+    G.close()
+
+
+def _decode(off):
+    off = off.astype(np.uint64)
+    start = (off & np.uint64((1 << 40) - 1)).astype(np.int64)
+    first = (off >> np.uint64(40)).astype(np.int64)
+    return start, first
+
+
+@pytest.mark.parametrize("scale,TH", [(8, 0), (10, 2), (10, 8), (12, 32), (12, 10**6)])
+def test_builder_layout_matches_oracle_split(inputs_mod, oracle_mod, scale, TH):
+    n, src, dst, O = _rmat(inputs_mod, oracle_mod, scale)
+    G = GpuGraph(src, dst, n, threshold=TH)
+    g = G.g
+    st = O.split_stats(TH)
+    for k in ("d", "e_nn", "e_nd", "e_dn", "e_dd", "n_ndsrc", "n_ddsrc", "n_dnsrc"):
+        assert G.stats[k] == st[k], k
+    assert G.stats["m_dir"] == O.m and G.stats["max_degree"] == st["max_deg"]
+    assert G.stats["bytes_layout"] == 8 * (n + 1) + 8 * (st["d"] + 1) + 4 * O.m
+    r = O.split_rows(TH)
+    d = st["d"]
+    np.testing.assert_array_equal(g.export(0, np.int32), O.degrees())
+    np.testing.assert_array_equal(g.export(1, np.int32), r["did"])
+    np.testing.assert_array_equal(g.export(2, np.int32), np.nonzero(r["did"] >= 0)[0])
+    np.testing.assert_array_equal(g.export(10, np.int64), O.off)
+    np.testing.assert_array_equal(g.export(11, np.int32), O.col)
+    ns, nf = _decode(g.export(3, np.uint64))
+    ncol = g.export(4, np.int32)
+    nn_len = np.diff(r["nn_off"])
+    nd_len = np.diff(r["nd_off"])
+    np.testing.assert_array_equal(nf[:n], nn_len)
+    np.testing.assert_array_equal(np.diff(ns), nn_len + nd_len)
+    for v in range(n):
+        row = ncol[ns[v]:ns[v + 1]]
+        assert row[:nf[v]].tolist() == r["nn_col"][r["nn_off"][v]:r["nn_off"][v + 1]].tolist()
+        assert row[nf[v]:].tolist() == r["nd_col"][r["nd_off"][v]:r["nd_off"][v + 1]].tolist()
+    ds, df = _decode(g.export(5, np.uint64))
+    dcol = g.export(6, np.int32)
+    assert len(ds) == d + 1
+    for k in range(d):
+        row = dcol[ds[k]:ds[k + 1]]
+        assert row[:df[k]].tolist() == r["dd_col"][r["dd_off"][k]:r["dd_off"][k + 1]].tolist()
+        assert row[df[k]:].tolist() == r["dn_col"][r["dn_off"][k]:r["dn_off"][k + 1]].tolist()
+    nd_src = np.nonzero(nd_len > 0)[0]
+    np.testing.assert_array_equal(g.export(7, np.int32), nd_src)
+    words = (d + 31) // 32
+    for which, lens in ((8, np.diff(r["dd_off"])), (9, np.diff(r["dn_off"]))):
+        m = g.export(which, np.uint32)
+        assert len(m) == words
+        bits = np.unpackbits(m.view(np.uint8), bitorder="little")[:d]
+        np.testing.assert_array_equal(bits, (lens > 0).astype(np.uint8))
+    G.close()
+
+
+def test_degenerate_inputs(oracle_mod):
+    # isolated source: depth 0 there, -1 elsewhere
+    src = np.array([1, 2, 3], np.int32)
+    dst = np.array([2, 3, 1], np.int32)
+    G = GpuGraph(src, dst, 6, threshold=1)
+    for mode in (0, 1):
+        depth, parent, st = G.bfs(0, mode=mode, want_stats=True)
+        assert depth.tolist() == [0, -1, -1, -1, -1, -1]
+        assert parent.tolist() == [0, -1, -1, -1, -1, -1]
+        assert st["reached"] == 1 and st["edges_cc"] == 0
+    G.close()
+    # no edges at all; one vertex; only self-loops and duplicates
+    for src, dst, n in ((np.zeros(0, np.int32), np.zeros(0, np.int32), 4),
+                        (np.zeros(0, np.int32), np.zeros(0, np.int32), 1),
+                        (np.array([0, 1, 1, 1, 2], np.int32), np.array([0, 1, 2, 2, 1], np.int32), 3)):
+        G = GpuGraph(src, dst, n, threshold=0)
+        O = oracle_mod.Graph(src, dst, n)
+        for s in range(n):
+            want, _ = O.bfs(s)
+            for mode in (0, 1):
+                depth, parent, _ = G.bfs(s, mode=mode)
+                np.testing.assert_array_equal(depth, want)
+                assert O.check(s, depth, parent, None)[0] == 0
+        G.close()
+
+
+def test_error_paths():
+    d = lib()
+    import torch
+    src = np.array([0, 1], np.int32)
+    dst = np.array([1, 2], np.int32)
+    G = GpuGraph(src, dst, 3, threshold=1)
+    for bad in (-1, 3, 1 << 30):
+        with pytest.raises(d.DsbfsError) as e:
+            G.bfs(bad)
+        assert e.value.status == d.ERR_INVALID_ARG
+    with pytest.raises(d.DsbfsError) as e:
+        d.bfs(G.g, G.ws, 0, G.depth, None, opts=d.run_opts(want_parent=True))
+    assert e.value.status == d.ERR_INVALID_ARG
+    G.close()
+    with pytest.raises(d.DsbfsError) as e:
+        d.Graph(np.array([0, 5], np.int32), np.array([1, 1], np.int32), 5)
+    assert e.value.status == d.ERR_INVALID_ARG
+    with pytest.raises(d.DsbfsError) as e:
+        d.Graph(np.array([0, -2], np.int32), np.array([1, 1], np.int32), 5)
+    assert e.value.status == d.ERR_INVALID_ARG
+    G2 = GpuGraph(src, dst, 3, threshold=1, keep_plain=False)
+    with pytest.raises(d.DsbfsError) as e:
+        G2.bfs(0, mode=0)
+    assert e.value.status == d.ERR_INVALID_ARG
+    depth, parent, _ = G2.bfs(0, mode=1)
+    assert depth.tolist() == [0, 1, 2]
+    G2.close()
+    torch.cuda.synchronize()
