@@ -100,7 +100,8 @@ typedef struct dsbfs_run_opts {
                            1 always forward; 2 backward wherever possible from
                            level 1 on; 3 seeded random per level and kernel.
                            Depths never depend on it (Section IV-B). */
-  int32_t reserved;
+  int32_t profile;      /* 1: time every kernel launch with HIP events on the
+                           call's stream and report per-kernel totals in stats */
   uint64_t forced_seed; /* seed of schedule 3 */
 } dsbfs_run_opts;
 
@@ -122,6 +123,33 @@ typedef struct dsbfs_level_stats {
   int64_t frontier_normal, frontier_delegate;
 } dsbfs_level_stats;
 
+/* Kernels of a search, for per-kernel profiles. */
+enum {
+  DSBFS_K_INIT = 0,        /* depth/parent fill and bitmap clear */
+  DSBFS_K_PREV_NORMAL = 1, /* previsit of the normal queue */
+  DSBFS_K_PREV_DELEG = 2,  /* previsit of the delegate frontier mask */
+  DSBFS_K_TD_NORMAL = 3,   /* top-down nn (+nd) from the normal queue */
+  DSBFS_K_TD_DELEG = 4,    /* top-down dd and/or dn from the delegate frontier */
+  DSBFS_K_BU_NORMAL = 5,   /* bottom-up dn over the nd source list */
+  DSBFS_K_BU_DELEG = 6,    /* bottom-up dd and/or nd over unvisited delegates */
+  DSBFS_K_CLOSE = 7,       /* level close */
+  DSBFS_K_PLAIN = 8,       /* mode 0: length, scan and expansion of one level */
+  DSBFS_NUM_KERNELS = 9
+};
+
+/* Per-kernel totals of one search. bytes is the algorithmic HBM traffic of the
+   work the kernel did, from counts the kernel itself keeps: 4 B per queue or
+   list entry read or written, 16 B per pair of 64-bit row offsets, 4 B per
+   adjacency entry read, 4 B per depth (+4 B per parent) written or filled,
+   4 B per delegate ID translated; bitmaps (at most n/8 bytes, cache
+   resident) are not counted. */
+typedef struct dsbfs_kernel_profile {
+  double ms;          /* sum of HIP-event durations of its launches (profile=1) */
+  int64_t launches;
+  int64_t bytes;      /* algorithmic bytes over all its launches */
+  int64_t edges;      /* adjacency entries it read */
+} dsbfs_kernel_profile;
+
 /* Summary of one search. levels[] is caller memory of `capacity` records;
    the first min(num_levels, capacity) are filled (mode 1 only). */
 typedef struct dsbfs_run_stats {
@@ -130,6 +158,7 @@ typedef struct dsbfs_run_stats {
   dsbfs_level_stats *levels;
   int64_t reached;      /* vertices with depth >= 0 */
   int64_t edges_cc;     /* undirected simple edges in the source's component */
+  dsbfs_kernel_profile kernels[DSBFS_NUM_KERNELS];
 } dsbfs_run_stats;
 
 typedef struct dsbfs_graph dsbfs_graph;

@@ -28,6 +28,7 @@ namespace dsbfs {
 
 Workspace::~Workspace() {
   if (hctr) (void)hipHostFree(hctr);
+  for (hipEvent_t e : events) (void)hipEventDestroy(e);
 }
 
 namespace {
@@ -169,20 +170,20 @@ struct Out {
   }
 };
 
-__device__ __forceinline__ void flush_work(LevelCtr *cur, unsigned long long tdv,
-                                           unsigned long long tde, unsigned long long buc,
-                                           unsigned long long bue, unsigned long long cl) {
-  tdv = wave_sum(tdv);
-  tde = wave_sum(tde);
-  buc = wave_sum(buc);
-  bue = wave_sum(bue);
-  cl = wave_sum(cl);
+// Adds four per-lane work counts of kernel k into cur->units[k] (one atomic
+// per wave and slot).
+__device__ __forceinline__ void add_units(LevelCtr *cur, int k, unsigned long long a,
+                                          unsigned long long b, unsigned long long c,
+                                          unsigned long long d) {
+  a = wave_sum(a);
+  b = wave_sum(b);
+  c = wave_sum(c);
+  d = wave_sum(d);
   if (lane_id() == 0) {
-    if (tdv) atomicAdd(&cur->td_vertices, tdv);
-    if (tde) atomicAdd(&cur->td_edges, tde);
-    if (buc) atomicAdd(&cur->bu_candidates, buc);
-    if (bue) atomicAdd(&cur->bu_edges, bue);
-    if (cl) atomicAdd(&cur->claimed, cl);
+    if (a) atomicAdd(&cur->units[k][0], a);
+    if (b) atomicAdd(&cur->units[k][1], b);
+    if (c) atomicAdd(&cur->units[k][2], c);
+    if (d) atomicAdd(&cur->units[k][3], d);
   }
 }
 
@@ -217,7 +218,7 @@ __global__ void __launch_bounds__(kBS) k_td_normal(const int32_t *Q, int64_t qn,
   s_nn[w][l] = nn;
   s_beg[w][l] = beg;
   __syncthreads();
-  unsigned long long claimed = 0;
+  unsigned long long cl_n = 0, cl_d = 0;
   for (int32_t e0 = 0; e0 < T; e0 += kWave) {
     const int32_t e = e0 + l;
     bool won = false;
@@ -237,16 +238,18 @@ __global__ void __launch_bounds__(kBS) k_td_normal(const int32_t *Q, int64_t qn,
         if (won) out.put(v, src);
       } else if (!bit_test(Vd, uint32_t(v)) && bit_claim(Nd, uint32_t(v))) {
         out.put(vid_of[v], src);
-        ++claimed;
+        ++cl_d;
       }
     }
     const int64_t pos = wave_append(won, &cur->qn_next);
     if (won) {
       Qnext[pos] = v;
-      ++claimed;
+      ++cl_n;
     }
   }
-  flush_work(cur, i < qn ? 1 : 0, l == 0 ? (unsigned long long)T : 0, 0, 0, claimed);
+  // units: queue entries, edges, normals claimed, delegates claimed
+  add_units(cur, DSBFS_K_TD_NORMAL, i < qn ? 1 : 0, l == 0 ? (unsigned long long)T : 0, cl_n,
+            cl_d);
 }
 
 // Largest idx in [0, cnt) with pre[idx] <= e (pre non-decreasing, pre[0] = 0).
@@ -287,7 +290,7 @@ __global__ void __launch_bounds__(kBS) k_td_deleg(const int32_t *dlist, const in
   const int64_t nd = int64_t(curc->nd_list);
   const int64_t E = dscan[nd];
   const int64_t nruns = (E + kRun - 1) / kRun;
-  unsigned long long claimed = 0, edges = 0;
+  unsigned long long cl_n = 0, cl_d = 0, edges = 0;
   const int64_t stride = int64_t(gridDim.x) * blockDim.x;
   for (int64_t r0 = int64_t(blockIdx.x) * blockDim.x; r0 < nruns; r0 += stride) {
     const int64_t r = r0 + threadIdx.x;
@@ -310,14 +313,14 @@ __global__ void __launch_bounds__(kBS) k_td_deleg(const int32_t *dlist, const in
         if (is_dd) {
           if (!bit_test(Vd, uint32_t(x)) && bit_claim(Nd, uint32_t(x))) {
             out.put(vid_of[x], vid_of[k]);
-            ++claimed;
+            ++cl_d;
           }
         } else {
           won = bit_claim(Vn, uint32_t(x));
           if (won) {
             v = x;
             out.put(x, vid_of[k]);
-            ++claimed;
+            ++cl_n;
           }
         }
       }
@@ -325,7 +328,8 @@ __global__ void __launch_bounds__(kBS) k_td_deleg(const int32_t *dlist, const in
       if (won) Qnext[pos] = v;
     }
   }
-  flush_work(cur, 0, edges, 0, 0, claimed);
+  // units: -, edges, normals claimed, delegates claimed
+  add_units(cur, DSBFS_K_TD_DELEG, 0, edges, cl_n, cl_d);
 }
 
 // Bottom-up dn (destination: normal vertices): every unvisited vertex of the
@@ -337,7 +341,7 @@ __global__ void __launch_bounds__(kBS) k_bu_normal(const int32_t *cin, int64_t n
                                                    const uint32_t *Fd, const int32_t *vid_of,
                                                    Out out, uint32_t *Vn, int32_t *Qnext,
                                                    int32_t *cout, LevelCtr *cur) {
-  unsigned long long cands = 0, edges = 0, claimed = 0;
+  unsigned long long reads = 0, cands = 0, edges = 0, claimed = 0;
   const int64_t stride = int64_t(gridDim.x) * blockDim.x;
   for (int64_t i0 = int64_t(blockIdx.x) * blockDim.x; i0 < nc; i0 += stride) {
     const int64_t i = i0 + threadIdx.x;
@@ -346,6 +350,7 @@ __global__ void __launch_bounds__(kBS) k_bu_normal(const int32_t *cin, int64_t n
     int32_t found = -1;
     if (i < nc) {
       v = cin[i];
+      ++reads;
       visited = bit_test(Vn, uint32_t(v));
       if (!visited) {
         ++cands;
@@ -372,7 +377,8 @@ __global__ void __launch_bounds__(kBS) k_bu_normal(const int32_t *cin, int64_t n
     const int64_t cpos = wave_append(keep, &cur->nc_next);
     if (keep) cout[cpos] = v;
   }
-  flush_work(cur, 0, 0, cands, edges, claimed);
+  // units: list entries read, unvisited scanned, edges inspected, claimed
+  add_units(cur, DSBFS_K_BU_NORMAL, reads, cands, edges, claimed);
 }
 
 // Bottom-up dd and/or nd (destination: delegates): one wave per unvisited
@@ -416,7 +422,8 @@ __global__ void __launch_bounds__(kBS) k_bu_deleg(const int32_t *dcand, const Le
       if (l == 0) edges += uint64_t(min<int64_t>(kWave, hi - p0));
     }
   }
-  flush_work(cur, 0, 0, cands, edges, claimed);
+  // units: candidates scanned, edges inspected, claimed
+  add_units(cur, DSBFS_K_BU_DELEG, cands, edges, claimed, 0);
 }
 
 // Level close: Vd |= Nd; Fd = Nd; Nd = 0; clear the normal frontier bitmap
@@ -479,27 +486,13 @@ __global__ void __launch_bounds__(kBS) k_plain_expand(const int32_t *Q, const Le
       if (won) Qnext[pos] = v;
     }
   }
-  unsigned long long edges = 0;
-  if (blockIdx.x == 0 && threadIdx.x == 0) edges = (unsigned long long)E;
-  flush_work(cur, 0, edges, 0, 0, claimed);
-}
-
-// reached vertices and the sum of their degrees (twice the component's edges)
-__global__ void k_reach_stats(const int32_t *depth, const int32_t *deg, int32_t n,
-                              unsigned long long *out) {
-  unsigned long long r = 0, s = 0;
-  for (int64_t v = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; v < n;
-       v += int64_t(gridDim.x) * blockDim.x)
-    if (depth[v] >= 0) {
-      ++r;
-      s += unsigned(deg[v]);
-    }
-  r = wave_sum(r);
-  s = wave_sum(s);
-  if (lane_id() == 0) {
-    if (r) atomicAdd(&out[0], r);
-    if (s) atomicAdd(&out[1], s);
+  unsigned long long entries = 0, edges = 0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    entries = (unsigned long long)qn;
+    edges = (unsigned long long)E;
   }
+  // units: queue entries, edges, claimed
+  add_units(cur, DSBFS_K_PLAIN, entries, edges, claimed, 0);
 }
 
 uint64_t mix64(uint64_t z) {
@@ -575,6 +568,44 @@ static double bv_estimate(int64_t U, int64_t q, int64_t s) {
   return double(U) * (double(q) + double(s)) / double(q);
 }
 
+// Per-kernel launch counts, unit totals and (optionally) HIP-event timing.
+struct Prof {
+  bool on = false;
+  hipStream_t s = nullptr;
+  Workspace *ws = nullptr;
+  size_t next = 0;
+  struct Span { int k, b, e; };
+  std::vector<Span> spans;
+  int64_t launches[DSBFS_NUM_KERNELS] = {};
+  double units[DSBFS_NUM_KERNELS][6] = {};
+
+  hipEvent_t ev() {
+    if (next == ws->events.size()) {
+      hipEvent_t e;
+      HIPCHK(hipEventCreate(&e));
+      ws->events.push_back(e);
+    }
+    return ws->events[next++];
+  }
+  int begin() {
+    if (!on) return -1;
+    const int i = int(next);
+    HIPCHK(hipEventRecord(ev(), s));
+    return i;
+  }
+  void end(int k, int b) {
+    ++launches[k];
+    if (!on) return;
+    const int i = int(next);
+    HIPCHK(hipEventRecord(ev(), s));
+    spans.push_back({k, b, i});
+  }
+  void add_level(const LevelCtr &c) {
+    for (int k = 0; k < DSBFS_NUM_KERNELS; ++k)
+      for (int j = 0; j < 4; ++j) units[k][j] += double(c.units[k][j]);
+  }
+};
+
 void bfs_run(const Graph *g, Workspace *ws, int32_t source, const dsbfs_run_opts *opts_in,
              int32_t *depth, int32_t *parent, dsbfs_run_stats *stats, hipStream_t s) {
   if (!ws || ws->g != g) fail(DSBFS_ERR_INVALID_ARG, "workspace does not belong to this graph");
@@ -595,7 +626,12 @@ void bfs_run(const Graph *g, Workspace *ws, int32_t source, const dsbfs_run_opts
   LevelCtr *ctr = ws->ctr.as<LevelCtr>();
   LevelCtr *h = ws->hctr;
   const int SG = stride_grid();
+  Prof P;
+  P.on = o.profile != 0 && stats != nullptr;
+  P.s = s;
+  P.ws = ws;
 
+  int b = P.begin();
   hipLaunchKernelGGL(k_init, dim3(grid_for(std::max(n, 1), kBS, 4096)), dim3(kBS), 0, s, depth,
                      par, n, Vn, Fn, g->nwords(), Vd, Fd, Nd, g->dwords());
   HIPCHK(hipGetLastError());
@@ -604,8 +640,11 @@ void bfs_run(const Graph *g, Workspace *ws, int32_t source, const dsbfs_run_opts
   hipLaunchKernelGGL(k_seed, dim3(1), dim3(1), 0, s, source, g->did.as<int32_t>(), depth, par,
                      Vn, Vd, Fd, Q[0], ctr + 1, o.mode);
   HIPCHK(hipGetLastError());
+  P.end(DSBFS_K_INIT, b);
+  P.units[DSBFS_K_INIT][0] = n;
 
   std::vector<dsbfs_level_stats> rec;
+  double deg_sum = 0;  // sum of degrees over all frontiers = over reached vertices
   int qi = 0;  // Q[qi] is the current queue
   Out out{depth, par, 0};
 
@@ -615,10 +654,12 @@ void bfs_run(const Graph *g, Workspace *ws, int32_t source, const dsbfs_run_opts
       // the previous level's queue length is the only input of this level
       HIPCHK(hipMemcpyAsync(h, prev, sizeof(LevelCtr), hipMemcpyDeviceToHost, s));
       HIPCHK(hipStreamSynchronize(s));
+      P.add_level(*h);
       const int64_t qn = int64_t(h->qn_next);
       if (qn == 0) break;
       HIPCHK(hipMemsetAsync(cur, 0, sizeof(LevelCtr), s));
       out.level1 = L + 1;
+      b = P.begin();
       hipLaunchKernelGGL(k_plain_len, dim3(grid_for(qn, kBS, 8192)), dim3(kBS), 0, s, Q[qi], prev,
                          g->poff.as<int64_t>(), ws->dlen.as<int32_t>());
       HIPCHK(hipGetLastError());
@@ -627,6 +668,7 @@ void bfs_run(const Graph *g, Workspace *ws, int32_t source, const dsbfs_run_opts
                          ws->dscan.as<int64_t>(), g->poff.as<int64_t>(), g->pcol.as<int32_t>(),
                          out, Vn, Q[qi ^ 1], cur);
       HIPCHK(hipGetLastError());
+      P.end(DSBFS_K_PLAIN, b);
       qi ^= 1;
       dsbfs_level_stats r{};
       r.frontier_normal = qn;
@@ -642,25 +684,35 @@ void bfs_run(const Graph *g, Workspace *ws, int32_t source, const dsbfs_run_opts
     for (int32_t L = 0;; ++L) {
       LevelCtr *cur = ctr + (L & 1), *prev = ctr + ((L + 1) & 1);
       HIPCHK(hipMemsetAsync(cur, 0, sizeof(LevelCtr), s));
+      b = P.begin();
       hipLaunchKernelGGL(k_prev_normal, dim3(SG), dim3(kBS), 0, s, Q[qi], prev,
                          g->noff.as<uint64_t>(), Fn, cur);
       HIPCHK(hipGetLastError());
+      P.end(DSBFS_K_PREV_NORMAL, b);
       if (d > 0) {
+        b = P.begin();
         hipLaunchKernelGGL(k_prev_deleg, dim3(grid_for(g->dwords(), kBS, 4096)), dim3(kBS), 0, s,
                            Fd, Vd, g->ddsrc_mask.as<uint32_t>(), g->dnsrc_mask.as<uint32_t>(),
                            g->dwords(), g->doff.as<uint64_t>(), ws->dlist.as<int32_t>(),
                            ws->dcand.as<int32_t>(), cur);
         HIPCHK(hipGetLastError());
+        P.end(DSBFS_K_PREV_DELEG, b);
       }
       HIPCHK(hipMemcpyAsync(h, ctr, 2 * sizeof(LevelCtr), hipMemcpyDeviceToHost, s));
       HIPCHK(hipStreamSynchronize(s));
       const LevelCtr &hc = h[L & 1], &hp = h[(L + 1) & 1];
+      P.add_level(hp);  // the previous level's kernels are complete
       const int64_t qn = int64_t(hp.qn_next);
       const int64_t fdn = int64_t(hc.nd_list);
+      P.units[DSBFS_K_PREV_NORMAL][0] += double(qn);
+      deg_sum += double(hc.fv_nn) + double(hc.fv_nd) + double(hc.fv_dd) + double(hc.fv_dn);
+      P.units[DSBFS_K_PREV_DELEG][0] += double(fdn);
+      P.units[DSBFS_K_PREV_DELEG][1] += double(hc.nd_cand);
       if (nc_pending) {
         // length of the candidate list the previous level's bottom-up normal
         // kernel compacted
         nc = int64_t(hp.nc_next);
+        P.units[DSBFS_K_BU_NORMAL][4] += double(nc);
         nc_pending = false;
       }
       if (qn == 0 && fdn == 0) break;
@@ -705,12 +757,15 @@ void bfs_run(const Graph *g, Workspace *ws, int32_t source, const dsbfs_run_opts
       const bool dd_bu = dir[0] == 1 && q[0] > 0, dn_bu = dir[1] == 1 && q[1] > 0;
       const bool nd_bu = dir[2] == 1 && q[2] > 0;
       if (qn > 0) {
+        b = P.begin();
         hipLaunchKernelGGL(k_td_normal, dim3(grid_for(qn, kBS, 1 << 30)), dim3(kBS), 0, s, Q[qi],
                            qn, g->noff.as<uint64_t>(), g->ncol.as<int32_t>(),
                            g->vid_of.as<int32_t>(), int(nd_td), out, Vn, Vd, Nd, Q[qi ^ 1], cur);
         HIPCHK(hipGetLastError());
+        P.end(DSBFS_K_TD_NORMAL, b);
       }
       if (dd_td || dn_td) {
+        b = P.begin();
         hipLaunchKernelGGL(k_dlen, dim3(grid_for(fdn, kBS, 4096)), dim3(kBS), 0, s,
                            ws->dlist.as<int32_t>(), cur, g->doff.as<uint64_t>(), int(dd_td),
                            int(dn_td), ws->dlen.as<int32_t>());
@@ -722,27 +777,36 @@ void bfs_run(const Graph *g, Workspace *ws, int32_t source, const dsbfs_run_opts
                            g->dcol.as<int32_t>(), g->vid_of.as<int32_t>(), int(dd_td), int(dn_td),
                            out, Vn, Vd, Nd, Q[qi ^ 1], cur);
         HIPCHK(hipGetLastError());
+        P.end(DSBFS_K_TD_DELEG, b);
+        P.units[DSBFS_K_TD_DELEG][0] += double(fdn);
       }
       if (dn_bu && nc > 0) {
         const int32_t *cin = cand_state < 0 ? g->ndsrc.as<int32_t>() : C[cand_state];
         const int nxt = cand_state < 0 ? 0 : (cand_state ^ 1);
+        b = P.begin();
         hipLaunchKernelGGL(k_bu_normal, dim3(grid_for(nc, kBS, 1 << 30)), dim3(kBS), 0, s, cin, nc,
                            g->noff.as<uint64_t>(), g->ncol.as<int32_t>(), Fd,
                            g->vid_of.as<int32_t>(), out, Vn, Q[qi ^ 1], C[nxt], cur);
         HIPCHK(hipGetLastError());
+        P.end(DSBFS_K_BU_NORMAL, b);
         cand_state = nxt;
         nc_pending = true;
       }
       if ((dd_bu || nd_bu) && hc.nd_cand > 0) {
+        b = P.begin();
         hipLaunchKernelGGL(k_bu_deleg, dim3(grid_for(int64_t(hc.nd_cand) * kWave, kBS, 8192)),
                            dim3(kBS), 0, s, ws->dcand.as<int32_t>(), cur, g->doff.as<uint64_t>(),
                            g->dcol.as<int32_t>(), Fd, Fn, g->vid_of.as<int32_t>(), int(dd_bu),
                            int(nd_bu), out, Nd, cur);
         HIPCHK(hipGetLastError());
+        P.end(DSBFS_K_BU_DELEG, b);
       }
+      b = P.begin();
       hipLaunchKernelGGL(k_close, dim3(grid_for(std::max<int64_t>(qn, g->dwords()), kBS, 4096)),
                          dim3(kBS), 0, s, Vd, Fd, Nd, g->dwords(), Fn, Q[qi], prev);
       HIPCHK(hipGetLastError());
+      P.end(DSBFS_K_CLOSE, b);
+      P.units[DSBFS_K_CLOSE][0] += double(qn);
       qi ^= 1;
     }
   }
@@ -752,16 +816,59 @@ void bfs_run(const Graph *g, Workspace *ws, int32_t source, const dsbfs_run_opts
     stats->num_levels = int32_t(rec.size());
     for (int32_t i = 0; i < stats->num_levels && i < stats->capacity && stats->levels; ++i)
       stats->levels[i] = rec[i];
-    unsigned long long *tmp = reinterpret_cast<unsigned long long *>(ws->dscan.p);
-    HIPCHK(hipMemsetAsync(tmp, 0, 2 * sizeof(unsigned long long), s));
-    hipLaunchKernelGGL(k_reach_stats, dim3(grid_for(n, kBS, 2048)), dim3(kBS), 0, s, depth,
-                       g->deg.as<int32_t>(), n, tmp);
-    HIPCHK(hipGetLastError());
-    unsigned long long hr[2];
-    HIPCHK(hipMemcpyAsync(hr, tmp, sizeof(hr), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
-    stats->reached = int64_t(hr[0]);
-    stats->edges_cc = int64_t(hr[1] / 2);
+    // Every reached vertex sits in exactly one level's frontier, whose previsit
+    // (or plain expansion) summed its full degree; each vertex but the source
+    // was claimed exactly once. So the component's size and edge count come
+    // from the level counters without another pass over depth[].
+    const auto &Uc = P.units;
+    const double claims = Uc[DSBFS_K_TD_NORMAL][2] + Uc[DSBFS_K_TD_NORMAL][3] +
+                          Uc[DSBFS_K_TD_DELEG][2] + Uc[DSBFS_K_TD_DELEG][3] +
+                          Uc[DSBFS_K_BU_NORMAL][3] + Uc[DSBFS_K_BU_DELEG][2] +
+                          Uc[DSBFS_K_PLAIN][2];
+    stats->reached = 1 + int64_t(claims);
+    if (o.mode == 0) deg_sum = Uc[DSBFS_K_PLAIN][1];
+    stats->edges_cc = int64_t(deg_sum / 2);
+
+    // Algorithmic bytes per kernel from its unit counts (see dsbfs.h).
+    const double out_b = o.want_parent ? 8.0 : 4.0;  // depth (+ parent) per vertex
+    const auto &U = P.units;
+    double bytes[DSBFS_NUM_KERNELS] = {};
+    double edges[DSBFS_NUM_KERNELS] = {};
+    bytes[DSBFS_K_INIT] = U[DSBFS_K_INIT][0] * out_b;
+    bytes[DSBFS_K_PREV_NORMAL] = U[DSBFS_K_PREV_NORMAL][0] * (4 + 16);
+    bytes[DSBFS_K_PREV_DELEG] = U[DSBFS_K_PREV_DELEG][0] * (4 + 16) + U[DSBFS_K_PREV_DELEG][1] * 4;
+    bytes[DSBFS_K_TD_NORMAL] = U[DSBFS_K_TD_NORMAL][0] * (4 + 16) + U[DSBFS_K_TD_NORMAL][1] * 4 +
+                               U[DSBFS_K_TD_NORMAL][2] * (out_b + 4) +
+                               U[DSBFS_K_TD_NORMAL][3] * (out_b + 4);
+    edges[DSBFS_K_TD_NORMAL] = U[DSBFS_K_TD_NORMAL][1];
+    bytes[DSBFS_K_TD_DELEG] = U[DSBFS_K_TD_DELEG][0] * (4 + 16) + U[DSBFS_K_TD_DELEG][1] * 4 +
+                              U[DSBFS_K_TD_DELEG][2] * (out_b + 4 + 4) +
+                              U[DSBFS_K_TD_DELEG][3] * (out_b + 4 + 4);
+    edges[DSBFS_K_TD_DELEG] = U[DSBFS_K_TD_DELEG][1];
+    bytes[DSBFS_K_BU_NORMAL] = U[DSBFS_K_BU_NORMAL][0] * 4 + U[DSBFS_K_BU_NORMAL][1] * 16 +
+                               U[DSBFS_K_BU_NORMAL][2] * 4 +
+                               U[DSBFS_K_BU_NORMAL][3] * (out_b + 4 + 4) +
+                               U[DSBFS_K_BU_NORMAL][4] * 4;
+    edges[DSBFS_K_BU_NORMAL] = U[DSBFS_K_BU_NORMAL][2];
+    bytes[DSBFS_K_BU_DELEG] = U[DSBFS_K_BU_DELEG][0] * (4 + 16) + U[DSBFS_K_BU_DELEG][1] * 4 +
+                              U[DSBFS_K_BU_DELEG][2] * (out_b + 4 + 4);
+    edges[DSBFS_K_BU_DELEG] = U[DSBFS_K_BU_DELEG][1];
+    bytes[DSBFS_K_CLOSE] = U[DSBFS_K_CLOSE][0] * 4;
+    bytes[DSBFS_K_PLAIN] = U[DSBFS_K_PLAIN][0] * (4 + 16) + U[DSBFS_K_PLAIN][1] * 4 +
+                           U[DSBFS_K_PLAIN][2] * (out_b + 4);
+    edges[DSBFS_K_PLAIN] = U[DSBFS_K_PLAIN][1];
+    double ms[DSBFS_NUM_KERNELS] = {};
+    for (const Prof::Span &sp : P.spans) {
+      float t = 0.f;
+      HIPCHK(hipEventElapsedTime(&t, ws->events[sp.b], ws->events[sp.e]));
+      ms[sp.k] += double(t);
+    }
+    for (int k = 0; k < DSBFS_NUM_KERNELS; ++k) {
+      stats->kernels[k].ms = ms[k];
+      stats->kernels[k].launches = P.launches[k];
+      stats->kernels[k].bytes = int64_t(bytes[k]);
+      stats->kernels[k].edges = int64_t(edges[k]);
+    }
   }
 }
 

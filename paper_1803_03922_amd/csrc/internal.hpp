@@ -100,10 +100,8 @@ struct LevelCtr {
   unsigned long long nd_cand;   // unvisited delegates with a dd or dn edge (length of dcand)
   unsigned long long fv_nn, q_nn, fv_nd, q_nd;  // normal previsit
   unsigned long long fv_dd, q_dd, fv_dn, q_dn;  // delegate previsit
-  unsigned long long td_vertices, td_edges;      // top-down work of this level
-  unsigned long long bu_candidates, bu_edges;    // bottom-up work of this level
-  unsigned long long claimed;                    // vertices discovered by this level
-  unsigned long long pad[3];
+  // Work units per kernel (index DSBFS_K_*), slot meanings in bfs.hip.
+  unsigned long long units[DSBFS_NUM_KERNELS][4];
 };
 
 // Scratch of one search at a time (single-source and multi-source).
@@ -118,6 +116,7 @@ struct Workspace {
   DevBuf ctr;                  // LevelCtr[2]
   DevBuf scan_tmp;
   LevelCtr *hctr = nullptr;    // pinned host copy of ctr
+  std::vector<hipEvent_t> events;  // profiling event pool
   // multi-source lane state
   DevBuf ms_seen, ms_front, ms_next;  // uint64[n]
   DevBuf ms_misc;

@@ -59,7 +59,7 @@ class dsbfs_graph_stats(ctypes.Structure):
 
 class dsbfs_run_opts(ctypes.Structure):
     _fields_ = [("mode", i32), ("want_parent", i32), ("factor0", ctypes.c_double * 3),
-                ("factor1", ctypes.c_double * 3), ("forced", i32), ("reserved", i32),
+                ("factor1", ctypes.c_double * 3), ("forced", i32), ("profile", i32),
                 ("forced_seed", ctypes.c_uint64)]
 
 
@@ -76,10 +76,18 @@ class dsbfs_level_stats(ctypes.Structure):
                 "frontier_delegate": int(self.frontier_delegate)}
 
 
+KERNEL_NAMES = ("init", "prev_normal", "prev_deleg", "td_normal", "td_deleg", "bu_normal",
+                "bu_deleg", "close", "plain")
+
+
+class dsbfs_kernel_profile(ctypes.Structure):
+    _fields_ = [("ms", ctypes.c_double), ("launches", i64), ("bytes", i64), ("edges", i64)]
+
+
 class dsbfs_run_stats(ctypes.Structure):
     _fields_ = [("num_levels", i32), ("capacity", i32),
                 ("levels", ctypes.POINTER(dsbfs_level_stats)), ("reached", i64),
-                ("edges_cc", i64)]
+                ("edges_cc", i64), ("kernels", dsbfs_kernel_profile * len(KERNEL_NAMES))]
 
 
 class dsbfs_ms_opts(ctypes.Structure):
@@ -206,7 +214,7 @@ DEFAULT_FACTOR0 = (0.5, 0.05, 1e-7)
 
 
 def run_opts(mode: int = 1, want_parent: bool = True, factor0=None, factor1=None,
-             forced: int = 0, forced_seed: int = 0) -> dsbfs_run_opts:
+             forced: int = 0, forced_seed: int = 0, profile: bool = False) -> dsbfs_run_opts:
     o = dsbfs_run_opts()
     check(dsbfs_run_opts_default(ctypes.byref(o)), "dsbfs_run_opts_default")
     o.mode = mode
@@ -217,6 +225,7 @@ def run_opts(mode: int = 1, want_parent: bool = True, factor0=None, factor1=None
         o.factor1 = (ctypes.c_double * 3)(*factor1)
     o.forced = forced
     o.forced_seed = forced_seed
+    o.profile = int(bool(profile))
     return o
 
 
@@ -302,15 +311,20 @@ def bfs(graph: Graph, ws: Workspace, source: int, depth, parent=None, opts=None,
     levels = None
     if want_stats:
         levels = (dsbfs_level_stats * capacity)()
-        st = dsbfs_run_stats(0, capacity, ctypes.cast(levels, ctypes.POINTER(dsbfs_level_stats)),
-                             0, 0)
+        st = dsbfs_run_stats()
+        st.capacity = capacity
+        st.levels = ctypes.cast(levels, ctypes.POINTER(dsbfs_level_stats))
     check(dsbfs_bfs(graph.h, ws.h, source, ctypes.byref(opts), _dev_ptr(depth), _dev_ptr(parent),
                     ctypes.byref(st) if st is not None else None, stream), "dsbfs_bfs")
     if not want_stats:
         return None
     nl = st.num_levels
+    kern = {name: {"ms": float(st.kernels[i].ms), "launches": int(st.kernels[i].launches),
+                   "bytes": int(st.kernels[i].bytes), "edges": int(st.kernels[i].edges)}
+            for i, name in enumerate(KERNEL_NAMES)}
     return {"num_levels": nl, "reached": int(st.reached), "edges_cc": int(st.edges_cc),
-            "levels": [levels[i].as_dict() for i in range(min(nl, capacity))]}
+            "levels": [levels[i].as_dict() for i in range(min(nl, capacity))],
+            "kernels": kern}
 
 
 def msbfs(graph: Graph, ws: Workspace, sources, depth, opts: dsbfs_ms_opts | None = None,
