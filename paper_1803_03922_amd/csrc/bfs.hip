@@ -81,9 +81,16 @@ __global__ void k_seed(int32_t s, const int32_t *did, int32_t *depth, int32_t *p
 // ---------------------------------------------------------------------------
 // previsit
 // ---------------------------------------------------------------------------
+// All per-level kernels are grid-stride loops over a bounded grid (a few
+// workgroups per CU) and publish counters and queue entries once per block:
+// device-scope atomics on one address serialize chip-wide, so one per wave
+// over a multi-million-entry frontier would dominate the level.
+constexpr int kQCap = 1536;  // LDS append buffer entries per queue per block
+
 __global__ void __launch_bounds__(kBS) k_prev_normal(const int32_t *Q, const LevelCtr *prev,
                                                      const uint64_t *noff, uint32_t *Fn,
                                                      LevelCtr *cur) {
+  __shared__ unsigned long long sh[4 * kNW];
   const int64_t qn = int64_t(prev->qn_next);
   unsigned long long fv_nn = 0, q_nn = 0, fv_nd = 0, q_nd = 0;
   for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < qn;
@@ -97,64 +104,75 @@ __global__ void __launch_bounds__(kBS) k_prev_normal(const int32_t *Q, const Lev
     q_nd += nd > 0;
     atomicOr(&Fn[u >> 5], 1u << (u & 31));
   }
-  fv_nn = wave_sum(fv_nn);
-  q_nn = wave_sum(q_nn);
-  fv_nd = wave_sum(fv_nd);
-  q_nd = wave_sum(q_nd);
-  if (lane_id() == 0) {
-    if (fv_nn) atomicAdd(&cur->fv_nn, fv_nn);
-    if (q_nn) atomicAdd(&cur->q_nn, q_nn);
-    if (fv_nd) atomicAdd(&cur->fv_nd, fv_nd);
-    if (q_nd) atomicAdd(&cur->q_nd, q_nd);
+  block_add4(&cur->fv_nn, fv_nn, q_nn, fv_nd, q_nd, sh);
+}
+
+// Exclusive scan over the block of one int per thread; *total = block sum.
+__device__ __forceinline__ int block_excl_scan_i32(int v, int *sh, int *total) {
+  const int w = threadIdx.x / kWave, l = lane_id();
+  const int incl = wave_incl_scan(v);
+  if (l == kWave - 1) sh[w] = incl;
+  __syncthreads();
+  int before = 0, all = 0;
+  for (int i = 0; i < kNW; ++i) {
+    const int t = sh[i];
+    before += i < w ? t : 0;
+    all += t;
   }
+  *total = all;
+  __syncthreads();
+  return before + incl - v;
 }
 
 // One thread per mask word: frontier delegates -> dlist (+ dd/dn workloads),
-// unvisited delegates with a dd or dn edge -> dcand.
+// unvisited delegates with a dd or dn edge -> dcand. Positions come from a
+// block scan plus one global atomic per block and list.
 __global__ void __launch_bounds__(kBS) k_prev_deleg(const uint32_t *Fd, const uint32_t *Vd,
                                                     const uint32_t *ddm, const uint32_t *dnm,
                                                     int32_t dwords, const uint64_t *doff,
                                                     int32_t *dlist, int32_t *dcand,
                                                     LevelCtr *cur) {
+  __shared__ int shf[kNW], shc[kNW];
+  __shared__ unsigned long long base[2];
+  __shared__ unsigned long long sh[4 * kNW];
   unsigned long long fv_dd = 0, q_dd = 0, fv_dn = 0, q_dn = 0;
-  for (int64_t w = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; w < dwords;
-       w += int64_t(gridDim.x) * blockDim.x) {
-    uint32_t f = Fd[w];
-    uint32_t c = ~Vd[w] & (ddm[w] | dnm[w]);
-    if (f) {
-      unsigned long long pos = atomicAdd(&cur->nd_list, (unsigned long long)__popc(f));
-      while (f) {
-        const int b = __ffs(f) - 1;
-        f &= f - 1;
-        const int32_t k = int32_t(w * 32 + b);
-        dlist[pos++] = k;
-        const uint64_t w0 = doff[k], w1 = doff[k + 1];
-        const int64_t dd = row_first(w0), dn = row_start(w1) - row_start(w0) - dd;
-        fv_dd += dd;
-        q_dd += dd > 0;
-        fv_dn += dn;
-        q_dn += dn > 0;
-      }
+  for (int64_t w0 = int64_t(blockIdx.x) * blockDim.x; w0 < dwords;
+       w0 += int64_t(gridDim.x) * blockDim.x) {
+    const int64_t w = w0 + threadIdx.x;
+    uint32_t f = 0, c = 0;
+    if (w < dwords) {
+      f = Fd[w];
+      c = ~Vd[w] & (ddm[w] | dnm[w]);
     }
-    if (c) {
-      unsigned long long pos = atomicAdd(&cur->nd_cand, (unsigned long long)__popc(c));
-      while (c) {
-        const int b = __ffs(c) - 1;
-        c &= c - 1;
-        dcand[pos++] = int32_t(w * 32 + b);
-      }
+    int tf, tc;
+    const int ef = block_excl_scan_i32(__popc(f), shf, &tf);
+    const int ec = block_excl_scan_i32(__popc(c), shc, &tc);
+    if (threadIdx.x == 0) {
+      base[0] = tf ? atomicAdd(&cur->nd_list, (unsigned long long)tf) : 0ull;
+      base[1] = tc ? atomicAdd(&cur->nd_cand, (unsigned long long)tc) : 0ull;
     }
+    __syncthreads();
+    unsigned long long pf = base[0] + ef, pc = base[1] + ec;
+    while (f) {
+      const int b = __ffs(f) - 1;
+      f &= f - 1;
+      const int32_t k = int32_t(w * 32 + b);
+      dlist[pf++] = k;
+      const uint64_t x0 = doff[k], x1 = doff[k + 1];
+      const int64_t dd = row_first(x0), dn = row_start(x1) - row_start(x0) - dd;
+      fv_dd += dd;
+      q_dd += dd > 0;
+      fv_dn += dn;
+      q_dn += dn > 0;
+    }
+    while (c) {
+      const int b = __ffs(c) - 1;
+      c &= c - 1;
+      dcand[pc++] = int32_t(w * 32 + b);
+    }
+    __syncthreads();
   }
-  fv_dd = wave_sum(fv_dd);
-  q_dd = wave_sum(q_dd);
-  fv_dn = wave_sum(fv_dn);
-  q_dn = wave_sum(q_dn);
-  if (lane_id() == 0) {
-    if (fv_dd) atomicAdd(&cur->fv_dd, fv_dd);
-    if (q_dd) atomicAdd(&cur->q_dd, q_dd);
-    if (fv_dn) atomicAdd(&cur->fv_dn, fv_dn);
-    if (q_dn) atomicAdd(&cur->q_dn, q_dn);
-  }
+  block_add4(&cur->fv_dd, fv_dd, q_dd, fv_dn, q_dn, sh);
 }
 
 // ---------------------------------------------------------------------------
@@ -170,27 +188,21 @@ struct Out {
   }
 };
 
-// Adds four per-lane work counts of kernel k into cur->units[k] (one atomic
-// per wave and slot).
-__device__ __forceinline__ void add_units(LevelCtr *cur, int k, unsigned long long a,
-                                          unsigned long long b, unsigned long long c,
-                                          unsigned long long d) {
-  a = wave_sum(a);
-  b = wave_sum(b);
-  c = wave_sum(c);
-  d = wave_sum(d);
-  if (lane_id() == 0) {
-    if (a) atomicAdd(&cur->units[k][0], a);
-    if (b) atomicAdd(&cur->units[k][1], b);
-    if (c) atomicAdd(&cur->units[k][2], c);
-    if (d) atomicAdd(&cur->units[k][3], d);
+// Largest index lo in [0, 64) with ex[lo] <= e (ex non-decreasing, ex[0] = 0).
+__device__ __forceinline__ int owner64(const int32_t *ex, int32_t e) {
+  int lo = 0;
+#pragma unroll
+  for (int step = 32; step > 0; step >>= 1) {
+    const int c = lo + step;
+    if (ex[c] <= e) lo = c;
   }
+  return lo;
 }
 
 // Top-down from the normal queue over nn (always) and nd (if nd_td). Each
-// wave owns 64 queue entries; their row lengths are prefix-summed across the
-// wave and the wave walks the concatenated edge range 64 edges at a time, so
-// lanes stay busy whatever the mix of degrees (all are <= TH).
+// wave owns 64 queue entries per step; their row lengths are prefix-summed
+// across the wave and the wave walks the concatenated edge range 64 edges at
+// a time, so lanes stay busy whatever the mix of degrees (all are <= TH).
 __global__ void __launch_bounds__(kBS) k_td_normal(const int32_t *Q, int64_t qn,
                                                    const uint64_t *noff, const int32_t *ncol,
                                                    const int32_t *vid_of, int nd_td, Out out,
@@ -200,56 +212,63 @@ __global__ void __launch_bounds__(kBS) k_td_normal(const int32_t *Q, int64_t qn,
   __shared__ int32_t s_u[kNW][kWave];
   __shared__ int32_t s_nn[kNW][kWave];
   __shared__ int64_t s_beg[kNW][kWave];
+  __shared__ int32_t qbuf[kQCap];
+  __shared__ int qcount;
+  __shared__ unsigned long long qbase;
+  __shared__ unsigned long long sh[4 * kNW];
+  BlockAppend qa{qbuf, &qcount, &qbase, kQCap, &cur->qn_next, Qnext};
+  qa.init();
   const int w = threadIdx.x / kWave, l = lane_id();
-  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  int32_t u = 0, nn = 0, len = 0;
-  int64_t beg = 0;
-  if (i < qn) {
-    u = Q[i];
-    const uint64_t w0 = noff[u], w1 = noff[u + 1];
-    beg = row_start(w0);
-    nn = int32_t(row_first(w0));
-    len = nd_td ? int32_t(row_start(w1) - beg) : nn;
-  }
-  const int32_t incl = wave_incl_scan(len);
-  const int32_t T = __shfl(incl, kWave - 1, kWave);
-  s_excl[w][l] = incl - len;
-  s_u[w][l] = u;
-  s_nn[w][l] = nn;
-  s_beg[w][l] = beg;
-  __syncthreads();
-  unsigned long long cl_n = 0, cl_d = 0;
-  for (int32_t e0 = 0; e0 < T; e0 += kWave) {
-    const int32_t e = e0 + l;
-    bool won = false;
-    int32_t v = 0;
-    if (e < T) {
-      int lo = 0;
-#pragma unroll
-      for (int step = 32; step > 0; step >>= 1) {
-        const int c = lo + step;
-        if (c < kWave && s_excl[w][c] <= e) lo = c;
-      }
-      const int32_t j = e - s_excl[w][lo];
-      const int32_t src = s_u[w][lo];
-      v = ncol[s_beg[w][lo] + j];
-      if (j < s_nn[w][lo]) {
-        won = bit_claim(Vn, uint32_t(v));
-        if (won) out.put(v, src);
-      } else if (!bit_test(Vd, uint32_t(v)) && bit_claim(Nd, uint32_t(v))) {
-        out.put(vid_of[v], src);
-        ++cl_d;
-      }
+  unsigned long long entries = 0, edges = 0, cl_n = 0, cl_d = 0;
+  for (int64_t b0 = int64_t(blockIdx.x) * blockDim.x; b0 < qn;
+       b0 += int64_t(gridDim.x) * blockDim.x) {
+    const int64_t i = b0 + threadIdx.x;
+    int32_t u = 0, nn = 0, len = 0;
+    int64_t beg = 0;
+    if (i < qn) {
+      u = Q[i];
+      const uint64_t w0 = noff[u], w1 = noff[u + 1];
+      beg = row_start(w0);
+      nn = int32_t(row_first(w0));
+      len = nd_td ? int32_t(row_start(w1) - beg) : nn;
+      ++entries;
     }
-    const int64_t pos = wave_append(won, &cur->qn_next);
-    if (won) {
-      Qnext[pos] = v;
-      ++cl_n;
+    const int32_t incl = wave_incl_scan(len);
+    const int32_t T = __shfl(incl, kWave - 1, kWave);
+    wave_sync();
+    s_excl[w][l] = incl - len;
+    s_u[w][l] = u;
+    s_nn[w][l] = nn;
+    s_beg[w][l] = beg;
+    wave_sync();
+    if (l == 0) edges += T;
+    for (int32_t e0 = 0; e0 < T; e0 += kWave) {
+      const int32_t e = e0 + l;
+      bool won = false;
+      int32_t v = 0;
+      if (e < T) {
+        const int lo = owner64(s_excl[w], e);
+        const int32_t j = e - s_excl[w][lo];
+        const int32_t src = s_u[w][lo];
+        v = ncol[s_beg[w][lo] + j];
+        if (j < s_nn[w][lo]) {
+          won = bit_claim(Vn, uint32_t(v));
+          if (won) {
+            out.put(v, src);
+            ++cl_n;
+          }
+        } else if (!bit_test(Vd, uint32_t(v)) && bit_claim(Nd, uint32_t(v))) {
+          out.put(vid_of[v], src);
+          ++cl_d;
+        }
+      }
+      qa.push(won, v);
     }
+    qa.maybe_flush(kBS * 2);
   }
+  qa.flush();
   // units: queue entries, edges, normals claimed, delegates claimed
-  add_units(cur, DSBFS_K_TD_NORMAL, i < qn ? 1 : 0, l == 0 ? (unsigned long long)T : 0, cl_n,
-            cl_d);
+  block_add4(cur->units[DSBFS_K_TD_NORMAL], entries, edges, cl_n, cl_d, sh);
 }
 
 // Largest idx in [0, cnt) with pre[idx] <= e (pre non-decreasing, pre[0] = 0).
@@ -287,6 +306,12 @@ __global__ void __launch_bounds__(kBS) k_td_deleg(const int32_t *dlist, const in
                                                   int dd_td, int dn_td, Out out, uint32_t *Vn,
                                                   const uint32_t *Vd, uint32_t *Nd,
                                                   int32_t *Qnext, LevelCtr *cur) {
+  __shared__ int32_t qbuf[kQCap];
+  __shared__ int qcount;
+  __shared__ unsigned long long qbase;
+  __shared__ unsigned long long sh[4 * kNW];
+  BlockAppend qa{qbuf, &qcount, &qbase, kQCap, &cur->qn_next, Qnext};
+  qa.init();
   const int64_t nd = int64_t(curc->nd_list);
   const int64_t E = dscan[nd];
   const int64_t nruns = (E + kRun - 1) / kRun;
@@ -324,106 +349,165 @@ __global__ void __launch_bounds__(kBS) k_td_deleg(const int32_t *dlist, const in
           }
         }
       }
-      const int64_t pos = wave_append(won, &cur->qn_next);
-      if (won) Qnext[pos] = v;
+      qa.push(won, v);
     }
+    qa.maybe_flush(kBS * kRun + kBS);
   }
+  qa.flush();
   // units: -, edges, normals claimed, delegates claimed
-  add_units(cur, DSBFS_K_TD_DELEG, 0, edges, cl_n, cl_d);
+  block_add4(cur->units[DSBFS_K_TD_DELEG], 0, edges, cl_n, cl_d, sh);
 }
 
-// Bottom-up dn (destination: normal vertices): every unvisited vertex of the
-// nd source list scans its nd part for a delegate in the frontier mask Fd and
-// stops at the first. Candidates still unvisited are compacted for the next
-// bottom-up level.
-__global__ void __launch_bounds__(kBS) k_bu_normal(const int32_t *cin, int64_t nc,
-                                                   const uint64_t *noff, const int32_t *ncol,
-                                                   const uint32_t *Fd, const int32_t *vid_of,
-                                                   Out out, uint32_t *Vn, int32_t *Qnext,
-                                                   int32_t *cout, LevelCtr *cur) {
-  unsigned long long reads = 0, cands = 0, edges = 0, claimed = 0;
-  const int64_t stride = int64_t(gridDim.x) * blockDim.x;
-  for (int64_t i0 = int64_t(blockIdx.x) * blockDim.x; i0 < nc; i0 += stride) {
-    const int64_t i = i0 + threadIdx.x;
-    int32_t v = 0;
+// Bottom-up dn (destination: normal vertices). Candidates are positions in
+// the nd source list; row p of the source-list-ordered nd copy holds the
+// delegate neighbours of ndsrc[p]. Each wave takes 64 candidates, drops the
+// visited ones, and walks the concatenation of the remaining rows 64 entries
+// at a time (consecutive candidates have consecutive rows, so the first pass
+// over the whole list streams them); the first entry of a row found in the
+// frontier mask Fd is kept with an LDS atomicMin, and the wave stops as soon
+// as every remaining candidate has one. Candidates still unvisited are
+// compacted (as positions) for the next bottom-up level.
+__global__ void __launch_bounds__(kBS) k_bu_normal(const int32_t *cin, int dense, int64_t nc,
+                                                   const int32_t *ndsrc, const int64_t *nds_off,
+                                                   const int32_t *nds_col, const uint32_t *Fd,
+                                                   const int32_t *vid_of, Out out, uint32_t *Vn,
+                                                   int32_t *Qnext, int32_t *cout, LevelCtr *cur) {
+  __shared__ int32_t s_excl[kNW][kWave];
+  __shared__ int32_t s_found[kNW][kWave];
+  __shared__ int64_t s_beg[kNW][kWave];
+  __shared__ int32_t qbuf[kQCap], cbuf[kQCap];
+  __shared__ int qcount, ccount;
+  __shared__ unsigned long long qbase, cbase;
+  __shared__ unsigned long long sh[4 * kNW];
+  BlockAppend qa{qbuf, &qcount, &qbase, kQCap, &cur->qn_next, Qnext};
+  BlockAppend ca{cbuf, &ccount, &cbase, kQCap, &cur->nc_next, cout};
+  qa.init();
+  ca.init();
+  const int w = threadIdx.x / kWave, l = lane_id();
+  constexpr int32_t kNone = 0x7fffffff;
+  unsigned long long reads = 0, scanned = 0, edges = 0, claimed = 0;
+  for (int64_t b0 = int64_t(blockIdx.x) * blockDim.x; b0 < nc;
+       b0 += int64_t(gridDim.x) * blockDim.x) {
+    const int64_t i = b0 + threadIdx.x;
+    const bool ok = i < nc;
+    int32_t pos = 0, v = 0, len = 0;
+    int64_t beg = 0;
     bool visited = true;
-    int32_t found = -1;
-    if (i < nc) {
-      v = cin[i];
+    if (ok) {
+      pos = dense ? int32_t(i) : cin[i];
+      v = ndsrc[pos];
       ++reads;
       visited = bit_test(Vn, uint32_t(v));
       if (!visited) {
-        ++cands;
-        const uint64_t w0 = noff[v], w1 = noff[v + 1];
-        const int64_t b = row_start(w0) + row_first(w0), e = row_start(w1);
-        for (int64_t p = b; p < e; ++p) {
-          const int32_t k = ncol[p];
-          ++edges;
-          if (bit_test(Fd, uint32_t(k))) {
-            found = k;
-            break;
-          }
-        }
+        beg = nds_off[pos];
+        len = int32_t(nds_off[pos + 1] - beg);
+        ++scanned;
       }
     }
-    const bool won = found >= 0 && bit_claim(Vn, uint32_t(v));
-    if (won) {
-      out.put(v, vid_of[found]);
-      ++claimed;
+    const int32_t incl = wave_incl_scan(len);
+    const int32_t T = __shfl(incl, kWave - 1, kWave);
+    wave_sync();
+    s_excl[w][l] = incl - len;
+    s_beg[w][l] = beg;
+    s_found[w][l] = kNone;
+    wave_sync();
+    uint64_t remaining = __ballot(len > 0);
+    for (int32_t e0 = 0; e0 < T && remaining; e0 += kWave) {
+      const int32_t e = e0 + l;
+      if (e < T) {
+        const int lo = owner64(s_excl[w], e);
+        const int32_t x = nds_col[s_beg[w][lo] + (e - s_excl[w][lo])];
+        ++edges;
+        if (bit_test(Fd, uint32_t(x))) atomicMin(&s_found[w][lo], e);
+      }
+      wave_sync();
+      remaining = __ballot(len > 0 && s_found[w][l] == kNone);
     }
-    const int64_t pos = wave_append(won, &cur->qn_next);
-    if (won) Qnext[pos] = v;
-    const bool keep = !visited && found < 0;
-    const int64_t cpos = wave_append(keep, &cur->nc_next);
-    if (keep) cout[cpos] = v;
+    const int32_t fe = s_found[w][l];
+    const bool found = len > 0 && fe != kNone;
+    bool won = false;
+    if (found) {
+      const int32_t k = nds_col[beg + (fe - (incl - len))];
+      won = bit_claim(Vn, uint32_t(v));
+      if (won) {
+        out.put(v, vid_of[k]);
+        ++claimed;
+      }
+    }
+    qa.push(won, v);
+    ca.push(ok && !visited && !found, pos);
+    __syncthreads();
+    if (qcount > kQCap - kBS || ccount > kQCap - kBS) {
+      qa.flush();
+      ca.flush();
+    }
   }
+  qa.flush();
+  ca.flush();
   // units: list entries read, unvisited scanned, edges inspected, claimed
-  add_units(cur, DSBFS_K_BU_NORMAL, reads, cands, edges, claimed);
+  block_add4(cur->units[DSBFS_K_BU_NORMAL], reads, scanned, edges, claimed, sh);
 }
 
-// Bottom-up dd and/or nd (destination: delegates): one wave per unvisited
-// delegate; the wave reads 64 row entries per step (dd part against Fd, dn
-// part against the normal frontier bitmap Fn) and stops at the first hit.
+// Bottom-up dd and/or nd (destination: delegates). Groups of 16 lanes take
+// one unvisited delegate each (4 per wave); a group reads 16 row entries per
+// step (dd part against Fd, dn part against the normal frontier bitmap Fn)
+// and stops at the first hit.
+constexpr int kGroup = 16;
+
 __global__ void __launch_bounds__(kBS) k_bu_deleg(const int32_t *dcand, const LevelCtr *curc,
                                                   const uint64_t *doff, const int32_t *dcol,
                                                   const uint32_t *Fd, const uint32_t *Fn,
                                                   const int32_t *vid_of, int dd_bu, int nd_bu,
                                                   Out out, uint32_t *Nd, LevelCtr *cur) {
+  __shared__ unsigned long long sh[4 * kNW];
   const int64_t nc = int64_t(curc->nd_cand);
-  const int l = lane_id();
+  const int l = lane_id(), gi = l / kGroup, gl = l % kGroup;
   const int64_t wid = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) / kWave;
   const int64_t nw = int64_t(gridDim.x) * blockDim.x / kWave;
+  const int per = kWave / kGroup;
   unsigned long long cands = 0, edges = 0, claimed = 0;
-  for (int64_t ci = wid; ci < nc; ci += nw) {
-    const int32_t k = dcand[ci];
-    const uint64_t w0 = doff[k], w1 = doff[k + 1];
-    const int64_t beg = row_start(w0), mid = beg + row_first(w0), end = row_start(w1);
-    const int64_t lo = dd_bu ? beg : mid, hi = nd_bu ? end : mid;
-    if (lo >= hi) continue;
-    if (l == 0) ++cands;
-    for (int64_t p0 = lo; p0 < hi; p0 += kWave) {
-      const int64_t p = p0 + l;
+  for (int64_t c0 = wid * per; c0 < nc; c0 += nw * per) {
+    const int64_t ci = c0 + gi;
+    int32_t k = 0;
+    int64_t p = 0, mid = 0, hi = 0;
+    if (ci < nc) {
+      k = dcand[ci];
+      const uint64_t w0 = doff[k], w1 = doff[k + 1];
+      const int64_t beg = row_start(w0), end = row_start(w1);
+      mid = beg + row_first(w0);
+      p = dd_bu ? beg : mid;
+      hi = nd_bu ? end : mid;
+      if (gl == 0 && p < hi) ++cands;
+    }
+    bool active = p < hi;
+    while (__ballot(active)) {
       bool hit = false;
       int32_t x = 0;
-      if (p < hi) {
-        x = dcol[p];
-        hit = p < mid ? bit_test(Fd, uint32_t(x)) : bit_test(Fn, uint32_t(x));
+      const int64_t q = p + gl;
+      if (active && q < hi) {
+        x = dcol[q];
+        hit = q < mid ? bit_test(Fd, uint32_t(x)) : bit_test(Fn, uint32_t(x));
       }
-      const uint64_t m = __ballot(hit);
-      if (m) {
-        const int f = __ffsll(static_cast<long long>(m)) - 1;
-        if (l == 0) edges += uint64_t(f + 1);
-        if (l == f && bit_claim(Nd, uint32_t(k))) {
-          out.put(vid_of[k], p < mid ? vid_of[x] : x);
-          ++claimed;
+      const uint32_t gm = uint32_t(__ballot(hit) >> (gi * kGroup)) & 0xffffu;
+      if (active) {
+        if (gm) {
+          const int f = __ffs(gm) - 1;
+          if (gl == 0) edges += uint64_t(f + 1);
+          if (gl == f && bit_claim(Nd, uint32_t(k))) {
+            out.put(vid_of[k], q < mid ? vid_of[x] : x);
+            ++claimed;
+          }
+          active = false;
+        } else {
+          if (gl == 0) edges += uint64_t(min<int64_t>(kGroup, hi - p));
+          p += kGroup;
+          active = p < hi;
         }
-        break;
       }
-      if (l == 0) edges += uint64_t(min<int64_t>(kWave, hi - p0));
     }
   }
   // units: candidates scanned, edges inspected, claimed
-  add_units(cur, DSBFS_K_BU_DELEG, cands, edges, claimed, 0);
+  block_add4(cur->units[DSBFS_K_BU_DELEG], cands, edges, claimed, 0, sh);
 }
 
 // Level close: Vd |= Nd; Fd = Nd; Nd = 0; clear the normal frontier bitmap
@@ -459,6 +543,12 @@ __global__ void __launch_bounds__(kBS) k_plain_expand(const int32_t *Q, const Le
                                                       const int64_t *scan, const int64_t *poff,
                                                       const int32_t *pcol, Out out, uint32_t *Vn,
                                                       int32_t *Qnext, LevelCtr *cur) {
+  __shared__ int32_t qbuf[kQCap];
+  __shared__ int qcount;
+  __shared__ unsigned long long qbase;
+  __shared__ unsigned long long sh[4 * kNW];
+  BlockAppend qa{qbuf, &qcount, &qbase, kQCap, &cur->qn_next, Qnext};
+  qa.init();
   const int64_t qn = int64_t(prev->qn_next);
   const int64_t E = scan[qn];
   const int64_t nruns = (E + kRun - 1) / kRun;
@@ -482,17 +572,18 @@ __global__ void __launch_bounds__(kBS) k_plain_expand(const int32_t *Q, const Le
           ++claimed;
         }
       }
-      const int64_t pos = wave_append(won, &cur->qn_next);
-      if (won) Qnext[pos] = v;
+      qa.push(won, v);
     }
+    qa.maybe_flush(kBS * kRun + kBS);
   }
+  qa.flush();
   unsigned long long entries = 0, edges = 0;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     entries = (unsigned long long)qn;
     edges = (unsigned long long)E;
   }
   // units: queue entries, edges, claimed
-  add_units(cur, DSBFS_K_PLAIN, entries, edges, claimed, 0);
+  block_add4(cur->units[DSBFS_K_PLAIN], entries, edges, claimed, 0, sh);
 }
 
 uint64_t mix64(uint64_t z) {
@@ -758,7 +849,7 @@ void bfs_run(const Graph *g, Workspace *ws, int32_t source, const dsbfs_run_opts
       const bool nd_bu = dir[2] == 1 && q[2] > 0;
       if (qn > 0) {
         b = P.begin();
-        hipLaunchKernelGGL(k_td_normal, dim3(grid_for(qn, kBS, 1 << 30)), dim3(kBS), 0, s, Q[qi],
+        hipLaunchKernelGGL(k_td_normal, dim3(grid_for(qn, kBS, SG)), dim3(kBS), 0, s, Q[qi],
                            qn, g->noff.as<uint64_t>(), g->ncol.as<int32_t>(),
                            g->vid_of.as<int32_t>(), int(nd_td), out, Vn, Vd, Nd, Q[qi ^ 1], cur);
         HIPCHK(hipGetLastError());
@@ -781,11 +872,14 @@ void bfs_run(const Graph *g, Workspace *ws, int32_t source, const dsbfs_run_opts
         P.units[DSBFS_K_TD_DELEG][0] += double(fdn);
       }
       if (dn_bu && nc > 0) {
-        const int32_t *cin = cand_state < 0 ? g->ndsrc.as<int32_t>() : C[cand_state];
+        // first pass: every position of the nd source list (dense); later
+        // passes: the positions the previous pass left unvisited
+        const int32_t *cin = cand_state < 0 ? nullptr : C[cand_state];
         const int nxt = cand_state < 0 ? 0 : (cand_state ^ 1);
         b = P.begin();
-        hipLaunchKernelGGL(k_bu_normal, dim3(grid_for(nc, kBS, 1 << 30)), dim3(kBS), 0, s, cin, nc,
-                           g->noff.as<uint64_t>(), g->ncol.as<int32_t>(), Fd,
+        hipLaunchKernelGGL(k_bu_normal, dim3(grid_for(nc, kBS, SG)), dim3(kBS), 0, s, cin,
+                           int(cand_state < 0), nc, g->ndsrc.as<int32_t>(),
+                           g->nds_off.as<int64_t>(), g->nds_col.as<int32_t>(), Fd,
                            g->vid_of.as<int32_t>(), out, Vn, Q[qi ^ 1], C[nxt], cur);
         HIPCHK(hipGetLastError());
         P.end(DSBFS_K_BU_NORMAL, b);
@@ -794,7 +888,7 @@ void bfs_run(const Graph *g, Workspace *ws, int32_t source, const dsbfs_run_opts
       }
       if ((dd_bu || nd_bu) && hc.nd_cand > 0) {
         b = P.begin();
-        hipLaunchKernelGGL(k_bu_deleg, dim3(grid_for(int64_t(hc.nd_cand) * kWave, kBS, 8192)),
+        hipLaunchKernelGGL(k_bu_deleg, dim3(grid_for(int64_t(hc.nd_cand) * kGroup, kBS, SG)),
                            dim3(kBS), 0, s, ws->dcand.as<int32_t>(), cur, g->doff.as<uint64_t>(),
                            g->dcol.as<int32_t>(), Fd, Fn, g->vid_of.as<int32_t>(), int(dd_bu),
                            int(nd_bu), out, Nd, cur);

@@ -253,6 +253,26 @@ __global__ void k_source_masks(const int32_t *vid_of, const int32_t *deg, const 
   }
 }
 
+__global__ void k_nds_len(const int32_t *ndsrc, int64_t cnt, const int32_t *cnt_del,
+                          int32_t *len) {
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < cnt;
+       i += int64_t(gridDim.x) * blockDim.x)
+    len[i] = cnt_del[ndsrc[i]];
+}
+
+// Copies the nd part of row ndsrc[i] to row i of the source-list-ordered copy.
+__global__ void k_nds_fill(const int32_t *ndsrc, int64_t cnt, const uint64_t *noff,
+                           const int32_t *ncol, const int64_t *nds_off, int32_t *nds_col) {
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < cnt;
+       i += int64_t(gridDim.x) * blockDim.x) {
+    const int32_t v = ndsrc[i];
+    const uint64_t w0 = noff[v];
+    const int64_t from = row_start(w0) + row_first(w0);
+    const int64_t to = nds_off[i], len = nds_off[i + 1] - to;
+    for (int64_t j = 0; j < len; ++j) nds_col[to + j] = ncol[from + j];
+  }
+}
+
 // [0] e_nn [1] e_nd [2] e_dn [3] e_dd [4] n_ndsrc [5] n_ddsrc [6] n_dnsrc [7] max degree
 __global__ void k_stats(const int32_t *deg, const int32_t *did, const int32_t *cnt_del, int32_t n,
                         unsigned long long *out) {
@@ -480,6 +500,29 @@ Graph *graph_create(const int32_t *src, const int32_t *dst, int64_t g, int32_t n
     HIPCHK(hipGetLastError());
     G->ndsrc.alloc(al, size_t(hs[4]) * 4, s);
     compact_flags_u8(flag.as<uint8_t>(), n, G->ndsrc.as<int32_t>(), cnt, tmp.p, s);
+    {
+      const int64_t nsrc = int64_t(hs[4]);
+      DevBuf len, stmp;
+      len.alloc(al, size_t(nsrc) * 4, s);
+      stmp.alloc(al, scan_tmp_bytes(nsrc), s);
+      G->nds_off.alloc(al, size_t(nsrc + 1) * 8, s);
+      G->nds_col.alloc(al, size_t(e_nd) * 4, s);
+      if (nsrc > 0) {
+        hipLaunchKernelGGL(k_nds_len, dim3(grid_for(nsrc, kBS, 8192)), dim3(kBS), 0, s,
+                           G->ndsrc.as<int32_t>(), nsrc, cnt_del.as<int32_t>(),
+                           len.as<int32_t>());
+        HIPCHK(hipGetLastError());
+      }
+      scan_excl_i32_to_i64(len.as<int32_t>(), G->nds_off.as<int64_t>(), nsrc, stmp.p, s);
+      if (nsrc > 0) {
+        hipLaunchKernelGGL(k_nds_fill, dim3(grid_for(nsrc, kBS, 16384)), dim3(kBS), 0, s,
+                           G->ndsrc.as<int32_t>(), nsrc, G->noff.as<uint64_t>(),
+                           G->ncol.as<int32_t>(), G->nds_off.as<int64_t>(),
+                           G->nds_col.as<int32_t>());
+        HIPCHK(hipGetLastError());
+      }
+      HIPCHK(hipStreamSynchronize(s));
+    }
     G->ddsrc_mask.alloc(al, size_t(G->dwords()) * 4, s);
     G->dnsrc_mask.alloc(al, size_t(G->dwords()) * 4, s);
     if (d > 0) {
@@ -503,6 +546,7 @@ Graph *graph_create(const int32_t *src, const int32_t *dst, int64_t g, int32_t n
     st.n_ndsrc = hs[4]; st.n_ddsrc = hs[5]; st.n_dnsrc = hs[6];
     st.max_degree = hs[7];
     st.threshold = o.threshold;
+    // the four subgraphs; the source-list-ordered nd copy is reported apart
     st.bytes_layout = int64_t(n + 1) * 8 + int64_t(d + 1) * 8 + 4 * m;
     st.bytes_plain = o.keep_plain_csr ? int64_t(n + 1) * 8 + 4 * m : 0;
     return G;
@@ -531,6 +575,8 @@ void graph_export(const Graph *G, int32_t which, void *host_out, int64_t cap, in
     case 9: b = &G->dnsrc_mask; nb = int64_t(G->dwords()) * 4; break;
     case 10: b = &G->poff; nb = G->poff.p ? (n + 1) * 8 : 0; break;
     case 11: b = &G->pcol; nb = G->pcol.p ? G->m * 4 : 0; break;
+    case 12: b = &G->nds_off; nb = (G->st.n_ndsrc + 1) * 8; break;
+    case 13: b = &G->nds_col; nb = G->st.e_nd * 4; break;
     default: fail(DSBFS_ERR_INVALID_ARG, "unknown array index");
   }
   *bytes = nb;

@@ -86,6 +86,10 @@ struct Graph {
   int64_t m = 0;
   dsbfs_graph_stats st{};
   DevBuf deg, did, vid_of, noff, ncol, doff, dcol, ndsrc, ddsrc_mask, dnsrc_mask;
+  // nd rows again, in nd-source-list order (row i = nd part of ndsrc[i]), so
+  // bottom-up passes over the source list stream them: int64 [n_ndsrc+1],
+  // int32 [e_nd] delegate IDs.
+  DevBuf nds_off, nds_col;
   DevBuf poff, pcol;  // plain CSR: int64 offsets [n+1], int32 columns [m]
   int32_t dwords() const { return (d + 31) / 32; }
   int32_t nwords() const { return (n + 31) / 32; }
@@ -169,6 +173,89 @@ __device__ __forceinline__ bool bit_claim(uint32_t *bm, uint32_t v) {
   const uint32_t b = 1u << (v & 31);
   if (__hip_atomic_load(&bm[v >> 5], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & b) return false;
   return !(atomicOr(&bm[v >> 5], b) & b);
+}
+
+// Orders LDS traffic of one wave around a point where lanes read what other
+// lanes of the same wave wrote.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Block-level append buffer in LDS for grid-stride kernels: lanes reserve
+// slots with one LDS atomic per wave; the block writes the buffer out with a
+// single global atomic per flush, coalesced. Device-scope atomics on one
+// global counter serialize across the chip, so kernels never do one per wave.
+// Appends beyond the buffer (only possible if one iteration produces more
+// than `cap - margin` entries) fall back to a wave-aggregated global append.
+struct BlockAppend {
+  int32_t *buf;              // LDS, cap entries
+  int *count;                // LDS
+  unsigned long long *base;  // LDS
+  int cap;
+  unsigned long long *gcount;
+  int32_t *gout;
+
+  __device__ void init() {
+    if (threadIdx.x == 0) *count = 0;
+  }
+  // Called by every lane of a wave (wave-uniform).
+  __device__ void push(bool want, int32_t v) {
+    const uint64_t m = __ballot(want);
+    if (m == 0) return;
+    const int leader = __ffsll(static_cast<long long>(m)) - 1;
+    int p = 0;
+    if (lane_id() == leader) p = atomicAdd(count, __popcll(m));
+    p = __shfl(p, leader, kWave);
+    const int pos = p + int(lanes_below(m));
+    const bool over = want && pos >= cap;
+    if (want && !over) buf[pos] = v;
+    const int64_t gp = wave_append(over, gcount);
+    if (over) gout[gp] = v;
+  }
+  // Block-uniform: writes the buffer out if it holds more than cap - margin.
+  __device__ void maybe_flush(int margin) {
+    __syncthreads();
+    if (*count > cap - margin) flush();
+  }
+  // Block-uniform.
+  __device__ void flush() {
+    __syncthreads();
+    const int c = min(*count, cap);
+    if (threadIdx.x == 0) *base = c ? atomicAdd(gcount, (unsigned long long)c) : 0ull;
+    __syncthreads();
+    const unsigned long long b = *base;
+    for (int i = threadIdx.x; i < c; i += blockDim.x) gout[b + i] = buf[i];
+    __syncthreads();
+    if (threadIdx.x == 0) *count = 0;
+    __syncthreads();
+  }
+};
+
+// Sums four per-thread counts over the block and adds them to dst[0..3] with
+// one global atomic each (block-uniform call; sh holds 4 * waves entries).
+__device__ __forceinline__ void block_add4(unsigned long long *dst, unsigned long long a,
+                                           unsigned long long b, unsigned long long c,
+                                           unsigned long long d, unsigned long long *sh) {
+  const int w = threadIdx.x / kWave, nw = blockDim.x / kWave;
+  a = wave_sum(a);
+  b = wave_sum(b);
+  c = wave_sum(c);
+  d = wave_sum(d);
+  if (lane_id() == 0) {
+    sh[w] = a;
+    sh[nw + w] = b;
+    sh[2 * nw + w] = c;
+    sh[3 * nw + w] = d;
+  }
+  __syncthreads();
+  if (threadIdx.x < 4) {
+    unsigned long long t = 0;
+    for (int i = 0; i < nw; ++i) t += sh[threadIdx.x * nw + i];
+    if (t) atomicAdd(&dst[threadIdx.x], t);
+  }
+  __syncthreads();
 }
 
 __device__ __forceinline__ int64_t row_start(uint64_t w) { return static_cast<int64_t>(w & kOffMask); }

@@ -176,6 +176,12 @@ def test_builder_layout_matches_oracle_split(inputs_mod, oracle_mod, scale, TH):
         assert row[df[k]:].tolist() == r["dn_col"][r["dn_off"][k]:r["dn_off"][k + 1]].tolist()
     nd_src = np.nonzero(nd_len > 0)[0]
     np.testing.assert_array_equal(g.export(7, np.int32), nd_src)
+    nds_off = g.export(12, np.int64)
+    nds_col = g.export(13, np.int32)
+    np.testing.assert_array_equal(np.diff(nds_off), nd_len[nd_src])
+    for i, v in enumerate(nd_src.tolist()):
+        assert nds_col[nds_off[i]:nds_off[i + 1]].tolist() == \
+            r["nd_col"][r["nd_off"][v]:r["nd_off"][v + 1]].tolist()
     words = (d + 31) // 32
     for which, lens in ((8, np.diff(r["dd_off"])), (9, np.diff(r["dn_off"]))):
         m = g.export(which, np.uint32)
