@@ -126,9 +126,10 @@ typedef struct dsbfs_level_stats {
 /* Kernels of a search, for per-kernel profiles. */
 enum {
   DSBFS_K_INIT = 0,        /* depth/parent fill and bitmap clear */
-  DSBFS_K_PREV_NORMAL = 1, /* previsit of the normal queue */
+  DSBFS_K_PREV_NORMAL = 1, /* previsit of the normal queue fused with its
+                              top-down nn visit (nn is always top-down) */
   DSBFS_K_PREV_DELEG = 2,  /* previsit of the delegate frontier mask */
-  DSBFS_K_TD_NORMAL = 3,   /* top-down nn (+nd) from the normal queue */
+  DSBFS_K_TD_NORMAL = 3,   /* top-down nd from the normal queue */
   DSBFS_K_TD_DELEG = 4,    /* top-down dd and/or dn from the delegate frontier */
   DSBFS_K_BU_NORMAL = 5,   /* bottom-up dn over the nd source list */
   DSBFS_K_BU_DELEG = 6,    /* bottom-up dd and/or nd over unvisited delegates */

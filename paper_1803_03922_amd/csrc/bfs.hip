@@ -13,10 +13,13 @@
 //               frontier's prefix sum; bottom-up: dn via the nd rows of the nd
 //               source list, dd and nd via the delegate rows of unvisited
 //               delegates, each stopping at the first frontier parent;
-//   close     - Vd |= Nd, Fd = Nd, Nd = 0, clear the normal frontier bitmap.
-// Exactly-once discovery comes from atomic test-and-set on the visited
-// bitmaps (normals: Vn; delegates: Nd, checked against Vd), so queues hold no
-// duplicates and depth/parent are written once per vertex.
+//   close     - Fd = Cd & ~Vd, Vd = Cd, clear the normal frontier bitmap.
+// Exactly-once discovery comes from atomic test-and-set on the claimed
+// bitmaps (normals: Vn; delegates: Cd = visited or found this level), so
+// queues hold no duplicates and depth/parent are written once per vertex.
+// The normal previsit and the nn top-down visit share one pass over the
+// queue: nn is always top-down, and its claims change none of the decision's
+// inputs (those come from the frontier and from running counts).
 //
 // Mode 0 is plain top-down BFS over the plain CSR (the paper's "BFS" beside
 // "DOBFS", Section VI-C), with the same load-balanced expansion.
@@ -40,7 +43,7 @@ constexpr int kNW = kBS / kWave;
 // init
 // ---------------------------------------------------------------------------
 __global__ void k_init(int32_t *depth, int32_t *parent, int32_t n, uint32_t *Vn, uint32_t *Fn,
-                       int32_t nwords, uint32_t *Vd, uint32_t *Fd, uint32_t *Nd, int32_t dwords) {
+                       int32_t nwords, uint32_t *Vd, uint32_t *Fd, uint32_t *Cd, int32_t dwords) {
   const int64_t stride = int64_t(gridDim.x) * blockDim.x;
   const int64_t t0 = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   for (int64_t v = t0; v < n; v += stride) {
@@ -54,21 +57,22 @@ __global__ void k_init(int32_t *depth, int32_t *parent, int32_t n, uint32_t *Vn,
   for (int64_t w = t0; w < dwords; w += stride) {
     Vd[w] = 0;
     Fd[w] = 0;
-    Nd[w] = 0;
+    Cd[w] = 0;
   }
 }
 
 // Seeds the source: a delegate enters the delegate frontier mask, a normal
 // vertex the normal queue. prev->qn_next becomes the level-0 queue length.
 __global__ void k_seed(int32_t s, const int32_t *did, int32_t *depth, int32_t *parent,
-                       uint32_t *Vn, uint32_t *Vd, uint32_t *Fd, int32_t *Q, LevelCtr *prev,
-                       int mode) {
+                       uint32_t *Vn, uint32_t *Vd, uint32_t *Fd, uint32_t *Cd, int32_t *Q,
+                       LevelCtr *prev, int mode) {
   depth[s] = 0;
   if (parent) parent[s] = s;
   const int32_t k = mode == 1 ? did[s] : -1;
   if (k >= 0) {
     Vd[k >> 5] |= 1u << (k & 31);
     Fd[k >> 5] |= 1u << (k & 31);
+    Cd[k >> 5] |= 1u << (k & 31);
     prev->qn_next = 0;
   } else {
     Vn[s >> 5] |= 1u << (s & 31);
@@ -87,26 +91,6 @@ __global__ void k_seed(int32_t s, const int32_t *did, int32_t *depth, int32_t *p
 // over a multi-million-entry frontier would dominate the level.
 constexpr int kQCap = 1536;  // LDS append buffer entries per queue per block
 
-__global__ void __launch_bounds__(kBS) k_prev_normal(const int32_t *Q, const LevelCtr *prev,
-                                                     const uint64_t *noff, uint32_t *Fn,
-                                                     LevelCtr *cur) {
-  __shared__ unsigned long long sh[4 * kNW];
-  const int64_t qn = int64_t(prev->qn_next);
-  unsigned long long fv_nn = 0, q_nn = 0, fv_nd = 0, q_nd = 0;
-  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < qn;
-       i += int64_t(gridDim.x) * blockDim.x) {
-    const int32_t u = Q[i];
-    const uint64_t w0 = noff[u], w1 = noff[u + 1];
-    const int64_t nn = row_first(w0), nd = row_start(w1) - row_start(w0) - nn;
-    fv_nn += nn;
-    q_nn += nn > 0;
-    fv_nd += nd;
-    q_nd += nd > 0;
-    atomicOr(&Fn[u >> 5], 1u << (u & 31));
-  }
-  block_add4(&cur->fv_nn, fv_nn, q_nn, fv_nd, q_nd, sh);
-}
-
 // Exclusive scan over the block of one int per thread; *total = block sum.
 __device__ __forceinline__ int block_excl_scan_i32(int v, int *sh, int *total) {
   const int w = threadIdx.x / kWave, l = lane_id();
@@ -124,35 +108,24 @@ __device__ __forceinline__ int block_excl_scan_i32(int v, int *sh, int *total) {
   return before + incl - v;
 }
 
-// One thread per mask word: frontier delegates -> dlist (+ dd/dn workloads),
-// unvisited delegates with a dd or dn edge -> dcand. Positions come from a
-// block scan plus one global atomic per block and list.
-__global__ void __launch_bounds__(kBS) k_prev_deleg(const uint32_t *Fd, const uint32_t *Vd,
-                                                    const uint32_t *ddm, const uint32_t *dnm,
-                                                    int32_t dwords, const uint64_t *doff,
-                                                    int32_t *dlist, int32_t *dcand,
+// One thread per mask word: frontier delegates -> dlist, with their dd/dn
+// workloads. Positions come from a block scan plus one global atomic per block.
+__global__ void __launch_bounds__(kBS) k_prev_deleg(const uint32_t *Fd, int32_t dwords,
+                                                    const uint64_t *doff, int32_t *dlist,
                                                     LevelCtr *cur) {
-  __shared__ int shf[kNW], shc[kNW];
-  __shared__ unsigned long long base[2];
+  __shared__ int shf[kNW];
+  __shared__ unsigned long long base;
   __shared__ unsigned long long sh[4 * kNW];
   unsigned long long fv_dd = 0, q_dd = 0, fv_dn = 0, q_dn = 0;
   for (int64_t w0 = int64_t(blockIdx.x) * blockDim.x; w0 < dwords;
        w0 += int64_t(gridDim.x) * blockDim.x) {
     const int64_t w = w0 + threadIdx.x;
-    uint32_t f = 0, c = 0;
-    if (w < dwords) {
-      f = Fd[w];
-      c = ~Vd[w] & (ddm[w] | dnm[w]);
-    }
-    int tf, tc;
+    uint32_t f = w < dwords ? Fd[w] : 0u;
+    int tf;
     const int ef = block_excl_scan_i32(__popc(f), shf, &tf);
-    const int ec = block_excl_scan_i32(__popc(c), shc, &tc);
-    if (threadIdx.x == 0) {
-      base[0] = tf ? atomicAdd(&cur->nd_list, (unsigned long long)tf) : 0ull;
-      base[1] = tc ? atomicAdd(&cur->nd_cand, (unsigned long long)tc) : 0ull;
-    }
+    if (threadIdx.x == 0) base = tf ? atomicAdd(&cur->nd_list, (unsigned long long)tf) : 0ull;
     __syncthreads();
-    unsigned long long pf = base[0] + ef, pc = base[1] + ec;
+    unsigned long long pf = base + ef;
     while (f) {
       const int b = __ffs(f) - 1;
       f &= f - 1;
@@ -165,6 +138,28 @@ __global__ void __launch_bounds__(kBS) k_prev_deleg(const uint32_t *Fd, const ui
       fv_dn += dn;
       q_dn += dn > 0;
     }
+    __syncthreads();
+  }
+  block_add4(&cur->fv_dd, fv_dd, q_dd, fv_dn, q_dn, sh);
+}
+
+// Unvisited delegates with an edge in a subgraph scanned bottom-up this level
+// (dd part if dd_bu, dn part if nd_bu) -> dcand, ascending.
+__global__ void __launch_bounds__(kBS) k_dcand(const uint32_t *Vd, const uint32_t *ddm,
+                                               const uint32_t *dnm, int32_t dwords, int dd_bu,
+                                               int nd_bu, int32_t *dcand, LevelCtr *cur) {
+  __shared__ int shc[kNW];
+  __shared__ unsigned long long base;
+  for (int64_t w0 = int64_t(blockIdx.x) * blockDim.x; w0 < dwords;
+       w0 += int64_t(gridDim.x) * blockDim.x) {
+    const int64_t w = w0 + threadIdx.x;
+    uint32_t c = 0;
+    if (w < dwords) c = ~Vd[w] & ((dd_bu ? ddm[w] : 0u) | (nd_bu ? dnm[w] : 0u));
+    int tc;
+    const int ec = block_excl_scan_i32(__popc(c), shc, &tc);
+    if (threadIdx.x == 0) base = tc ? atomicAdd(&cur->nd_cand, (unsigned long long)tc) : 0ull;
+    __syncthreads();
+    unsigned long long pc = base + ec;
     while (c) {
       const int b = __ffs(c) - 1;
       c &= c - 1;
@@ -172,7 +167,6 @@ __global__ void __launch_bounds__(kBS) k_prev_deleg(const uint32_t *Fd, const ui
     }
     __syncthreads();
   }
-  block_add4(&cur->fv_dd, fv_dd, q_dd, fv_dn, q_dn, sh);
 }
 
 // ---------------------------------------------------------------------------
@@ -199,18 +193,60 @@ __device__ __forceinline__ int owner64(const int32_t *ex, int32_t e) {
   return lo;
 }
 
-// Top-down from the normal queue over nn (always) and nd (if nd_td). Each
-// wave owns 64 queue entries per step; their row lengths are prefix-summed
-// across the wave and the wave walks the concatenated edge range 64 edges at
-// a time, so lanes stay busy whatever the mix of degrees (all are <= TH).
-__global__ void __launch_bounds__(kBS) k_td_normal(const int32_t *Q, int64_t qn,
-                                                   const uint64_t *noff, const int32_t *ncol,
-                                                   const int32_t *vid_of, int nd_td, Out out,
-                                                   uint32_t *Vn, const uint32_t *Vd, uint32_t *Nd,
-                                                   int32_t *Qnext, LevelCtr *cur) {
+// Wave-balanced top-down expansion of one part of the rows of the normal
+// queue: each wave owns 64 queue entries per step; their part lengths are
+// prefix-summed across the wave and the wave walks the concatenated edge
+// range 64 edges at a time, so lanes stay busy whatever the mix of degrees
+// (all are <= TH). `part` 0 = nn (claims normals, enqueues them), 1 = nd
+// (claims delegates in Cd).
+template <int part>
+__device__ __forceinline__ void expand_normal_rows(int32_t u, int32_t len, int64_t beg,
+                                                   int32_t (&s_excl)[kWave],
+                                                   int32_t (&s_u)[kWave],
+                                                   int64_t (&s_beg)[kWave], const int32_t *ncol,
+                                                   const int32_t *vid_of, const Out &out,
+                                                   uint32_t *Vn, uint32_t *Cd, BlockAppend &qa,
+                                                   unsigned long long &edges,
+                                                   unsigned long long &claimed) {
+  const int l = lane_id();
+  const int32_t incl = wave_incl_scan(len);
+  const int32_t T = __shfl(incl, kWave - 1, kWave);
+  wave_sync();
+  s_excl[l] = incl - len;
+  s_u[l] = u;
+  s_beg[l] = beg;
+  wave_sync();
+  if (l == 0) edges += T;
+  for (int32_t e0 = 0; e0 < T; e0 += kWave) {
+    const int32_t e = e0 + l;
+    bool won = false;
+    int32_t v = 0;
+    if (e < T) {
+      const int lo = owner64(s_excl, e);
+      v = ncol[s_beg[lo] + (e - s_excl[lo])];
+      if (part == 0) {
+        won = bit_claim(Vn, uint32_t(v));
+        if (won) {
+          out.put(v, s_u[lo]);
+          ++claimed;
+        }
+      } else if (bit_claim(Cd, uint32_t(v))) {
+        out.put(vid_of[v], s_u[lo]);
+        ++claimed;
+      }
+    }
+    if (part == 0) qa.push(won, v);
+  }
+}
+
+// One pass over the normal queue: previsit (nn/nd workloads and counts of
+// the frontier, normal frontier bitmap Fn) fused with the nn top-down visit.
+__global__ void __launch_bounds__(kBS) k_normal_level(const int32_t *Q, const LevelCtr *prev,
+                                                      const uint64_t *noff, const int32_t *ncol,
+                                                      Out out, uint32_t *Vn, uint32_t *Fn,
+                                                      int32_t *Qnext, LevelCtr *cur) {
   __shared__ int32_t s_excl[kNW][kWave];
   __shared__ int32_t s_u[kNW][kWave];
-  __shared__ int32_t s_nn[kNW][kWave];
   __shared__ int64_t s_beg[kNW][kWave];
   __shared__ int32_t qbuf[kQCap];
   __shared__ int qcount;
@@ -218,57 +254,64 @@ __global__ void __launch_bounds__(kBS) k_td_normal(const int32_t *Q, int64_t qn,
   __shared__ unsigned long long sh[4 * kNW];
   BlockAppend qa{qbuf, &qcount, &qbase, kQCap, &cur->qn_next, Qnext};
   qa.init();
-  const int w = threadIdx.x / kWave, l = lane_id();
-  unsigned long long entries = 0, edges = 0, cl_n = 0, cl_d = 0;
+  const int w = threadIdx.x / kWave;
+  const int64_t qn = int64_t(prev->qn_next);
+  unsigned long long fv_nn = 0, q_nn = 0, fv_nd = 0, q_nd = 0, edges = 0, claimed = 0;
   for (int64_t b0 = int64_t(blockIdx.x) * blockDim.x; b0 < qn;
        b0 += int64_t(gridDim.x) * blockDim.x) {
     const int64_t i = b0 + threadIdx.x;
-    int32_t u = 0, nn = 0, len = 0;
+    int32_t u = 0, nn = 0;
     int64_t beg = 0;
     if (i < qn) {
       u = Q[i];
       const uint64_t w0 = noff[u], w1 = noff[u + 1];
       beg = row_start(w0);
       nn = int32_t(row_first(w0));
-      len = nd_td ? int32_t(row_start(w1) - beg) : nn;
-      ++entries;
+      const int64_t nd = row_start(w1) - beg - nn;
+      fv_nn += nn;
+      q_nn += nn > 0;
+      fv_nd += nd;
+      q_nd += nd > 0;
+      atomicOr(&Fn[u >> 5], 1u << (u & 31));
     }
-    const int32_t incl = wave_incl_scan(len);
-    const int32_t T = __shfl(incl, kWave - 1, kWave);
-    wave_sync();
-    s_excl[w][l] = incl - len;
-    s_u[w][l] = u;
-    s_nn[w][l] = nn;
-    s_beg[w][l] = beg;
-    wave_sync();
-    if (l == 0) edges += T;
-    for (int32_t e0 = 0; e0 < T; e0 += kWave) {
-      const int32_t e = e0 + l;
-      bool won = false;
-      int32_t v = 0;
-      if (e < T) {
-        const int lo = owner64(s_excl[w], e);
-        const int32_t j = e - s_excl[w][lo];
-        const int32_t src = s_u[w][lo];
-        v = ncol[s_beg[w][lo] + j];
-        if (j < s_nn[w][lo]) {
-          won = bit_claim(Vn, uint32_t(v));
-          if (won) {
-            out.put(v, src);
-            ++cl_n;
-          }
-        } else if (!bit_test(Vd, uint32_t(v)) && bit_claim(Nd, uint32_t(v))) {
-          out.put(vid_of[v], src);
-          ++cl_d;
-        }
-      }
-      qa.push(won, v);
-    }
+    expand_normal_rows<0>(u, nn, beg, s_excl[w], s_u[w], s_beg[w], ncol, nullptr, out, Vn,
+                          nullptr, qa, edges, claimed);
     qa.maybe_flush(kBS * 2);
   }
   qa.flush();
-  // units: queue entries, edges, normals claimed, delegates claimed
-  block_add4(cur->units[DSBFS_K_TD_NORMAL], entries, edges, cl_n, cl_d, sh);
+  block_add4(&cur->fv_nn, fv_nn, q_nn, fv_nd, q_nd, sh);
+  // units: queue entries (counted on the host), nn edges, normals claimed
+  block_add4(cur->units[DSBFS_K_PREV_NORMAL], 0, edges, claimed, 0, sh);
+}
+
+// Top-down nd from the normal queue (only on levels where nd goes forward).
+__global__ void __launch_bounds__(kBS) k_td_nd(const int32_t *Q, int64_t qn,
+                                               const uint64_t *noff, const int32_t *ncol,
+                                               const int32_t *vid_of, Out out, uint32_t *Cd,
+                                               LevelCtr *cur) {
+  __shared__ int32_t s_excl[kNW][kWave];
+  __shared__ int32_t s_u[kNW][kWave];
+  __shared__ int64_t s_beg[kNW][kWave];
+  __shared__ unsigned long long sh[4 * kNW];
+  const int w = threadIdx.x / kWave;
+  BlockAppend none{nullptr, nullptr, nullptr, 0, nullptr, nullptr};
+  unsigned long long edges = 0, claimed = 0;
+  for (int64_t b0 = int64_t(blockIdx.x) * blockDim.x; b0 < qn;
+       b0 += int64_t(gridDim.x) * blockDim.x) {
+    const int64_t i = b0 + threadIdx.x;
+    int32_t u = 0, len = 0;
+    int64_t beg = 0;
+    if (i < qn) {
+      u = Q[i];
+      const uint64_t w0 = noff[u], w1 = noff[u + 1];
+      beg = row_start(w0) + row_first(w0);
+      len = int32_t(row_start(w1) - beg);
+    }
+    expand_normal_rows<1>(u, len, beg, s_excl[w], s_u[w], s_beg[w], ncol, vid_of, out, nullptr,
+                          Cd, none, edges, claimed);
+  }
+  // units: -, edges, -, delegates claimed
+  block_add4(cur->units[DSBFS_K_TD_NORMAL], 0, edges, 0, claimed, sh);
 }
 
 // Largest idx in [0, cnt) with pre[idx] <= e (pre non-decreasing, pre[0] = 0).
@@ -304,8 +347,7 @@ __global__ void __launch_bounds__(kBS) k_td_deleg(const int32_t *dlist, const in
                                                   const LevelCtr *curc, const uint64_t *doff,
                                                   const int32_t *dcol, const int32_t *vid_of,
                                                   int dd_td, int dn_td, Out out, uint32_t *Vn,
-                                                  const uint32_t *Vd, uint32_t *Nd,
-                                                  int32_t *Qnext, LevelCtr *cur) {
+                                                  uint32_t *Cd, int32_t *Qnext, LevelCtr *cur) {
   __shared__ int32_t qbuf[kQCap];
   __shared__ int qcount;
   __shared__ unsigned long long qbase;
@@ -336,7 +378,7 @@ __global__ void __launch_bounds__(kBS) k_td_deleg(const int32_t *dlist, const in
         const int32_t x = dcol[p];
         ++edges;
         if (is_dd) {
-          if (!bit_test(Vd, uint32_t(x)) && bit_claim(Nd, uint32_t(x))) {
+          if (bit_claim(Cd, uint32_t(x))) {
             out.put(vid_of[x], vid_of[k]);
             ++cl_d;
           }
@@ -397,6 +439,8 @@ __global__ void __launch_bounds__(kBS) k_bu_normal(const int32_t *cin, int dense
       pos = dense ? int32_t(i) : cin[i];
       v = ndsrc[pos];
       ++reads;
+      // Visited candidates are dropped before their rows are read: when the
+      // first bottom-up pass comes late, a large part of the list is reached.
       visited = bit_test(Vn, uint32_t(v));
       if (!visited) {
         beg = nds_off[pos];
@@ -428,7 +472,8 @@ __global__ void __launch_bounds__(kBS) k_bu_normal(const int32_t *cin, int dense
     bool won = false;
     if (found) {
       const int32_t k = nds_col[beg + (fe - (incl - len))];
-      won = bit_claim(Vn, uint32_t(v));
+      const uint32_t bit = 1u << (v & 31);
+      won = !(atomicOr(&Vn[v >> 5], bit) & bit);
       if (won) {
         out.put(v, vid_of[k]);
         ++claimed;
@@ -458,7 +503,7 @@ __global__ void __launch_bounds__(kBS) k_bu_deleg(const int32_t *dcand, const Le
                                                   const uint64_t *doff, const int32_t *dcol,
                                                   const uint32_t *Fd, const uint32_t *Fn,
                                                   const int32_t *vid_of, int dd_bu, int nd_bu,
-                                                  Out out, uint32_t *Nd, LevelCtr *cur) {
+                                                  Out out, uint32_t *Cd, LevelCtr *cur) {
   __shared__ unsigned long long sh[4 * kNW];
   const int64_t nc = int64_t(curc->nd_cand);
   const int l = lane_id(), gi = l / kGroup, gl = l % kGroup;
@@ -493,7 +538,7 @@ __global__ void __launch_bounds__(kBS) k_bu_deleg(const int32_t *dcand, const Le
         if (gm) {
           const int f = __ffs(gm) - 1;
           if (gl == 0) edges += uint64_t(f + 1);
-          if (gl == f && bit_claim(Nd, uint32_t(k))) {
+          if (gl == f && bit_claim(Cd, uint32_t(k))) {
             out.put(vid_of[k], q < mid ? vid_of[x] : x);
             ++claimed;
           }
@@ -510,18 +555,20 @@ __global__ void __launch_bounds__(kBS) k_bu_deleg(const int32_t *dcand, const Le
   block_add4(cur->units[DSBFS_K_BU_DELEG], cands, edges, claimed, 0, sh);
 }
 
-// Level close: Vd |= Nd; Fd = Nd; Nd = 0; clear the normal frontier bitmap
-// (only words holding bits of this level's queue can be non-zero).
-__global__ void k_close(uint32_t *Vd, uint32_t *Fd, uint32_t *Nd, int32_t dwords,
-                        uint32_t *Fn, const int32_t *Q, const LevelCtr *prev) {
+// Level close: the next delegate frontier is what was claimed this level
+// (Fd = Cd & ~Vd, Vd = Cd); the normal frontier bitmap is cleared either
+// word by word under this level's queue (small levels) or, when the host has
+// cleared it in bulk, not at all (clear_fn = 0).
+__global__ void k_close(uint32_t *Vd, uint32_t *Fd, const uint32_t *Cd, int32_t dwords,
+                        uint32_t *Fn, const int32_t *Q, const LevelCtr *prev, int clear_fn) {
   const int64_t stride = int64_t(gridDim.x) * blockDim.x;
   const int64_t t0 = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   for (int64_t w = t0; w < dwords; w += stride) {
-    const uint32_t x = Nd[w];
-    Vd[w] |= x;
-    Fd[w] = x;
-    Nd[w] = 0;
+    const uint32_t c = Cd[w];
+    Fd[w] = c & ~Vd[w];
+    Vd[w] = c;
   }
+  if (!clear_fn) return;
   const int64_t qn = int64_t(prev->qn_next);
   for (int64_t i = t0; i < qn; i += stride) Fn[Q[i] >> 5] = 0;
 }
@@ -611,7 +658,7 @@ Workspace *workspace_create(const Graph *g, int32_t max_lanes) {
     ws->Fn.alloc(al, size_t(g->nwords()) * 4, s);
     ws->Vd.alloc(al, size_t(g->dwords()) * 4, s);
     ws->Fd.alloc(al, size_t(g->dwords()) * 4, s);
-    ws->Nd.alloc(al, size_t(g->dwords()) * 4, s);
+    ws->Cd.alloc(al, size_t(g->dwords()) * 4, s);
     ws->q0.alloc(al, size_t(n) * 4, s);
     ws->q1.alloc(al, size_t(n) * 4, s);
     ws->dlist.alloc(al, size_t(d) * 4, s);
@@ -712,7 +759,7 @@ void bfs_run(const Graph *g, Workspace *ws, int32_t source, const dsbfs_run_opts
 
   const int32_t n = g->n, d = g->d;
   uint32_t *Vn = ws->Vn.as<uint32_t>(), *Fn = ws->Fn.as<uint32_t>();
-  uint32_t *Vd = ws->Vd.as<uint32_t>(), *Fd = ws->Fd.as<uint32_t>(), *Nd = ws->Nd.as<uint32_t>();
+  uint32_t *Vd = ws->Vd.as<uint32_t>(), *Fd = ws->Fd.as<uint32_t>(), *Cd = ws->Cd.as<uint32_t>();
   int32_t *Q[2] = {ws->q0.as<int32_t>(), ws->q1.as<int32_t>()};
   LevelCtr *ctr = ws->ctr.as<LevelCtr>();
   LevelCtr *h = ws->hctr;
@@ -724,12 +771,12 @@ void bfs_run(const Graph *g, Workspace *ws, int32_t source, const dsbfs_run_opts
 
   int b = P.begin();
   hipLaunchKernelGGL(k_init, dim3(grid_for(std::max(n, 1), kBS, 4096)), dim3(kBS), 0, s, depth,
-                     par, n, Vn, Fn, g->nwords(), Vd, Fd, Nd, g->dwords());
+                     par, n, Vn, Fn, g->nwords(), Vd, Fd, Cd, g->dwords());
   HIPCHK(hipGetLastError());
   HIPCHK(hipMemsetAsync(ctr, 0, 2 * sizeof(LevelCtr), s));
   // level L uses ctr[L & 1]; the seed plays the part of "level -1" (ctr[1]).
   hipLaunchKernelGGL(k_seed, dim3(1), dim3(1), 0, s, source, g->did.as<int32_t>(), depth, par,
-                     Vn, Vd, Fd, Q[0], ctr + 1, o.mode);
+                     Vn, Vd, Fd, Cd, Q[0], ctr + 1, o.mode);
   HIPCHK(hipGetLastError());
   P.end(DSBFS_K_INIT, b);
   P.units[DSBFS_K_INIT][0] = n;
@@ -775,17 +822,17 @@ void bfs_run(const Graph *g, Workspace *ws, int32_t source, const dsbfs_run_opts
     for (int32_t L = 0;; ++L) {
       LevelCtr *cur = ctr + (L & 1), *prev = ctr + ((L + 1) & 1);
       HIPCHK(hipMemsetAsync(cur, 0, sizeof(LevelCtr), s));
+      out.level1 = L + 1;
       b = P.begin();
-      hipLaunchKernelGGL(k_prev_normal, dim3(SG), dim3(kBS), 0, s, Q[qi], prev,
-                         g->noff.as<uint64_t>(), Fn, cur);
+      hipLaunchKernelGGL(k_normal_level, dim3(SG), dim3(kBS), 0, s, Q[qi], prev,
+                         g->noff.as<uint64_t>(), g->ncol.as<int32_t>(), out, Vn, Fn, Q[qi ^ 1],
+                         cur);
       HIPCHK(hipGetLastError());
       P.end(DSBFS_K_PREV_NORMAL, b);
       if (d > 0) {
         b = P.begin();
         hipLaunchKernelGGL(k_prev_deleg, dim3(grid_for(g->dwords(), kBS, 4096)), dim3(kBS), 0, s,
-                           Fd, Vd, g->ddsrc_mask.as<uint32_t>(), g->dnsrc_mask.as<uint32_t>(),
-                           g->dwords(), g->doff.as<uint64_t>(), ws->dlist.as<int32_t>(),
-                           ws->dcand.as<int32_t>(), cur);
+                           Fd, g->dwords(), g->doff.as<uint64_t>(), ws->dlist.as<int32_t>(), cur);
         HIPCHK(hipGetLastError());
         P.end(DSBFS_K_PREV_DELEG, b);
       }
@@ -798,7 +845,6 @@ void bfs_run(const Graph *g, Workspace *ws, int32_t source, const dsbfs_run_opts
       P.units[DSBFS_K_PREV_NORMAL][0] += double(qn);
       deg_sum += double(hc.fv_nn) + double(hc.fv_nd) + double(hc.fv_dd) + double(hc.fv_dn);
       P.units[DSBFS_K_PREV_DELEG][0] += double(fdn);
-      P.units[DSBFS_K_PREV_DELEG][1] += double(hc.nd_cand);
       if (nc_pending) {
         // length of the candidate list the previous level's bottom-up normal
         // kernel compacted
@@ -842,18 +888,20 @@ void bfs_run(const Graph *g, Workspace *ws, int32_t source, const dsbfs_run_opts
       r.frontier_delegate = fdn;
       rec.push_back(r);
 
-      out.level1 = L + 1;
+      // nn went top-down inside k_normal_level already
       const bool dd_td = dir[0] == 0 && q[0] > 0, dn_td = dir[1] == 0 && q[1] > 0;
       const bool nd_td = dir[2] == 0 && q[2] > 0;
-      const bool dd_bu = dir[0] == 1 && q[0] > 0, dn_bu = dir[1] == 1 && q[1] > 0;
-      const bool nd_bu = dir[2] == 1 && q[2] > 0;
-      if (qn > 0) {
+      const bool dd_bu = dir[0] == 1 && q[0] > 0 && U[0] > 0;
+      const bool dn_bu = dir[1] == 1 && q[1] > 0 && U[1] > 0;
+      const bool nd_bu = dir[2] == 1 && q[2] > 0 && U[2] > 0;
+      if (nd_td) {
         b = P.begin();
-        hipLaunchKernelGGL(k_td_normal, dim3(grid_for(qn, kBS, SG)), dim3(kBS), 0, s, Q[qi],
-                           qn, g->noff.as<uint64_t>(), g->ncol.as<int32_t>(),
-                           g->vid_of.as<int32_t>(), int(nd_td), out, Vn, Vd, Nd, Q[qi ^ 1], cur);
+        hipLaunchKernelGGL(k_td_nd, dim3(grid_for(qn, kBS, SG)), dim3(kBS), 0, s, Q[qi], qn,
+                           g->noff.as<uint64_t>(), g->ncol.as<int32_t>(),
+                           g->vid_of.as<int32_t>(), out, Cd, cur);
         HIPCHK(hipGetLastError());
         P.end(DSBFS_K_TD_NORMAL, b);
+        P.units[DSBFS_K_TD_NORMAL][0] += double(qn);
       }
       if (dd_td || dn_td) {
         b = P.begin();
@@ -866,7 +914,7 @@ void bfs_run(const Graph *g, Workspace *ws, int32_t source, const dsbfs_run_opts
         hipLaunchKernelGGL(k_td_deleg, dim3(SG), dim3(kBS), 0, s, ws->dlist.as<int32_t>(),
                            ws->dscan.as<int64_t>(), cur, g->doff.as<uint64_t>(),
                            g->dcol.as<int32_t>(), g->vid_of.as<int32_t>(), int(dd_td), int(dn_td),
-                           out, Vn, Vd, Nd, Q[qi ^ 1], cur);
+                           out, Vn, Cd, Q[qi ^ 1], cur);
         HIPCHK(hipGetLastError());
         P.end(DSBFS_K_TD_DELEG, b);
         P.units[DSBFS_K_TD_DELEG][0] += double(fdn);
@@ -886,21 +934,36 @@ void bfs_run(const Graph *g, Workspace *ws, int32_t source, const dsbfs_run_opts
         cand_state = nxt;
         nc_pending = true;
       }
-      if ((dd_bu || nd_bu) && hc.nd_cand > 0) {
+      if (dd_bu || nd_bu) {
+        // candidates: unvisited delegates with an edge in a subgraph scanned
+        // bottom-up; at most U_dd + U_nd of them
+        const int64_t ncand_max = (dd_bu ? U[0] : 0) + (nd_bu ? U[2] : 0);
         b = P.begin();
-        hipLaunchKernelGGL(k_bu_deleg, dim3(grid_for(int64_t(hc.nd_cand) * kGroup, kBS, SG)),
+        hipLaunchKernelGGL(k_dcand, dim3(grid_for(g->dwords(), kBS, 4096)), dim3(kBS), 0, s, Vd,
+                           g->ddsrc_mask.as<uint32_t>(), g->dnsrc_mask.as<uint32_t>(),
+                           g->dwords(), int(dd_bu), int(nd_bu), ws->dcand.as<int32_t>(), cur);
+        HIPCHK(hipGetLastError());
+        hipLaunchKernelGGL(k_bu_deleg,
+                           dim3(grid_for(std::min<int64_t>(ncand_max, d) * kGroup, kBS, SG)),
                            dim3(kBS), 0, s, ws->dcand.as<int32_t>(), cur, g->doff.as<uint64_t>(),
                            g->dcol.as<int32_t>(), Fd, Fn, g->vid_of.as<int32_t>(), int(dd_bu),
-                           int(nd_bu), out, Nd, cur);
+                           int(nd_bu), out, Cd, cur);
         HIPCHK(hipGetLastError());
         P.end(DSBFS_K_BU_DELEG, b);
       }
+      // Large levels clear the normal frontier bitmap with one streaming fill
+      // instead of one scattered store per queue entry.
+      const bool bulk_fn = qn * 16 > int64_t(g->nwords());
       b = P.begin();
-      hipLaunchKernelGGL(k_close, dim3(grid_for(std::max<int64_t>(qn, g->dwords()), kBS, 4096)),
-                         dim3(kBS), 0, s, Vd, Fd, Nd, g->dwords(), Fn, Q[qi], prev);
+      if (bulk_fn) HIPCHK(hipMemsetAsync(Fn, 0, size_t(g->nwords()) * 4, s));
+      hipLaunchKernelGGL(k_close,
+                         dim3(grid_for(std::max<int64_t>(bulk_fn ? 0 : qn, g->dwords()), kBS,
+                                       4096)),
+                         dim3(kBS), 0, s, Vd, Fd, Cd, g->dwords(), Fn, Q[qi], prev,
+                         int(!bulk_fn));
       HIPCHK(hipGetLastError());
       P.end(DSBFS_K_CLOSE, b);
-      P.units[DSBFS_K_CLOSE][0] += double(qn);
+      P.units[DSBFS_K_CLOSE][0] += double(bulk_fn ? g->nwords() / 4 : qn);
       qi ^= 1;
     }
   }
@@ -915,7 +978,7 @@ void bfs_run(const Graph *g, Workspace *ws, int32_t source, const dsbfs_run_opts
     // was claimed exactly once. So the component's size and edge count come
     // from the level counters without another pass over depth[].
     const auto &Uc = P.units;
-    const double claims = Uc[DSBFS_K_TD_NORMAL][2] + Uc[DSBFS_K_TD_NORMAL][3] +
+    const double claims = Uc[DSBFS_K_PREV_NORMAL][2] + Uc[DSBFS_K_TD_NORMAL][3] +
                           Uc[DSBFS_K_TD_DELEG][2] + Uc[DSBFS_K_TD_DELEG][3] +
                           Uc[DSBFS_K_BU_NORMAL][3] + Uc[DSBFS_K_BU_DELEG][2] +
                           Uc[DSBFS_K_PLAIN][2];
@@ -929,10 +992,12 @@ void bfs_run(const Graph *g, Workspace *ws, int32_t source, const dsbfs_run_opts
     double bytes[DSBFS_NUM_KERNELS] = {};
     double edges[DSBFS_NUM_KERNELS] = {};
     bytes[DSBFS_K_INIT] = U[DSBFS_K_INIT][0] * out_b;
-    bytes[DSBFS_K_PREV_NORMAL] = U[DSBFS_K_PREV_NORMAL][0] * (4 + 16);
-    bytes[DSBFS_K_PREV_DELEG] = U[DSBFS_K_PREV_DELEG][0] * (4 + 16) + U[DSBFS_K_PREV_DELEG][1] * 4;
+    bytes[DSBFS_K_PREV_NORMAL] = U[DSBFS_K_PREV_NORMAL][0] * (4 + 16) +
+                                 U[DSBFS_K_PREV_NORMAL][1] * 4 +
+                                 U[DSBFS_K_PREV_NORMAL][2] * (out_b + 4);
+    edges[DSBFS_K_PREV_NORMAL] = U[DSBFS_K_PREV_NORMAL][1];
+    bytes[DSBFS_K_PREV_DELEG] = U[DSBFS_K_PREV_DELEG][0] * (4 + 16);
     bytes[DSBFS_K_TD_NORMAL] = U[DSBFS_K_TD_NORMAL][0] * (4 + 16) + U[DSBFS_K_TD_NORMAL][1] * 4 +
-                               U[DSBFS_K_TD_NORMAL][2] * (out_b + 4) +
                                U[DSBFS_K_TD_NORMAL][3] * (out_b + 4);
     edges[DSBFS_K_TD_NORMAL] = U[DSBFS_K_TD_NORMAL][1];
     bytes[DSBFS_K_TD_DELEG] = U[DSBFS_K_TD_DELEG][0] * (4 + 16) + U[DSBFS_K_TD_DELEG][1] * 4 +
@@ -944,8 +1009,8 @@ void bfs_run(const Graph *g, Workspace *ws, int32_t source, const dsbfs_run_opts
                                U[DSBFS_K_BU_NORMAL][3] * (out_b + 4 + 4) +
                                U[DSBFS_K_BU_NORMAL][4] * 4;
     edges[DSBFS_K_BU_NORMAL] = U[DSBFS_K_BU_NORMAL][2];
-    bytes[DSBFS_K_BU_DELEG] = U[DSBFS_K_BU_DELEG][0] * (4 + 16) + U[DSBFS_K_BU_DELEG][1] * 4 +
-                              U[DSBFS_K_BU_DELEG][2] * (out_b + 4 + 4);
+    bytes[DSBFS_K_BU_DELEG] = U[DSBFS_K_BU_DELEG][0] * (4 + 4 + 16) +
+                              U[DSBFS_K_BU_DELEG][1] * 4 + U[DSBFS_K_BU_DELEG][2] * (out_b + 4 + 4);
     edges[DSBFS_K_BU_DELEG] = U[DSBFS_K_BU_DELEG][1];
     bytes[DSBFS_K_CLOSE] = U[DSBFS_K_CLOSE][0] * 4;
     bytes[DSBFS_K_PLAIN] = U[DSBFS_K_PLAIN][0] * (4 + 16) + U[DSBFS_K_PLAIN][1] * 4 +

@@ -112,7 +112,9 @@ struct LevelCtr {
 struct Workspace {
   const Graph *g = nullptr;
   int32_t max_lanes = 0;
-  DevBuf Vn, Fn, Vd, Fd, Nd;   // uint32 bitmaps: visited/frontier normals, delegates
+  // uint32 bitmaps: visited / frontier normals; visited at level start,
+  // frontier, and claimed (visited or found this level) delegates
+  DevBuf Vn, Fn, Vd, Fd, Cd;
   DevBuf q0, q1;               // normal queues, int32[n]
   DevBuf dlist, dcand, dlen;   // int32[d]
   DevBuf dscan;                // int64[max(n, d) + 1]: prefix of top-down lengths
