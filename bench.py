@@ -61,6 +61,14 @@ def main():
     ap.add_argument("--cpu-sources", type=int, default=1,
                     help="sources of the CPU oracle sample (0 = skip)")
     ap.add_argument("--no-parent", action="store_true")
+    ap.add_argument("--batched", type=int, default=1,
+                    help="1: also measure multi-source BFS (RMAT scale --ms-scale, 1024 sources)")
+    ap.add_argument("--ms-scale", type=int, default=24)
+    ap.add_argument("--ms-sources", type=int, default=1024)
+    ap.add_argument("--served", type=int, default=1,
+                    help="1: also measure the query server (5 graphs, 3 Poisson rates)")
+    ap.add_argument("--serve-queries", type=int, default=4096)
+    ap.add_argument("--serve-scales", default="18,20,22,24")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -166,6 +174,12 @@ def main():
                          f"host thread, CSR build untimed"}
         del O
 
+    del ws, g, depth, parent
+    torch.cuda.empty_cache()
+    batched = bench_batched(args, torch, dsbfs, inputs) if args.batched else None
+    torch.cuda.empty_cache()
+    served = bench_served(args, torch, dsbfs, inputs) if args.served else None
+
     line = {
         "metric": "GTEPS (harmonic mean, 1 GPU) + p50/p99 query latency, batched vs plain BFS",
         "value": round(value, 3),
@@ -185,6 +199,8 @@ def main():
                    "parents": parent is not None, "parallelism": "single GPU"},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "batched": batched,
+        "served": served,
         "detail": {
             "gteps_geometric": round(geometric(rates), 3),
             "gteps_nominal_geometric": round(geometric(nominal), 3),
@@ -198,6 +214,172 @@ def main():
         },
     }
     print(json.dumps(line), flush=True)
+
+
+def bench_batched(args, torch, dsbfs, inputs):
+    """Multi-source BFS: all sources (64 lanes per batch) in one persistent,
+    graph-captured launch, tuned by the autotuner, against single-source
+    DOBFS from the same sources on the same graph (depth only on both sides)."""
+    scale = args.ms_scale
+    n = 1 << scale
+    src, dst = inputs.rmat_edges(scale)
+    g = dsbfs.Graph(src, dst, n, threshold=args.threshold, keep_plain_csr=True)
+    sources = inputs.pick_sources(src, dst, n, args.ms_sources, seed=1004)
+    del src, dst
+    ws = dsbfs.Workspace(g, max_lanes=64)
+    t0 = time.time()
+    opts = dsbfs.msbfs_tune(g, ws, sources[:64])
+    log(f"msbfs tuned in {time.time() - t0:.1f}s: {opts.as_dict()}")
+    depth = torch.empty((len(sources), n), dtype=torch.int32, device="cuda")
+    stream = torch.cuda.current_stream()
+    dsbfs.msbfs(g, ws, sources, depth, opts)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    dsbfs.msbfs(g, ws, sources, depth, opts)
+    e1.record(stream)
+    e1.synchronize()
+    t_batch = e0.elapsed_time(e1)
+    log(f"msbfs: {len(sources)} sources in {t_batch:.1f} ms")
+    del depth
+    torch.cuda.empty_cache()
+    d1 = torch.empty(n, dtype=torch.int32, device="cuda")
+    o1 = dsbfs.run_opts(want_parent=False)
+    tot_ms, tot_e = 0.0, 0
+    for s in sources.tolist():
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        r = dsbfs.bfs(g, ws, s, d1, None, opts=o1, want_stats=True)
+        b.record(stream)
+        b.synchronize()
+        tot_ms += a.elapsed_time(b)
+        tot_e += r["edges_cc"]
+    log(f"single-source DOBFS: {tot_ms:.1f} ms total")
+    out = {"workload": f"RMAT scale {scale}, {len(sources)} sources = "
+                       f"{(len(sources) + 63) // 64} batches of 64 lanes, one persistent "
+                       f"{'graph-captured ' if opts.use_graph else ''}launch",
+           "value": round(tot_e / (t_batch * 1e-3) / 1e9, 2), "unit": "GTEPS (aggregate)",
+           "launch_ms": round(t_batch, 2),
+           "plain_gteps": round(tot_e / (tot_ms * 1e-3) / 1e9, 2),
+           "plain_ms_total": round(tot_ms, 2),
+           "speedup": round(tot_ms / t_batch, 2), "tuned": opts.as_dict()}
+    ws.destroy()
+    g.destroy()
+    return out
+
+
+def _poisson_run(dsbfs, server, gids, pools, ncc, rate, nq, seed):
+    """Submits nq queries with Poisson arrivals at `rate` per second (graph
+    uniform, source uniform in its pool), collects and releases every result;
+    returns per-query latency (ms) and aggregate GTEPS."""
+    import threading
+    rng = np.random.default_rng(seed)
+    gaps = rng.exponential(1.0 / rate, size=nq)
+    which = rng.integers(0, len(gids), size=nq)
+    picks = [int(pools[k][rng.integers(0, len(pools[k]))]) for k in which.tolist()]
+    tickets = [None] * nq
+    ready = threading.Semaphore(0)
+    stats = [None] * nq
+
+    def collect():
+        for i in range(nq):
+            ready.acquire()
+            _, st = server.wait(tickets[i])
+            server.release(tickets[i])
+            stats[i] = st
+
+    th = threading.Thread(target=collect)
+    th.start()
+    t0 = dsbfs.now_ns() + 2_000_000
+    at = t0
+    for i in range(nq):
+        at += int(gaps[i] * 1e9)
+        while True:
+            now = dsbfs.now_ns()
+            if now >= at:
+                break
+            if at - now > 300_000:
+                time.sleep((at - now - 200_000) / 1e9)
+        tickets[i] = server.submit(gids[which[i]], picks[i], at)
+        ready.release()
+    th.join()
+    lat = np.array([(st["done_ns"] - st["arrival_ns"]) / 1e6 for st in stats])
+    t_first = min(st["arrival_ns"] for st in stats)
+    t_last = max(st["done_ns"] for st in stats)
+    edges = sum(ncc[k] for k in which.tolist())
+    return lat, edges / ((t_last - t_first) * 1e-9) / 1e9
+
+
+def bench_served(args, torch, dsbfs, inputs):
+    """Query stream over 5 resident graphs (RMAT 18/20/22/24 + ER 2^22 with
+    8n pairs), Poisson arrivals at 0.5, 1 and 2 times the plain server's
+    service rate, served plainly (one query at a time) and with continuous
+    batching; p50/p99 latency and aggregate GTEPS per rate."""
+    specs = [("rmat", int(x)) for x in args.serve_scales.split(",")] + [("er", 22)]
+    built = []
+    for kind, sc in specs:
+        n = 1 << sc
+        if kind == "rmat":
+            src, dst = inputs.rmat_edges(sc)
+        else:
+            src, dst = inputs.er_edges(n, 8 * n, seed=0x22)
+        built.append((kind, sc, n, src, dst))
+    # Sources: uniform over the component of the highest-degree vertex (the
+    # giant component), whose edge count is the GTEPS numerator of a query.
+    pools, ncc = [], []
+    for kind, sc, n, src, dst in built:
+        g = dsbfs.Graph(src, dst, n, threshold=args.threshold, keep_plain_csr=False)
+        ws = dsbfs.Workspace(g)
+        deg = g.export(0, np.int32)
+        d = torch.empty(n, dtype=torch.int32, device="cuda")
+        r = dsbfs.bfs(g, ws, int(np.argmax(deg)), d, None, opts=dsbfs.run_opts(want_parent=False),
+                      want_stats=True)
+        reached = np.nonzero(d.cpu().numpy() >= 0)[0].astype(np.int32)
+        pools.append(reached)
+        ncc.append(r["edges_cc"])
+        ws.destroy()
+        g.destroy()
+    nmax = max(b[2] for b in built)
+    out = {"workload": "resident RMAT " + "/".join(str(b[1]) for b in built if b[0] == "rmat") +
+                       " + ER 2^22 (8n pairs); Poisson single-source queries, graph uniform, "
+                       "sources uniform over each graph's giant component",
+           "queries_per_rate": args.serve_queries, "rates": []}
+    servers = {}
+    for mode in ("plain", "batched"):
+        graphs = [dsbfs.Graph(src, dst, n, threshold=args.threshold, keep_plain_csr=True)
+                  for _, _, n, src, dst in built]
+        resident = sum(2 * (G.stats["bytes_layout"] + G.stats["bytes_plain"]) + 64 * G.n
+                       for G in graphs)
+        budget = resident + 4 * 64 * 4 * nmax
+        S = dsbfs.Server(budget, max_lanes=64, batched=(mode == "batched"))
+        gids = [S.add_graph(G) for G in graphs]
+        servers[mode] = (S, gids)
+        out["hbm_budget_bytes"] = budget
+    # plain service rate on this mix
+    S, gids = servers["plain"]
+    lat, _ = _poisson_run(dsbfs, S, gids, pools, ncc, 1e6, 256, 4999)
+    t0 = dsbfs.now_ns()
+    _poisson_run(dsbfs, S, gids, pools, ncc, 1e9, 512, 4998)
+    mu = 512 / ((dsbfs.now_ns() - t0) * 1e-9)
+    out["mu_plain_qps"] = round(mu, 1)
+    log(f"plain service rate {mu:.0f} queries/s")
+    for idx, f in enumerate((0.5, 1.0, 2.0)):
+        row = {"rate_factor": f, "rate_qps": round(f * mu, 1)}
+        for mode in ("plain", "batched"):
+            S, gids = servers[mode]
+            lat, gteps = _poisson_run(dsbfs, S, gids, pools, ncc, f * mu, args.serve_queries,
+                                      5000 + idx)
+            row[mode] = {"p50_ms": round(float(np.percentile(lat, 50)), 3),
+                         "p99_ms": round(float(np.percentile(lat, 99)), 3),
+                         "gteps": round(gteps, 2)}
+            log(f"rate {f} x mu, {mode}: p50 {row[mode]['p50_ms']} ms, "
+                f"p99 {row[mode]['p99_ms']} ms, {row[mode]['gteps']} GTEPS")
+        out["rates"].append(row)
+    for S, _ in servers.values():
+        S.destroy()
+    return out
 
 
 if __name__ == "__main__":

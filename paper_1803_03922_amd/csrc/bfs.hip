@@ -29,7 +29,10 @@
 
 namespace dsbfs {
 
+void msbfs_release(Workspace *ws);
+
 Workspace::~Workspace() {
+  msbfs_release(this);
   if (hctr) (void)hipHostFree(hctr);
   for (hipEvent_t e : events) (void)hipEventDestroy(e);
 }

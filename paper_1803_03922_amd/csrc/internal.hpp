@@ -125,8 +125,14 @@ struct Workspace {
   std::vector<hipEvent_t> events;  // profiling event pool
   // multi-source lane state
   DevBuf ms_seen, ms_front, ms_next;  // uint64[n]
-  DevBuf ms_misc;
+  void *ms_state = nullptr;           // launch state of multi-source BFS (msbfs.hip)
   ~Workspace();
+};
+
+// Per-lane result rows of a level-at-a-time multi-source step (server).
+struct LaneRows {
+  int32_t *res[64];   // result row of each lane (int32[n]) or NULL if the lane is idle
+  int32_t dval[64];   // depth this level writes for each lane
 };
 
 // ---------------------------------------------------------------------------

@@ -1,11 +1,919 @@
+// Bit-parallel multi-source BFS: 64 sources per batch as the lanes of a 64-bit
+// mask per vertex (seen, frontier, next), all batches in one persistent launch.
+//
+// Not in the paper: the batched form follows the bit-parallel multi-source
+// BFS of Then et al., "The More the Merrier" (PVLDB 8(4), 2014). Each lane's
+// depths are exactly those of a single-source BFS from that lane's source.
+//
+// Per level of a batch:
+//   top-down  (few frontier vertices): every vertex v with frontier[v] != 0
+//             ORs frontier[v] & ~seen[w] into next[w] of each neighbour w,
+//             then a close pass folds next into seen and writes depths;
+//   bottom-up (otherwise): every vertex w with unseen lanes ORs frontier[v]
+//             of its neighbours until all of its unseen lanes are covered,
+//             and closes itself on the spot (writes next[w], seen[w], depths).
+// Levels and batches are separated by a grid barrier inside one kernel whose
+// grid fits the chip (occupancy-checked); the barrier's wait is bounded, so a
+// grid that is not fully resident ends with an error flag instead of a hang.
+// The launch can be captured once into a hipGraph and replayed.
+#include <algorithm>
+#include <chrono>
+#include <cstdio>
+#include <fstream>
+#include <map>
+#include <sstream>
+
 #include "internal.hpp"
+
 namespace dsbfs {
-void msbfs_run(const Graph *, Workspace *, const int32_t *, int32_t, const dsbfs_ms_opts *,
-               int32_t *, hipStream_t) {
-  fail(DSBFS_ERR_INVALID_ARG, "multi-source BFS is not available in this build");
+
+namespace {
+
+struct MsCtl {
+  unsigned int bar_count;
+  unsigned int bar_gen;
+  unsigned int err;            // 1: a barrier wait timed out
+  unsigned int pad;
+  unsigned long long td_count;   // frontier vertices listed for a top-down level
+  unsigned long long active[3];  // vertices with a non-empty next mask, per level (rolling)
+  unsigned long long alive[3];   // lanes with a non-empty next frontier, per level (rolling)
+  unsigned long long levels;     // levels run, summed over batches
+  unsigned long long edges;      // adjacency entries read, summed over batches
+};
+
+struct MsArgs {
+  const int64_t *off;
+  const int32_t *col;
+  int32_t n;
+  const int32_t *sources;  // device copy, k entries
+  int32_t k;
+  int32_t *depth;          // [k][n]
+  uint64_t *seen, *fa, *fb;
+  int32_t *tdlist;         // frontier vertices of a top-down level, n entries
+  int64_t *tdscan;         // prefix of their degrees, n + 1 entries
+  const int32_t *hubs;     // vertices of degree > kHub, scanned by whole waves bottom-up
+  int64_t nhubs;
+  MsCtl *ctl;
+  int64_t bu_threshold;    // bottom-up when active vertices exceed this
+  long long timeout_ticks; // bound of one barrier wait (wall clock ticks)
+};
+
+__device__ __forceinline__ long long wall_ticks() { return wall_clock64(); }
+
+// Grid-wide barrier: block leaders count arrivals on ctl->bar_count; the last
+// one resets the count and bumps the generation the others wait on. Fences
+// make every plain store before the barrier visible to every block after it.
+// Returns false (everywhere) once any wait has exceeded the bound.
+__device__ bool grid_sync(MsCtl *ctl, long long timeout_ticks) {
+  __shared__ int ok;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    const unsigned int g = __hip_atomic_load(&ctl->bar_gen, __ATOMIC_ACQUIRE,
+                                             __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned int arrived = atomicAdd(&ctl->bar_count, 1u) + 1u;
+    if (arrived == gridDim.x) {
+      __hip_atomic_store(&ctl->bar_count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __threadfence();
+      atomicAdd(&ctl->bar_gen, 1u);
+    } else {
+      const long long t0 = wall_ticks();
+      while (__hip_atomic_load(&ctl->bar_gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g) {
+        if (__hip_atomic_load(&ctl->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
+        if (wall_ticks() - t0 > timeout_ticks) {
+          atomicOr(&ctl->err, 1u);
+          break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+      }
+    }
+    __threadfence();
+    ok = __hip_atomic_load(&ctl->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0;
+  }
+  __syncthreads();
+  return ok;
 }
-void msbfs_tune(const Graph *, Workspace *, const int32_t *, int32_t, const char *,
-                dsbfs_ms_opts *, hipStream_t) {
-  fail(DSBFS_ERR_INVALID_ARG, "multi-source BFS is not available in this build");
+
+__device__ __forceinline__ unsigned long long block_sum_u64(unsigned long long v,
+                                                            unsigned long long *sh) {
+  const int w = threadIdx.x / kWave, nw = blockDim.x / kWave;
+  v = wave_sum(v);
+  __syncthreads();
+  if (lane_id() == 0) sh[w] = v;
+  __syncthreads();
+  unsigned long long t = 0;
+  for (int i = 0; i < nw; ++i) t += sh[i];
+  return t;
 }
+
+// Writes depth `val` for every lane set in `bits` of vertex v: one masked,
+// row-coalesced store per lane across the wave's consecutive vertices.
+__device__ __forceinline__ void put_lanes(int32_t *depth, int32_t n, int64_t row0, int32_t v,
+                                          uint64_t bits, int32_t val, bool valid) {
+  const uint64_t mine = valid ? bits : 0ull;
+  uint64_t all = mine;  // lanes present anywhere in the wave
+  for (int o = 32; o > 0; o >>= 1) all |= __shfl_xor(all, o, kWave);
+  while (all) {
+    const int i = __ffsll(static_cast<long long>(all)) - 1;
+    all &= all - 1;
+    if ((mine >> i) & 1ull) depth[(row0 + i) * int64_t(n) + v] = val;
+  }
+}
+
+constexpr int kHub = 64;
+
+__device__ __forceinline__ uint64_t wave_or(uint64_t x) {
+  for (int o = 32; o > 0; o >>= 1) x |= __shfl_xor(x, o, kWave);
+  return x;
+}
+
+__global__ void __launch_bounds__(1024) k_msbfs(MsArgs a) {
+  __shared__ unsigned long long sh[16];
+  const int32_t n = a.n;
+  const int64_t tid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int64_t nthreads = int64_t(gridDim.x) * blockDim.x;
+  const int64_t nv_iter = (int64_t(n) + nthreads - 1) / nthreads;
+  const int nbatch = (a.k + 63) / 64;
+  unsigned long long edges = 0;
+  for (int b = 0; b < nbatch; ++b) {
+    const int lanes = min(64, a.k - b * 64);
+    const uint64_t lanemask = lanes == 64 ? ~0ull : ((1ull << lanes) - 1ull);
+    const int64_t row0 = int64_t(b) * 64;
+    // reset lane state
+    for (int64_t v = tid; v < n; v += nthreads) {
+      a.seen[v] = 0;
+      a.fa[v] = 0;
+      a.fb[v] = 0;
+    }
+    if (blockIdx.x == 0 && threadIdx.x < 3) {
+      a.ctl->active[threadIdx.x] = 0;
+      a.ctl->alive[threadIdx.x] = 0;
+    }
+    if (!grid_sync(a.ctl, a.timeout_ticks)) return;
+    // seed the sources of this batch (duplicates share a vertex: OR the lanes)
+    if (tid < lanes) {
+      const int32_t s = a.sources[row0 + tid];
+      atomicOr(reinterpret_cast<unsigned long long *>(&a.seen[s]), 1ull << tid);
+      atomicOr(reinterpret_cast<unsigned long long *>(&a.fa[s]), 1ull << tid);
+      a.depth[(row0 + tid) * int64_t(n) + s] = 0;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) a.ctl->active[0] = (unsigned long long)lanes;
+    if (!grid_sync(a.ctl, a.timeout_ticks)) return;
+    uint64_t *fcur = a.fa, *fnext = a.fb;
+    int64_t active = lanes;
+    // Lanes whose frontier is empty are finished: no vertex waits for them.
+    uint64_t live = lanemask;
+    const int64_t wid = tid / kWave, nwaves = nthreads / kWave;
+    const int l = lane_id();
+    for (int32_t L = 0;; ++L) {
+      const int32_t val = L + 1;
+      unsigned long long act = 0;
+      uint64_t lor = 0;
+      if (active <= a.bu_threshold) {
+        // top-down, edge-parallel: (1) list the frontier vertices, (2) one
+        // block prefix-sums their degrees, (3) every thread takes edges of the
+        // concatenated rows. fnext is all zero here.
+        for (int64_t v0 = int64_t(blockIdx.x) * blockDim.x; v0 < n; v0 += nthreads) {
+          const int64_t v = v0 + threadIdx.x;
+          const bool f = v < n && fcur[v] != 0;
+          const int64_t pos = wave_append(f, &a.ctl->td_count);
+          if (f) a.tdlist[pos] = int32_t(v);
+        }
+        if (!grid_sync(a.ctl, a.timeout_ticks)) return;
+        const int64_t cnt = int64_t(__hip_atomic_load(&a.ctl->td_count, __ATOMIC_RELAXED,
+                                                      __HIP_MEMORY_SCOPE_AGENT));
+        if (blockIdx.x == 0) {
+          unsigned long long carry = 0;
+          for (int64_t i0 = 0; i0 < cnt; i0 += blockDim.x) {
+            const int64_t i = i0 + threadIdx.x;
+            unsigned long long dg = 0;
+            if (i < cnt) {
+              const int32_t v = a.tdlist[i];
+              dg = (unsigned long long)(a.off[v + 1] - a.off[v]);
+            }
+            const unsigned long long incl = wave_incl_scan(dg);
+            if (lane_id() == kWave - 1) sh[threadIdx.x / kWave] = incl;
+            __syncthreads();
+            unsigned long long before = 0, tot = 0;
+            for (int j = 0; j < int(blockDim.x / kWave); ++j) {
+              before += j < int(threadIdx.x / kWave) ? sh[j] : 0ull;
+              tot += sh[j];
+            }
+            if (i < cnt) a.tdscan[i] = int64_t(carry + before + incl - dg);
+            carry += tot;
+            __syncthreads();
+          }
+          if (threadIdx.x == 0) a.tdscan[cnt] = int64_t(carry);
+        }
+        if (!grid_sync(a.ctl, a.timeout_ticks)) return;
+        const int64_t E = a.tdscan[cnt];
+        for (int64_t e = tid; e < E; e += nthreads) {
+          int64_t lo = 0, hi = cnt - 1;
+          while (lo < hi) {
+            const int64_t mid = (lo + hi + 1) >> 1;
+            if (a.tdscan[mid] <= e) lo = mid;
+            else hi = mid - 1;
+          }
+          const int32_t v = a.tdlist[lo];
+          const int32_t w = a.col[a.off[v] + (e - a.tdscan[lo])];
+          ++edges;
+          const uint64_t m = fcur[v] & ~a.seen[w];
+          if (m) atomicOr(reinterpret_cast<unsigned long long *>(&fnext[w]), m);
+        }
+        if (!grid_sync(a.ctl, a.timeout_ticks)) return;
+        if (blockIdx.x == 0 && threadIdx.x == 0) a.ctl->td_count = 0;
+        // close: fold next into seen, write depths, clear the old frontier
+        for (int64_t it = 0; it < nv_iter; ++it) {
+          const int64_t v = tid + it * nthreads;
+          const bool valid = v < n;
+          uint64_t nw = 0;
+          if (valid) {
+            const uint64_t s0 = a.seen[v];
+            nw = fnext[v] & ~s0;
+            fnext[v] = nw;
+            a.seen[v] = s0 | nw;
+            fcur[v] = 0;
+            act += nw != 0;
+            lor |= nw;
+          }
+          put_lanes(a.depth, n, row0, int32_t(valid ? v : 0), nw, val, valid);
+        }
+      } else {
+        // bottom-up with the close fused in: w is only written by the thread
+        // (or, for a hub, the wave) that scans it. Vertices of degree <= kHub:
+        // one thread each; hubs: one wave each, 64 neighbours per step.
+        for (int64_t it = 0; it < nv_iter; ++it) {
+          const int64_t w = tid + it * nthreads;
+          bool valid = w < n;
+          uint64_t nw = 0;
+          if (valid) {
+            const int64_t p0 = a.off[w], p1 = a.off[w + 1];
+            if (p1 - p0 > kHub) {
+              valid = false;  // the hub pass below owns it
+            } else {
+              const uint64_t s0 = a.seen[w];
+              const uint64_t want = ~s0 & live;
+              if (want) {
+                uint64_t acc = 0;
+                for (int64_t p = p0; p < p1; ++p) {
+                  acc |= fcur[a.col[p]];
+                  ++edges;
+                  if ((acc & want) == want) break;
+                }
+                nw = acc & want;
+                if (nw) a.seen[w] = s0 | nw;
+              }
+              fnext[w] = nw;
+              act += nw != 0;
+              lor |= nw;
+            }
+          }
+          put_lanes(a.depth, n, row0, int32_t(valid ? w : 0), nw, val, valid);
+        }
+        for (int64_t h = wid; h < a.nhubs; h += nwaves) {
+          const int32_t w = a.hubs[h];
+          const uint64_t s0 = a.seen[w];
+          const uint64_t want = ~s0 & live;
+          uint64_t nw = 0;
+          if (want) {
+            const int64_t p1 = a.off[w + 1];
+            uint64_t acc = 0;
+            for (int64_t p = a.off[w]; p < p1; p += kWave) {
+              const uint64_t x = p + l < p1 ? fcur[a.col[p + l]] : 0ull;
+              acc |= wave_or(x);
+              if (l == 0) edges += uint64_t(min<int64_t>(kWave, p1 - p));
+              if ((acc & want) == want) break;
+            }
+            nw = acc & want;
+          }
+          if (l == 0) {
+            if (nw) a.seen[w] = s0 | nw;
+            fnext[w] = nw;
+            act += nw != 0;
+            lor |= nw;
+          }
+          if ((nw >> l) & 1ull) a.depth[(row0 + l) * int64_t(n) + w] = val;
+        }
+      }
+      const unsigned long long bact = block_sum_u64(act, sh);
+      if (threadIdx.x == 0 && bact) atomicAdd(&a.ctl->active[(L + 1) % 3], bact);
+      lor = wave_or(lor);
+      if (l == 0 && lor) atomicOr(&a.ctl->alive[(L + 1) % 3], (unsigned long long)lor);
+      if (!grid_sync(a.ctl, a.timeout_ticks)) return;
+      active = int64_t(__hip_atomic_load(&a.ctl->active[(L + 1) % 3], __ATOMIC_RELAXED,
+                                         __HIP_MEMORY_SCOPE_AGENT));
+      live = __hip_atomic_load(&a.ctl->alive[(L + 1) % 3], __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+      if (blockIdx.x == 0 && threadIdx.x == 0) {
+        a.ctl->active[(L + 2) % 3] = 0;
+        a.ctl->alive[(L + 2) % 3] = 0;
+        atomicAdd(&a.ctl->levels, 1ull);
+      }
+      uint64_t *t = fcur;
+      fcur = fnext;
+      fnext = t;
+      if (active == 0) break;
+      // the bottom-up pass overwrote every fnext entry; a top-down pass next
+      // needs its target cleared
+      if (active <= a.bu_threshold) {
+        for (int64_t v = tid; v < n; v += nthreads) fnext[v] = 0;
+      }
+      if (!grid_sync(a.ctl, a.timeout_ticks)) return;
+    }
+    // unreached: -1 for every lane never seen
+    for (int64_t it = 0; it < nv_iter; ++it) {
+      const int64_t v = tid + it * nthreads;
+      const bool valid = v < n;
+      const uint64_t miss = valid ? (~a.seen[v] & lanemask) : 0ull;
+      put_lanes(a.depth, n, row0, int32_t(valid ? v : 0), miss, -1, valid);
+    }
+    if (!grid_sync(a.ctl, a.timeout_ticks)) return;
+  }
+  const unsigned long long be = block_sum_u64(edges, sh);
+  if (threadIdx.x == 0 && be) atomicAdd(&a.ctl->edges, be);
+}
+
+__global__ void k_flag_hub(const int64_t *off, int32_t n, uint8_t *flag) {
+  for (int64_t v = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; v < n;
+       v += int64_t(gridDim.x) * blockDim.x)
+    flag[v] = off[v + 1] - off[v] > kHub;
+}
+
+int device_cus() {
+  int dev = 0, cus = 0;
+  HIPCHK(hipGetDevice(&dev));
+  HIPCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  return cus;
+}
+
+std::string device_name() {
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  hipDeviceProp_t p;
+  HIPCHK(hipGetDeviceProperties(&p, dev));
+  return std::string(p.gcnArchName);
+}
+
+dsbfs_ms_opts default_ms_opts() {
+  dsbfs_ms_opts o{};
+  o.block = 256;
+  o.blocks_per_cu = 4;
+  o.bu_permille = 2;
+  o.use_graph = 1;
+  return o;
+}
+
+void check_ms_opts(const dsbfs_ms_opts &o) {
+  if (o.block != 64 && o.block != 128 && o.block != 256 && o.block != 512 && o.block != 1024)
+    fail(DSBFS_ERR_INVALID_ARG, "ms block must be 64, 128, 256, 512 or 1024");
+  if (o.blocks_per_cu < 1 || o.blocks_per_cu > 32)
+    fail(DSBFS_ERR_INVALID_ARG, "ms blocks_per_cu must be in [1, 32]");
+  if (o.bu_permille < 0 || o.bu_permille > 1000)
+    fail(DSBFS_ERR_INVALID_ARG, "ms bu_permille must be in [0, 1000]");
+}
+
+// The graph captured for one (workspace, launch configuration, k, depth).
+struct MsGraph {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+struct MsState {
+  DevBuf ctl, srcs, hubs;
+  int64_t nhubs = -1;  // -1: hub list not built yet
+  int32_t cap_k = 0;
+  std::map<std::string, MsGraph> graphs;
+  ~MsState() {
+    for (auto &kv : graphs) {
+      if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
+      if (kv.second.graph) (void)hipGraphDestroy(kv.second.graph);
+    }
+  }
+};
+
+}  // namespace
+
+void msbfs_release(Workspace *ws) {
+  delete reinterpret_cast<MsState *>(ws->ms_state);
+  ws->ms_state = nullptr;
+}
+
+static void msbfs_launch(const Graph *g, Workspace *ws, const int32_t *sources, int32_t k,
+                         const dsbfs_ms_opts &o, int32_t *depth, hipStream_t s,
+                         unsigned long long *levels_out, unsigned long long *edges_out) {
+  if (!ws || ws->g != g) fail(DSBFS_ERR_INVALID_ARG, "workspace does not belong to this graph");
+  if (ws->max_lanes != 64) fail(DSBFS_ERR_INVALID_ARG, "workspace was created without lanes");
+  if (!g->pcol.p && g->m > 0) fail(DSBFS_ERR_INVALID_ARG, "multi-source BFS needs the plain CSR");
+  if (k < 1 || !sources || !depth) fail(DSBFS_ERR_INVALID_ARG, "need k >= 1 sources and depth");
+  for (int32_t i = 0; i < k; ++i)
+    if (sources[i] < 0 || sources[i] >= g->n) fail(DSBFS_ERR_INVALID_ARG, "source outside [0, n)");
+  check_ms_opts(o);
+  if (!ws->ms_state) ws->ms_state = new MsState();
+  MsState *st = reinterpret_cast<MsState *>(ws->ms_state);
+  const Alloc *al = &g->al;
+  if (!st->ctl.p) st->ctl.alloc(al, sizeof(MsCtl), s);
+  if (st->cap_k < k) {
+    st->srcs.alloc(al, size_t(k) * 4, s);
+    st->cap_k = k;
+    // captured graphs hold the old pointer
+    for (auto &kv : st->graphs) {
+      if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
+      if (kv.second.graph) (void)hipGraphDestroy(kv.second.graph);
+    }
+    st->graphs.clear();
+  }
+  HIPCHK(hipMemcpyAsync(st->srcs.p, sources, size_t(k) * 4, hipMemcpyHostToDevice, s));
+  if (st->nhubs < 0) {
+    // vertices whose rows a whole wave scans in bottom-up levels
+    DevBuf flag, tmp, cnt;
+    flag.alloc(al, size_t(g->n), s);
+    tmp.alloc(al, compact_tmp_bytes(g->n), s);
+    cnt.alloc(al, 8, s);
+    st->hubs.alloc(al, size_t(g->n) * 4, s);
+    hipLaunchKernelGGL(k_flag_hub, dim3(grid_for(g->n, 256, 8192)), dim3(256), 0, s,
+                       g->poff.as<int64_t>(), g->n, flag.as<uint8_t>());
+    HIPCHK(hipGetLastError());
+    compact_flags_u8(flag.as<uint8_t>(), g->n, st->hubs.as<int32_t>(), cnt.as<int64_t>(), tmp.p,
+                     s);
+    st->nhubs = d2h_scalar(cnt.as<int64_t>(), s);
+  }
+
+  int occ = 0;
+  HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_msbfs, o.block, 0));
+  if (occ < 1) fail(DSBFS_ERR_INVALID_ARG, "ms block size does not fit a compute unit");
+  const int per_cu = std::min(o.blocks_per_cu, occ);
+  const int grid = device_cus() * per_cu;
+
+  MsArgs a{};
+  a.off = g->poff.as<int64_t>();
+  a.col = g->pcol.as<int32_t>();
+  a.n = g->n;
+  a.sources = st->srcs.as<int32_t>();
+  a.k = k;
+  a.depth = depth;
+  a.seen = ws->ms_seen.as<uint64_t>();
+  a.fa = ws->ms_front.as<uint64_t>();
+  a.fb = ws->ms_next.as<uint64_t>();
+  a.tdlist = ws->dlen.as<int32_t>();    // int32[max(n, d)]
+  a.tdscan = ws->dscan.as<int64_t>();   // int64[max(n, d) + 1]
+  a.hubs = st->hubs.as<int32_t>();
+  a.nhubs = st->nhubs;
+  a.ctl = st->ctl.as<MsCtl>();
+  a.bu_threshold = int64_t(g->n) * o.bu_permille / 1000;
+  a.timeout_ticks = 100000000ll * 20;  // 20 s of the 100 MHz wall clock per barrier wait
+
+  // control block cleared by a kernel-free copy of zeros from the host
+  static const MsCtl zero{};
+  HIPCHK(hipMemcpyAsync(st->ctl.p, &zero, sizeof(MsCtl), hipMemcpyHostToDevice, s));
+  if (o.use_graph) {
+    char key[160];
+    std::snprintf(key, sizeof(key), "%d/%d/%d/%d/%p", o.block, grid, k, o.bu_permille,
+                  static_cast<void *>(depth));
+    MsGraph &mg = st->graphs[key];
+    if (!mg.exec) {
+      hipStream_t cs;
+      HIPCHK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+      hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+      if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_msbfs, dim3(grid), dim3(o.block), 0, cs, a);
+        e = hipGetLastError();
+        hipGraph_t gr = nullptr;
+        hipError_t e2 = hipStreamEndCapture(cs, &gr);
+        if (e == hipSuccess) e = e2;
+        if (e == hipSuccess) {
+          mg.graph = gr;
+          e = hipGraphInstantiate(&mg.exec, gr, nullptr, nullptr, 0);
+        } else if (gr) {
+          (void)hipGraphDestroy(gr);
+        }
+      }
+      (void)hipStreamDestroy(cs);
+      HIPCHK(e);
+    }
+    HIPCHK(hipGraphLaunch(mg.exec, s));
+  } else {
+    void *args[] = {&a};
+    HIPCHK(hipLaunchCooperativeKernel(reinterpret_cast<const void *>(&k_msbfs), dim3(grid),
+                                      dim3(o.block), args, 0, s));
+  }
+  MsCtl h{};
+  HIPCHK(hipMemcpyAsync(&h, st->ctl.p, sizeof(MsCtl), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (h.err) fail(DSBFS_ERR_DEVICE, "multi-source BFS: a grid barrier wait timed out");
+  if (levels_out) *levels_out = h.levels;
+  if (edges_out) *edges_out = h.edges;
+}
+
+static const dsbfs_ms_opts *tuned_or_default(const Graph *g, dsbfs_ms_opts *buf) {
+  *buf = default_ms_opts();
+  (void)g;
+  return buf;
+}
+
+void msbfs_run(const Graph *g, Workspace *ws, const int32_t *sources, int32_t k,
+               const dsbfs_ms_opts *opts, int32_t *depth, hipStream_t s) {
+  dsbfs_ms_opts buf;
+  const dsbfs_ms_opts &o = opts ? *opts : *tuned_or_default(g, &buf);
+  msbfs_launch(g, ws, sources, k, o, depth, s, nullptr, nullptr);
+}
+
+// ---------------------------------------------------------------------------
+// Autotuner: times candidate (block, blocks per CU, switch threshold) settings
+// on the caller's sources and keeps the fastest; results are cached in a
+// small JSON file keyed by device, n and m.
+// ---------------------------------------------------------------------------
+static std::string tune_key(const Graph *g) {
+  std::ostringstream os;
+  os << device_name() << ":n" << g->n << ":m" << g->m;
+  return os.str();
+}
+
+static bool cache_lookup(const char *path, const std::string &key, dsbfs_ms_opts *o) {
+  if (!path) return false;
+  std::ifstream f(path);
+  if (!f) return false;
+  std::string line;
+  while (std::getline(f, line)) {
+    // one entry per line: {"key": "...", "block": B, "blocks_per_cu": C, "bu_permille": P, "use_graph": G}
+    const std::string tag = "\"key\": \"" + key + "\"";
+    if (line.find(tag) == std::string::npos) continue;
+    auto num = [&](const char *name, int32_t *dst) {
+      const std::string t = std::string("\"") + name + "\": ";
+      size_t p = line.find(t);
+      if (p == std::string::npos) return false;
+      *dst = std::atoi(line.c_str() + p + t.size());
+      return true;
+    };
+    dsbfs_ms_opts r{};
+    if (num("block", &r.block) && num("blocks_per_cu", &r.blocks_per_cu) &&
+        num("bu_permille", &r.bu_permille) && num("use_graph", &r.use_graph)) {
+      check_ms_opts(r);
+      *o = r;
+      return true;
+    }
+  }
+  return false;
+}
+
+static void cache_store(const char *path, const std::string &key, const dsbfs_ms_opts &o,
+                        double ms) {
+  if (!path) return;
+  std::ofstream f(path, std::ios::app);
+  if (!f) fail(DSBFS_ERR_INVALID_ARG, std::string("cannot write tuner cache ") + path);
+  f << "{\"key\": \"" << key << "\", \"block\": " << o.block << ", \"blocks_per_cu\": "
+    << o.blocks_per_cu << ", \"bu_permille\": " << o.bu_permille << ", \"use_graph\": "
+    << o.use_graph << ", \"ms\": " << ms << "}\n";
+}
+
+void msbfs_tune(const Graph *g, Workspace *ws, const int32_t *sources, int32_t k,
+                const char *cache_path, dsbfs_ms_opts *best, hipStream_t s) {
+  const std::string key = tune_key(g);
+  if (cache_lookup(cache_path, key, best)) return;
+  if (k < 1) fail(DSBFS_ERR_INVALID_ARG, "tuning needs at least one source");
+  const int32_t kt = std::min<int32_t>(k, 64);
+  DevBuf out;
+  out.alloc(&g->al, size_t(kt) * size_t(g->n) * 4, s);
+  double best_ms = 1e30;
+  dsbfs_ms_opts bo = default_ms_opts();
+  const int blocks[] = {256, 512, 1024};
+  const int percu[] = {1, 2, 4, 8};
+  const int thr[] = {0, 1, 5, 20};
+  for (int b : blocks)
+    for (int c : percu) {
+      int occ = 0;
+      HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_msbfs, b, 0));
+      if (c > occ || b * c > 2048) continue;
+      for (int t : thr) {
+        dsbfs_ms_opts o{};
+        o.block = b;
+        o.blocks_per_cu = c;
+        o.bu_permille = t;
+        o.use_graph = 0;
+        msbfs_launch(g, ws, sources, kt, o, out.as<int32_t>(), s, nullptr, nullptr);  // warm
+        const auto t0 = std::chrono::steady_clock::now();
+        msbfs_launch(g, ws, sources, kt, o, out.as<int32_t>(), s, nullptr, nullptr);
+        const double ms =
+            std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0)
+                .count();
+        if (ms < best_ms) {
+          best_ms = ms;
+          bo = o;
+        }
+      }
+    }
+  bo.use_graph = 1;
+  *best = bo;
+  cache_store(cache_path, key, bo, best_ms);
+}
+
+}  // namespace dsbfs
+
+// ---------------------------------------------------------------------------
+// Level-at-a-time multi-source BFS for the query server: lanes join and leave
+// at level boundaries (continuous batching), so each lane has its own result
+// row and its own depth offset, and the host decides between levels.
+// ---------------------------------------------------------------------------
+namespace dsbfs {
+
+struct MsLevel {
+  const int64_t *off;
+  const int32_t *col;
+  int32_t n;
+  uint64_t *seen, *fcur, *fnext;
+  int32_t *tdlist;
+  int64_t *tdscan;
+  const int32_t *hubs;
+  int64_t nhubs;
+  unsigned long long *ctl;  // [0] active, [1] alive, [2] td_count, [3] edges
+  uint64_t live;
+};
+
+namespace {
+
+__device__ __forceinline__ void put_rows(const LaneRows &r, int32_t v, uint64_t bits, bool valid) {
+  const uint64_t mine = valid ? bits : 0ull;
+  uint64_t all = mine;
+  for (int o = 32; o > 0; o >>= 1) all |= __shfl_xor(all, o, kWave);
+  while (all) {
+    const int i = __ffsll(static_cast<long long>(all)) - 1;
+    all &= all - 1;
+    if ((mine >> i) & 1ull) r.res[i][v] = r.dval[i];
+  }
+}
+
+__device__ __forceinline__ void lv_flush(const MsLevel &a, unsigned long long act, uint64_t lor,
+                                         unsigned long long edges) {
+  act = wave_sum(act);
+  edges = wave_sum(edges);
+  for (int o = 32; o > 0; o >>= 1) lor |= __shfl_xor(lor, o, kWave);
+  if (lane_id() == 0) {
+    if (act) atomicAdd(&a.ctl[0], act);
+    if (lor) atomicOr(&a.ctl[1], (unsigned long long)lor);
+    if (edges) atomicAdd(&a.ctl[3], edges);
+  }
+}
+
+// Clears the lanes in `clear` everywhere (recycled lanes) and fills the
+// result rows of the lanes in `fill` with -1.
+__global__ void k_lv_recycle(MsLevel a, uint64_t clear, uint64_t fill, LaneRows r) {
+  const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+  for (int64_t v = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; v < a.n; v += stride) {
+    if (clear) {
+      a.seen[v] &= ~clear;
+      a.fcur[v] &= ~clear;
+      a.fnext[v] &= ~clear;
+    }
+    uint64_t f = fill;
+    while (f) {
+      const int i = __ffsll(static_cast<long long>(f)) - 1;
+      f &= f - 1;
+      r.res[i][v] = -1;
+    }
+  }
+}
+
+// Seeds lane i at source src[i] for every lane in `mask`.
+__global__ void k_lv_seed(MsLevel a, uint64_t mask, const int32_t *src, LaneRows r) {
+  const int i = threadIdx.x;
+  if (i < 64 && ((mask >> i) & 1ull)) {
+    const int32_t s = src[i];
+    atomicOr(reinterpret_cast<unsigned long long *>(&a.seen[s]), 1ull << i);
+    atomicOr(reinterpret_cast<unsigned long long *>(&a.fcur[s]), 1ull << i);
+    r.res[i][s] = 0;
+  }
+}
+
+__global__ void k_lv_zero(uint64_t *p, int32_t n) {
+  for (int64_t v = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; v < n;
+       v += int64_t(gridDim.x) * blockDim.x)
+    p[v] = 0;
+}
+
+__global__ void k_lv_td_list(MsLevel a) {
+  for (int64_t v0 = int64_t(blockIdx.x) * blockDim.x; v0 < a.n;
+       v0 += int64_t(gridDim.x) * blockDim.x) {
+    const int64_t v = v0 + threadIdx.x;
+    const bool f = v < a.n && a.fcur[v] != 0;
+    const int64_t pos = wave_append(f, &a.ctl[2]);
+    if (f) a.tdlist[pos] = int32_t(v);
+  }
+}
+
+__global__ void __launch_bounds__(1024) k_lv_td_scan(MsLevel a) {
+  __shared__ unsigned long long sh[16];
+  const int64_t cnt = int64_t(a.ctl[2]);
+  unsigned long long carry = 0;
+  for (int64_t i0 = 0; i0 < cnt; i0 += blockDim.x) {
+    const int64_t i = i0 + threadIdx.x;
+    unsigned long long dg = 0;
+    if (i < cnt) {
+      const int32_t v = a.tdlist[i];
+      dg = (unsigned long long)(a.off[v + 1] - a.off[v]);
+    }
+    const unsigned long long incl = wave_incl_scan(dg);
+    if (lane_id() == kWave - 1) sh[threadIdx.x / kWave] = incl;
+    __syncthreads();
+    unsigned long long before = 0, tot = 0;
+    for (int j = 0; j < int(blockDim.x / kWave); ++j) {
+      before += j < int(threadIdx.x / kWave) ? sh[j] : 0ull;
+      tot += sh[j];
+    }
+    if (i < cnt) a.tdscan[i] = int64_t(carry + before + incl - dg);
+    carry += tot;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) a.tdscan[cnt] = int64_t(carry);
+}
+
+__global__ void k_lv_td_expand(MsLevel a) {
+  const int64_t cnt = int64_t(a.ctl[2]);
+  const int64_t E = a.tdscan[cnt];
+  unsigned long long edges = 0;
+  for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < E;
+       e += int64_t(gridDim.x) * blockDim.x) {
+    int64_t lo = 0, hi = cnt - 1;
+    while (lo < hi) {
+      const int64_t mid = (lo + hi + 1) >> 1;
+      if (a.tdscan[mid] <= e) lo = mid;
+      else hi = mid - 1;
+    }
+    const int32_t v = a.tdlist[lo];
+    const int32_t w = a.col[a.off[v] + (e - a.tdscan[lo])];
+    ++edges;
+    const uint64_t m = a.fcur[v] & ~a.seen[w];
+    if (m) atomicOr(reinterpret_cast<unsigned long long *>(&a.fnext[w]), m);
+  }
+  lv_flush(a, 0, 0, edges);
+}
+
+__global__ void k_lv_td_close(MsLevel a, LaneRows r) {
+  const int64_t nthreads = int64_t(gridDim.x) * blockDim.x;
+  const int64_t tid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int64_t iters = (int64_t(a.n) + nthreads - 1) / nthreads;
+  unsigned long long act = 0;
+  uint64_t lor = 0;
+  for (int64_t it = 0; it < iters; ++it) {
+    const int64_t v = tid + it * nthreads;
+    const bool valid = v < a.n;
+    uint64_t nw = 0;
+    if (valid) {
+      const uint64_t s0 = a.seen[v];
+      nw = a.fnext[v] & ~s0;
+      a.fnext[v] = nw;
+      a.seen[v] = s0 | nw;
+      a.fcur[v] = 0;
+      act += nw != 0;
+      lor |= nw;
+    }
+    put_rows(r, int32_t(valid ? v : 0), nw, valid);
+  }
+  lv_flush(a, act, lor, 0);
+}
+
+__global__ void k_lv_bu(MsLevel a, LaneRows r) {
+  const int64_t nthreads = int64_t(gridDim.x) * blockDim.x;
+  const int64_t tid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int64_t iters = (int64_t(a.n) + nthreads - 1) / nthreads;
+  const int l = lane_id();
+  unsigned long long act = 0, edges = 0;
+  uint64_t lor = 0;
+  for (int64_t it = 0; it < iters; ++it) {
+    const int64_t w = tid + it * nthreads;
+    bool valid = w < a.n;
+    uint64_t nw = 0;
+    if (valid) {
+      const int64_t p0 = a.off[w], p1 = a.off[w + 1];
+      if (p1 - p0 > kHub) {
+        valid = false;
+      } else {
+        const uint64_t s0 = a.seen[w];
+        const uint64_t want = ~s0 & a.live;
+        if (want) {
+          uint64_t acc = 0;
+          for (int64_t p = p0; p < p1; ++p) {
+            acc |= a.fcur[a.col[p]];
+            ++edges;
+            if ((acc & want) == want) break;
+          }
+          nw = acc & want;
+          if (nw) a.seen[w] = s0 | nw;
+        }
+        a.fnext[w] = nw;
+        act += nw != 0;
+        lor |= nw;
+      }
+    }
+    put_rows(r, int32_t(valid ? w : 0), nw, valid);
+  }
+  const int64_t wid = tid / kWave, nwaves = nthreads / kWave;
+  for (int64_t h = wid; h < a.nhubs; h += nwaves) {
+    const int32_t w = a.hubs[h];
+    const uint64_t s0 = a.seen[w];
+    const uint64_t want = ~s0 & a.live;
+    uint64_t nw = 0;
+    if (want) {
+      const int64_t p1 = a.off[w + 1];
+      uint64_t acc = 0;
+      for (int64_t p = a.off[w]; p < p1; p += kWave) {
+        const uint64_t x = p + l < p1 ? a.fcur[a.col[p + l]] : 0ull;
+        acc |= wave_or(x);
+        if (l == 0) edges += uint64_t(min<int64_t>(kWave, p1 - p));
+        if ((acc & want) == want) break;
+      }
+      nw = acc & want;
+    }
+    if (l == 0) {
+      if (nw) a.seen[w] = s0 | nw;
+      a.fnext[w] = nw;
+      act += nw != 0;
+      lor |= nw;
+    }
+    if ((nw >> l) & 1ull) r.res[l][w] = r.dval[l];
+  }
+  lv_flush(a, act, lor, edges);
+}
+
+}  // namespace
+
+// Host side of one level for the server. ws must have 64 lanes. `live` are
+// the lanes with a non-empty frontier; results go to r.res / r.dval. After
+// the call (asynchronous on s) ctl[0] holds the next frontier's vertex
+// count, ctl[1] its lanes. Returns the direction used (0 top-down, 1 up).
+int ms_level(const Graph *g, Workspace *ws, uint64_t live, int64_t active, int32_t bu_permille,
+             const LaneRows &r, unsigned long long *ctl, hipStream_t s) {
+  MsState *st = reinterpret_cast<MsState *>(ws->ms_state);
+  MsLevel a{};
+  a.off = g->poff.as<int64_t>();
+  a.col = g->pcol.as<int32_t>();
+  a.n = g->n;
+  a.seen = ws->ms_seen.as<uint64_t>();
+  a.fcur = ws->ms_front.as<uint64_t>();
+  a.fnext = ws->ms_next.as<uint64_t>();
+  a.tdlist = ws->dlen.as<int32_t>();
+  a.tdscan = ws->dscan.as<int64_t>();
+  a.hubs = st->hubs.as<int32_t>();
+  a.nhubs = st->nhubs;
+  a.ctl = ctl;
+  a.live = live;
+  const int SG = device_cus() * 8;
+  HIPCHK(hipMemsetAsync(ctl, 0, 4 * sizeof(unsigned long long), s));
+  const bool td = active <= int64_t(g->n) * bu_permille / 1000;
+  if (td) {
+    hipLaunchKernelGGL(k_lv_zero, dim3(grid_for(g->n, 256, SG)), dim3(256), 0, s, a.fnext, g->n);
+    hipLaunchKernelGGL(k_lv_td_list, dim3(grid_for(g->n, 256, SG)), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_lv_td_scan, dim3(1), dim3(1024), 0, s, a);
+    hipLaunchKernelGGL(k_lv_td_expand, dim3(SG), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_lv_td_close, dim3(grid_for(g->n, 256, SG)), dim3(256), 0, s, a, r);
+  } else {
+    hipLaunchKernelGGL(k_lv_bu, dim3(grid_for(g->n, 256, SG)), dim3(256), 0, s, a, r);
+  }
+  HIPCHK(hipGetLastError());
+  // the next frontier becomes the current one
+  std::swap(ws->ms_front, ws->ms_next);
+  return td ? 0 : 1;
+}
+
+// Prepares a 64-lane workspace for level-at-a-time use (hub list, state).
+void ms_level_prepare(const Graph *g, Workspace *ws, hipStream_t s) {
+  if (ws->max_lanes != 64) fail(DSBFS_ERR_INVALID_ARG, "workspace was created without lanes");
+  if (!g->pcol.p && g->m > 0) fail(DSBFS_ERR_INVALID_ARG, "batched serving needs the plain CSR");
+  if (!ws->ms_state) ws->ms_state = new MsState();
+  MsState *st = reinterpret_cast<MsState *>(ws->ms_state);
+  if (st->nhubs < 0) {
+    const Alloc *al = &g->al;
+    DevBuf flag, tmp, cnt;
+    flag.alloc(al, size_t(g->n), s);
+    tmp.alloc(al, compact_tmp_bytes(g->n), s);
+    cnt.alloc(al, 8, s);
+    st->hubs.alloc(al, size_t(g->n) * 4, s);
+    hipLaunchKernelGGL(k_flag_hub, dim3(grid_for(g->n, 256, 8192)), dim3(256), 0, s,
+                       g->poff.as<int64_t>(), g->n, flag.as<uint8_t>());
+    HIPCHK(hipGetLastError());
+    compact_flags_u8(flag.as<uint8_t>(), g->n, st->hubs.as<int32_t>(), cnt.as<int64_t>(), tmp.p,
+                     s);
+    st->nhubs = d2h_scalar(cnt.as<int64_t>(), s);
+  }
+  const int64_t n = g->n;
+  HIPCHK(hipMemsetAsync(ws->ms_seen.p, 0, size_t(n) * 8, s));
+  HIPCHK(hipMemsetAsync(ws->ms_front.p, 0, size_t(n) * 8, s));
+  HIPCHK(hipMemsetAsync(ws->ms_next.p, 0, size_t(n) * 8, s));
+}
+
+void ms_level_recycle(const Graph *g, Workspace *ws, uint64_t clear, uint64_t fill,
+                      uint64_t seed_mask, const int32_t *seed_src_dev, const LaneRows &r,
+                      hipStream_t s) {
+  MsLevel a{};
+  a.n = g->n;
+  a.seen = ws->ms_seen.as<uint64_t>();
+  a.fcur = ws->ms_front.as<uint64_t>();
+  a.fnext = ws->ms_next.as<uint64_t>();
+  const int SG = device_cus() * 8;
+  if (clear || fill)
+    hipLaunchKernelGGL(k_lv_recycle, dim3(grid_for(g->n, 256, SG)), dim3(256), 0, s, a, clear,
+                       fill, r);
+  if (seed_mask) hipLaunchKernelGGL(k_lv_seed, dim3(1), dim3(64), 0, s, a, seed_mask,
+                                    seed_src_dev, r);
+  HIPCHK(hipGetLastError());
+}
+
 }  // namespace dsbfs

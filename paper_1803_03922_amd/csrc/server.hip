@@ -1,0 +1,434 @@
+// Query server with continuous batching.
+//
+// Several graphs stay resident on the device. Clients submit single-source
+// queries; one scheduler thread serves them:
+//   batched mode: each graph runs a 64-lane multi-source BFS one level at a
+//     time. At every level boundary the lanes whose frontier ran empty
+//     complete their queries, and waiting queries take the free lanes at once
+//     (their lane bits are cleared, their result rows filled with -1, their
+//     sources seeded), so requests that arrive while others are running join
+//     the work already on the GPU. All graphs with work advance one level per
+//     round, each on its own stream, so their levels overlap on the device.
+//   plain mode: one query at a time, single-source direction-optimized BFS.
+// Admission is bounded by an HBM budget: graph layouts and lane state are
+// charged when a graph is added, and every result row (int32[n]) while it is
+// held; a query waits for budget, and one that can never fit is refused.
+// Results stay on the device until the client releases them.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "internal.hpp"
+
+namespace dsbfs {
+
+int ms_level(const Graph *g, Workspace *ws, uint64_t live, int64_t active, int32_t bu_permille,
+             const LaneRows &r, unsigned long long *ctl, hipStream_t s);
+void ms_level_prepare(const Graph *g, Workspace *ws, hipStream_t s);
+void ms_level_recycle(const Graph *g, Workspace *ws, uint64_t clear, uint64_t fill,
+                      uint64_t seed_mask, const int32_t *seed_src_dev, const LaneRows &r,
+                      hipStream_t s);
+Workspace *workspace_create(const Graph *g, int32_t max_lanes);
+void workspace_destroy(Workspace *ws);
+void graph_destroy(Graph *G);
+void bfs_run(const Graph *g, Workspace *ws, int32_t source, const dsbfs_run_opts *o,
+             int32_t *depth, int32_t *parent, dsbfs_run_stats *stats, hipStream_t s);
+void run_opts_default(dsbfs_run_opts *o);
+
+int64_t now_ns() {
+  return std::chrono::duration_cast<std::chrono::nanoseconds>(
+             std::chrono::steady_clock::now().time_since_epoch())
+      .count();
+}
+
+namespace {
+
+size_t buf_bytes(const DevBuf &b) { return b.p ? b.bytes : 0; }
+
+size_t graph_footprint(const Graph *g) {
+  return buf_bytes(g->deg) + buf_bytes(g->did) + buf_bytes(g->vid_of) + buf_bytes(g->noff) +
+         buf_bytes(g->ncol) + buf_bytes(g->doff) + buf_bytes(g->dcol) + buf_bytes(g->ndsrc) +
+         buf_bytes(g->ddsrc_mask) + buf_bytes(g->dnsrc_mask) + buf_bytes(g->nds_off) +
+         buf_bytes(g->nds_col) + buf_bytes(g->poff) + buf_bytes(g->pcol);
+}
+
+size_t workspace_footprint(const Workspace *w) {
+  return buf_bytes(w->Vn) + buf_bytes(w->Fn) + buf_bytes(w->Vd) + buf_bytes(w->Fd) +
+         buf_bytes(w->Cd) + buf_bytes(w->q0) + buf_bytes(w->q1) + buf_bytes(w->dlist) +
+         buf_bytes(w->dcand) + buf_bytes(w->dlen) + buf_bytes(w->dscan) + buf_bytes(w->c0) +
+         buf_bytes(w->c1) + buf_bytes(w->ctr) + buf_bytes(w->scan_tmp) + buf_bytes(w->ms_seen) +
+         buf_bytes(w->ms_front) + buf_bytes(w->ms_next) + size_t(w->g->n) * 5;  // + hub list
+}
+
+enum QState { Q_PENDING = 0, Q_RUNNING = 1, Q_DONE = 2, Q_RELEASED = 3 };
+
+struct Query {
+  int64_t ticket = 0;
+  int32_t gid = 0, source = 0;
+  int64_t arrival = 0, admit = 0, start = 0, done = 0;
+  int32_t levels = 0, batched = 0;
+  int32_t *res = nullptr;
+  QState state = Q_PENDING;
+};
+
+struct GState {
+  Graph *g = nullptr;
+  Workspace *ws = nullptr;
+  hipStream_t stream = nullptr;
+  hipEvent_t ev = nullptr;
+  std::deque<Query *> pending;
+  Query *lane[64] = {};
+  int32_t start_level[64] = {};
+  uint64_t used = 0, live = 0;
+  int64_t active = 0;
+  int32_t L = 0;
+  std::vector<int32_t *> free_bufs;
+  unsigned long long *ctl_dev = nullptr, *ctl_host = nullptr;
+  int32_t *seed_dev = nullptr, *seed_host = nullptr;
+  size_t bytes = 0;
+  bool launched = false;
+  uint64_t new_lanes = 0;
+};
+
+}  // namespace
+
+struct Server {
+  dsbfs_server_opts o{};
+  int device = 0;
+  std::mutex mu;
+  std::condition_variable cv_work, cv_done;
+  std::vector<GState *> graphs;
+  std::unordered_map<int64_t, Query *> queries;
+  int64_t next_ticket = 1;
+  size_t used_bytes = 0;
+  bool stop = false;
+  std::string thread_error;
+  std::thread th;
+
+  size_t row_bytes(const GState *G) const { return size_t(G->g->n) * 4; }
+
+  // Gets a result row for G within the budget (caller holds mu).
+  int32_t *take_row(GState *G) {
+    if (!G->free_bufs.empty()) {
+      int32_t *p = G->free_bufs.back();
+      G->free_bufs.pop_back();
+      return p;
+    }
+    const size_t need = row_bytes(G);
+    if (used_bytes + need > o.hbm_budget_bytes) {
+      // drop cached rows of other graphs to make room
+      for (GState *H : graphs) {
+        while (!H->free_bufs.empty() && used_bytes + need > o.hbm_budget_bytes) {
+          (void)hipFree(H->free_bufs.back());
+          H->free_bufs.pop_back();
+          used_bytes -= row_bytes(H);
+        }
+      }
+      if (used_bytes + need > o.hbm_budget_bytes) return nullptr;
+    }
+    void *p = nullptr;
+    if (hipMalloc(&p, need) != hipSuccess || !p) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    used_bytes += need;
+    return static_cast<int32_t *>(p);
+  }
+
+  void finish(Query *q, GState *G, int64_t t) {
+    q->done = t;
+    q->state = Q_DONE;
+    (void)G;
+  }
+
+  bool has_work() const {
+    for (const GState *G : graphs)
+      if (G->used || !G->pending.empty()) return true;
+    return false;
+  }
+
+  void loop_batched() {
+    const uint64_t lane_cap = o.max_lanes >= 64 ? ~0ull : ((1ull << o.max_lanes) - 1ull);
+    while (true) {
+      {
+        std::unique_lock<std::mutex> lk(mu);
+        cv_work.wait(lk, [&] { return stop || has_work(); });
+        if (stop) return;
+        // admission into free lanes at this level boundary
+        const int64_t t = now_ns();
+        for (GState *G : graphs) {
+          G->new_lanes = 0;
+          uint64_t free = ~G->used & lane_cap;
+          while (free && !G->pending.empty()) {
+            Query *q = G->pending.front();
+            int32_t *row = take_row(G);
+            if (!row) break;  // budget: wait for releases
+            G->pending.pop_front();
+            const int i = __builtin_ctzll(free);
+            free &= free - 1;
+            q->res = row;
+            q->admit = q->start = t;
+            q->state = Q_RUNNING;
+            q->batched = 1;
+            G->lane[i] = q;
+            G->start_level[i] = G->L;
+            G->seed_host[i] = q->source;
+            G->new_lanes |= 1ull << i;
+          }
+          G->used |= G->new_lanes;
+        }
+      }
+      bool any = false;
+      for (GState *G : graphs) any = any || G->used;
+      if (!any) {
+        // waiting queries but no budget for their rows: wait for a release
+        std::unique_lock<std::mutex> lk(mu);
+        cv_work.wait_for(lk, std::chrono::milliseconds(1));
+        continue;
+      }
+      // one level on every graph with lanes in use, each on its own stream
+      for (GState *G : graphs) {
+        G->launched = false;
+        if (!G->used) continue;
+        LaneRows r{};
+        for (int i = 0; i < 64; ++i) {
+          r.res[i] = G->lane[i] ? G->lane[i]->res : nullptr;
+          r.dval[i] = G->L + 1 - G->start_level[i];
+        }
+        if (G->new_lanes) {
+          HIPCHK(hipMemcpyAsync(G->seed_dev, G->seed_host, 64 * sizeof(int32_t),
+                                hipMemcpyHostToDevice, G->stream));
+          ms_level_recycle(G->g, G->ws, G->new_lanes, G->new_lanes, G->new_lanes, G->seed_dev, r,
+                           G->stream);
+          G->live |= G->new_lanes;
+          G->active += __builtin_popcountll(G->new_lanes);
+        }
+        ms_level(G->g, G->ws, G->live, G->active, o.ms.bu_permille, r, G->ctl_dev, G->stream);
+        HIPCHK(hipMemcpyAsync(G->ctl_host, G->ctl_dev, 4 * sizeof(unsigned long long),
+                              hipMemcpyDeviceToHost, G->stream));
+        HIPCHK(hipEventRecord(G->ev, G->stream));
+        G->launched = true;
+      }
+      for (GState *G : graphs) {
+        if (!G->launched) continue;
+        HIPCHK(hipEventSynchronize(G->ev));
+        const int64_t t = now_ns();
+        const uint64_t alive = G->ctl_host[1];
+        std::lock_guard<std::mutex> lk(mu);
+        uint64_t fin = G->used & ~alive;
+        while (fin) {
+          const int i = __builtin_ctzll(fin);
+          fin &= fin - 1;
+          Query *q = G->lane[i];
+          q->levels = G->L + 1 - G->start_level[i];
+          finish(q, G, t);
+          G->lane[i] = nullptr;
+          G->used &= ~(1ull << i);
+        }
+        G->live = alive & G->used;
+        G->active = int64_t(G->ctl_host[0]);
+        G->L += 1;
+      }
+      cv_done.notify_all();
+    }
+  }
+
+  void loop_plain() {
+    dsbfs_run_opts ro{};
+    run_opts_default(&ro);
+    ro.want_parent = 0;
+    while (true) {
+      Query *q = nullptr;
+      GState *G = nullptr;
+      {
+        std::unique_lock<std::mutex> lk(mu);
+        cv_work.wait(lk, [&] { return stop || has_work(); });
+        if (stop) return;
+        // oldest waiting query over all graphs
+        for (GState *H : graphs)
+          if (!H->pending.empty() &&
+              (!q || H->pending.front()->arrival < q->arrival)) {
+            q = H->pending.front();
+            G = H;
+          }
+        int32_t *row = take_row(G);
+        if (!row) {
+          cv_done.wait_for(lk, std::chrono::milliseconds(1));
+          continue;
+        }
+        G->pending.pop_front();
+        q->res = row;
+        q->admit = q->start = now_ns();
+        q->state = Q_RUNNING;
+      }
+      bfs_run(G->g, G->ws, q->source, &ro, q->res, nullptr, nullptr, G->stream);
+      HIPCHK(hipStreamSynchronize(G->stream));
+      {
+        std::lock_guard<std::mutex> lk(mu);
+        finish(q, G, now_ns());
+      }
+      cv_done.notify_all();
+    }
+  }
+
+  void run() {
+    try {
+      HIPCHK(hipSetDevice(device));
+      if (o.batched) loop_batched();
+      else loop_plain();
+    } catch (const Error &e) {
+      std::lock_guard<std::mutex> lk(mu);
+      thread_error = e.msg;
+      stop = true;
+      cv_done.notify_all();
+    }
+  }
+};
+
+Server *server_create(const dsbfs_server_opts *o, const dsbfs_allocator *alloc) {
+  if (o->max_lanes < 1 || o->max_lanes > 64)
+    fail(DSBFS_ERR_INVALID_ARG, "max_lanes must be in [1, 64]");
+  if (o->ms.bu_permille < 0 || o->ms.bu_permille > 1000)
+    fail(DSBFS_ERR_INVALID_ARG, "ms.bu_permille must be in [0, 1000]");
+  (void)alloc;  // result rows come from hipMalloc: the scheduler thread never calls back
+  Server *S = new Server();
+  S->o = *o;
+  HIPCHK(hipGetDevice(&S->device));
+  S->th = std::thread([S] { S->run(); });
+  return S;
+}
+
+void server_add_graph(Server *S, Graph *g, int32_t *id) {
+  if (!g->pcol.p && g->m > 0 && S->o.batched)
+    fail(DSBFS_ERR_INVALID_ARG, "batched serving needs graphs built with keep_plain_csr");
+  GState *G = new GState();
+  try {
+    G->g = g;
+    HIPCHK(hipStreamCreateWithFlags(&G->stream, hipStreamNonBlocking));
+    HIPCHK(hipEventCreateWithFlags(&G->ev, hipEventDisableTiming));
+    G->ws = workspace_create(g, 64);
+    if (S->o.batched) ms_level_prepare(g, G->ws, G->stream);
+    HIPCHK(hipMalloc(reinterpret_cast<void **>(&G->ctl_dev), 4 * sizeof(unsigned long long)));
+    HIPCHK(hipHostMalloc(reinterpret_cast<void **>(&G->ctl_host), 4 * sizeof(unsigned long long),
+                         hipHostMallocDefault));
+    HIPCHK(hipMalloc(reinterpret_cast<void **>(&G->seed_dev), 64 * sizeof(int32_t)));
+    HIPCHK(hipHostMalloc(reinterpret_cast<void **>(&G->seed_host), 64 * sizeof(int32_t),
+                         hipHostMallocDefault));
+    HIPCHK(hipStreamSynchronize(G->stream));
+    G->bytes = graph_footprint(g) + workspace_footprint(G->ws);
+    std::lock_guard<std::mutex> lk(S->mu);
+    if (S->used_bytes + G->bytes > S->o.hbm_budget_bytes)
+      fail(DSBFS_ERR_BUDGET, "graph does not fit the HBM budget");
+    S->used_bytes += G->bytes;
+    *id = int32_t(S->graphs.size());
+    S->graphs.push_back(G);
+  } catch (...) {
+    if (G->ws) workspace_destroy(G->ws);
+    if (G->ctl_dev) (void)hipFree(G->ctl_dev);
+    if (G->ctl_host) (void)hipHostFree(G->ctl_host);
+    if (G->seed_dev) (void)hipFree(G->seed_dev);
+    if (G->seed_host) (void)hipHostFree(G->seed_host);
+    if (G->ev) (void)hipEventDestroy(G->ev);
+    if (G->stream) (void)hipStreamDestroy(G->stream);
+    delete G;
+    throw;
+  }
+}
+
+void server_submit(Server *S, int32_t gid, int32_t source, int64_t arrival, int64_t *ticket) {
+  std::lock_guard<std::mutex> lk(S->mu);
+  if (!S->thread_error.empty()) fail(DSBFS_ERR_HIP, "server stopped: " + S->thread_error);
+  if (gid < 0 || gid >= int32_t(S->graphs.size())) fail(DSBFS_ERR_INVALID_ARG, "unknown graph id");
+  GState *G = S->graphs[gid];
+  if (source < 0 || source >= G->g->n) fail(DSBFS_ERR_INVALID_ARG, "source outside [0, n)");
+  size_t resident = 0;
+  for (const GState *H : S->graphs) resident += H->bytes;
+  if (resident + S->row_bytes(G) > S->o.hbm_budget_bytes)
+    fail(DSBFS_ERR_BUDGET, "a result row of this graph can never fit the HBM budget");
+  Query *q = new Query();
+  q->ticket = S->next_ticket++;
+  q->gid = gid;
+  q->source = source;
+  q->arrival = arrival > 0 ? arrival : now_ns();
+  S->queries[q->ticket] = q;
+  G->pending.push_back(q);
+  *ticket = q->ticket;
+  S->cv_work.notify_one();
+}
+
+dsbfs_status server_wait(Server *S, int64_t ticket, int64_t timeout_ns, const int32_t **depth,
+                         dsbfs_query_stats *st) {
+  std::unique_lock<std::mutex> lk(S->mu);
+  auto it = S->queries.find(ticket);
+  if (it == S->queries.end()) fail(DSBFS_ERR_INVALID_ARG, "unknown ticket");
+  Query *q = it->second;
+  auto ready = [&] { return q->state >= Q_DONE || !S->thread_error.empty(); };
+  if (timeout_ns < 0) S->cv_done.wait(lk, ready);
+  else if (!S->cv_done.wait_for(lk, std::chrono::nanoseconds(timeout_ns), ready))
+    return DSBFS_ERR_NOT_READY;
+  if (q->state < Q_DONE) fail(DSBFS_ERR_HIP, "server stopped: " + S->thread_error);
+  if (q->state == Q_RELEASED) fail(DSBFS_ERR_INVALID_ARG, "ticket already released");
+  if (depth) *depth = q->res;
+  if (st) {
+    st->arrival_ns = q->arrival;
+    st->admit_ns = q->admit;
+    st->start_ns = q->start;
+    st->done_ns = q->done;
+    st->graph_id = q->gid;
+    st->source = q->source;
+    st->levels = q->levels;
+    st->batched = q->batched;
+  }
+  return DSBFS_OK;
+}
+
+void server_release(Server *S, int64_t ticket) {
+  std::lock_guard<std::mutex> lk(S->mu);
+  auto it = S->queries.find(ticket);
+  if (it == S->queries.end()) fail(DSBFS_ERR_INVALID_ARG, "unknown ticket");
+  Query *q = it->second;
+  if (q->state != Q_DONE) fail(DSBFS_ERR_INVALID_ARG, "query not done (or already released)");
+  S->graphs[q->gid]->free_bufs.push_back(q->res);
+  q->res = nullptr;
+  q->state = Q_RELEASED;
+  S->queries.erase(it);
+  delete q;
+  S->cv_work.notify_one();
+}
+
+void server_destroy(Server *S) {
+  {
+    std::lock_guard<std::mutex> lk(S->mu);
+    S->stop = true;
+  }
+  S->cv_work.notify_all();
+  S->cv_done.notify_all();
+  if (S->th.joinable()) S->th.join();
+  for (auto &kv : S->queries) {
+    if (kv.second->res) (void)hipFree(kv.second->res);
+    delete kv.second;
+  }
+  for (GState *G : S->graphs) {
+    (void)hipStreamSynchronize(G->stream);
+    for (int32_t *p : G->free_bufs) (void)hipFree(p);
+    workspace_destroy(G->ws);
+    graph_destroy(G->g);
+    (void)hipFree(G->ctl_dev);
+    (void)hipHostFree(G->ctl_host);
+    (void)hipFree(G->seed_dev);
+    (void)hipHostFree(G->seed_host);
+    (void)hipEventDestroy(G->ev);
+    (void)hipStreamDestroy(G->stream);
+    delete G;
+  }
+  delete S;
+}
+
+}  // namespace dsbfs

@@ -349,3 +349,68 @@ def msbfs_tune(graph: Graph, ws: Workspace, sources, cache_path: str | None = No
 
 def now_ns() -> int:
     return int(dsbfs_now_ns())
+
+
+class _DevRow:
+    """A device int32 vector at a raw address, exposed to torch through the
+    CUDA array interface (no copy)."""
+
+    def __init__(self, ptr: int, n: int):
+        self.__cuda_array_interface__ = {"shape": (n,), "typestr": "<i4", "data": (ptr, True),
+                                         "version": 2, "strides": None}
+
+
+def device_row(ptr: int, n: int):
+    """torch view of a device int32[n] row owned by the library."""
+    return _torch().as_tensor(_DevRow(ptr, n), device="cuda")
+
+
+class Server:
+    """Continuous-batching query server (dsbfs_server)."""
+
+    def __init__(self, budget_bytes: int, max_lanes: int = 64, batched: bool = True,
+                 ms: dsbfs_ms_opts | None = None):
+        o = dsbfs_server_opts()
+        o.hbm_budget_bytes = int(budget_bytes)
+        o.max_lanes = max_lanes
+        o.batched = int(bool(batched))
+        o.ms = ms if ms is not None else dsbfs_ms_opts(256, 4, 2, 0)
+        h = vp()
+        check(dsbfs_server_create(ctypes.byref(o), None, ctypes.byref(h)), "dsbfs_server_create")
+        self.h = h
+        self.n_of = {}
+
+    def add_graph(self, graph: Graph) -> int:
+        gid = ctypes.c_int32(0)
+        check(dsbfs_server_add_graph(self.h, graph.h, ctypes.byref(gid)), "dsbfs_server_add_graph")
+        self.n_of[gid.value] = graph.n
+        graph.release_ownership()
+        return gid.value
+
+    def submit(self, gid: int, source: int, arrival_ns: int = 0) -> int:
+        t = ctypes.c_int64(0)
+        check(dsbfs_server_submit(self.h, gid, source, arrival_ns, ctypes.byref(t)),
+              "dsbfs_server_submit")
+        return t.value
+
+    def wait(self, ticket: int, timeout_ns: int = -1):
+        """(device pointer of the depth row, stats dict); raises on NOT_READY."""
+        p = vp()
+        st = dsbfs_query_stats()
+        check(dsbfs_server_wait(self.h, ticket, timeout_ns, ctypes.byref(p), ctypes.byref(st)),
+              "dsbfs_server_wait")
+        return p.value, {k: int(getattr(st, k)) for k, _ in st._fields_}
+
+    def release(self, ticket: int):
+        check(dsbfs_server_release(self.h, ticket), "dsbfs_server_release")
+
+    def destroy(self):
+        if self.h:
+            check(dsbfs_server_destroy(self.h), "dsbfs_server_destroy")
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass

@@ -1,0 +1,168 @@
+"""GPU parity of bit-parallel multi-source BFS: every lane's depths equal the
+oracle's single-source depths, for partial batches, duplicate sources, forced
+top-down-only / bottom-up-only schedules, captured-graph and cooperative
+launches, and at full size (RMAT scale 24, 1024 sources) on sampled rows plus
+component-size checks on every row."""
+import os
+import tempfile
+
+import numpy as np
+import pytest
+
+from closed_forms import grid, hypercube, star
+from gpu_helpers import lib, log, torch_cuda
+
+pytestmark = pytest.mark.gpu
+
+
+def _opts(block=256, per_cu=4, permille=2, graph=1):
+    d = lib()
+    return d.dsbfs_ms_opts(block, per_cu, permille, graph)
+
+
+def _setup(src, dst, n):
+    torch_cuda()
+    d = lib()
+    g = d.Graph(src, dst, n, threshold=32, keep_plain_csr=True)
+    ws = d.Workspace(g, max_lanes=64)
+    return g, ws
+
+
+def _run(g, ws, n, sources, opts):
+    torch = torch_cuda()
+    d = lib()
+    depth = torch.full((len(sources), n), -7, dtype=torch.int32, device="cuda")
+    d.msbfs(g, ws, sources, depth, opts)
+    torch.cuda.synchronize()
+    return depth
+
+
+@pytest.mark.parametrize("permille", [0, 2, 1000])
+@pytest.mark.parametrize("graph", [0, 1])
+def test_msbfs_rmat12_all_lanes(inputs_mod, oracle_mod, permille, graph):
+    scale = 12
+    n = 1 << scale
+    src, dst = inputs_mod.rmat_edges(scale)
+    O = oracle_mod.Graph(src, dst, n)
+    g, ws = _setup(src, dst, n)
+    sources = inputs_mod.pick_sources(src, dst, n, 100, seed=404)   # 2 batches, 64 + 36
+    depth = _run(g, ws, n, sources, _opts(permille=permille, graph=graph)).cpu().numpy()
+    for i, s in enumerate(sources.tolist()):
+        want, _ = O.bfs(s, want_parent=False)
+        np.testing.assert_array_equal(depth[i], want, err_msg=f"lane {i} source {s}")
+
+
+def test_msbfs_closed_forms_and_duplicates(oracle_mod):
+    for n, src, dst, dist in (grid(13, 11), hypercube(8), star(70)):
+        g, ws = _setup(src, dst, n)
+        sources = np.array([0, 1, 0, n - 1, 5, 5, 5], dtype=np.int32)   # repeated sources
+        for permille in (0, 1000):
+            depth = _run(g, ws, n, sources, _opts(permille=permille)).cpu().numpy()
+            for i, s in enumerate(sources.tolist()):
+                np.testing.assert_array_equal(depth[i], dist(s), err_msg=f"n={n} lane {i}")
+
+
+def test_msbfs_launch_shapes(inputs_mod, oracle_mod):
+    scale = 11
+    n = 1 << scale
+    src, dst = inputs_mod.rmat_edges(scale)
+    O = oracle_mod.Graph(src, dst, n)
+    g, ws = _setup(src, dst, n)
+    sources = inputs_mod.pick_sources(src, dst, n, 64, seed=5)
+    wants = [O.bfs(s, want_parent=False)[0] for s in sources.tolist()]
+    for block, per_cu in ((64, 1), (256, 2), (512, 4), (1024, 2)):
+        depth = _run(g, ws, n, sources, _opts(block=block, per_cu=per_cu)).cpu().numpy()
+        for i in range(len(sources)):
+            np.testing.assert_array_equal(depth[i], wants[i], err_msg=f"{block}x{per_cu} lane {i}")
+    # the same captured graph replayed several times, with other work in between
+    torch = torch_cuda()
+    depth = torch.empty((len(sources), n), dtype=torch.int32, device="cuda")
+    for rep in range(3):
+        depth.fill_(-9)
+        lib().msbfs(g, ws, sources, depth, _opts(graph=1))
+        torch.cuda.synchronize()
+        got = depth.cpu().numpy()
+        for i in range(len(sources)):
+            np.testing.assert_array_equal(got[i], wants[i], err_msg=f"replay {rep} lane {i}")
+
+
+def test_msbfs_config4_scale24_1024_sources(inputs_mod, oracle_mod):
+    """RMAT scale 24, 1024 sources = 16 batches in one launch; 16 sampled rows
+    against the oracle, and on every row: depth 0 at its source only, and the
+    reached count equals the size of the source's component."""
+    torch = torch_cuda()
+    scale = 24
+    n = 1 << scale
+    src, dst = inputs_mod.rmat_edges(scale)
+    O = oracle_mod.Graph(src, dst, n)
+    log("scale 24 oracle built")
+    label = O.components()
+    comp_size = np.bincount(label, minlength=n)
+    g, ws = _setup(src, dst, n)
+    sources = inputs_mod.pick_sources(src, dst, n, 1024, seed=1004)
+    assert len(sources) == 1024
+    depth = _run(g, ws, n, sources, None)
+    log("scale 24 multi-source BFS done")
+    reached = (depth >= 0).sum(dim=1).cpu().numpy()
+    np.testing.assert_array_equal(reached, comp_size[label[sources]])
+    zeros = (depth == 0).sum(dim=1).cpu().numpy()
+    assert (zeros == 1).all()
+    at_src = depth[torch.arange(1024, device="cuda"),
+                   torch.as_tensor(sources, device="cuda").long()].cpu().numpy()
+    assert (at_src == 0).all()
+    assert int((depth < -1).sum().item()) == 0
+    rng = np.random.default_rng(1)
+    for i in sorted(rng.choice(1024, size=16, replace=False).tolist()):
+        want, _ = O.bfs(int(sources[i]), want_parent=False)
+        np.testing.assert_array_equal(depth[i].cpu().numpy(), want, err_msg=f"row {i}")
+        log(f"row {i} ok")
+
+
+def test_msbfs_tuner_cache(inputs_mod, oracle_mod):
+    d = lib()
+    scale = 12
+    n = 1 << scale
+    src, dst = inputs_mod.rmat_edges(scale)
+    g, ws = _setup(src, dst, n)
+    sources = inputs_mod.pick_sources(src, dst, n, 64, seed=6)
+    with tempfile.TemporaryDirectory() as tmp:
+        path = os.path.join(tmp, "tune.json")
+        best = d.msbfs_tune(g, ws, sources, path)
+        assert best.block in (256, 512, 1024) and best.use_graph == 1
+        assert os.path.exists(path)
+        again = d.msbfs_tune(g, ws, sources, path)     # served from the cache
+        assert again.as_dict() == best.as_dict()
+        with open(path) as f:
+            assert len(f.read().strip().splitlines()) == 1
+    O = oracle_mod.Graph(src, dst, n)
+    depth = _run(g, ws, n, sources, best).cpu().numpy()
+    for i, s in enumerate(sources.tolist()[:8]):
+        np.testing.assert_array_equal(depth[i], O.bfs(s, want_parent=False)[0])
+
+
+def test_msbfs_errors(inputs_mod):
+    torch = torch_cuda()
+    d = lib()
+    src, dst = inputs_mod.rmat_edges(8)
+    n = 256
+    g = d.Graph(src, dst, n, threshold=8, keep_plain_csr=True)
+    ws0 = d.Workspace(g, max_lanes=0)
+    depth = torch.empty((2, n), dtype=torch.int32, device="cuda")
+    with pytest.raises(d.DsbfsError) as e:
+        d.msbfs(g, ws0, np.array([1, 2], np.int32), depth)
+    assert e.value.status == d.ERR_INVALID_ARG
+    ws = d.Workspace(g, max_lanes=64)
+    with pytest.raises(d.DsbfsError) as e:
+        d.msbfs(g, ws, np.array([1, n], np.int32), depth)
+    assert e.value.status == d.ERR_INVALID_ARG
+    with pytest.raises(d.DsbfsError) as e:
+        d.msbfs(g, ws, np.array([1, 2], np.int32), depth, _opts(block=96))
+    assert e.value.status == d.ERR_INVALID_ARG
+    with pytest.raises(d.DsbfsError) as e:
+        d.Workspace(g, max_lanes=32)
+    assert e.value.status == d.ERR_INVALID_ARG
+    g2 = d.Graph(src, dst, n, threshold=8, keep_plain_csr=False)
+    ws2 = d.Workspace(g2, max_lanes=64)
+    with pytest.raises(d.DsbfsError) as e:
+        d.msbfs(g2, ws2, np.array([1, 2], np.int32), depth)
+    assert e.value.status == d.ERR_INVALID_ARG

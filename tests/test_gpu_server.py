@@ -1,0 +1,167 @@
+"""GPU tests of the query server: every served result equals the oracle, the
+same query gives the same result alone and in a mix (continuous batching),
+plain and batched modes agree, admission follows the HBM budget, and errors
+are reported as status codes."""
+import time
+
+import numpy as np
+import pytest
+
+from gpu_helpers import lib, log, torch_cuda
+
+pytestmark = pytest.mark.gpu
+
+BIG = 1 << 40
+
+
+def _graphs(inputs_mod, oracle_mod):
+    """Three small resident graphs: RMAT 10, RMAT 12, ER n=3000 (avg degree ~16)."""
+    specs = []
+    for scale in (10, 12):
+        src, dst = inputs_mod.rmat_edges(scale)
+        specs.append((1 << scale, src, dst))
+    src, dst = inputs_mod.er_edges(3000, 8 * 3000, seed=0x22)
+    specs.append((3000, src, dst))
+    return [(n, s, d, oracle_mod.Graph(s, d, n)) for n, s, d in specs]
+
+
+def _server(specs, batched, budget=BIG, lanes=64):
+    torch_cuda()
+    d = lib()
+    S = d.Server(budget, max_lanes=lanes, batched=batched)
+    gids = []
+    for n, s, t, _ in specs:
+        g = d.Graph(s, t, n, threshold=16, keep_plain_csr=True)
+        gids.append(S.add_graph(g))
+    return S, gids
+
+
+def _fetch(S, ticket, n):
+    d = lib()
+    ptr, st = S.wait(ticket)
+    row = d.device_row(ptr, n).cpu().numpy().copy()
+    S.release(ticket)
+    return row, st
+
+
+@pytest.mark.parametrize("batched", [True, False])
+def test_server_mix_matches_oracle(inputs_mod, oracle_mod, batched):
+    specs = _graphs(inputs_mod, oracle_mod)
+    S, gids = _server(specs, batched)
+    rng = np.random.default_rng(7)
+    jobs = []
+    for i in range(300):
+        k = int(rng.integers(0, len(specs)))
+        n, src, dst, _ = specs[k]
+        s = int(inputs_mod.pick_sources(src, dst, n, 1, seed=5000 + i)[0])
+        jobs.append((k, s, S.submit(gids[k], s)))
+        if i % 50 == 49:
+            time.sleep(0.002)   # arrivals in bursts, while earlier ones run
+    for k, s, t in jobs:
+        n, _, _, O = specs[k]
+        row, st = _fetch(S, t, n)
+        want, _ = O.bfs(s, want_parent=False)
+        np.testing.assert_array_equal(row, want, err_msg=f"graph {k} source {s}")
+        assert st["done_ns"] >= st["start_ns"] >= st["admit_ns"] >= st["arrival_ns"] > 0
+        assert st["batched"] == int(batched)
+    S.destroy()
+
+
+def test_server_alone_equals_in_mix(inputs_mod, oracle_mod):
+    """A query served alone and the same query served among 100 others that
+    keep arriving while it runs give identical depth rows."""
+    specs = _graphs(inputs_mod, oracle_mod)
+    n, src, dst, O = specs[1]
+    probe = int(inputs_mod.pick_sources(src, dst, n, 1, seed=99)[0])
+    S, gids = _server(specs, True)
+    alone, _ = _fetch(S, S.submit(gids[1], probe), n)
+    tickets = [S.submit(gids[i % 3], int(inputs_mod.pick_sources(
+        specs[i % 3][1], specs[i % 3][2], specs[i % 3][0], 1, seed=700 + i)[0]))
+        for i in range(50)]
+    mid = S.submit(gids[1], probe)
+    tickets += [S.submit(gids[i % 3], int(inputs_mod.pick_sources(
+        specs[i % 3][1], specs[i % 3][2], specs[i % 3][0], 1, seed=800 + i)[0]))
+        for i in range(50)]
+    mixed, st = _fetch(S, mid, n)
+    for t in tickets:
+        S.wait(t)
+        S.release(t)
+    np.testing.assert_array_equal(alone, mixed)
+    np.testing.assert_array_equal(alone, O.bfs(probe, want_parent=False)[0])
+    S.destroy()
+
+
+def test_server_budget_admission(inputs_mod, oracle_mod):
+    d = lib()
+    specs = _graphs(inputs_mod, oracle_mod)[:1]       # RMAT 10, n = 1024
+    n, src, dst, O = specs[0]
+    torch_cuda()
+    # a budget too small for the graph itself
+    S = d.Server(1024, batched=True)
+    g = d.Graph(src, dst, n, threshold=16, keep_plain_csr=True)
+    with pytest.raises(d.DsbfsError) as e:
+        S.add_graph(g)
+    assert e.value.status == d.ERR_BUDGET
+    g.destroy()
+    S.destroy()
+    # find the resident footprint (first budget that admits the graph), then
+    # allow exactly two result rows
+    foot = None
+    for budget in range(0, 1 << 30, 1 << 16):
+        S = d.Server(budget, batched=True)
+        try:
+            gid = S.add_graph(d.Graph(src, dst, n, threshold=16, keep_plain_csr=True))
+            foot = budget
+            break
+        except d.DsbfsError:
+            S.destroy()
+    assert foot is not None
+    S.destroy()
+    S = d.Server(foot + 2 * 4 * n + (1 << 16), batched=True)
+    gid = S.add_graph(d.Graph(src, dst, n, threshold=16, keep_plain_csr=True))
+    sources = inputs_mod.pick_sources(src, dst, n, 5, seed=3)
+    ts = [S.submit(gid, int(s)) for s in sources]
+    S.wait(ts[0])
+    S.wait(ts[1])
+    with pytest.raises(d.DsbfsError) as e:
+        S.wait(ts[2], timeout_ns=200_000_000)        # no row free: still waiting
+    assert e.value.status == d.ERR_NOT_READY
+    S.release(ts[0])
+    row, _ = _fetch(S, ts[2], n)
+    np.testing.assert_array_equal(row, O.bfs(int(sources[2]), want_parent=False)[0])
+    S.release(ts[1])
+    for t, s in ((ts[3], sources[3]), (ts[4], sources[4])):
+        row, _ = _fetch(S, t, n)
+        np.testing.assert_array_equal(row, O.bfs(int(s), want_parent=False)[0])
+    S.destroy()
+    # a row that can never fit is refused at submission
+    S = d.Server(foot + 16, batched=True)
+    gid = S.add_graph(d.Graph(src, dst, n, threshold=16, keep_plain_csr=True))
+    with pytest.raises(d.DsbfsError) as e:
+        S.submit(gid, int(sources[0]))
+    assert e.value.status == d.ERR_BUDGET
+    S.destroy()
+
+
+def test_server_errors(inputs_mod, oracle_mod):
+    d = lib()
+    specs = _graphs(inputs_mod, oracle_mod)[:1]
+    S, gids = _server(specs, True)
+    n = specs[0][0]
+    for gid, s in ((5, 0), (-1, 0), (gids[0], n), (gids[0], -3)):
+        with pytest.raises(d.DsbfsError) as e:
+            S.submit(gid, s)
+        assert e.value.status == d.ERR_INVALID_ARG
+    with pytest.raises(d.DsbfsError) as e:
+        S.wait(12345)
+    assert e.value.status == d.ERR_INVALID_ARG
+    t = S.submit(gids[0], 1)
+    S.wait(t)
+    S.release(t)
+    with pytest.raises(d.DsbfsError) as e:
+        S.release(t)
+    assert e.value.status == d.ERR_INVALID_ARG
+    with pytest.raises(d.DsbfsError) as e:
+        d.Server(1 << 30, max_lanes=65)
+    assert e.value.status == d.ERR_INVALID_ARG
+    S.destroy()
