@@ -39,6 +39,25 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` from a committed rocprofv3 summary in
+    profiles/ (FETCH_SIZE + WRITE_SIZE runs, calibrated on a copy kernel), if
+    one exists for this workload and for the current kernel source; else None."""
+    import glob
+    import hashlib
+    src = os.path.join(ROOT, "paper_1803_03922_amd", "csrc", "bfs.hip")
+    h = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    for f in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
+        for line in open(f):
+            if not line.startswith("traffic: "):
+                continue
+            kv = dict(t.split("=", 1) for t in line.split()[1:])
+            if (kv.get("kernel") == kernel and kv.get("workload") == workload.replace(" ", "_")
+                    and kv.get("source_sha256") == h):
+                return float(kv["bytes_per_launch"])
+    return None
+
+
 def harmonic(xs):
     xs = [x for x in xs if x > 0]
     return len(xs) / sum(1.0 / x for x in xs) if xs else 0.0
@@ -141,8 +160,15 @@ def main():
     dname, dk = dom
     achieved = dk["bytes"] / (dk["ms"] * 1e-3) / 1e9 if dk["ms"] > 0 else 0.0
     total_kernel_ms = sum(k["ms"] for k in kern.values())
+    kname = {"prev_normal": "k_normal_level", "td_normal": "k_td_nd", "bu_normal": "k_bu_normal",
+             "bu_deleg": "k_bu_deleg", "td_deleg": "k_td_deleg", "prev_deleg": "k_prev_deleg",
+             "close": "k_close", "init": "k_init", "plain": "k_plain_expand"}[dname]
+    wl = f"RMAT{args.scale} TH{args.threshold} {args.mode} {args.sources}src parents={int(parent is not None)}"
+    tr = measured_traffic(kname, wl)
     roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
+                "traffic": None if tr is None else round(tr / 1e6, 2),
+                "traffic_unit": "MB per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE)",
                 "kernel": dname, "launches_per_step": dk["launches"] / args.steps,
                 "bytes_per_launch": dk["bytes"] / max(dk["launches"], 1),
                 "avg_launch_ms": dk["ms"] / max(dk["launches"], 1)}

@@ -202,7 +202,10 @@ dsbfs_status dsbfs_graph_stats_get(const dsbfs_graph *g, dsbfs_graph_stats *out)
  * of its first part (nn for normal rows, dd for delegate rows); the row ends
  * at the start of the next row. Normal row v holds nn neighbours (vertex IDs)
  * then nd neighbours (delegate IDs); delegate row k holds dd neighbours
- * (delegate IDs) then dn neighbours (vertex IDs); each part ascending.
+ * (delegate IDs) then dn neighbours (vertex IDs). nn and dn parts are in
+ * ascending ID; dd parts, and nd parts of at most 64 entries, are ordered by
+ * neighbour degree, highest first (dd: by a log-scale degree bucket, 8 per
+ * power of two; ties by ascending ID), so bottom-up scans meet hubs first.
  * *bytes receives the array size; nothing is copied if capacity is smaller.
  * Synchronizes the graph's stream.
  */

@@ -438,6 +438,7 @@ __global__ void __launch_bounds__(kBS) k_bu_normal(const int32_t *cin, int dense
     int32_t pos = 0, v = 0, len = 0;
     int64_t beg = 0;
     bool visited = true;
+    int32_t hit0 = -1;  // delegate found at the first entry of the row
     if (ok) {
       pos = dense ? int32_t(i) : cin[i];
       v = ndsrc[pos];
@@ -449,6 +450,14 @@ __global__ void __launch_bounds__(kBS) k_bu_normal(const int32_t *cin, int dense
         beg = nds_off[pos];
         len = int32_t(nds_off[pos + 1] - beg);
         ++scanned;
+        // Rows start with their highest-degree delegate, the likeliest to be
+        // in the frontier: a hit there skips the wave's walk for this row.
+        const int32_t k0 = nds_col[beg];
+        ++edges;
+        if (bit_test(Fd, uint32_t(k0))) {
+          hit0 = k0;
+          len = 0;
+        }
       }
     }
     const int32_t incl = wave_incl_scan(len);
@@ -471,10 +480,10 @@ __global__ void __launch_bounds__(kBS) k_bu_normal(const int32_t *cin, int dense
       remaining = __ballot(len > 0 && s_found[w][l] == kNone);
     }
     const int32_t fe = s_found[w][l];
-    const bool found = len > 0 && fe != kNone;
+    const bool found = hit0 >= 0 || (len > 0 && fe != kNone);
     bool won = false;
     if (found) {
-      const int32_t k = nds_col[beg + (fe - (incl - len))];
+      const int32_t k = hit0 >= 0 ? hit0 : nds_col[beg + (fe - (incl - len))];
       const uint32_t bit = 1u << (v & 31);
       won = !(atomicOr(&Vn[v >> 5], bit) & bit);
       if (won) {

@@ -305,6 +305,82 @@ int bits_for(int64_t n) {
   return B;
 }
 
+// Degree bucket of a vertex on a log scale (8 buckets per power of two), so
+// that sorting by bucket orders neighbours by degree with a short key.
+__device__ __forceinline__ uint32_t deg_bucket(int32_t deg) {
+  if (deg <= 1) return 0;
+  const uint32_t lg = 31u - __clz(uint32_t(deg));          // floor(log2)
+  const uint32_t frac = lg >= 3 ? (uint32_t(deg) >> (lg - 3)) & 7u : (uint32_t(deg) << (3 - lg)) & 7u;
+  const uint32_t b = lg * 8u + frac;
+  return b > 255u ? 255u : b;
+}
+
+// Keys of every dd entry: (row k, 255 - degree bucket of the neighbour,
+// neighbour delegate ID), so one radix sort orders each dd part by
+// neighbour degree, highest first (ties by ID). One wave per row.
+__global__ void k_dd_keys(const uint64_t *doff, const int32_t *dcol, const int64_t *ddpre,
+                          const int32_t *vid_of, const int32_t *deg, int32_t d, int Bd,
+                          uint64_t *keys) {
+  const int l = lane_id();
+  const int64_t wid = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) / kWave;
+  const int64_t nw = int64_t(gridDim.x) * blockDim.x / kWave;
+  for (int64_t k = wid; k < d; k += nw) {
+    const uint64_t w = doff[k];
+    const int64_t beg = row_start(w), len = row_first(w);
+    const int64_t out = ddpre[k];
+    for (int64_t j = l; j < len; j += kWave) {
+      const int32_t x = dcol[beg + j];
+      const uint64_t b = 255u - deg_bucket(deg[vid_of[x]]);
+      keys[out + j] = (uint64_t(k) << (Bd + 8)) | (b << Bd) | uint64_t(uint32_t(x));
+    }
+  }
+}
+
+// Writes the sorted dd entries back into their rows.
+__global__ void k_dd_back(const uint64_t *keys, int64_t e_dd, const uint64_t *doff,
+                          const int64_t *ddpre, int Bd, int32_t *dcol) {
+  const uint64_t xmask = (uint64_t(1) << Bd) - 1;
+  for (int64_t j = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; j < e_dd;
+       j += int64_t(gridDim.x) * blockDim.x) {
+    const uint64_t key = keys[j];
+    const int64_t k = int64_t(key >> (Bd + 8));
+    dcol[row_start(doff[k]) + (j - ddpre[k])] = int32_t(key & xmask);
+  }
+}
+
+__global__ void k_dd_len(const uint64_t *doff, int32_t d, int32_t *len) {
+  for (int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; k < d;
+       k += int64_t(gridDim.x) * blockDim.x)
+    len[k] = int32_t(row_first(doff[k]));
+}
+
+// nd part of every normal row (at most a few dozen entries when TH is small):
+// insertion sort by neighbour degree, highest first, ties by delegate ID.
+// Parts longer than 64 entries keep ascending ID order.
+__global__ void k_nd_sort(const uint64_t *noff, int32_t n, const int32_t *did, int32_t *ncol,
+                          const int32_t *vid_of, const int32_t *deg) {
+  for (int64_t v = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; v < n;
+       v += int64_t(gridDim.x) * blockDim.x) {
+    if (did[v] >= 0) continue;
+    const uint64_t w0 = noff[v], w1 = noff[v + 1];
+    const int64_t b = row_start(w0) + row_first(w0), e = row_start(w1);
+    if (e - b < 2 || e - b > 64) continue;
+    for (int64_t i = b + 1; i < e; ++i) {
+      const int32_t x = ncol[i];
+      const int32_t dx = deg[vid_of[x]];
+      int64_t j = i - 1;
+      while (j >= b) {
+        const int32_t y = ncol[j];
+        const int32_t dy = deg[vid_of[y]];
+        if (dy > dx || (dy == dx && y < x)) break;
+        ncol[j + 1] = y;
+        --j;
+      }
+      ncol[j + 1] = x;
+    }
+  }
+}
+
 }  // namespace
 
 Graph *graph_create(const int32_t *src, const int32_t *dst, int64_t g, int32_t n,
@@ -492,6 +568,47 @@ Graph *graph_create(const int32_t *src, const int32_t *dst, int64_t g, int32_t n
                          G->dcol.as<int32_t>());
       HIPCHK(hipGetLastError());
       HIPCHK(hipStreamSynchronize(s));
+    }
+
+    // 8b. delegate-neighbour parts ordered by neighbour degree, highest first:
+    //     bottom-up scans meet frontier hubs early. (Order inside a part is
+    //     free; the four subgraphs are unchanged.)
+    if (d > 0 && e_dd > 1) {
+      const int Bd = bits_for(d);
+      DevBuf ddlen, ddpre, keys, alt2, stmp;
+      ddlen.alloc(al, size_t(d) * 4, s);
+      ddpre.alloc(al, size_t(d + 1) * 8, s);
+      stmp.alloc(al, scan_tmp_bytes(d), s);
+      hipLaunchKernelGGL(k_dd_len, dim3(grid_for(d, kBS, 4096)), dim3(kBS), 0, s,
+                         G->doff.as<uint64_t>(), int32_t(d), ddlen.as<int32_t>());
+      HIPCHK(hipGetLastError());
+      scan_excl_i32_to_i64(ddlen.as<int32_t>(), ddpre.as<int64_t>(), d, stmp.p, s);
+      keys.alloc(al, size_t(e_dd) * 8, s);
+      alt2.alloc(al, size_t(e_dd) * 8, s);
+      hipLaunchKernelGGL(k_dd_keys, dim3(4096), dim3(kBS), 0, s, G->doff.as<uint64_t>(),
+                         G->dcol.as<int32_t>(), ddpre.as<int64_t>(), G->vid_of.as<int32_t>(),
+                         G->deg.as<int32_t>(), int32_t(d), Bd, keys.as<uint64_t>());
+      HIPCHK(hipGetLastError());
+      {
+        DevBuf rtmp;
+        rtmp.alloc(al, radix_tmp_bytes(e_dd), s);
+        // keys are written row by row with IDs ascending inside a row, so a
+        // stable sort on the (row, bucket) fields alone keeps IDs ascending
+        // among equal buckets
+        radix_sort_u64_bits(keys.as<uint64_t>(), alt2.as<uint64_t>(), e_dd, Bd, 2 * Bd + 8,
+                            rtmp.p, s);
+      }
+      hipLaunchKernelGGL(k_dd_back, dim3(grid_for(e_dd, kBS, 16384)), dim3(kBS), 0, s,
+                         keys.as<uint64_t>(), e_dd, G->doff.as<uint64_t>(), ddpre.as<int64_t>(),
+                         Bd, G->dcol.as<int32_t>());
+      HIPCHK(hipGetLastError());
+      HIPCHK(hipStreamSynchronize(s));
+    }
+    if (d > 0 && e_nd > 1) {
+      hipLaunchKernelGGL(k_nd_sort, dim3(grid_for(n, kBS, 16384)), dim3(kBS), 0, s,
+                         G->noff.as<uint64_t>(), n, G->did.as<int32_t>(), G->ncol.as<int32_t>(),
+                         G->vid_of.as<int32_t>(), G->deg.as<int32_t>());
+      HIPCHK(hipGetLastError());
     }
 
     // 9. source list of nd, source masks of dd and dn

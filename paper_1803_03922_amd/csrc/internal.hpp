@@ -290,6 +290,10 @@ void scan_excl_i64(const int64_t *in, int64_t *out, int64_t N, void *tmp, hipStr
 size_t radix_tmp_bytes(int64_t N);
 void radix_sort_u64(uint64_t *keys, uint64_t *alt, int64_t N, int key_bits, void *hist_tmp,
                     hipStream_t s);
+// Stable sort on bits [lo_bit, hi_bit) only (keys already ordered below lo_bit
+// keep that order among equal sort fields).
+void radix_sort_u64_bits(uint64_t *keys, uint64_t *alt, int64_t N, int lo_bit, int hi_bit,
+                         void *hist_tmp, hipStream_t s);
 
 // Order-preserving compaction of indices i in [0, N) with flag[i] != 0 into
 // out; *count (device) gets the number kept. tmp: compact_tmp_bytes(N).

@@ -127,7 +127,61 @@ __device__ __forceinline__ uint64_t wave_or(uint64_t x) {
   return x;
 }
 
+// Bottom-up for the 64 vertices of a wave (one per lane; lanes with want = 0
+// take no part): the rows are prefix-summed across the wave and walked 64
+// entries at a time, so consecutive vertices' rows are read coalesced and 64
+// frontier words are in flight per step. Each vertex's frontier OR collects in
+// an LDS slot; the walk stops once every vertex's wanted lanes are covered.
+// Called by every lane of the wave; returns the lanes found for this lane's
+// vertex. LDS rows are per wave (64 entries each).
+__device__ uint64_t bu_wave(const int64_t *off, const int32_t *col, const uint64_t *fcur,
+                            int64_t w, uint64_t want, int32_t *s_ex, int64_t *s_beg,
+                            unsigned long long *s_want, unsigned long long *s_acc,
+                            unsigned long long &edges) {
+  const int l = lane_id();
+  int32_t len = 0;
+  int64_t beg = 0;
+  if (want) {
+    beg = off[w];
+    len = int32_t(off[w + 1] - beg);
+  }
+  const int32_t incl = wave_incl_scan(len);
+  const int32_t T = __shfl(incl, kWave - 1, kWave);
+  wave_sync();
+  s_ex[l] = incl - len;
+  s_beg[l] = beg;
+  s_want[l] = want;
+  s_acc[l] = 0;
+  wave_sync();
+  uint64_t pend = __ballot(len > 0);
+  for (int32_t e0 = 0; e0 < T && pend; e0 += kWave) {
+    const int32_t e = e0 + l;
+    if (e < T) {
+      int lo = 0;
+#pragma unroll
+      for (int step = 32; step > 0; step >>= 1) {
+        const int c = lo + step;
+        if (s_ex[c] <= e) lo = c;
+      }
+      const uint64_t wl = s_want[lo];
+      if ((s_acc[lo] & wl) != wl) {
+        const uint64_t m = fcur[col[s_beg[lo] + (e - s_ex[lo])]] & wl;
+        ++edges;
+        if (m) atomicOr(&s_acc[lo], (unsigned long long)m);
+      }
+    }
+    wave_sync();
+    pend = __ballot(len > 0 && (s_acc[l] & want) != want);
+  }
+  const uint64_t r = s_acc[l] & want;
+  wave_sync();
+  return r;
+}
+
 __global__ void __launch_bounds__(1024) k_msbfs(MsArgs a) {
+  __shared__ int32_t s_ex[16][kWave];
+  __shared__ int64_t s_beg[16][kWave];
+  __shared__ unsigned long long s_want[16][kWave], s_acc[16][kWave];
   __shared__ unsigned long long sh[16];
   const int32_t n = a.n;
   const int64_t tid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -242,31 +296,26 @@ __global__ void __launch_bounds__(1024) k_msbfs(MsArgs a) {
         // bottom-up with the close fused in: w is only written by the thread
         // (or, for a hub, the wave) that scans it. Vertices of degree <= kHub:
         // one thread each; hubs: one wave each, 64 neighbours per step.
+        const int wv = threadIdx.x / kWave;
         for (int64_t it = 0; it < nv_iter; ++it) {
           const int64_t w = tid + it * nthreads;
           bool valid = w < n;
-          uint64_t nw = 0;
+          uint64_t s0 = 0, want = 0;
           if (valid) {
-            const int64_t p0 = a.off[w], p1 = a.off[w + 1];
-            if (p1 - p0 > kHub) {
+            if (a.off[w + 1] - a.off[w] > kHub) {
               valid = false;  // the hub pass below owns it
             } else {
-              const uint64_t s0 = a.seen[w];
-              const uint64_t want = ~s0 & live;
-              if (want) {
-                uint64_t acc = 0;
-                for (int64_t p = p0; p < p1; ++p) {
-                  acc |= fcur[a.col[p]];
-                  ++edges;
-                  if ((acc & want) == want) break;
-                }
-                nw = acc & want;
-                if (nw) a.seen[w] = s0 | nw;
-              }
-              fnext[w] = nw;
-              act += nw != 0;
-              lor |= nw;
+              s0 = a.seen[w];
+              want = ~s0 & live;
             }
+          }
+          const uint64_t nw = bu_wave(a.off, a.col, fcur, w, want, s_ex[wv], s_beg[wv],
+                                      s_want[wv], s_acc[wv], edges);
+          if (valid) {
+            if (nw) a.seen[w] = s0 | nw;
+            fnext[w] = nw;
+            act += nw != 0;
+            lor |= nw;
           }
           put_lanes(a.depth, n, row0, int32_t(valid ? w : 0), nw, val, valid);
         }
@@ -770,38 +819,35 @@ __global__ void k_lv_td_close(MsLevel a, LaneRows r) {
   lv_flush(a, act, lor, 0);
 }
 
-__global__ void k_lv_bu(MsLevel a, LaneRows r) {
+__global__ void __launch_bounds__(256) k_lv_bu(MsLevel a, LaneRows r) {
+  __shared__ int32_t s_ex[4][kWave];
+  __shared__ int64_t s_beg[4][kWave];
+  __shared__ unsigned long long s_want[4][kWave], s_acc[4][kWave];
   const int64_t nthreads = int64_t(gridDim.x) * blockDim.x;
   const int64_t tid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   const int64_t iters = (int64_t(a.n) + nthreads - 1) / nthreads;
-  const int l = lane_id();
+  const int l = lane_id(), wv = threadIdx.x / kWave;
   unsigned long long act = 0, edges = 0;
   uint64_t lor = 0;
   for (int64_t it = 0; it < iters; ++it) {
     const int64_t w = tid + it * nthreads;
     bool valid = w < a.n;
-    uint64_t nw = 0;
+    uint64_t s0 = 0, want = 0;
     if (valid) {
-      const int64_t p0 = a.off[w], p1 = a.off[w + 1];
-      if (p1 - p0 > kHub) {
+      if (a.off[w + 1] - a.off[w] > kHub) {
         valid = false;
       } else {
-        const uint64_t s0 = a.seen[w];
-        const uint64_t want = ~s0 & a.live;
-        if (want) {
-          uint64_t acc = 0;
-          for (int64_t p = p0; p < p1; ++p) {
-            acc |= a.fcur[a.col[p]];
-            ++edges;
-            if ((acc & want) == want) break;
-          }
-          nw = acc & want;
-          if (nw) a.seen[w] = s0 | nw;
-        }
-        a.fnext[w] = nw;
-        act += nw != 0;
-        lor |= nw;
+        s0 = a.seen[w];
+        want = ~s0 & a.live;
       }
+    }
+    const uint64_t nw = bu_wave(a.off, a.col, a.fcur, w, want, s_ex[wv], s_beg[wv], s_want[wv],
+                                s_acc[wv], edges);
+    if (valid) {
+      if (nw) a.seen[w] = s0 | nw;
+      a.fnext[w] = nw;
+      act += nw != 0;
+      lor |= nw;
     }
     put_rows(r, int32_t(valid ? w : 0), nw, valid);
   }

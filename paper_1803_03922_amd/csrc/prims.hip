@@ -294,7 +294,12 @@ size_t radix_tmp_bytes(int64_t N) {
 
 void radix_sort_u64(uint64_t *keys, uint64_t *alt, int64_t N, int key_bits, void *tmp,
                     hipStream_t s) {
-  if (N <= 1 || key_bits <= 0) return;
+  radix_sort_u64_bits(keys, alt, N, 0, key_bits, tmp, s);
+}
+
+void radix_sort_u64_bits(uint64_t *keys, uint64_t *alt, int64_t N, int lo_bit, int hi_bit,
+                         void *tmp, hipStream_t s) {
+  if (N <= 1 || hi_bit <= lo_bit) return;
   const int64_t nb = ntiles(N, kRadixTile);
   const int64_t H = 256 * nb;
   char *t = static_cast<char *>(tmp);
@@ -303,7 +308,7 @@ void radix_sort_u64(uint64_t *keys, uint64_t *alt, int64_t N, int key_bits, void
   int64_t *gscan = reinterpret_cast<int64_t *>(t);
   t += align256(size_t(H + 1) * 8);
   uint64_t *src = keys, *dst = alt;
-  for (int shift = 0; shift < key_bits; shift += 8) {
+  for (int shift = lo_bit; shift < hi_bit; shift += 8) {
     hipLaunchKernelGGL(k_radix_hist, dim3(unsigned(nb)), dim3(kRadixBS), 0, s, src, N, shift, nb,
                        ghist);
     HIPCHK(hipGetLastError());

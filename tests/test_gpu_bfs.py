@@ -133,6 +133,16 @@ def test_direction_schedule_matches_oracle_replay(inputs_mod, oracle_mod, scale,
     G.close()
 
 
+def _deg_bucket(x):
+    """Log-scale degree bucket: 8 per power of two (floor(log2) and the next
+    three bits), capped at 255."""
+    if x <= 1:
+        return 0
+    lg = x.bit_length() - 1
+    frac = (x >> (lg - 3)) & 7 if lg >= 3 else (x << (3 - lg)) & 7
+    return min(lg * 8 + frac, 255)
+
+
 def _decode(off):
     off = off.astype(np.uint64)
     start = (off & np.uint64((1 << 40) - 1)).astype(np.int64)
@@ -163,16 +173,27 @@ def test_builder_layout_matches_oracle_split(inputs_mod, oracle_mod, scale, TH):
     nd_len = np.diff(r["nd_off"])
     np.testing.assert_array_equal(nf[:n], nn_len)
     np.testing.assert_array_equal(np.diff(ns), nn_len + nd_len)
+    deg = O.degrees()
+    vid = np.nonzero(r["did"] >= 0)[0]
     for v in range(n):
         row = ncol[ns[v]:ns[v + 1]]
         assert row[:nf[v]].tolist() == r["nn_col"][r["nn_off"][v]:r["nn_off"][v + 1]].tolist()
-        assert row[nf[v]:].tolist() == r["nd_col"][r["nd_off"][v]:r["nd_off"][v + 1]].tolist()
+        nd_part = row[nf[v]:]
+        want = r["nd_col"][r["nd_off"][v]:r["nd_off"][v + 1]]
+        assert sorted(nd_part.tolist()) == want.tolist()
+        if len(nd_part) <= 64:   # degree descending, ties by ascending delegate ID
+            keys = [(-int(deg[vid[x]]), int(x)) for x in nd_part]
+            assert keys == sorted(keys), v
     ds, df = _decode(g.export(5, np.uint64))
     dcol = g.export(6, np.int32)
     assert len(ds) == d + 1
     for k in range(d):
         row = dcol[ds[k]:ds[k + 1]]
-        assert row[:df[k]].tolist() == r["dd_col"][r["dd_off"][k]:r["dd_off"][k + 1]].tolist()
+        dd_part = row[:df[k]]
+        assert sorted(dd_part.tolist()) == \
+            r["dd_col"][r["dd_off"][k]:r["dd_off"][k + 1]].tolist()
+        keys = [(-_deg_bucket(int(deg[vid[x]])), int(x)) for x in dd_part]
+        assert keys == sorted(keys), k
         assert row[df[k]:].tolist() == r["dn_col"][r["dn_off"][k]:r["dn_off"][k + 1]].tolist()
     nd_src = np.nonzero(nd_len > 0)[0]
     np.testing.assert_array_equal(g.export(7, np.int32), nd_src)
