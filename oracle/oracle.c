@@ -99,7 +99,16 @@ int or_graph_build(const int32_t *src, const int32_t *dst, int64_t g, int32_t n,
   for (int32_t v = 0; v < n; ++v) {
     int32_t *row = tmp + start[v];
     int64_t len = start[v + 1] - start[v];
-    if (len > 1) qsort(row, (size_t)len, sizeof(int32_t), cmp_i32);
+    if (len > 64) {
+      qsort(row, (size_t)len, sizeof(int32_t), cmp_i32);
+    } else {
+      for (int64_t i = 1; i < len; ++i) {   /* insertion sort for short rows */
+        int32_t x = row[i];
+        int64_t j = i - 1;
+        while (j >= 0 && row[j] > x) { row[j + 1] = row[j]; --j; }
+        row[j + 1] = x;
+      }
+    }
     int64_t k = 0;
     for (int64_t i = 0; i < len; ++i)
       if (k == 0 || row[i] != row[k - 1]) row[k++] = row[i];

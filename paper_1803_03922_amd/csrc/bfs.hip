@@ -244,10 +244,13 @@ __device__ __forceinline__ void expand_normal_rows(int32_t u, int32_t len, int64
 
 // One pass over the normal queue: previsit (nn/nd workloads and counts of
 // the frontier, normal frontier bitmap Fn) fused with the nn top-down visit.
+// Fn is only read by a bottom-up nd visit; mark_fn = 0 when none can happen
+// (no unvisited delegate has a dn edge).
 __global__ void __launch_bounds__(kBS) k_normal_level(const int32_t *Q, const LevelCtr *prev,
                                                       const uint64_t *noff, const int32_t *ncol,
                                                       Out out, uint32_t *Vn, uint32_t *Fn,
-                                                      int32_t *Qnext, LevelCtr *cur) {
+                                                      int mark_fn, int32_t *Qnext,
+                                                      LevelCtr *cur) {
   __shared__ int32_t s_excl[kNW][kWave];
   __shared__ int32_t s_u[kNW][kWave];
   __shared__ int64_t s_beg[kNW][kWave];
@@ -275,7 +278,7 @@ __global__ void __launch_bounds__(kBS) k_normal_level(const int32_t *Q, const Le
       q_nn += nn > 0;
       fv_nd += nd;
       q_nd += nd > 0;
-      atomicOr(&Fn[u >> 5], 1u << (u & 31));
+      if (mark_fn) atomicOr(&Fn[u >> 5], 1u << (u & 31));
     }
     expand_normal_rows<0>(u, nn, beg, s_excl[w], s_u[w], s_beg[w], ncol, nullptr, out, Vn,
                           nullptr, qa, edges, claimed);
@@ -835,10 +838,13 @@ void bfs_run(const Graph *g, Workspace *ws, int32_t source, const dsbfs_run_opts
       LevelCtr *cur = ctr + (L & 1), *prev = ctr + ((L + 1) & 1);
       HIPCHK(hipMemsetAsync(cur, 0, sizeof(LevelCtr), s));
       out.level1 = L + 1;
+      // rem_dn counts unvisited delegates with a dn edge before this level's
+      // frontier is subtracted: zero means no bottom-up nd visit is possible
+      const int mark_fn = rem_dn > 0;
       b = P.begin();
       hipLaunchKernelGGL(k_normal_level, dim3(SG), dim3(kBS), 0, s, Q[qi], prev,
-                         g->noff.as<uint64_t>(), g->ncol.as<int32_t>(), out, Vn, Fn, Q[qi ^ 1],
-                         cur);
+                         g->noff.as<uint64_t>(), g->ncol.as<int32_t>(), out, Vn, Fn, mark_fn,
+                         Q[qi ^ 1], cur);
       HIPCHK(hipGetLastError());
       P.end(DSBFS_K_PREV_NORMAL, b);
       if (d > 0) {
@@ -965,14 +971,14 @@ void bfs_run(const Graph *g, Workspace *ws, int32_t source, const dsbfs_run_opts
       }
       // Large levels clear the normal frontier bitmap with one streaming fill
       // instead of one scattered store per queue entry.
-      const bool bulk_fn = qn * 16 > int64_t(g->nwords());
+      const bool bulk_fn = mark_fn && qn * 16 > int64_t(g->nwords());
       b = P.begin();
       if (bulk_fn) HIPCHK(hipMemsetAsync(Fn, 0, size_t(g->nwords()) * 4, s));
       hipLaunchKernelGGL(k_close,
                          dim3(grid_for(std::max<int64_t>(bulk_fn ? 0 : qn, g->dwords()), kBS,
                                        4096)),
                          dim3(kBS), 0, s, Vd, Fd, Cd, g->dwords(), Fn, Q[qi], prev,
-                         int(!bulk_fn));
+                         int(mark_fn && !bulk_fn));
       HIPCHK(hipGetLastError());
       P.end(DSBFS_K_CLOSE, b);
       P.units[DSBFS_K_CLOSE][0] += double(bulk_fn ? g->nwords() / 4 : qn);
