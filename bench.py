@@ -88,6 +88,8 @@ def main():
                     help="1: also measure the query server (5 graphs, 3 Poisson rates)")
     ap.add_argument("--serve-queries", type=int, default=4096)
     ap.add_argument("--serve-scales", default="18,20,22,24")
+    ap.add_argument("--th-sweep", default="16,32,64,128",
+                    help="thresholds re-run on the same graph and sources ('' = none)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -200,7 +202,38 @@ def main():
                          f"host thread, CSR build untimed"}
         del O
 
-    del ws, g, depth, parent
+    del ws, g
+    torch.cuda.empty_cache()
+    sweep = []
+    for th in [int(x) for x in args.th_sweep.split(",") if x.strip()]:
+        gs = dsbfs.Graph(src, dst, n, threshold=th, keep_plain_csr=False)
+        wss = dsbfs.Workspace(gs)
+        o2 = dsbfs.run_opts(want_parent=parent is not None)
+        dsbfs.bfs(gs, wss, int(sources[0]), depth, parent, opts=o2)
+        tt, rr, byts = [], [], 0
+        for i in range(args.steps):
+            s = int(sources[i % len(sources)])
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            r = dsbfs.bfs(gs, wss, s, depth, parent, opts=opts, want_stats=True, capacity=64)
+            e1.record(stream)
+            e1.synchronize()
+            ms = e0.elapsed_time(e1)
+            tt.append(ms)
+            rr.append(r["edges_cc"] / (ms * 1e-3) / 1e9)
+            byts += sum(k["bytes"] for k in r["kernels"].values())
+        gst = gs.stats
+        sweep.append({"threshold": th, "gteps": round(harmonic(rr), 3),
+                      "ms_per_step": round(sum(tt) / len(tt), 4),
+                      "algorithmic_gbs": round(byts / (sum(tt) * 1e-3) / 1e9, 2),
+                      "d": gst["d"], "e_nn": gst["e_nn"], "e_nd": gst["e_nd"],
+                      "e_dn": gst["e_dn"], "e_dd": gst["e_dd"],
+                      "bytes_layout": gst["bytes_layout"]})
+        log(f"TH {th}: {sweep[-1]['gteps']} GTEPS, d={gst['d']}")
+        wss.destroy()
+        gs.destroy()
+    del depth, parent, src, dst
     torch.cuda.empty_cache()
     batched = bench_batched(args, torch, dsbfs, inputs) if args.batched else None
     torch.cuda.empty_cache()
@@ -225,6 +258,7 @@ def main():
                    "parents": parent is not None, "parallelism": "single GPU"},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "th_sweep": sweep,
         "batched": batched,
         "served": served,
         "detail": {
