@@ -88,6 +88,10 @@ def main():
                     help="1: also measure the query server (5 graphs, 3 Poisson rates)")
     ap.add_argument("--serve-queries", type=int, default=4096)
     ap.add_argument("--serve-scales", default="18,20,22,24")
+    ap.add_argument("--factor-sweep", default="",
+                    help="comma-separated factor0 values tried for each of dd, dn, nd in turn "
+                         "(the other two at their defaults), e.g. 1e-8,1e-6,1e-4,1e-2,0.05,0.5,2,10")
+    ap.add_argument("--factor-steps", type=int, default=16)
     ap.add_argument("--th-sweep", default="16,32,64,128",
                     help="thresholds re-run on the same graph and sources ('' = none)")
     args = ap.parse_args()
@@ -177,6 +181,30 @@ def main():
     all_bytes = sum(k["bytes"] for k in kern.values())
     path_gbs = all_bytes / (sum(times) * 1e-3) / 1e9
 
+    fsweep = []
+    fvals = [float(x) for x in args.factor_sweep.split(",") if x.strip()]
+    base = list(dsbfs.run_opts().factor0)
+    for ki, kname_f in enumerate(("dd", "dn", "nd")):
+        for v in fvals:
+            f0 = list(base)
+            f0[ki] = v
+            o3 = dsbfs.run_opts(want_parent=parent is not None, factor0=f0)
+            tt, rr = [], []
+            for i in range(args.factor_steps):
+                s = int(sources[i % len(sources)])
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                r = dsbfs.bfs(g, ws, s, depth, parent, opts=o3, want_stats=True, capacity=64)
+                e1.record(stream)
+                e1.synchronize()
+                ms = e0.elapsed_time(e1)
+                tt.append(ms)
+                rr.append(r["edges_cc"] / (ms * 1e-3) / 1e9)
+            fsweep.append({"kernel": kname_f, "factor0": v, "gteps": round(harmonic(rr), 3),
+                           "ms_per_step": round(sum(tt) / len(tt), 4)})
+            log(f"factor0[{kname_f}] = {v:g}: {fsweep[-1]['gteps']} GTEPS")
+
     cpu = None
     if args.cpu_sources > 0:
         import oracle
@@ -233,6 +261,7 @@ def main():
         log(f"TH {th}: {sweep[-1]['gteps']} GTEPS, d={gst['d']}")
         wss.destroy()
         gs.destroy()
+    want_parent = parent is not None
     del depth, parent, src, dst
     torch.cuda.empty_cache()
     batched = bench_batched(args, torch, dsbfs, inputs) if args.batched else None
@@ -255,10 +284,11 @@ def main():
         "config": {"workload": f"single-source {'DOBFS' if args.mode == 'do' else 'top-down BFS'}"
                                f", RMAT scale {args.scale} edge factor 16, TH {args.threshold}",
                    "scale": args.scale, "threshold": args.threshold, "sources": len(sources),
-                   "parents": parent is not None, "parallelism": "single GPU"},
+                   "parents": want_parent, "parallelism": "single GPU"},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "th_sweep": sweep,
+        "factor_sweep": fsweep,
         "batched": batched,
         "served": served,
         "detail": {

@@ -524,8 +524,11 @@ static void msbfs_launch(const Graph *g, Workspace *ws, const int32_t *sources, 
       HIPCHK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
       hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
       if (e == hipSuccess) {
-        hipLaunchKernelGGL(k_msbfs, dim3(grid), dim3(o.block), 0, cs, a);
-        e = hipGetLastError();
+        // captured as a cooperative launch, so the runtime still checks that
+        // the whole grid is co-resident when the graph is replayed
+        void *args[] = {&a};
+        e = hipLaunchCooperativeKernel(reinterpret_cast<const void *>(&k_msbfs), dim3(grid),
+                                       dim3(o.block), args, 0, cs);
         hipGraph_t gr = nullptr;
         hipError_t e2 = hipStreamEndCapture(cs, &gr);
         if (e == hipSuccess) e = e2;

@@ -353,10 +353,11 @@ def now_ns() -> int:
 
 class _DevRow:
     """A device int32 vector at a raw address, exposed to torch through the
-    CUDA array interface (no copy)."""
+    CUDA array interface (no copy). torch accepts only writable views; the
+    row stays the library's and callers treat it as read-only."""
 
     def __init__(self, ptr: int, n: int):
-        self.__cuda_array_interface__ = {"shape": (n,), "typestr": "<i4", "data": (ptr, True),
+        self.__cuda_array_interface__ = {"shape": (n,), "typestr": "<i4", "data": (ptr, False),
                                          "version": 2, "strides": None}
 
 

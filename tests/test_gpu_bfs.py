@@ -200,9 +200,9 @@ def test_builder_layout_matches_oracle_split(inputs_mod, oracle_mod, scale, TH):
     nds_off = g.export(12, np.int64)
     nds_col = g.export(13, np.int32)
     np.testing.assert_array_equal(np.diff(nds_off), nd_len[nd_src])
-    for i, v in enumerate(nd_src.tolist()):
+    for i, v in enumerate(nd_src.tolist()):   # the row's own nd part, in the same order
         assert nds_col[nds_off[i]:nds_off[i + 1]].tolist() == \
-            r["nd_col"][r["nd_off"][v]:r["nd_off"][v + 1]].tolist()
+            ncol[ns[v] + nf[v]:ns[v + 1]].tolist()
     words = (d + 31) // 32
     for which, lens in ((8, np.diff(r["dd_off"])), (9, np.diff(r["dn_off"]))):
         m = g.export(which, np.uint32)

@@ -104,20 +104,31 @@ def test_server_budget_admission(inputs_mod, oracle_mod):
     assert e.value.status == d.ERR_BUDGET
     g.destroy()
     S.destroy()
-    # find the resident footprint (first budget that admits the graph), then
-    # allow exactly two result rows
-    foot = None
-    for budget in range(0, 1 << 30, 1 << 16):
+    # find the exact resident footprint (smallest budget that admits the
+    # graph, by bisection), then allow exactly two result rows of 4n bytes
+    def admits(budget):
         S = d.Server(budget, batched=True)
+        g = d.Graph(src, dst, n, threshold=16, keep_plain_csr=True)
         try:
-            gid = S.add_graph(d.Graph(src, dst, n, threshold=16, keep_plain_csr=True))
-            foot = budget
-            break
-        except d.DsbfsError:
+            S.add_graph(g)
+            return True
+        except d.DsbfsError as err:
+            assert err.status == d.ERR_BUDGET
+            g.destroy()
+            return False
+        finally:
             S.destroy()
-    assert foot is not None
-    S.destroy()
-    S = d.Server(foot + 2 * 4 * n + (1 << 16), batched=True)
+
+    lo, hi = 0, 1 << 30
+    assert admits(hi)
+    while hi - lo > 1:
+        mid = (lo + hi) // 2
+        if admits(mid):
+            hi = mid
+        else:
+            lo = mid
+    foot = hi
+    S = d.Server(foot + 3 * 4 * n - 1, batched=True)
     gid = S.add_graph(d.Graph(src, dst, n, threshold=16, keep_plain_csr=True))
     sources = inputs_mod.pick_sources(src, dst, n, 5, seed=3)
     ts = [S.submit(gid, int(s)) for s in sources]
