@@ -2,7 +2,8 @@
 
 Each source compiles to an object under _build/ (in parallel), then all link
 into paper_1803_03922_amd/libdsbfs.so. Also builds the seeded input
-generators (inputs/libdsbfs_inputs.so).
+generators (inputs/libdsbfs_inputs.so) and the copy kernel that calibrates
+the HBM traffic counters (calib/copy_calib).
 
     python -m paper_1803_03922_amd.build_lib
 """
@@ -63,6 +64,15 @@ def build(verbose: bool = False) -> str:
     if r.returncode != 0:
         raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
     os.replace(tmp, LIB)
+    # copy kernel of known size, the calibration for HBM traffic counters
+    calib = os.path.join(PKG, "calib", "copy_calib")
+    cmd = [hipcc(), "-O3", "-std=c++17", f"--offload-arch={ARCH}",
+           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+           os.path.join(PKG, "calib", "copy_calib.hip"), "-o", calib + ".tmp"]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"calibration build failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
+    os.replace(calib + ".tmp", calib)
     from . import inputs
     inputs.build(force=True)
     if verbose:
