@@ -399,14 +399,16 @@ def _poisson_run(dsbfs, server, gids, pools, ncc, rate, nq, seed):
     t_first = min(st["arrival_ns"] for st in stats)
     t_last = max(st["done_ns"] for st in stats)
     edges = sum(ncc[k] for k in which.tolist())
-    return lat, edges / ((t_last - t_first) * 1e-9) / 1e9
+    lanes = sum(st["batched"] for st in stats) / nq
+    return lat, edges / ((t_last - t_first) * 1e-9) / 1e9, lanes
 
 
 def bench_served(args, torch, dsbfs, inputs):
     """Query stream over 5 resident graphs (RMAT 18/20/22/24 + ER 2^22 with
     8n pairs), Poisson arrivals at 0.5, 1 and 2 times the plain server's
-    service rate, served plainly (one query at a time) and with continuous
-    batching; p50/p99 latency and aggregate GTEPS per rate."""
+    service rate, served plainly (one query at a time), with continuous
+    batching, and adaptively (single-source searches while the queue is short,
+    batches once it is long); p50/p99 latency and aggregate GTEPS per rate."""
     specs = [("rmat", int(x)) for x in args.serve_scales.split(",")] + [("er", 22)]
     built = []
     for kind, sc in specs:
@@ -437,19 +439,20 @@ def bench_served(args, torch, dsbfs, inputs):
                        "sources uniform over each graph's giant component",
            "queries_per_rate": args.serve_queries, "rates": []}
     servers = {}
-    for mode in ("plain", "batched"):
+    modes = {"plain": 0, "batched": 1, "adaptive": 2}
+    for mode in modes:
         graphs = [dsbfs.Graph(src, dst, n, threshold=args.threshold, keep_plain_csr=True)
                   for _, _, n, src, dst in built]
         resident = sum(2 * (G.stats["bytes_layout"] + G.stats["bytes_plain"]) + 64 * G.n
                        for G in graphs)
         budget = resident + 4 * 64 * 4 * nmax
-        S = dsbfs.Server(budget, max_lanes=64, batched=(mode == "batched"))
+        S = dsbfs.Server(budget, max_lanes=64, batched=modes[mode])
         gids = [S.add_graph(G) for G in graphs]
         servers[mode] = (S, gids)
         out["hbm_budget_bytes"] = budget
     # plain service rate on this mix
     S, gids = servers["plain"]
-    lat, _ = _poisson_run(dsbfs, S, gids, pools, ncc, 1e6, 256, 4999)
+    _poisson_run(dsbfs, S, gids, pools, ncc, 1e6, 256, 4999)
     t0 = dsbfs.now_ns()
     _poisson_run(dsbfs, S, gids, pools, ncc, 1e9, 512, 4998)
     mu = 512 / ((dsbfs.now_ns() - t0) * 1e-9)
@@ -457,13 +460,13 @@ def bench_served(args, torch, dsbfs, inputs):
     log(f"plain service rate {mu:.0f} queries/s")
     for idx, f in enumerate((0.5, 1.0, 2.0)):
         row = {"rate_factor": f, "rate_qps": round(f * mu, 1)}
-        for mode in ("plain", "batched"):
+        for mode in modes:
             S, gids = servers[mode]
-            lat, gteps = _poisson_run(dsbfs, S, gids, pools, ncc, f * mu, args.serve_queries,
-                                      5000 + idx)
+            lat, gteps, lanes = _poisson_run(dsbfs, S, gids, pools, ncc, f * mu,
+                                             args.serve_queries, 5000 + idx)
             row[mode] = {"p50_ms": round(float(np.percentile(lat, 50)), 3),
                          "p99_ms": round(float(np.percentile(lat, 99)), 3),
-                         "gteps": round(gteps, 2)}
+                         "gteps": round(gteps, 2), "share_as_lanes": round(lanes, 3)}
             log(f"rate {f} x mu, {mode}: p50 {row[mode]['p50_ms']} ms, "
                 f"p99 {row[mode]['p99_ms']} ms, {row[mode]['gteps']} GTEPS")
         out["rates"].append(row)

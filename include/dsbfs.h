@@ -281,7 +281,11 @@ typedef struct dsbfs_server_opts {
   size_t hbm_budget_bytes; /* cap on graphs + lane state + result buffers */
   int32_t max_lanes;       /* lanes per running batch, 1..64 */
   int32_t batched;         /* 1: continuous batching into multi-source lanes;
-                              0: one query at a time with single-source BFS */
+                              0: one query at a time with single-source BFS;
+                              2: adaptive: a graph with no batch running serves
+                                 its queue one query at a time while that is
+                                 cheaper than one batch (measured per graph),
+                                 else batches as in 1 */
   dsbfs_ms_opts ms;        /* kernel parameters of the batched path */
 } dsbfs_server_opts;
 

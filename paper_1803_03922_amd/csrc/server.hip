@@ -7,9 +7,17 @@
 //     complete their queries, and waiting queries take the free lanes at once
 //     (their lane bits are cleared, their result rows filled with -1, their
 //     sources seeded), so requests that arrive while others are running join
-//     the work already on the GPU. All graphs with work advance one level per
-//     round, each on its own stream, so their levels overlap on the device.
+//     the work already on the GPU. Each graph advances on its own stream and
+//     at its own pace: a graph whose level has finished is relaunched at
+//     once, so the levels of different graphs overlap on the device and a
+//     small graph never waits for a large one.
 //   plain mode: one query at a time, single-source direction-optimized BFS.
+//   adaptive mode: batched, except that a graph with no batch running serves
+//     a short queue one query at a time with single-source DOBFS. A batch is
+//     opened once serving the waiting queries one by one would take longer
+//     than one batch: queue length x (measured time of one single-source
+//     search) >= (measured time of one batched level) x (measured levels per
+//     query). Both times are running averages kept per graph.
 // Admission is bounded by an HBM budget: graph layouts and lane state are
 // charged when a graph is added, and every result row (int32[n]) while it is
 // held; a query waits for budget, and one that can never fit is refused.
@@ -95,7 +103,14 @@ struct GState {
   size_t bytes = 0;
   bool launched = false;
   uint64_t new_lanes = 0;
+  // adaptive mode: cost model and the query served alone this round
+  hipEvent_t ev0 = nullptr;
+  double t_single_ms = 0, t_level_ms = 0, levels_per_query = 0;
+  Query *single = nullptr;
 };
+
+// running average with weight 1/4 for the newest sample (first sample taken as is)
+void ema(double &avg, double x) { avg = avg > 0 ? 0.75 * avg + 0.25 * x : x; }
 
 }  // namespace
 
@@ -154,89 +169,166 @@ struct Server {
     return false;
   }
 
+  // Adaptive mode: should G (no batch running) serve its head query alone?
+  bool serve_alone(const GState *G) const {
+    if (G->t_single_ms <= 0) return true;  // nothing measured yet: a single search measures it
+    // until a batched level has been timed, assume a batch costs 8 single searches
+    const double batch_ms = G->t_level_ms > 0 && G->levels_per_query > 0
+                                ? G->t_level_ms * G->levels_per_query
+                                : 8.0 * G->t_single_ms;
+    return double(G->pending.size()) * G->t_single_ms < batch_ms;
+  }
+
+  // Admits waiting queries of G at its level boundary (caller holds mu):
+  // in adaptive mode the head query alone when that is cheaper, else into
+  // free lanes.
+  void admit(GState *G, uint64_t lane_cap, bool adaptive, int64_t t) {
+    G->new_lanes = 0;
+    if (adaptive && !G->used && !G->pending.empty() && serve_alone(G)) {
+      Query *q = G->pending.front();
+      int32_t *row = take_row(G);
+      if (!row) return;  // budget: wait for releases
+      G->pending.pop_front();
+      q->res = row;
+      q->admit = q->start = t;
+      q->state = Q_RUNNING;
+      q->batched = 0;
+      G->single = q;
+      return;
+    }
+    uint64_t free = ~G->used & lane_cap;
+    while (free && !G->pending.empty()) {
+      Query *q = G->pending.front();
+      int32_t *row = take_row(G);
+      if (!row) break;  // budget: wait for releases
+      G->pending.pop_front();
+      const int i = __builtin_ctzll(free);
+      free &= free - 1;
+      q->res = row;
+      q->admit = q->start = t;
+      q->state = Q_RUNNING;
+      q->batched = 1;
+      G->lane[i] = q;
+      G->start_level[i] = G->L;
+      G->seed_host[i] = q->source;
+      G->new_lanes |= 1ull << i;
+    }
+    G->used |= G->new_lanes;
+  }
+
+  // Enqueues one multi-source level of G on its stream.
+  void launch_level(GState *G) {
+    LaneRows r{};
+    for (int i = 0; i < 64; ++i) {
+      r.res[i] = G->lane[i] ? G->lane[i]->res : nullptr;
+      r.dval[i] = G->L + 1 - G->start_level[i];
+    }
+    HIPCHK(hipEventRecord(G->ev0, G->stream));
+    if (G->new_lanes) {
+      HIPCHK(hipMemcpyAsync(G->seed_dev, G->seed_host, 64 * sizeof(int32_t),
+                            hipMemcpyHostToDevice, G->stream));
+      ms_level_recycle(G->g, G->ws, G->new_lanes, G->new_lanes, G->new_lanes, G->seed_dev, r,
+                       G->stream);
+      G->live |= G->new_lanes;
+      G->active += __builtin_popcountll(G->new_lanes);
+      G->new_lanes = 0;
+    }
+    ms_level(G->g, G->ws, G->live, G->active, o.ms.bu_permille, r, G->ctl_dev, G->stream);
+    HIPCHK(hipMemcpyAsync(G->ctl_host, G->ctl_dev, 4 * sizeof(unsigned long long),
+                          hipMemcpyDeviceToHost, G->stream));
+    HIPCHK(hipEventRecord(G->ev, G->stream));
+    G->launched = true;
+  }
+
+  // Level of G done on the device: complete the lanes whose frontier ran empty.
+  void complete_level(GState *G) {
+    const int64_t t = now_ns();
+    float level_ms = 0;
+    HIPCHK(hipEventElapsedTime(&level_ms, G->ev0, G->ev));
+    ema(G->t_level_ms, double(level_ms));
+    const uint64_t alive = G->ctl_host[1];
+    std::lock_guard<std::mutex> lk(mu);
+    uint64_t fin = G->used & ~alive;
+    while (fin) {
+      const int i = __builtin_ctzll(fin);
+      fin &= fin - 1;
+      Query *q = G->lane[i];
+      q->levels = G->L + 1 - G->start_level[i];
+      ema(G->levels_per_query, double(q->levels));
+      finish(q, G, t);
+      G->lane[i] = nullptr;
+      G->used &= ~(1ull << i);
+    }
+    G->live = alive & G->used;
+    G->active = int64_t(G->ctl_host[0]);
+    G->L += 1;
+    G->launched = false;
+  }
+
+  // Every graph advances on its own: a graph whose level finished is admitted
+  // into and relaunched at once, without waiting for the other graphs.
   void loop_batched() {
     const uint64_t lane_cap = o.max_lanes >= 64 ? ~0ull : ((1ull << o.max_lanes) - 1ull);
+    const bool adaptive = o.batched == 2;
+    dsbfs_run_opts ro{};
+    run_opts_default(&ro);
+    ro.want_parent = 0;
     while (true) {
+      bool in_flight = false;
+      for (const GState *G : graphs) in_flight = in_flight || G->launched;
       {
         std::unique_lock<std::mutex> lk(mu);
-        cv_work.wait(lk, [&] { return stop || has_work(); });
+        if (!in_flight) cv_work.wait(lk, [&] { return stop || has_work(); });
         if (stop) return;
-        // admission into free lanes at this level boundary
         const int64_t t = now_ns();
-        for (GState *G : graphs) {
-          G->new_lanes = 0;
-          uint64_t free = ~G->used & lane_cap;
-          while (free && !G->pending.empty()) {
-            Query *q = G->pending.front();
-            int32_t *row = take_row(G);
-            if (!row) break;  // budget: wait for releases
-            G->pending.pop_front();
-            const int i = __builtin_ctzll(free);
-            free &= free - 1;
-            q->res = row;
-            q->admit = q->start = t;
-            q->state = Q_RUNNING;
-            q->batched = 1;
-            G->lane[i] = q;
-            G->start_level[i] = G->L;
-            G->seed_host[i] = q->source;
-            G->new_lanes |= 1ull << i;
-          }
-          G->used |= G->new_lanes;
+        for (GState *G : graphs)
+          if (!G->launched && !G->single) admit(G, lane_cap, adaptive, t);
+      }
+      bool started = false;
+      for (GState *G : graphs)
+        if (!G->launched && G->used) {
+          launch_level(G);
+          started = true;
         }
-      }
-      bool any = false;
-      for (GState *G : graphs) any = any || G->used;
-      if (!any) {
-        // waiting queries but no budget for their rows: wait for a release
-        std::unique_lock<std::mutex> lk(mu);
-        cv_work.wait_for(lk, std::chrono::milliseconds(1));
-        continue;
-      }
-      // one level on every graph with lanes in use, each on its own stream
+      // queries served alone run while the levels of other graphs are in flight
+      bool progressed = false;
       for (GState *G : graphs) {
-        G->launched = false;
-        if (!G->used) continue;
-        LaneRows r{};
-        for (int i = 0; i < 64; ++i) {
-          r.res[i] = G->lane[i] ? G->lane[i]->res : nullptr;
-          r.dval[i] = G->L + 1 - G->start_level[i];
-        }
-        if (G->new_lanes) {
-          HIPCHK(hipMemcpyAsync(G->seed_dev, G->seed_host, 64 * sizeof(int32_t),
-                                hipMemcpyHostToDevice, G->stream));
-          ms_level_recycle(G->g, G->ws, G->new_lanes, G->new_lanes, G->new_lanes, G->seed_dev, r,
-                           G->stream);
-          G->live |= G->new_lanes;
-          G->active += __builtin_popcountll(G->new_lanes);
-        }
-        ms_level(G->g, G->ws, G->live, G->active, o.ms.bu_permille, r, G->ctl_dev, G->stream);
-        HIPCHK(hipMemcpyAsync(G->ctl_host, G->ctl_dev, 4 * sizeof(unsigned long long),
-                              hipMemcpyDeviceToHost, G->stream));
-        HIPCHK(hipEventRecord(G->ev, G->stream));
-        G->launched = true;
+        Query *q = G->single;
+        if (!q) continue;
+        dsbfs_run_stats rs{};
+        const int64_t t0 = now_ns();
+        bfs_run(G->g, G->ws, q->source, &ro, q->res, nullptr, &rs, G->stream);
+        HIPCHK(hipStreamSynchronize(G->stream));
+        const int64_t t = now_ns();
+        ema(G->t_single_ms, double(t - t0) * 1e-6);
+        ema(G->levels_per_query, double(rs.num_levels));
+        std::lock_guard<std::mutex> lk(mu);
+        q->levels = rs.num_levels;
+        finish(q, G, t);
+        G->single = nullptr;
+        progressed = true;
       }
       for (GState *G : graphs) {
         if (!G->launched) continue;
-        HIPCHK(hipEventSynchronize(G->ev));
-        const int64_t t = now_ns();
-        const uint64_t alive = G->ctl_host[1];
-        std::lock_guard<std::mutex> lk(mu);
-        uint64_t fin = G->used & ~alive;
-        while (fin) {
-          const int i = __builtin_ctzll(fin);
-          fin &= fin - 1;
-          Query *q = G->lane[i];
-          q->levels = G->L + 1 - G->start_level[i];
-          finish(q, G, t);
-          G->lane[i] = nullptr;
-          G->used &= ~(1ull << i);
-        }
-        G->live = alive & G->used;
-        G->active = int64_t(G->ctl_host[0]);
-        G->L += 1;
+        const hipError_t e = hipEventQuery(G->ev);
+        if (e == hipErrorNotReady) continue;
+        HIPCHK(e);
+        complete_level(G);
+        progressed = true;
       }
-      cv_done.notify_all();
+      if (progressed) {
+        cv_done.notify_all();
+        continue;
+      }
+      in_flight = false;
+      for (const GState *G : graphs) in_flight = in_flight || G->launched;
+      if (in_flight) {
+        if (!started) std::this_thread::sleep_for(std::chrono::microseconds(20));
+      } else {
+        // waiting queries but no budget for their rows: wait for a release
+        std::unique_lock<std::mutex> lk(mu);
+        cv_work.wait_for(lk, std::chrono::milliseconds(1));
+      }
     }
   }
 
@@ -295,6 +387,8 @@ struct Server {
 Server *server_create(const dsbfs_server_opts *o, const dsbfs_allocator *alloc) {
   if (o->max_lanes < 1 || o->max_lanes > 64)
     fail(DSBFS_ERR_INVALID_ARG, "max_lanes must be in [1, 64]");
+  if (o->batched < 0 || o->batched > 2)
+    fail(DSBFS_ERR_INVALID_ARG, "batched must be 0 (plain), 1 (batched) or 2 (adaptive)");
   if (o->ms.bu_permille < 0 || o->ms.bu_permille > 1000)
     fail(DSBFS_ERR_INVALID_ARG, "ms.bu_permille must be in [0, 1000]");
   (void)alloc;  // result rows come from hipMalloc: the scheduler thread never calls back
@@ -312,7 +406,8 @@ void server_add_graph(Server *S, Graph *g, int32_t *id) {
   try {
     G->g = g;
     HIPCHK(hipStreamCreateWithFlags(&G->stream, hipStreamNonBlocking));
-    HIPCHK(hipEventCreateWithFlags(&G->ev, hipEventDisableTiming));
+    HIPCHK(hipEventCreate(&G->ev));
+    HIPCHK(hipEventCreate(&G->ev0));
     G->ws = workspace_create(g, 64);
     if (S->o.batched) ms_level_prepare(g, G->ws, G->stream);
     HIPCHK(hipMalloc(reinterpret_cast<void **>(&G->ctl_dev), 4 * sizeof(unsigned long long)));
@@ -336,6 +431,7 @@ void server_add_graph(Server *S, Graph *g, int32_t *id) {
     if (G->seed_dev) (void)hipFree(G->seed_dev);
     if (G->seed_host) (void)hipHostFree(G->seed_host);
     if (G->ev) (void)hipEventDestroy(G->ev);
+    if (G->ev0) (void)hipEventDestroy(G->ev0);
     if (G->stream) (void)hipStreamDestroy(G->stream);
     delete G;
     throw;
@@ -425,6 +521,7 @@ void server_destroy(Server *S) {
     (void)hipFree(G->seed_dev);
     (void)hipHostFree(G->seed_host);
     (void)hipEventDestroy(G->ev);
+    (void)hipEventDestroy(G->ev0);
     (void)hipStreamDestroy(G->stream);
     delete G;
   }

@@ -369,12 +369,15 @@ def device_row(ptr: int, n: int):
 class Server:
     """Continuous-batching query server (dsbfs_server)."""
 
-    def __init__(self, budget_bytes: int, max_lanes: int = 64, batched: bool = True,
+    PLAIN, BATCHED, ADAPTIVE = 0, 1, 2
+
+    def __init__(self, budget_bytes: int, max_lanes: int = 64, batched: bool | int = True,
                  ms: dsbfs_ms_opts | None = None):
+        """batched: False/0 plain, True/1 continuous batching, 2 adaptive."""
         o = dsbfs_server_opts()
         o.hbm_budget_bytes = int(budget_bytes)
         o.max_lanes = max_lanes
-        o.batched = int(bool(batched))
+        o.batched = int(batched)
         o.ms = ms if ms is not None else dsbfs_ms_opts(256, 4, 2, 0)
         h = vp()
         check(dsbfs_server_create(ctypes.byref(o), None, ctypes.byref(h)), "dsbfs_server_create")

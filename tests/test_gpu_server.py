@@ -1,6 +1,6 @@
 """GPU tests of the query server: every served result equals the oracle, the
 same query gives the same result alone and in a mix (continuous batching),
-plain and batched modes agree, admission follows the HBM budget, and errors
+plain, batched and adaptive modes agree, admission follows the HBM budget, and errors
 are reported as status codes."""
 import time
 
@@ -44,7 +44,7 @@ def _fetch(S, ticket, n):
     return row, st
 
 
-@pytest.mark.parametrize("batched", [True, False])
+@pytest.mark.parametrize("batched", [1, 0, 2])
 def test_server_mix_matches_oracle(inputs_mod, oracle_mod, batched):
     specs = _graphs(inputs_mod, oracle_mod)
     S, gids = _server(specs, batched)
@@ -63,8 +63,38 @@ def test_server_mix_matches_oracle(inputs_mod, oracle_mod, batched):
         want, _ = O.bfs(s, want_parent=False)
         np.testing.assert_array_equal(row, want, err_msg=f"graph {k} source {s}")
         assert st["done_ns"] >= st["start_ns"] >= st["admit_ns"] >= st["arrival_ns"] > 0
-        assert st["batched"] == int(batched)
+        assert st["batched"] == int(batched) or (batched == 2 and st["batched"] in (0, 1))
     S.destroy()
+
+
+def test_server_adaptive_uses_both_forms(inputs_mod, oracle_mod):
+    """Adaptive mode: a lone query runs as a single-source search; a burst of
+    48 queries on one graph opens a batch. Every row equals the oracle's."""
+    specs = _graphs(inputs_mod, oracle_mod)
+    S, gids = _server(specs, 2)
+    n, src, dst, O = specs[1]
+    srcs = inputs_mod.pick_sources(src, dst, n, 49, seed=31).tolist()
+    row, st = _fetch(S, S.submit(gids[1], int(srcs[0])), n)
+    assert st["batched"] == 0
+    np.testing.assert_array_equal(row, O.bfs(int(srcs[0]), want_parent=False)[0])
+    tickets = [S.submit(gids[1], int(s)) for s in srcs[1:]]
+    forms = []
+    for s, t in zip(srcs[1:], tickets):
+        row, st = _fetch(S, t, n)
+        forms.append(st["batched"])
+        np.testing.assert_array_equal(row, O.bfs(int(s), want_parent=False)[0],
+                                      err_msg=f"source {s}")
+    log(f"adaptive burst: {sum(forms)} of {len(forms)} queries ran as lanes")
+    assert sum(forms) > 0
+    S.destroy()
+
+
+def test_server_rejects_unknown_mode():
+    d = lib()
+    torch_cuda()
+    with pytest.raises(d.DsbfsError) as e:
+        d.Server(BIG, batched=3)
+    assert e.value.status == d.ERR_INVALID_ARG
 
 
 def test_server_alone_equals_in_mix(inputs_mod, oracle_mod):
