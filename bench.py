@@ -92,6 +92,9 @@ def main():
                     help="comma-separated factor0 values tried for each of dd, dn, nd in turn "
                          "(the other two at their defaults), e.g. 1e-8,1e-6,1e-4,1e-2,0.05,0.5,2,10")
     ap.add_argument("--factor-steps", type=int, default=16)
+    ap.add_argument("--factor-grid", default="",
+                    help="joint sweep: 'dd values;dn values;nd values', each comma-separated; "
+                         "every combination is timed over --factor-steps sources")
     ap.add_argument("--th-sweep", default="16,32,64,128",
                     help="thresholds re-run on the same graph and sources ('' = none)")
     args = ap.parse_args()
@@ -181,6 +184,22 @@ def main():
     all_bytes = sum(k["bytes"] for k in kern.values())
     path_gbs = all_bytes / (sum(times) * 1e-3) / 1e9
 
+    def time_factors(f0):
+        o3 = dsbfs.run_opts(want_parent=parent is not None, factor0=f0)
+        tt, rr = [], []
+        for i in range(args.factor_steps):
+            s = int(sources[i % len(sources)])
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            r = dsbfs.bfs(g, ws, s, depth, parent, opts=o3, want_stats=True, capacity=64)
+            e1.record(stream)
+            e1.synchronize()
+            ms = e0.elapsed_time(e1)
+            tt.append(ms)
+            rr.append(r["edges_cc"] / (ms * 1e-3) / 1e9)
+        return round(harmonic(rr), 3), round(sum(tt) / len(tt), 4)
+
     fsweep = []
     fvals = [float(x) for x in args.factor_sweep.split(",") if x.strip()]
     base = list(dsbfs.run_opts().factor0)
@@ -188,22 +207,17 @@ def main():
         for v in fvals:
             f0 = list(base)
             f0[ki] = v
-            o3 = dsbfs.run_opts(want_parent=parent is not None, factor0=f0)
-            tt, rr = [], []
-            for i in range(args.factor_steps):
-                s = int(sources[i % len(sources)])
-                e0 = torch.cuda.Event(enable_timing=True)
-                e1 = torch.cuda.Event(enable_timing=True)
-                e0.record(stream)
-                r = dsbfs.bfs(g, ws, s, depth, parent, opts=o3, want_stats=True, capacity=64)
-                e1.record(stream)
-                e1.synchronize()
-                ms = e0.elapsed_time(e1)
-                tt.append(ms)
-                rr.append(r["edges_cc"] / (ms * 1e-3) / 1e9)
-            fsweep.append({"kernel": kname_f, "factor0": v, "gteps": round(harmonic(rr), 3),
-                           "ms_per_step": round(sum(tt) / len(tt), 4)})
-            log(f"factor0[{kname_f}] = {v:g}: {fsweep[-1]['gteps']} GTEPS")
+            gt, mss = time_factors(f0)
+            fsweep.append({"kernel": kname_f, "factor0": v, "gteps": gt, "ms_per_step": mss})
+            log(f"factor0[{kname_f}] = {v:g}: {gt} GTEPS")
+    if args.factor_grid:
+        import itertools
+        axes = [[float(x) for x in part.split(",") if x.strip()]
+                for part in args.factor_grid.split(";")]
+        for f0 in itertools.product(*axes):
+            gt, mss = time_factors(list(f0))
+            fsweep.append({"factor0": list(f0), "gteps": gt, "ms_per_step": mss})
+            log(f"factor0 = {list(f0)}: {gt} GTEPS, {mss} ms")
 
     cpu = None
     if args.cpu_sources > 0:

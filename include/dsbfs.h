@@ -88,13 +88,27 @@ typedef struct dsbfs_graph_stats {
   int32_t reserved;
 } dsbfs_graph_stats;
 
+/*
+ * Direction-switch factors printed in Section VI-B for (dd, dn, nd), tuned
+ * there for the paper's layout and GPUs. The library's defaults differ (see
+ * dsbfs_run_opts.factor0); pass these to reproduce the paper's schedule.
+ */
+#define DSBFS_PAPER_FACTOR0_DD 0.5
+#define DSBFS_PAPER_FACTOR0_DN 0.05
+#define DSBFS_PAPER_FACTOR0_ND 1e-7
+
 /* Per-search options. */
 typedef struct dsbfs_run_opts {
   int32_t mode;         /* 0: plain top-down BFS on the plain CSR;
                            1: degree-separated direction-optimized BFS */
   int32_t want_parent;  /* 1: write parent[] as well as depth[] */
   double factor0[3];    /* forward->backward switch factors for dd, dn, nd
-                           (Section IV-B); defaults 0.5, 0.05, 1e-7 (Section VI-B) */
+                           (Section IV-B). Defaults 0.05, 0.5, 1e-6: a joint
+                           sweep on this layout (rows ordered by decreasing
+                           neighbour degree, so bottom-up finds a parent
+                           sooner than the paper's BV model assumes) on
+                           RMAT scale 26, TH 32. The paper's values are the
+                           DSBFS_PAPER_FACTOR0_* constants. */
   double factor1[3];    /* backward->forward switch factors; default 0 */
   int32_t forced;       /* direction schedule: 0 heuristic (Section IV-B);
                            1 always forward; 2 backward wherever possible from

@@ -704,9 +704,10 @@ static dsbfs_run_opts default_opts() {
   dsbfs_run_opts o{};
   o.mode = 1;
   o.want_parent = 1;
-  o.factor0[0] = 0.5;
-  o.factor0[1] = 0.05;
-  o.factor0[2] = 1e-7;
+  // tuned for this layout (see the header); the paper's are DSBFS_PAPER_FACTOR0_*
+  o.factor0[0] = 0.05;
+  o.factor0[1] = 0.5;
+  o.factor0[2] = 1e-6;
   o.factor1[0] = o.factor1[1] = o.factor1[2] = 0.0;
   o.forced = 0;
   o.forced_seed = 0;

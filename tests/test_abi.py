@@ -34,12 +34,16 @@ def test_status_strings():
     assert dsbfs.dsbfs_status_str(-99) == b"unknown status"
 
 
-def test_default_factors_match_paper():
-    """Defaults are the paper's tuned factors (Section VI-B) in dd, dn, nd order."""
+def test_default_factors():
+    """Defaults are the factors tuned for this layout, in dd, dn, nd order;
+    the header also carries the paper's (Section VI-B) as named constants."""
     from paper_1803_03922_amd import dsbfs
     o = dsbfs.dsbfs_run_opts()
     assert dsbfs.dsbfs_run_opts_default(ctypes.byref(o)) == 0
-    assert list(o.factor0) == [0.5, 0.05, 1e-7]
+    assert list(o.factor0) == [0.05, 0.5, 1e-6]
+    hdr = open(os.path.join(os.path.dirname(__file__), "..", "include", "dsbfs.h")).read()
+    paper = {k: float(v) for k, v in re.findall(r"#define DSBFS_PAPER_FACTOR0_(\w+) (\S+)", hdr)}
+    assert paper == {"DD": 0.5, "DN": 0.05, "ND": 1e-7}
     assert list(o.factor1) == [0.0, 0.0, 0.0]
     assert o.mode == 1 and o.want_parent == 1 and o.forced == 0
 
