@@ -278,8 +278,9 @@ __global__ void __launch_bounds__(kBS) k_normal_level(const int32_t *Q, const Le
       q_nn += nn > 0;
       fv_nd += nd;
       q_nd += nd > 0;
-      if (mark_fn) atomicOr(&Fn[u >> 5], 1u << (u & 31));
     }
+    // queues filled by the bottom-up pass are in ascending order: mark word by word
+    if (mark_fn) wave_bit_set(Fn, uint32_t(u), i < qn, true);
     expand_normal_rows<0>(u, nn, beg, s_excl[w], s_u[w], s_beg[w], ncol, nullptr, out, Vn,
                           nullptr, qa, edges, claimed);
     qa.maybe_flush(kBS * 2);
@@ -484,15 +485,12 @@ __global__ void __launch_bounds__(kBS) k_bu_normal(const int32_t *cin, int dense
     }
     const int32_t fe = s_found[w][l];
     const bool found = hit0 >= 0 || (len > 0 && fe != kNone);
-    bool won = false;
-    if (found) {
+    // candidates come in ascending vertex order: claim word by word
+    const bool won = wave_bit_claim(Vn, uint32_t(v), ok, found);
+    if (won) {
       const int32_t k = hit0 >= 0 ? hit0 : nds_col[beg + (fe - (incl - len))];
-      const uint32_t bit = 1u << (v & 31);
-      won = !(atomicOr(&Vn[v >> 5], bit) & bit);
-      if (won) {
-        out.put(v, vid_of[k]);
-        ++claimed;
-      }
+      out.put(v, vid_of[k]);
+      ++claimed;
     }
     qa.push(won, v);
     ca.push(ok && !visited && !found, pos);

@@ -183,6 +183,72 @@ __device__ __forceinline__ bool bit_claim(uint32_t *bm, uint32_t v) {
   return !(atomicOr(&bm[v >> 5], b) & b);
 }
 
+// Wave-cooperative bitmap update for lanes whose bits tend to share words
+// (vertices visited in ascending order). Adjacent lanes with the same word
+// form a run; a segmented OR-scan combines the run's bits and the run's last
+// lane issues the one atomicOr. Atomics on one word from many lanes of one
+// instruction serialize in the cache, so this is several times faster than a
+// per-lane atomicOr on ascending patterns. Must be called by the whole wave.
+//   claim: returns true for exactly one lane per bit that was 0 before the
+//   call (a bit wanted by several lanes of one run goes to the lowest lane).
+struct WaveBits {
+  uint32_t word, bit, incl, old;
+  bool want;
+  // valid: v is a vertex (its word joins a run even without a bit, so the
+  // runs of an ascending list are not cut by lanes that want nothing)
+  __device__ __forceinline__ void run(uint32_t *bm, uint32_t v, bool valid, bool w,
+                                      bool need_old) {
+    const int l = lane_id();
+    want = valid && w;
+    word = valid ? (v >> 5) : 0xffffffffu;
+    bit = want ? (1u << (v & 31)) : 0u;
+    const uint32_t prev_word = __shfl_up(word, 1, kWave);
+    const uint32_t next_word = __shfl_down(word, 1, kWave);
+    const bool head = l == 0 || prev_word != word;
+    const bool tail = l == kWave - 1 || next_word != word;
+    // segmented inclusive OR-scan: incl = OR of bits from the run's head to this lane
+    incl = bit;
+    uint32_t f = head;
+    for (int o = 1; o < kWave; o <<= 1) {
+      const uint32_t ti = __shfl_up(incl, o, kWave);
+      const uint32_t tf = __shfl_up(f, o, kWave);
+      if (l >= o) {
+        if (!f) incl |= ti;
+        f |= tf;
+      }
+    }
+    old = 0;
+    if (tail && word != 0xffffffffu && incl) old = atomicOr(&bm[word], incl);
+    if (need_old) {
+      // nearest tail at or after this lane is the run's tail
+      uint32_t tp = tail ? uint32_t(l) : uint32_t(kWave);
+      for (int o = 1; o < kWave; o <<= 1) {
+        const uint32_t t = __shfl_down(tp, o, kWave);
+        if (l + o < kWave) tp = min(tp, t);
+      }
+      old = __shfl(old, int(tp), kWave);
+    }
+  }
+  // true iff this lane set its bit first (bit was 0 and no lower lane of the run wanted it)
+  __device__ __forceinline__ bool won() const {
+    const uint32_t before = __shfl_up(incl, 1, kWave);
+    const bool head = lane_id() == 0 || __shfl_up(word, 1, kWave) != word;
+    const uint32_t excl = head ? 0u : before;
+    return want && !(old & bit) && !(excl & bit);
+  }
+};
+
+__device__ __forceinline__ bool wave_bit_claim(uint32_t *bm, uint32_t v, bool valid, bool want) {
+  WaveBits wb;
+  wb.run(bm, v, valid, want, true);
+  return wb.won();
+}
+
+__device__ __forceinline__ void wave_bit_set(uint32_t *bm, uint32_t v, bool valid, bool want) {
+  WaveBits wb;
+  wb.run(bm, v, valid, want, false);
+}
+
 // Orders LDS traffic of one wave around a point where lanes read what other
 // lanes of the same wave wrote.
 __device__ __forceinline__ void wave_sync() {
