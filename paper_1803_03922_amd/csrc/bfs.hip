@@ -146,9 +146,10 @@ __global__ void __launch_bounds__(kBS) k_prev_deleg(const uint32_t *Fd, int32_t 
   block_add4(&cur->fv_dd, fv_dd, q_dd, fv_dn, q_dn, sh);
 }
 
-// Unvisited delegates with an edge in a subgraph scanned bottom-up this level
-// (dd part if dd_bu, dn part if nd_bu) -> dcand, ascending.
-__global__ void __launch_bounds__(kBS) k_dcand(const uint32_t *Vd, const uint32_t *ddm,
+// Unclaimed delegates (not visited and not claimed earlier in this level)
+// with an edge in a subgraph scanned bottom-up this level (dd part if dd_bu,
+// dn part if nd_bu) -> dcand, ascending.
+__global__ void __launch_bounds__(kBS) k_dcand(const uint32_t *Cd, const uint32_t *ddm,
                                                const uint32_t *dnm, int32_t dwords, int dd_bu,
                                                int nd_bu, int32_t *dcand, LevelCtr *cur) {
   __shared__ int shc[kNW];
@@ -157,7 +158,7 @@ __global__ void __launch_bounds__(kBS) k_dcand(const uint32_t *Vd, const uint32_
        w0 += int64_t(gridDim.x) * blockDim.x) {
     const int64_t w = w0 + threadIdx.x;
     uint32_t c = 0;
-    if (w < dwords) c = ~Vd[w] & ((dd_bu ? ddm[w] : 0u) | (nd_bu ? dnm[w] : 0u));
+    if (w < dwords) c = ~Cd[w] & ((dd_bu ? ddm[w] : 0u) | (nd_bu ? dnm[w] : 0u));
     int tc;
     const int ec = block_excl_scan_i32(__popc(c), shc, &tc);
     if (threadIdx.x == 0) base = tc ? atomicAdd(&cur->nd_cand, (unsigned long long)tc) : 0ull;
@@ -506,62 +507,85 @@ __global__ void __launch_bounds__(kBS) k_bu_normal(const int32_t *cin, int dense
   block_add4(cur->units[DSBFS_K_BU_NORMAL], reads, scanned, edges, claimed, sh);
 }
 
-// Bottom-up dd and/or nd (destination: delegates). Groups of 16 lanes take
-// one unvisited delegate each (4 per wave); a group reads 16 row entries per
-// step (dd part against Fd, dn part against the normal frontier bitmap Fn)
-// and stops at the first hit.
-constexpr int kGroup = 16;
-
+// Bottom-up dd and/or nd (destination: delegates). One unvisited delegate
+// per lane: it first tests the first entry of its scanned range (dd parts
+// start with their highest-degree neighbour, the likeliest to be in the
+// frontier); the rows that miss are then walked together, 64 entries per step
+// over their concatenation (prefix sums across the wave), until each has a
+// hit or ends. dd entries are tested against Fd, dn entries against the
+// normal frontier bitmap Fn. Candidates are ascending, so claims go word by
+// word.
 __global__ void __launch_bounds__(kBS) k_bu_deleg(const int32_t *dcand, const LevelCtr *curc,
                                                   const uint64_t *doff, const int32_t *dcol,
                                                   const uint32_t *Fd, const uint32_t *Fn,
                                                   const int32_t *vid_of, int dd_bu, int nd_bu,
                                                   Out out, uint32_t *Cd, LevelCtr *cur) {
+  __shared__ int32_t s_excl[kNW][kWave];
+  __shared__ int32_t s_found[kNW][kWave];
+  __shared__ int64_t s_beg[kNW][kWave];
+  __shared__ int64_t s_mid[kNW][kWave];
   __shared__ unsigned long long sh[4 * kNW];
   const int64_t nc = int64_t(curc->nd_cand);
-  const int l = lane_id(), gi = l / kGroup, gl = l % kGroup;
-  const int64_t wid = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) / kWave;
-  const int64_t nw = int64_t(gridDim.x) * blockDim.x / kWave;
-  const int per = kWave / kGroup;
+  const int w = threadIdx.x / kWave, l = lane_id();
+  constexpr int32_t kNone = 0x7fffffff;
   unsigned long long cands = 0, edges = 0, claimed = 0;
-  for (int64_t c0 = wid * per; c0 < nc; c0 += nw * per) {
-    const int64_t ci = c0 + gi;
-    int32_t k = 0;
-    int64_t p = 0, mid = 0, hi = 0;
-    if (ci < nc) {
-      k = dcand[ci];
+  for (int64_t b0 = int64_t(blockIdx.x) * blockDim.x; b0 < nc;
+       b0 += int64_t(gridDim.x) * blockDim.x) {
+    const int64_t i = b0 + threadIdx.x;
+    const bool ok = i < nc;
+    int32_t k = 0, len = 0;
+    int64_t p = 0, mid = 0, hit = -1;
+    if (ok) {
+      k = dcand[i];
       const uint64_t w0 = doff[k], w1 = doff[k + 1];
-      const int64_t beg = row_start(w0), end = row_start(w1);
+      const int64_t beg = row_start(w0);
       mid = beg + row_first(w0);
       p = dd_bu ? beg : mid;
-      hi = nd_bu ? end : mid;
-      if (gl == 0 && p < hi) ++cands;
+      const int64_t hi = nd_bu ? row_start(w1) : mid;
+      if (p < hi) {
+        ++cands;
+        const int32_t x = dcol[p];
+        ++edges;
+        if (p < mid ? bit_test(Fd, uint32_t(x)) : bit_test(Fn, uint32_t(x))) hit = p;
+        else ++p;
+        // delegate degrees are below 2^24, so 64 rows sum below 2^31
+        if (hit < 0) len = int32_t(hi - p);
+      }
     }
-    bool active = p < hi;
-    while (__ballot(active)) {
-      bool hit = false;
-      int32_t x = 0;
-      const int64_t q = p + gl;
-      if (active && q < hi) {
-        x = dcol[q];
-        hit = q < mid ? bit_test(Fd, uint32_t(x)) : bit_test(Fn, uint32_t(x));
-      }
-      const uint32_t gm = uint32_t(__ballot(hit) >> (gi * kGroup)) & 0xffffu;
-      if (active) {
-        if (gm) {
-          const int f = __ffs(gm) - 1;
-          if (gl == 0) edges += uint64_t(f + 1);
-          if (gl == f && bit_claim(Cd, uint32_t(k))) {
-            out.put(vid_of[k], q < mid ? vid_of[x] : x);
-            ++claimed;
+    const int32_t incl = wave_incl_scan(len);
+    const int32_t T = __shfl(incl, kWave - 1, kWave);
+    if (T > 0) {
+      wave_sync();
+      s_excl[w][l] = incl - len;
+      s_beg[w][l] = p;
+      s_mid[w][l] = mid;
+      s_found[w][l] = kNone;
+      wave_sync();
+      uint64_t remaining = __ballot(len > 0);
+      for (int32_t e0 = 0; e0 < T && remaining; e0 += kWave) {
+        const int32_t e = e0 + l;
+        if (e < T) {
+          const int lo = owner64(s_excl[w], e);
+          if (s_found[w][lo] == kNone) {
+            const int64_t q = s_beg[w][lo] + (e - s_excl[w][lo]);
+            const int32_t x = dcol[q];
+            ++edges;
+            if (q < s_mid[w][lo] ? bit_test(Fd, uint32_t(x)) : bit_test(Fn, uint32_t(x)))
+              atomicMin(&s_found[w][lo], e);
           }
-          active = false;
-        } else {
-          if (gl == 0) edges += uint64_t(min<int64_t>(kGroup, hi - p));
-          p += kGroup;
-          active = p < hi;
         }
+        wave_sync();
+        remaining = __ballot(len > 0 && s_found[w][l] == kNone);
       }
+      const int32_t fe = s_found[w][l];
+      if (len > 0 && fe != kNone) hit = p + (fe - (incl - len));
+      wave_sync();
+    }
+    const bool won = wave_bit_claim(Cd, uint32_t(k), ok, hit >= 0);
+    if (won) {
+      const int32_t x = dcol[hit];
+      out.put(vid_of[k], hit < mid ? vid_of[x] : x);
+      ++claimed;
     }
   }
   // units: candidates scanned, edges inspected, claimed
@@ -956,12 +980,11 @@ void bfs_run(const Graph *g, Workspace *ws, int32_t source, const dsbfs_run_opts
         // bottom-up; at most U_dd + U_nd of them
         const int64_t ncand_max = (dd_bu ? U[0] : 0) + (nd_bu ? U[2] : 0);
         b = P.begin();
-        hipLaunchKernelGGL(k_dcand, dim3(grid_for(g->dwords(), kBS, 4096)), dim3(kBS), 0, s, Vd,
+        hipLaunchKernelGGL(k_dcand, dim3(grid_for(g->dwords(), kBS, 4096)), dim3(kBS), 0, s, Cd,
                            g->ddsrc_mask.as<uint32_t>(), g->dnsrc_mask.as<uint32_t>(),
                            g->dwords(), int(dd_bu), int(nd_bu), ws->dcand.as<int32_t>(), cur);
         HIPCHK(hipGetLastError());
-        hipLaunchKernelGGL(k_bu_deleg,
-                           dim3(grid_for(std::min<int64_t>(ncand_max, d) * kGroup, kBS, SG)),
+        hipLaunchKernelGGL(k_bu_deleg, dim3(grid_for(std::min<int64_t>(ncand_max, d), kBS, SG)),
                            dim3(kBS), 0, s, ws->dcand.as<int32_t>(), cur, g->doff.as<uint64_t>(),
                            g->dcol.as<int32_t>(), Fd, Fn, g->vid_of.as<int32_t>(), int(dd_bu),
                            int(nd_bu), out, Cd, cur);
