@@ -103,7 +103,7 @@ typedef struct dsbfs_run_opts {
                            1: degree-separated direction-optimized BFS */
   int32_t want_parent;  /* 1: write parent[] as well as depth[] */
   double factor0[3];    /* forward->backward switch factors for dd, dn, nd
-                           (Section IV-B). Defaults 0.05, 0.5, 1e-6: a joint
+                           (Section IV-B). Defaults 0.02, 0.001, 1e-6: a joint
                            sweep on this layout (rows ordered by decreasing
                            neighbour degree, so bottom-up finds a parent
                            sooner than the paper's BV model assumes) on

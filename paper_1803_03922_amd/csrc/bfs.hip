@@ -727,8 +727,8 @@ static dsbfs_run_opts default_opts() {
   o.mode = 1;
   o.want_parent = 1;
   // tuned for this layout (see the header); the paper's are DSBFS_PAPER_FACTOR0_*
-  o.factor0[0] = 0.05;
-  o.factor0[1] = 0.5;
+  o.factor0[0] = 0.02;
+  o.factor0[1] = 0.001;
   o.factor0[2] = 1e-6;
   o.factor1[0] = o.factor1[1] = o.factor1[2] = 0.0;
   o.forced = 0;

@@ -40,7 +40,7 @@ def test_default_factors():
     from paper_1803_03922_amd import dsbfs
     o = dsbfs.dsbfs_run_opts()
     assert dsbfs.dsbfs_run_opts_default(ctypes.byref(o)) == 0
-    assert list(o.factor0) == [0.05, 0.5, 1e-6]
+    assert list(o.factor0) == [0.02, 0.001, 1e-6]
     hdr = open(os.path.join(os.path.dirname(__file__), "..", "include", "dsbfs.h")).read()
     paper = {k: float(v) for k, v in re.findall(r"#define DSBFS_PAPER_FACTOR0_(\w+) (\S+)", hdr)}
     assert paper == {"DD": 0.5, "DN": 0.05, "ND": 1e-7}
