@@ -444,20 +444,26 @@ __global__ void __launch_bounds__(kBS) k_bu_normal(const int32_t *cin, int dense
     int64_t beg = 0;
     bool visited = true;
     int32_t hit0 = -1;  // delegate found at the first entry of the row
+    int32_t pk0 = 0;  // vertex of the row's first delegate (its parent if it is a hit)
     if (ok) {
       pos = dense ? int32_t(i) : cin[i];
+      // The loads are ordered to keep the chain of dependent accesses short:
+      // the vertex and its row bounds both depend on pos only; the row's
+      // first entry (rows in the list are never empty) does not wait for the
+      // visited test, and the parent candidate is fetched beside the
+      // frontier test.
       v = ndsrc[pos];
+      beg = nds_off[pos];
+      const int64_t end = nds_off[pos + 1];
+      const int32_t k0 = nds_col[beg];
       ++reads;
-      // Visited candidates are dropped before their rows are read: when the
-      // first bottom-up pass comes late, a large part of the list is reached.
       visited = bit_test(Vn, uint32_t(v));
       if (!visited) {
-        beg = nds_off[pos];
-        len = int32_t(nds_off[pos + 1] - beg);
+        len = int32_t(end - beg);
         ++scanned;
         // Rows start with their highest-degree delegate, the likeliest to be
         // in the frontier: a hit there skips the wave's walk for this row.
-        const int32_t k0 = nds_col[beg];
+        pk0 = vid_of[k0];
         ++edges;
         if (bit_test(Fd, uint32_t(k0))) {
           hit0 = k0;
@@ -489,8 +495,7 @@ __global__ void __launch_bounds__(kBS) k_bu_normal(const int32_t *cin, int dense
     // candidates come in ascending vertex order: claim word by word
     const bool won = wave_bit_claim(Vn, uint32_t(v), ok, found);
     if (won) {
-      const int32_t k = hit0 >= 0 ? hit0 : nds_col[beg + (fe - (incl - len))];
-      out.put(v, vid_of[k]);
+      out.put(v, hit0 >= 0 ? pk0 : vid_of[nds_col[beg + (fe - (incl - len))]]);
       ++claimed;
     }
     qa.push(won, v);
@@ -533,11 +538,12 @@ __global__ void __launch_bounds__(kBS) k_bu_deleg(const int32_t *dcand, const Le
        b0 += int64_t(gridDim.x) * blockDim.x) {
     const int64_t i = b0 + threadIdx.x;
     const bool ok = i < nc;
-    int32_t k = 0, len = 0;
+    int32_t k = 0, len = 0, vk = 0, px = 0;
     int64_t p = 0, mid = 0, hit = -1;
     if (ok) {
       k = dcand[i];
       const uint64_t w0 = doff[k], w1 = doff[k + 1];
+      vk = vid_of[k];  // fetched beside the row bounds
       const int64_t beg = row_start(w0);
       mid = beg + row_first(w0);
       p = dd_bu ? beg : mid;
@@ -546,12 +552,15 @@ __global__ void __launch_bounds__(kBS) k_bu_deleg(const int32_t *dcand, const Le
         ++cands;
         const int32_t x = dcol[p];
         ++edges;
-        if (p < mid ? bit_test(Fd, uint32_t(x)) : bit_test(Fn, uint32_t(x))) hit = p;
+        const bool in_dd = p < mid;
+        px = in_dd ? vid_of[x] : x;  // the parent if this entry is a hit
+        if (in_dd ? bit_test(Fd, uint32_t(x)) : bit_test(Fn, uint32_t(x))) hit = p;
         else ++p;
         // delegate degrees are below 2^24, so 64 rows sum below 2^31
         if (hit < 0) len = int32_t(hi - p);
       }
     }
+    const bool probe_hit = hit >= 0;
     const int32_t incl = wave_incl_scan(len);
     const int32_t T = __shfl(incl, kWave - 1, kWave);
     if (T > 0) {
@@ -583,8 +592,12 @@ __global__ void __launch_bounds__(kBS) k_bu_deleg(const int32_t *dcand, const Le
     }
     const bool won = wave_bit_claim(Cd, uint32_t(k), ok, hit >= 0);
     if (won) {
-      const int32_t x = dcol[hit];
-      out.put(vid_of[k], hit < mid ? vid_of[x] : x);
+      int32_t par = px;
+      if (!probe_hit) {
+        const int32_t x = dcol[hit];
+        par = hit < mid ? vid_of[x] : x;
+      }
+      out.put(vk, par);
       ++claimed;
     }
   }
