@@ -214,7 +214,7 @@ __device__ __forceinline__ void expand_normal_rows(int32_t u, int32_t len, int64
                                                    unsigned long long &claimed) {
   const int l = lane_id();
   const int32_t incl = wave_incl_scan(len);
-  const int32_t T = __shfl(incl, kWave - 1, kWave);
+  const int32_t T = lane_read(incl, kWave - 1);
   wave_sync();
   s_excl[l] = incl - len;
   s_u[l] = u;
@@ -472,7 +472,7 @@ __global__ void __launch_bounds__(kBS) k_bu_normal(const int32_t *cin, int dense
       }
     }
     const int32_t incl = wave_incl_scan(len);
-    const int32_t T = __shfl(incl, kWave - 1, kWave);
+    const int32_t T = lane_read(incl, kWave - 1);
     wave_sync();
     s_excl[w][l] = incl - len;
     s_beg[w][l] = beg;
@@ -562,7 +562,7 @@ __global__ void __launch_bounds__(kBS) k_bu_deleg(const int32_t *dcand, const Le
     }
     const bool probe_hit = hit >= 0;
     const int32_t incl = wave_incl_scan(len);
-    const int32_t T = __shfl(incl, kWave - 1, kWave);
+    const int32_t T = lane_read(incl, kWave - 1);
     if (T > 0) {
       wave_sync();
       s_excl[w][l] = incl - len;

@@ -151,6 +151,29 @@ template <class T> __device__ __forceinline__ T wave_sum(T v) {
   return v;
 }
 
+// Cross-lane moves through DPP (data-parallel primitives: a VALU operand
+// modifier, no LDS round trip, unlike ds_bpermute behind __shfl). Lanes whose
+// source is outside the row / wave, or whose row is masked off, read `old`.
+constexpr int kDppRowShr = 0x110;   // + n (1..15): lane l reads l - n within its 16-lane row
+constexpr int kDppWaveShl1 = 0x130; // lane l reads l + 1
+constexpr int kDppWaveShr1 = 0x138; // lane l reads l - 1
+constexpr int kDppBcast15 = 0x142;  // rows 1..3 read lane 15 of the previous row
+constexpr int kDppBcast31 = 0x143;  // rows 2..3 read lane 31
+template <int Ctrl, int RowMask = 0xf>
+__device__ __forceinline__ uint32_t dpp_u32(uint32_t old, uint32_t v) {
+  return uint32_t(__builtin_amdgcn_update_dpp(int(old), int(v), Ctrl, RowMask, 0xf, false));
+}
+
+// Lane `src` (wave-uniform) of v, through a scalar register.
+__device__ __forceinline__ int32_t lane_read(int32_t v, int src) {
+  return __builtin_amdgcn_readlane(v, src);
+}
+__device__ __forceinline__ unsigned long long lane_read(unsigned long long v, int src) {
+  const uint32_t lo = uint32_t(__builtin_amdgcn_readlane(int(uint32_t(v)), src));
+  const uint32_t hi = uint32_t(__builtin_amdgcn_readlane(int(uint32_t(v >> 32)), src));
+  return (static_cast<unsigned long long>(hi) << 32) | lo;
+}
+
 // Inclusive prefix sum across the 64 lanes of a wave.
 template <class T> __device__ __forceinline__ T wave_incl_scan(T v) {
   const int l = lane_id();
@@ -159,6 +182,18 @@ template <class T> __device__ __forceinline__ T wave_incl_scan(T v) {
     if (l >= o) v += t;
   }
   return v;
+}
+// 32-bit version with DPP: Hillis-Steele inside each 16-lane row, then the
+// row totals carried across rows by two broadcasts.
+template <> __device__ __forceinline__ int32_t wave_incl_scan<int32_t>(int32_t v) {
+  uint32_t x = uint32_t(v);
+  x += dpp_u32<kDppRowShr + 1>(0u, x);
+  x += dpp_u32<kDppRowShr + 2>(0u, x);
+  x += dpp_u32<kDppRowShr + 4>(0u, x);
+  x += dpp_u32<kDppRowShr + 8>(0u, x);
+  x += dpp_u32<kDppBcast15, 0xa>(0u, x);
+  x += dpp_u32<kDppBcast31, 0xc>(0u, x);
+  return int32_t(x);
 }
 
 // Wave-aggregated append: every lane with `want` gets a distinct slot of
@@ -169,7 +204,7 @@ __device__ __forceinline__ int64_t wave_append(bool want, unsigned long long *co
   int leader = __ffsll(static_cast<long long>(m)) - 1;
   unsigned long long base = 0;
   if (lane_id() == leader) base = atomicAdd(counter, static_cast<unsigned long long>(__popcll(m)));
-  base = __shfl(base, leader, kWave);
+  base = lane_read(base, leader);
   return want ? static_cast<int64_t>(base + lanes_below(m)) : -1;
 }
 
@@ -193,7 +228,7 @@ __device__ __forceinline__ bool bit_claim(uint32_t *bm, uint32_t v) {
 //   call (a bit wanted by several lanes of one run goes to the lowest lane).
 struct WaveBits {
   uint32_t word, bit, incl, old;
-  bool want;
+  bool want, head;
   // valid: v is a vertex (its word joins a run even without a bit, so the
   // runs of an ascending list are not cut by lanes that want nothing)
   __device__ __forceinline__ void run(uint32_t *bm, uint32_t v, bool valid, bool w,
@@ -202,37 +237,39 @@ struct WaveBits {
     want = valid && w;
     word = valid ? (v >> 5) : 0xffffffffu;
     bit = want ? (1u << (v & 31)) : 0u;
-    const uint32_t prev_word = __shfl_up(word, 1, kWave);
-    const uint32_t next_word = __shfl_down(word, 1, kWave);
-    const bool head = l == 0 || prev_word != word;
+    // neighbours' words (lane 0 / lane 63 read a value no word can take)
+    const uint32_t prev_word = dpp_u32<kDppWaveShr1>(0xfffffffeu, word);
+    const uint32_t next_word = dpp_u32<kDppWaveShl1>(0xfffffffeu, word);
+    head = l == 0 || prev_word != word;
     const bool tail = l == kWave - 1 || next_word != word;
-    // segmented inclusive OR-scan: incl = OR of bits from the run's head to this lane
+    // segmented inclusive OR-scan (incl = OR of the bits from the run's head
+    // to this lane) with DPP; f marks that a head lies within the span so far
     incl = bit;
-    uint32_t f = head;
-    for (int o = 1; o < kWave; o <<= 1) {
-      const uint32_t ti = __shfl_up(incl, o, kWave);
-      const uint32_t tf = __shfl_up(f, o, kWave);
-      if (l >= o) {
-        if (!f) incl |= ti;
-        f |= tf;
-      }
-    }
+    uint32_t f = head ? 1u : 0u, t, tf;
+#define DSBFS_SEG_STEP(CTRL, MASK)              \
+    t = dpp_u32<CTRL, MASK>(0u, incl);           \
+    tf = dpp_u32<CTRL, MASK>(0u, f);             \
+    if (!f) incl |= t;                           \
+    f |= tf;
+    DSBFS_SEG_STEP(kDppRowShr + 1, 0xf)
+    DSBFS_SEG_STEP(kDppRowShr + 2, 0xf)
+    DSBFS_SEG_STEP(kDppRowShr + 4, 0xf)
+    DSBFS_SEG_STEP(kDppRowShr + 8, 0xf)
+    DSBFS_SEG_STEP(kDppBcast15, 0xa)
+    DSBFS_SEG_STEP(kDppBcast31, 0xc)
+#undef DSBFS_SEG_STEP
     old = 0;
     if (tail && word != 0xffffffffu && incl) old = atomicOr(&bm[word], incl);
     if (need_old) {
-      // nearest tail at or after this lane is the run's tail
-      uint32_t tp = tail ? uint32_t(l) : uint32_t(kWave);
-      for (int o = 1; o < kWave; o <<= 1) {
-        const uint32_t t = __shfl_down(tp, o, kWave);
-        if (l + o < kWave) tp = min(tp, t);
-      }
-      old = __shfl(old, int(tp), kWave);
+      // the run's tail is the first tail lane at or after this lane
+      const uint64_t tails = __ballot(tail);
+      const int tp = l + __builtin_ctzll(tails >> l);
+      old = uint32_t(__shfl(int(old), tp, kWave));
     }
   }
   // true iff this lane set its bit first (bit was 0 and no lower lane of the run wanted it)
   __device__ __forceinline__ bool won() const {
-    const uint32_t before = __shfl_up(incl, 1, kWave);
-    const bool head = lane_id() == 0 || __shfl_up(word, 1, kWave) != word;
+    const uint32_t before = dpp_u32<kDppWaveShr1>(0u, incl);
     const uint32_t excl = head ? 0u : before;
     return want && !(old & bit) && !(excl & bit);
   }
@@ -281,7 +318,7 @@ struct BlockAppend {
     const int leader = __ffsll(static_cast<long long>(m)) - 1;
     int p = 0;
     if (lane_id() == leader) p = atomicAdd(count, __popcll(m));
-    p = __shfl(p, leader, kWave);
+    p = lane_read(p, leader);
     const int pos = p + int(lanes_below(m));
     const bool over = want && pos >= cap;
     if (want && !over) buf[pos] = v;

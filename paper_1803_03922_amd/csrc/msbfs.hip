@@ -146,7 +146,7 @@ __device__ uint64_t bu_wave(const int64_t *off, const int32_t *col, const uint64
     len = int32_t(off[w + 1] - beg);
   }
   const int32_t incl = wave_incl_scan(len);
-  const int32_t T = __shfl(incl, kWave - 1, kWave);
+  const int32_t T = lane_read(incl, kWave - 1);
   wave_sync();
   s_ex[l] = incl - len;
   s_beg[l] = beg;
