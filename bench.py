@@ -127,36 +127,39 @@ def main():
     ws = dsbfs.Workspace(g)
     depth = torch.empty(n, dtype=torch.int32, device="cuda")
     parent = None if args.no_parent else torch.empty(n, dtype=torch.int32, device="cuda")
-    opts = dsbfs.run_opts(mode=1 if args.mode == "do" else 0, want_parent=parent is not None,
-                          profile=True)
+    mode = 1 if args.mode == "do" else 0
+    opts = dsbfs.run_opts(mode=mode, want_parent=parent is not None)
+    popts = dsbfs.run_opts(mode=mode, want_parent=parent is not None, profile=True)
     stream = torch.cuda.current_stream()
 
-    def step(s):
+    def timed(gr, wsp, s, o, want_stats=False):
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
         e0.record(stream)
-        r = dsbfs.bfs(g, ws, int(s), depth, parent, opts=opts, want_stats=True, capacity=64)
+        r = dsbfs.bfs(gr, wsp, int(s), depth, parent, opts=o, want_stats=want_stats,
+                      capacity=64)
         e1.record(stream)
         e1.synchronize()
         return e0.elapsed_time(e1), r
 
+    # The GTEPS numerator of a source (edges of its component) comes from an
+    # untimed search with statistics; the timed searches run without them.
+    edges_cc, nlev = {}, {}
+    for s in sources.tolist():
+        _, r = timed(g, ws, s, opts, want_stats=True)
+        edges_cc[s], nlev[s] = r["edges_cc"], r["num_levels"]
     for i in range(args.warmup):
-        step(sources[i % len(sources)])
+        timed(g, ws, sources[i % len(sources)], opts)
     torch.cuda.synchronize()
 
     times, rates, levels = [], [], []
-    kern = {}
     t_wall = time.time()
     for i in range(args.steps):
-        s = sources[i % len(sources)]
-        ms, r = step(s)
+        s = int(sources[i % len(sources)])
+        ms, _ = timed(g, ws, s, opts)
         times.append(ms)
-        rates.append(r["edges_cc"] / (ms * 1e-3) / 1e9)
-        levels.append(r["num_levels"])
-        for name, k in r["kernels"].items():
-            a = kern.setdefault(name, {"ms": 0.0, "launches": 0, "bytes": 0, "edges": 0})
-            for f in a:
-                a[f] += k[f]
+        rates.append(edges_cc[s] / (ms * 1e-3) / 1e9)
+        levels.append(nlev[s])
         if i % 16 == 15:
             log(f"step {i + 1}/{args.steps}: {ms:.3f} ms, {rates[-1]:.1f} GTEPS")
     torch.cuda.synchronize()
@@ -164,6 +167,18 @@ def main():
     value = harmonic(rates)
     ms_per_step = sum(times) / len(times)
     nominal = [(16 << args.scale) / (t * 1e-3) / 1e9 for t in times]
+
+    # Kernel breakdown: the same searches again with every kernel timed by HIP
+    # events on the search's stream (direct launches instead of graphs).
+    kern, ptimes = {}, []
+    for i in range(args.steps):
+        ms, r = timed(g, ws, sources[i % len(sources)], popts, want_stats=True)
+        ptimes.append(ms)
+        for name, k in r["kernels"].items():
+            a = kern.setdefault(name, {"ms": 0.0, "launches": 0, "bytes": 0, "edges": 0})
+            for f in a:
+                a[f] += k[f]
+    torch.cuda.synchronize()
 
     dom = max(kern.items(), key=lambda kv: kv[1]["ms"])
     dname, dk = dom
@@ -189,15 +204,9 @@ def main():
         tt, rr = [], []
         for i in range(args.factor_steps):
             s = int(sources[i % len(sources)])
-            e0 = torch.cuda.Event(enable_timing=True)
-            e1 = torch.cuda.Event(enable_timing=True)
-            e0.record(stream)
-            r = dsbfs.bfs(g, ws, s, depth, parent, opts=o3, want_stats=True, capacity=64)
-            e1.record(stream)
-            e1.synchronize()
-            ms = e0.elapsed_time(e1)
+            ms, _ = timed(g, ws, s, o3)
             tt.append(ms)
-            rr.append(r["edges_cc"] / (ms * 1e-3) / 1e9)
+            rr.append(edges_cc[s] / (ms * 1e-3) / 1e9)
         return round(harmonic(rr), 3), round(sum(tt) / len(tt), 4)
 
     fsweep = []
@@ -251,17 +260,10 @@ def main():
         gs = dsbfs.Graph(src, dst, n, threshold=th, keep_plain_csr=False)
         wss = dsbfs.Workspace(gs)
         o2 = dsbfs.run_opts(want_parent=parent is not None)
-        dsbfs.bfs(gs, wss, int(sources[0]), depth, parent, opts=o2)
         tt, rr, byts = [], [], 0
-        for i in range(args.steps):
-            s = int(sources[i % len(sources)])
-            e0 = torch.cuda.Event(enable_timing=True)
-            e1 = torch.cuda.Event(enable_timing=True)
-            e0.record(stream)
-            r = dsbfs.bfs(gs, wss, s, depth, parent, opts=opts, want_stats=True, capacity=64)
-            e1.record(stream)
-            e1.synchronize()
-            ms = e0.elapsed_time(e1)
+        for s in sources.tolist()[:min(args.steps, len(sources))]:
+            _, r = timed(gs, wss, s, o2, want_stats=True)   # untimed: numerator and bytes
+            ms, _ = timed(gs, wss, s, o2)
             tt.append(ms)
             rr.append(r["edges_cc"] / (ms * 1e-3) / 1e9)
             byts += sum(k["bytes"] for k in r["kernels"].values())
@@ -313,7 +315,8 @@ def main():
             "kernel_ms_per_step": {k: round(v["ms"] / args.steps, 4) for k, v in kern.items()},
             "kernel_gbs": {k: round(v["bytes"] / (v["ms"] * 1e-3) / 1e9, 1)
                            for k, v in kern.items() if v["ms"] > 0},
-            "kernel_share": round(total_kernel_ms / sum(times), 3),
+            "kernel_share_profiled": round(total_kernel_ms / sum(ptimes), 3),
+            "ms_per_step_profiled": round(sum(ptimes) / len(ptimes), 4),
             "graph": st, "build_s": round(build_s, 2), "timed_wall_s": round(wall, 2),
         },
     }

@@ -24,6 +24,7 @@
 // Mode 0 is plain top-down BFS over the plain CSR (the paper's "BFS" beside
 // "DOBFS", Section VI-C), with the same load-balanced expansion.
 #include <cmath>
+#include <cstring>
 
 #include "internal.hpp"
 
@@ -31,16 +32,75 @@ namespace dsbfs {
 
 void msbfs_release(Workspace *ws);
 
+void level_graphs_release(Workspace *ws);
+
 Workspace::~Workspace() {
   msbfs_release(this);
+  level_graphs_release(this);
   if (hctr) (void)hipHostFree(hctr);
+  if (hstat) (void)hipHostFree(hstat);
   for (hipEvent_t e : events) (void)hipEventDestroy(e);
+  for (hipEvent_t e : lev_ev)
+    if (e) (void)hipEventDestroy(e);
 }
 
 namespace {
 
 constexpr int kBS = 256;
 constexpr int kNW = kBS / kWave;
+
+// Search state of degree-separated DOBFS on the device. One small kernel per
+// level (k_decide) makes the direction decision and writes the level's plan
+// here; every other kernel of the level reads its flag and returns at once
+// when it has no work, so the levels run back to back without a host round
+// trip (the host only learns, a level or two later, that the search ended).
+struct DevCtl {
+  double f0[3], f1[3];     // direction-switch factors (dd, dn, nd)
+  uint64_t forced_seed;
+  int32_t forced;
+  int32_t done;            // the frontier is empty: every later kernel returns
+  int32_t level;           // level in progress
+  int32_t level1;          // depth this level writes (level + 1)
+  int32_t dir[3];          // current direction per kernel (0 forward, 1 backward)
+  int32_t cand_state;      // -1: the next bottom-up normal pass scans the whole nd source list
+  int32_t nc_pending;      // the previous pass compacted a candidate list of unknown length
+  int32_t mark_fn;         // this level marks the normal frontier bitmap
+  int32_t nd_td, dd_td, dn_td, dn_bu, dd_bu, nd_bu;  // plan of this level
+  int32_t bulk_fn, clear_fn, cin_sel, cout_sel;
+  int64_t nwords;
+  int64_t rem[3];          // unvisited: delegates with a dd edge, with a dn edge, nd-list normals
+  int64_t nc;              // candidates of the next bottom-up normal pass
+  int64_t qn, fdn;         // frontier sizes of this level
+  unsigned long long deg_sum;                         // sum of frontier degrees so far
+  unsigned long long units[DSBFS_NUM_KERNELS][6];     // work units per kernel so far
+};
+
+// What the host learns of each level, written by k_decide into pinned host
+// memory (a ring of 4 slots, slot = level & 3).
+struct LevelStatus {
+  int32_t done, level;
+  int32_t plan[8];  // nd_td, dd_td, dn_td, dn_bu (runs), dd_bu, nd_bu, bulk_fn, mark_fn
+  dsbfs_level_stats rec;
+};
+constexpr int kStatusSlots = 4;
+
+// Bytes of one of the two tile arrays of the delegate-frontier prefix sum.
+inline size_t dtiles_half(int64_t d) {
+  const size_t nb = size_t((d + kBS * 8 - 1) / (kBS * 8)) + 1;
+  return (nb * 8 + 255) / 256 * 256;
+}
+
+__host__ __device__ inline uint64_t mix64_hd(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+  return z ^ (z >> 31);
+}
+
+// Backward workload estimate |U|(q+s)/q (Section IV-B), 0 when q or |U| is 0.
+__host__ __device__ inline double bv_estimate_hd(int64_t U, int64_t q, int64_t s) {
+  if (q <= 0 || U <= 0) return 0.0;
+  return double(U) * (double(q) + double(s)) / double(q);
+}
 
 // ---------------------------------------------------------------------------
 // init
@@ -115,7 +175,8 @@ __device__ __forceinline__ int block_excl_scan_i32(int v, int *sh, int *total) {
 // workloads. Positions come from a block scan plus one global atomic per block.
 __global__ void __launch_bounds__(kBS) k_prev_deleg(const uint32_t *Fd, int32_t dwords,
                                                     const uint64_t *doff, int32_t *dlist,
-                                                    LevelCtr *cur) {
+                                                    LevelCtr *cur, const DevCtl *c) {
+  if (c->done) return;
   __shared__ int shf[kNW];
   __shared__ unsigned long long base;
   __shared__ unsigned long long sh[4 * kNW];
@@ -150,8 +211,10 @@ __global__ void __launch_bounds__(kBS) k_prev_deleg(const uint32_t *Fd, int32_t 
 // with an edge in a subgraph scanned bottom-up this level (dd part if dd_bu,
 // dn part if nd_bu) -> dcand, ascending.
 __global__ void __launch_bounds__(kBS) k_dcand(const uint32_t *Cd, const uint32_t *ddm,
-                                               const uint32_t *dnm, int32_t dwords, int dd_bu,
-                                               int nd_bu, int32_t *dcand, LevelCtr *cur) {
+                                               const uint32_t *dnm, int32_t dwords,
+                                               const DevCtl *ctl, int32_t *dcand, LevelCtr *cur) {
+  if (ctl->done || !(ctl->dd_bu || ctl->nd_bu)) return;
+  const int dd_bu = ctl->dd_bu, nd_bu = ctl->nd_bu;
   __shared__ int shc[kNW];
   __shared__ unsigned long long base;
   for (int64_t w0 = int64_t(blockIdx.x) * blockDim.x; w0 < dwords;
@@ -250,8 +313,11 @@ __device__ __forceinline__ void expand_normal_rows(int32_t u, int32_t len, int64
 __global__ void __launch_bounds__(kBS) k_normal_level(const int32_t *Q, const LevelCtr *prev,
                                                       const uint64_t *noff, const int32_t *ncol,
                                                       Out out, uint32_t *Vn, uint32_t *Fn,
-                                                      int mark_fn, int32_t *Qnext,
+                                                      const DevCtl *c, int32_t *Qnext,
                                                       LevelCtr *cur) {
+  if (c->done) return;
+  const int mark_fn = c->mark_fn;
+  out.level1 = c->level1;
   __shared__ int32_t s_excl[kNW][kWave];
   __shared__ int32_t s_u[kNW][kWave];
   __shared__ int64_t s_beg[kNW][kWave];
@@ -293,10 +359,13 @@ __global__ void __launch_bounds__(kBS) k_normal_level(const int32_t *Q, const Le
 }
 
 // Top-down nd from the normal queue (only on levels where nd goes forward).
-__global__ void __launch_bounds__(kBS) k_td_nd(const int32_t *Q, int64_t qn,
+__global__ void __launch_bounds__(kBS) k_td_nd(const int32_t *Q, const DevCtl *c,
                                                const uint64_t *noff, const int32_t *ncol,
                                                const int32_t *vid_of, Out out, uint32_t *Cd,
                                                LevelCtr *cur) {
+  if (c->done || !c->nd_td) return;
+  const int64_t qn = c->qn;
+  out.level1 = c->level1;
   __shared__ int32_t s_excl[kNW][kWave];
   __shared__ int32_t s_u[kNW][kWave];
   __shared__ int64_t s_beg[kNW][kWave];
@@ -333,18 +402,6 @@ __device__ __forceinline__ int64_t seg_search(const int64_t *pre, int64_t cnt, i
   return lo;
 }
 
-__global__ void k_dlen(const int32_t *dlist, const LevelCtr *cur, const uint64_t *doff, int dd_td,
-                       int dn_td, int32_t *dlen) {
-  const int64_t nd = int64_t(cur->nd_list);
-  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < nd;
-       i += int64_t(gridDim.x) * blockDim.x) {
-    const int32_t k = dlist[i];
-    const uint64_t w0 = doff[k], w1 = doff[k + 1];
-    const int64_t dd = row_first(w0), dn = row_start(w1) - row_start(w0) - dd;
-    dlen[i] = int32_t((dd_td ? dd : 0) + (dn_td ? dn : 0));
-  }
-}
-
 // Top-down from the delegate frontier over dd and/or dn. Delegate degrees span
 // a wide range, so the work is balanced over edges: every thread takes runs of
 // consecutive edges of the frontier's concatenated lists, located by a binary
@@ -354,8 +411,11 @@ constexpr int kRun = 4;
 __global__ void __launch_bounds__(kBS) k_td_deleg(const int32_t *dlist, const int64_t *dscan,
                                                   const LevelCtr *curc, const uint64_t *doff,
                                                   const int32_t *dcol, const int32_t *vid_of,
-                                                  int dd_td, int dn_td, Out out, uint32_t *Vn,
+                                                  const DevCtl *c, Out out, uint32_t *Vn,
                                                   uint32_t *Cd, int32_t *Qnext, LevelCtr *cur) {
+  if (c->done || !(c->dd_td || c->dn_td)) return;
+  const int dd_td = c->dd_td, dn_td = c->dn_td;
+  out.level1 = c->level1;
   __shared__ int32_t qbuf[kQCap];
   __shared__ int qcount;
   __shared__ unsigned long long qbase;
@@ -417,11 +477,19 @@ __global__ void __launch_bounds__(kBS) k_td_deleg(const int32_t *dlist, const in
 // frontier mask Fd is kept with an LDS atomicMin, and the wave stops as soon
 // as every remaining candidate has one. Candidates still unvisited are
 // compacted (as positions) for the next bottom-up level.
-__global__ void __launch_bounds__(kBS) k_bu_normal(const int32_t *cin, int dense, int64_t nc,
+__global__ void __launch_bounds__(kBS) k_bu_normal(const DevCtl *c, int32_t *c0, int32_t *c1,
                                                    const int32_t *ndsrc, const int64_t *nds_off,
                                                    const int32_t *nds_col, const uint32_t *Fd,
                                                    const int32_t *vid_of, Out out, uint32_t *Vn,
-                                                   int32_t *Qnext, int32_t *cout, LevelCtr *cur) {
+                                                   int32_t *Qnext, LevelCtr *cur) {
+  if (c->done || !c->dn_bu) return;
+  // first pass: every position of the nd source list (dense); later passes:
+  // the positions the previous pass left unvisited
+  const int dense = c->cin_sel < 0;
+  const int32_t *cin = c->cin_sel == 0 ? c0 : c1;
+  int32_t *cout = c->cout_sel == 0 ? c0 : c1;
+  const int64_t nc = c->nc;
+  out.level1 = c->level1;
   __shared__ int32_t s_excl[kNW][kWave];
   __shared__ int32_t s_found[kNW][kWave];
   __shared__ int64_t s_beg[kNW][kWave];
@@ -523,8 +591,11 @@ __global__ void __launch_bounds__(kBS) k_bu_normal(const int32_t *cin, int dense
 __global__ void __launch_bounds__(kBS) k_bu_deleg(const int32_t *dcand, const LevelCtr *curc,
                                                   const uint64_t *doff, const int32_t *dcol,
                                                   const uint32_t *Fd, const uint32_t *Fn,
-                                                  const int32_t *vid_of, int dd_bu, int nd_bu,
+                                                  const int32_t *vid_of, const DevCtl *c,
                                                   Out out, uint32_t *Cd, LevelCtr *cur) {
+  if (c->done || !(c->dd_bu || c->nd_bu)) return;
+  const int dd_bu = c->dd_bu, nd_bu = c->nd_bu;
+  out.level1 = c->level1;
   __shared__ int32_t s_excl[kNW][kWave];
   __shared__ int32_t s_found[kNW][kWave];
   __shared__ int64_t s_beg[kNW][kWave];
@@ -610,17 +681,220 @@ __global__ void __launch_bounds__(kBS) k_bu_deleg(const int32_t *dcand, const Le
 // word by word under this level's queue (small levels) or, when the host has
 // cleared it in bulk, not at all (clear_fn = 0).
 __global__ void k_close(uint32_t *Vd, uint32_t *Fd, const uint32_t *Cd, int32_t dwords,
-                        uint32_t *Fn, const int32_t *Q, const LevelCtr *prev, int clear_fn) {
+                        uint32_t *Fn, int64_t nwords, const int32_t *Q, DevCtl *c,
+                        LevelCtr *next) {
+  if (c->done) return;
+  const int clear_fn = c->clear_fn, bulk_fn = c->bulk_fn;
+  const int64_t qn = c->qn;
   const int64_t stride = int64_t(gridDim.x) * blockDim.x;
   const int64_t t0 = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   for (int64_t w = t0; w < dwords; w += stride) {
-    const uint32_t c = Cd[w];
-    Fd[w] = c & ~Vd[w];
-    Vd[w] = c;
+    const uint32_t cw = Cd[w];
+    Fd[w] = cw & ~Vd[w];
+    Vd[w] = cw;
   }
-  if (!clear_fn) return;
-  const int64_t qn = int64_t(prev->qn_next);
-  for (int64_t i = t0; i < qn; i += stride) Fn[Q[i] >> 5] = 0;
+  if (bulk_fn) {
+    for (int64_t w = t0; w < nwords; w += stride) Fn[w] = 0;
+  } else if (clear_fn) {
+    for (int64_t i = t0; i < qn; i += stride) Fn[Q[i] >> 5] = 0;
+  }
+  // Open the next level: clear its counters (this level's "previous" ones,
+  // which nothing reads after the decision) and fix its depth and whether it
+  // marks the normal frontier bitmap (only read by a bottom-up nd visit,
+  // impossible once no unvisited delegate has a dn edge).
+  if (blockIdx.x == 0) {
+    unsigned long long *w = reinterpret_cast<unsigned long long *>(next);
+    for (int i = threadIdx.x; i < int(sizeof(LevelCtr) / 8); i += blockDim.x) w[i] = 0;
+    if (threadIdx.x == 0) {
+      c->level += 1;
+      c->level1 = c->level + 1;
+      c->mark_fn = c->rem[1] > 0;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// level control on the device
+// ---------------------------------------------------------------------------
+__global__ void k_ctl_init(DevCtl *c, DevCtl init) { *c = init; }
+
+// Direction decision of Section IV-B for dd, dn, nd (indices 0, 1, 2) from
+// this level's previsit counts, in FP64 with the same expression as the
+// oracle's replay, and the plan of the rest of the level. One thread.
+__global__ void k_decide(DevCtl *c, const LevelCtr *cur, const LevelCtr *prev,
+                         LevelStatus *hs) {
+  if (threadIdx.x != 0 || c->done) return;
+  const int32_t L = c->level;
+  // the previous level's kernels are complete: their work units
+  for (int k = 0; k < DSBFS_NUM_KERNELS; ++k)
+    for (int j = 0; j < 4; ++j) c->units[k][j] += prev->units[k][j];
+  const int64_t qn = int64_t(prev->qn_next), fdn = int64_t(cur->nd_list);
+  c->units[DSBFS_K_PREV_NORMAL][0] += qn;
+  c->units[DSBFS_K_PREV_DELEG][0] += fdn;
+  c->deg_sum += cur->fv_nn + cur->fv_nd + cur->fv_dd + cur->fv_dn;
+  if (c->nc_pending) {
+    // length of the candidate list the previous bottom-up normal pass compacted
+    c->nc = int64_t(prev->nc_next);
+    c->units[DSBFS_K_BU_NORMAL][4] += prev->nc_next;
+    c->nc_pending = 0;
+  }
+  LevelStatus *st = hs + (L & (kStatusSlots - 1));
+  if (qn == 0 && fdn == 0) {
+    c->done = 1;
+    st->level = L;
+    st->done = 1;
+    return;
+  }
+  const int64_t q[3] = {int64_t(cur->q_dd), int64_t(cur->q_dn), int64_t(cur->q_nd)};
+  const int64_t FV[3] = {int64_t(cur->fv_dd), int64_t(cur->fv_dn), int64_t(cur->fv_nd)};
+  c->rem[0] -= q[0];
+  c->rem[1] -= q[1];
+  c->rem[2] -= q[2];
+  const int64_t U[3] = {c->rem[0], c->rem[2], c->rem[1]};
+  const int64_t S[3] = {c->rem[0], c->rem[1], c->rem[2]};
+  double BV[3];
+  for (int k = 0; k < 3; ++k) {
+    BV[k] = bv_estimate_hd(U[k], q[k], S[k]);
+    int d = c->dir[k];
+    if (c->forced == 1) d = 0;
+    else if (c->forced == 2) d = L >= 1 ? 1 : 0;
+    else if (c->forced == 3) d = int(mix64_hd(c->forced_seed + uint64_t(L) * 3 + k) & 1);
+    else if (q[k] > 0) {
+      if (d == 0 && double(FV[k]) > c->f0[k] * BV[k]) d = 1;
+      else if (d == 1 && double(FV[k]) < c->f1[k] * BV[k]) d = 0;
+    }
+    c->dir[k] = d;
+    st->rec.q[k] = q[k];
+    st->rec.s[k] = S[k];
+    st->rec.U[k] = U[k];
+    st->rec.FV[k] = FV[k];
+    st->rec.BV[k] = BV[k];
+    st->rec.dir[k] = d;
+  }
+  st->rec.FV_nn = int64_t(cur->fv_nn);
+  st->rec.q_nn = int64_t(cur->q_nn);
+  st->rec.frontier_normal = qn;
+  st->rec.frontier_delegate = fdn;
+  // nn went top-down inside k_normal_level already
+  const int dd_td = c->dir[0] == 0 && q[0] > 0, dn_td = c->dir[1] == 0 && q[1] > 0;
+  const int nd_td = c->dir[2] == 0 && q[2] > 0;
+  const int dd_bu = c->dir[0] == 1 && q[0] > 0 && U[0] > 0;
+  const int dn_bu = c->dir[1] == 1 && q[1] > 0 && U[1] > 0 && c->nc > 0;
+  const int nd_bu = c->dir[2] == 1 && q[2] > 0 && U[2] > 0;
+  // large levels clear the normal frontier bitmap with one streaming fill
+  // instead of one scattered store per queue entry
+  const int bulk_fn = c->mark_fn && qn * 16 > c->nwords;
+  c->nd_td = nd_td;
+  c->dd_td = dd_td;
+  c->dn_td = dn_td;
+  c->dn_bu = dn_bu;
+  c->dd_bu = dd_bu;
+  c->nd_bu = nd_bu;
+  c->bulk_fn = bulk_fn;
+  c->clear_fn = c->mark_fn && !bulk_fn;
+  c->qn = qn;
+  c->fdn = fdn;
+  if (dn_bu) {
+    c->cin_sel = c->cand_state;
+    c->cout_sel = c->cand_state < 0 ? 0 : (c->cand_state ^ 1);
+    c->cand_state = c->cout_sel;
+    c->nc_pending = 1;
+  }
+  if (nd_td) c->units[DSBFS_K_TD_NORMAL][0] += qn;
+  if (dd_td || dn_td) c->units[DSBFS_K_TD_DELEG][0] += fdn;
+  c->units[DSBFS_K_CLOSE][0] += bulk_fn ? c->nwords / 4 : qn;
+  const int plan[8] = {nd_td, dd_td, dn_td, dn_bu, dd_bu, nd_bu, bulk_fn, c->mark_fn};
+  for (int i = 0; i < 8; ++i) st->plan[i] = plan[i];
+  st->level = L;
+  st->done = 0;
+}
+
+// Exclusive prefix sum of the top-down row lengths of the frontier delegates
+// (count on the device): tile sums, a scan of the tile sums in one block, and
+// the per-tile scans. Grids cover every delegate; tiles past the count return.
+constexpr int kScanItems = 8, kScanTile = kBS * kScanItems;
+
+__device__ __forceinline__ int64_t block_excl_scan_i64(int64_t v, int64_t *sh, int64_t *total) {
+  const int w = threadIdx.x / kWave, l = lane_id(), nw = blockDim.x / kWave;
+  const int64_t incl = wave_incl_scan(v);
+  if (l == kWave - 1) sh[w] = incl;
+  __syncthreads();
+  int64_t before = 0, all = 0;
+  for (int i = 0; i < nw; ++i) {
+    before += i < w ? sh[i] : 0;
+    all += sh[i];
+  }
+  *total = all;
+  __syncthreads();
+  return before + incl - v;
+}
+
+// First pass: the top-down length of each frontier delegate's row (dd part
+// if dd goes forward, dn part if dn does) and the sum of each tile.
+__global__ void __launch_bounds__(kBS) k_dscan_reduce(const int32_t *dlist, const uint64_t *doff,
+                                                      const LevelCtr *cur, const DevCtl *c,
+                                                      int32_t *len, int64_t *bsum) {
+  if (c->done || !(c->dd_td || c->dn_td)) return;
+  __shared__ int64_t sh[kNW];
+  const int dd_td = c->dd_td, dn_td = c->dn_td;
+  const int64_t N = int64_t(cur->nd_list);
+  const int64_t base = int64_t(blockIdx.x) * kScanTile;
+  if (base >= N) return;
+  int64_t x = 0;
+  for (int k = 0; k < kScanItems; ++k) {
+    const int64_t i = base + int64_t(threadIdx.x) * kScanItems + k;
+    if (i < N) {
+      const int32_t kd = dlist[i];
+      const uint64_t w0 = doff[kd], w1 = doff[kd + 1];
+      const int64_t dd = row_first(w0), dn = row_start(w1) - row_start(w0) - dd;
+      const int32_t l = int32_t((dd_td ? dd : 0) + (dn_td ? dn : 0));
+      len[i] = l;
+      x += l;
+    }
+  }
+  int64_t tot;
+  (void)block_excl_scan_i64(x, sh, &tot);
+  if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
+}
+
+__global__ void __launch_bounds__(1024) k_dscan_top(const int64_t *bsum, int64_t *bscan,
+                                                    int64_t *out, const LevelCtr *cur,
+                                                    const DevCtl *c) {
+  if (c->done || !(c->dd_td || c->dn_td)) return;
+  __shared__ int64_t sh[1024 / kWave];
+  const int64_t N = int64_t(cur->nd_list);
+  const int64_t nb = (N + kScanTile - 1) / kScanTile;
+  int64_t carry = 0;
+  for (int64_t i0 = 0; i0 < nb; i0 += blockDim.x) {
+    const int64_t i = i0 + threadIdx.x;
+    const int64_t x = i < nb ? bsum[i] : 0;
+    int64_t tot;
+    const int64_t ex = block_excl_scan_i64(x, sh, &tot);
+    if (i < nb) bscan[i] = carry + ex;
+    carry += tot;
+  }
+  if (threadIdx.x == 0) out[N] = carry;
+}
+
+__global__ void __launch_bounds__(kBS) k_dscan_down(const int32_t *len, int64_t *out,
+                                                    const LevelCtr *cur, const DevCtl *c,
+                                                    const int64_t *bscan) {
+  if (c->done || !(c->dd_td || c->dn_td)) return;
+  __shared__ int64_t sh[kNW];
+  const int64_t N = int64_t(cur->nd_list);
+  const int64_t base = int64_t(blockIdx.x) * kScanTile;
+  if (base >= N) return;
+  const int64_t t0 = base + int64_t(threadIdx.x) * kScanItems;
+  int64_t x = 0;
+  for (int k = 0; k < kScanItems; ++k)
+    if (t0 + k < N) x += len[t0 + k];
+  int64_t tot;
+  int64_t run = bscan[blockIdx.x] + block_excl_scan_i64(x, sh, &tot);
+  for (int k = 0; k < kScanItems; ++k)
+    if (t0 + k < N) {
+      out[t0 + k] = run;
+      run += len[t0 + k];
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -721,6 +995,11 @@ Workspace *workspace_create(const Graph *g, int32_t max_lanes) {
     ws->scan_tmp.alloc(al, scan_tmp_bytes(std::max(n, d)), s);
     HIPCHK(hipHostMalloc(reinterpret_cast<void **>(&ws->hctr), 2 * sizeof(LevelCtr),
                          hipHostMallocDefault));
+    ws->dctl.alloc(al, sizeof(DevCtl), s);
+    ws->dtiles.alloc(al, 2 * dtiles_half(d), s);
+    HIPCHK(hipHostMalloc(&ws->hstat, kStatusSlots * sizeof(LevelStatus), hipHostMallocDefault));
+    std::memset(ws->hstat, 0, kStatusSlots * sizeof(LevelStatus));
+    for (hipEvent_t &e : ws->lev_ev) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     if (max_lanes == 64) {
       ws->ms_seen.alloc(al, size_t(n) * 8, s);
       ws->ms_front.alloc(al, size_t(n) * 8, s);
@@ -795,6 +1074,186 @@ struct Prof {
   }
 };
 
+namespace {
+
+// The kernels of one level of degree-separated DOBFS (queue parity p: the
+// level reads Q[p] and ctr[p ^ 1], writes Q[p ^ 1] and ctr[p]). Every kernel
+// reads the plan from the control block, so the same sequence serves every
+// level and can be captured once.
+struct LevelLaunch {
+  const Graph *g;
+  Workspace *ws;
+  Out out;
+  DevCtl *c;
+  LevelCtr *ctr;
+  int32_t *Q[2], *C[2];
+  uint32_t *Vn, *Fn, *Vd, *Fd, *Cd;
+  LevelStatus *hs;
+  int64_t *bsum, *bscan;
+
+  void enqueue(int p, hipStream_t s, Prof *P) const {
+    const int32_t n = g->n, d = g->d;
+    LevelCtr *cur = ctr + p, *prev = ctr + (p ^ 1);
+    const int SG = stride_grid();
+    auto begin = [&]() { return P ? P->begin() : -1; };
+    auto end = [&](int k, int b) {
+      if (P) P->end(k, b);
+    };
+    int b = begin();
+    hipLaunchKernelGGL(k_normal_level, dim3(SG), dim3(kBS), 0, s, Q[p], prev,
+                       g->noff.as<uint64_t>(), g->ncol.as<int32_t>(), out, Vn, Fn,
+                       static_cast<const DevCtl *>(c), Q[p ^ 1], cur);
+    HIPCHK(hipGetLastError());
+    end(DSBFS_K_PREV_NORMAL, b);
+    if (d > 0) {
+      b = begin();
+      hipLaunchKernelGGL(k_prev_deleg, dim3(grid_for(g->dwords(), kBS, 4096)), dim3(kBS), 0, s,
+                         Fd, g->dwords(), g->doff.as<uint64_t>(), ws->dlist.as<int32_t>(), cur,
+                         static_cast<const DevCtl *>(c));
+      HIPCHK(hipGetLastError());
+      end(DSBFS_K_PREV_DELEG, b);
+    }
+    hipLaunchKernelGGL(k_decide, dim3(1), dim3(kWave), 0, s, c, static_cast<const LevelCtr *>(cur),
+                       static_cast<const LevelCtr *>(prev), hs);
+    HIPCHK(hipGetLastError());
+    if (d > 0) {
+      b = begin();
+      hipLaunchKernelGGL(k_td_nd, dim3(SG), dim3(kBS), 0, s, static_cast<const int32_t *>(Q[p]),
+                         static_cast<const DevCtl *>(c), g->noff.as<uint64_t>(),
+                         g->ncol.as<int32_t>(), g->vid_of.as<int32_t>(), out, Cd, cur);
+      HIPCHK(hipGetLastError());
+      end(DSBFS_K_TD_NORMAL, b);
+      b = begin();
+      const unsigned nb = unsigned((int64_t(d) + kScanTile - 1) / kScanTile);
+      hipLaunchKernelGGL(k_dscan_reduce, dim3(nb), dim3(kBS), 0, s,
+                         static_cast<const int32_t *>(ws->dlist.as<int32_t>()),
+                         g->doff.as<uint64_t>(), static_cast<const LevelCtr *>(cur),
+                         static_cast<const DevCtl *>(c), ws->dlen.as<int32_t>(), bsum);
+      hipLaunchKernelGGL(k_dscan_top, dim3(1), dim3(1024), 0, s, static_cast<const int64_t *>(bsum),
+                         bscan, ws->dscan.as<int64_t>(), static_cast<const LevelCtr *>(cur),
+                         static_cast<const DevCtl *>(c));
+      hipLaunchKernelGGL(k_dscan_down, dim3(nb), dim3(kBS), 0, s, ws->dlen.as<int32_t>(),
+                         ws->dscan.as<int64_t>(), static_cast<const LevelCtr *>(cur),
+                         static_cast<const DevCtl *>(c), static_cast<const int64_t *>(bscan));
+      hipLaunchKernelGGL(k_td_deleg, dim3(SG), dim3(kBS), 0, s, ws->dlist.as<int32_t>(),
+                         ws->dscan.as<int64_t>(), static_cast<const LevelCtr *>(cur),
+                         g->doff.as<uint64_t>(), g->dcol.as<int32_t>(), g->vid_of.as<int32_t>(),
+                         static_cast<const DevCtl *>(c), out, Vn, Cd, Q[p ^ 1], cur);
+      HIPCHK(hipGetLastError());
+      end(DSBFS_K_TD_DELEG, b);
+      if (g->st.n_ndsrc > 0) {
+        b = begin();
+        hipLaunchKernelGGL(k_bu_normal, dim3(SG), dim3(kBS), 0, s, static_cast<const DevCtl *>(c),
+                           C[0], C[1], g->ndsrc.as<int32_t>(), g->nds_off.as<int64_t>(),
+                           g->nds_col.as<int32_t>(), static_cast<const uint32_t *>(Fd),
+                           g->vid_of.as<int32_t>(), out, Vn, Q[p ^ 1], cur);
+        HIPCHK(hipGetLastError());
+        end(DSBFS_K_BU_NORMAL, b);
+      }
+      b = begin();
+      hipLaunchKernelGGL(k_dcand, dim3(grid_for(g->dwords(), kBS, 4096)), dim3(kBS), 0, s,
+                         static_cast<const uint32_t *>(Cd), g->ddsrc_mask.as<uint32_t>(),
+                         g->dnsrc_mask.as<uint32_t>(), g->dwords(), static_cast<const DevCtl *>(c),
+                         ws->dcand.as<int32_t>(), cur);
+      hipLaunchKernelGGL(k_bu_deleg, dim3(SG), dim3(kBS), 0, s, ws->dcand.as<int32_t>(),
+                         static_cast<const LevelCtr *>(cur), g->doff.as<uint64_t>(),
+                         g->dcol.as<int32_t>(), static_cast<const uint32_t *>(Fd),
+                         static_cast<const uint32_t *>(Fn), g->vid_of.as<int32_t>(),
+                         static_cast<const DevCtl *>(c), out, Cd, cur);
+      HIPCHK(hipGetLastError());
+      end(DSBFS_K_BU_DELEG, b);
+    }
+    b = begin();
+    hipLaunchKernelGGL(k_close, dim3(grid_for(std::max<int64_t>(n, g->dwords()), kBS, 4096)),
+                       dim3(kBS), 0, s, Vd, Fd, static_cast<const uint32_t *>(Cd), g->dwords(), Fn,
+                       int64_t(g->nwords()), static_cast<const int32_t *>(Q[p]), c, prev);
+    HIPCHK(hipGetLastError());
+    end(DSBFS_K_CLOSE, b);
+  }
+};
+
+LevelLaunch level_launch(const Graph *g, Workspace *ws, const Out &out) {
+  LevelLaunch ll{};
+  ll.g = g;
+  ll.ws = ws;
+  ll.out = out;
+  ll.c = ws->dctl.as<DevCtl>();
+  ll.ctr = ws->ctr.as<LevelCtr>();
+  ll.Q[0] = ws->q0.as<int32_t>();
+  ll.Q[1] = ws->q1.as<int32_t>();
+  ll.C[0] = ws->c0.as<int32_t>();
+  ll.C[1] = ws->c1.as<int32_t>();
+  ll.Vn = ws->Vn.as<uint32_t>();
+  ll.Fn = ws->Fn.as<uint32_t>();
+  ll.Vd = ws->Vd.as<uint32_t>();
+  ll.Fd = ws->Fd.as<uint32_t>();
+  ll.Cd = ws->Cd.as<uint32_t>();
+  ll.hs = static_cast<LevelStatus *>(ws->hstat);
+  // tile sums and their scan of the delegate-frontier prefix sum
+  const size_t half = dtiles_half(g->d);
+  ll.bsum = ws->dtiles.as<int64_t>();
+  ll.bscan = reinterpret_cast<int64_t *>(ws->dtiles.as<char>() + half);
+  return ll;
+}
+
+// Two captured level graphs per workspace (one per queue parity), for the
+// depth / parent buffers they were captured with.
+struct LevelGraphs {
+  int32_t *depth = nullptr, *parent = nullptr;
+  hipGraph_t graph[2] = {nullptr, nullptr};
+  hipGraphExec_t exec[2] = {nullptr, nullptr};
+};
+
+}  // namespace
+
+void level_graphs_release(Workspace *ws) {
+  auto *lg = static_cast<LevelGraphs *>(ws->lvl);
+  if (!lg) return;
+  for (int i = 0; i < 2; ++i) {
+    if (lg->exec[i]) (void)hipGraphExecDestroy(lg->exec[i]);
+    if (lg->graph[i]) (void)hipGraphDestroy(lg->graph[i]);
+  }
+  delete lg;
+  ws->lvl = nullptr;
+}
+
+namespace {
+
+const LevelGraphs &level_graphs(Workspace *ws, const LevelLaunch &ll) {
+  auto *lg = static_cast<LevelGraphs *>(ws->lvl);
+  if (lg && lg->depth == ll.out.depth && lg->parent == ll.out.parent) return *lg;
+  level_graphs_release(ws);
+  lg = new LevelGraphs();
+  ws->lvl = lg;
+  lg->depth = ll.out.depth;
+  lg->parent = ll.out.parent;
+  hipStream_t cs = nullptr;
+  HIPCHK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+  try {
+    for (int p = 0; p < 2; ++p) {
+      HIPCHK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+      try {
+        ll.enqueue(p, cs, nullptr);
+      } catch (...) {
+        hipGraph_t gr = nullptr;
+        (void)hipStreamEndCapture(cs, &gr);
+        if (gr) (void)hipGraphDestroy(gr);
+        throw;
+      }
+      HIPCHK(hipStreamEndCapture(cs, &lg->graph[p]));
+      HIPCHK(hipGraphInstantiate(&lg->exec[p], lg->graph[p], nullptr, nullptr, 0));
+    }
+  } catch (...) {
+    (void)hipStreamDestroy(cs);
+    level_graphs_release(ws);
+    throw;
+  }
+  (void)hipStreamDestroy(cs);
+  return *lg;
+}
+
+}  // namespace
+
 void bfs_run(const Graph *g, Workspace *ws, int32_t source, const dsbfs_run_opts *opts_in,
              int32_t *depth, int32_t *parent, dsbfs_run_stats *stats, hipStream_t s) {
   if (!ws || ws->g != g) fail(DSBFS_ERR_INVALID_ARG, "workspace does not belong to this graph");
@@ -864,160 +1323,93 @@ void bfs_run(const Graph *g, Workspace *ws, int32_t source, const dsbfs_run_opts
       rec.push_back(r);
     }
   } else {
-    int64_t rem_dd = g->st.n_ddsrc, rem_dn = g->st.n_dnsrc, rem_nd = g->st.n_ndsrc;
-    int dir[3] = {0, 0, 0};
-    int cand_state = -1;  // -1: candidates = nd source list; else ws->c[cand_state]
-    int64_t nc = g->st.n_ndsrc;
-    bool nc_pending = false;
-    int32_t *C[2] = {ws->c0.as<int32_t>(), ws->c1.as<int32_t>()};
-    for (int32_t L = 0;; ++L) {
-      LevelCtr *cur = ctr + (L & 1), *prev = ctr + ((L + 1) & 1);
-      HIPCHK(hipMemsetAsync(cur, 0, sizeof(LevelCtr), s));
-      out.level1 = L + 1;
-      // rem_dn counts unvisited delegates with a dn edge before this level's
-      // frontier is subtracted: zero means no bottom-up nd visit is possible
-      const int mark_fn = rem_dn > 0;
-      b = P.begin();
-      hipLaunchKernelGGL(k_normal_level, dim3(SG), dim3(kBS), 0, s, Q[qi], prev,
-                         g->noff.as<uint64_t>(), g->ncol.as<int32_t>(), out, Vn, Fn, mark_fn,
-                         Q[qi ^ 1], cur);
-      HIPCHK(hipGetLastError());
-      P.end(DSBFS_K_PREV_NORMAL, b);
-      if (d > 0) {
-        b = P.begin();
-        hipLaunchKernelGGL(k_prev_deleg, dim3(grid_for(g->dwords(), kBS, 4096)), dim3(kBS), 0, s,
-                           Fd, g->dwords(), g->doff.as<uint64_t>(), ws->dlist.as<int32_t>(), cur);
-        HIPCHK(hipGetLastError());
-        P.end(DSBFS_K_PREV_DELEG, b);
+    // Degree-separated DOBFS with the level control on the device.
+    DevCtl *c = ws->dctl.as<DevCtl>();
+    DevCtl init{};
+    for (int k = 0; k < 3; ++k) {
+      init.f0[k] = o.factor0[k];
+      init.f1[k] = o.factor1[k];
+    }
+    init.forced = o.forced;
+    init.forced_seed = o.forced_seed;
+    init.level = 0;  // level 0 is open: counters cleared above, depth 1 next
+    init.level1 = 1;
+    init.mark_fn = g->st.n_dnsrc > 0;
+    init.cand_state = -1;
+    init.nwords = g->nwords();
+    init.rem[0] = g->st.n_ddsrc;
+    init.rem[1] = g->st.n_dnsrc;
+    init.rem[2] = g->st.n_ndsrc;
+    init.nc = g->st.n_ndsrc;
+    hipLaunchKernelGGL(k_ctl_init, dim3(1), dim3(1), 0, s, c, init);
+    HIPCHK(hipGetLastError());
+    LevelStatus *hs = static_cast<LevelStatus *>(ws->hstat);
+    const LevelLaunch ll = level_launch(g, ws, out);
+    std::vector<LevelStatus> seen;
+    if (P.on) {
+      // direct launches with an event around each kernel and one stream
+      // synchronization per level, so that only kernels with work are counted
+      for (int32_t L = 0;; ++L) {
+        const size_t sp0 = P.spans.size();
+        ll.enqueue(L & 1, s, &P);
+        HIPCHK(hipStreamSynchronize(s));
+        const LevelStatus st = hs[L & (kStatusSlots - 1)];
+        const int32_t ran[DSBFS_NUM_KERNELS] = {
+            0, 1, d > 0, !st.done && st.plan[0], !st.done && (st.plan[1] || st.plan[2]),
+            !st.done && st.plan[3], !st.done && (st.plan[4] || st.plan[5]), !st.done, 0};
+        std::vector<Prof::Span> keep;
+        for (size_t i = sp0; i < P.spans.size(); ++i) {
+          if (ran[P.spans[i].k]) keep.push_back(P.spans[i]);
+          else --P.launches[P.spans[i].k];
+        }
+        P.spans.resize(sp0);
+        P.spans.insert(P.spans.end(), keep.begin(), keep.end());
+        if (st.done) break;
+        seen.push_back(st);
       }
-      HIPCHK(hipMemcpyAsync(h, ctr, 2 * sizeof(LevelCtr), hipMemcpyDeviceToHost, s));
-      HIPCHK(hipStreamSynchronize(s));
-      const LevelCtr &hc = h[L & 1], &hp = h[(L + 1) & 1];
-      P.add_level(hp);  // the previous level's kernels are complete
-      const int64_t qn = int64_t(hp.qn_next);
-      const int64_t fdn = int64_t(hc.nd_list);
-      P.units[DSBFS_K_PREV_NORMAL][0] += double(qn);
-      deg_sum += double(hc.fv_nn) + double(hc.fv_nd) + double(hc.fv_dd) + double(hc.fv_dn);
-      P.units[DSBFS_K_PREV_DELEG][0] += double(fdn);
-      if (nc_pending) {
-        // length of the candidate list the previous level's bottom-up normal
-        // kernel compacted
-        nc = int64_t(hp.nc_next);
-        P.units[DSBFS_K_BU_NORMAL][4] += double(nc);
-        nc_pending = false;
-      }
-      if (qn == 0 && fdn == 0) break;
-
-      // Direction decision (Section IV-B), indices dd = 0, dn = 1, nd = 2.
-      const int64_t q[3] = {int64_t(hc.q_dd), int64_t(hc.q_dn), int64_t(hc.q_nd)};
-      const int64_t FV[3] = {int64_t(hc.fv_dd), int64_t(hc.fv_dn), int64_t(hc.fv_nd)};
-      rem_dd -= q[0];
-      rem_dn -= q[1];
-      rem_nd -= q[2];
-      const int64_t U[3] = {rem_dd, rem_nd, rem_dn};
-      const int64_t S[3] = {rem_dd, rem_dn, rem_nd};
-      double BV[3];
-      for (int k = 0; k < 3; ++k) {
-        BV[k] = bv_estimate(U[k], q[k], S[k]);
-        if (o.forced == 1) dir[k] = 0;
-        else if (o.forced == 2) dir[k] = L >= 1 ? 1 : 0;
-        else if (o.forced == 3) dir[k] = int(mix64(o.forced_seed + uint64_t(L) * 3 + k) & 1);
-        else if (q[k] > 0) {
-          if (dir[k] == 0 && double(FV[k]) > o.factor0[k] * BV[k]) dir[k] = 1;
-          else if (dir[k] == 1 && double(FV[k]) < o.factor1[k] * BV[k]) dir[k] = 0;
+    } else {
+      // one captured graph per level; the host stays two levels ahead and
+      // stops once a finished level reports an empty frontier (the levels
+      // already queued behind it return at once)
+      const LevelGraphs &lg = level_graphs(ws, ll);
+      for (int32_t L = 0;; ++L) {
+        HIPCHK(hipGraphLaunch(lg.exec[L & 1], s));
+        HIPCHK(hipEventRecord(ws->lev_ev[L % 3], s));
+        if (L >= 2) {
+          HIPCHK(hipEventSynchronize(ws->lev_ev[(L - 2) % 3]));
+          const LevelStatus &st = hs[(L - 2) & (kStatusSlots - 1)];
+          if (st.done) break;
+          seen.push_back(st);
         }
       }
-      dsbfs_level_stats r{};
-      for (int k = 0; k < 3; ++k) {
-        r.q[k] = q[k];
-        r.s[k] = S[k];
-        r.U[k] = U[k];
-        r.FV[k] = FV[k];
-        r.BV[k] = BV[k];
-        r.dir[k] = dir[k];
+    }
+    for (const LevelStatus &st : seen) {
+      rec.push_back(st.rec);
+      if (!P.on) {
+        const int32_t *pl = st.plan;
+        ++P.launches[DSBFS_K_PREV_NORMAL];
+        if (d > 0) ++P.launches[DSBFS_K_PREV_DELEG];
+        if (pl[0]) ++P.launches[DSBFS_K_TD_NORMAL];
+        if (pl[1] || pl[2]) ++P.launches[DSBFS_K_TD_DELEG];
+        if (pl[3]) ++P.launches[DSBFS_K_BU_NORMAL];
+        if (pl[4] || pl[5]) ++P.launches[DSBFS_K_BU_DELEG];
+        ++P.launches[DSBFS_K_CLOSE];
       }
-      r.FV_nn = int64_t(hc.fv_nn);
-      r.q_nn = int64_t(hc.q_nn);
-      r.frontier_normal = qn;
-      r.frontier_delegate = fdn;
-      rec.push_back(r);
-
-      // nn went top-down inside k_normal_level already
-      const bool dd_td = dir[0] == 0 && q[0] > 0, dn_td = dir[1] == 0 && q[1] > 0;
-      const bool nd_td = dir[2] == 0 && q[2] > 0;
-      const bool dd_bu = dir[0] == 1 && q[0] > 0 && U[0] > 0;
-      const bool dn_bu = dir[1] == 1 && q[1] > 0 && U[1] > 0;
-      const bool nd_bu = dir[2] == 1 && q[2] > 0 && U[2] > 0;
-      if (nd_td) {
-        b = P.begin();
-        hipLaunchKernelGGL(k_td_nd, dim3(grid_for(qn, kBS, SG)), dim3(kBS), 0, s, Q[qi], qn,
-                           g->noff.as<uint64_t>(), g->ncol.as<int32_t>(),
-                           g->vid_of.as<int32_t>(), out, Cd, cur);
-        HIPCHK(hipGetLastError());
-        P.end(DSBFS_K_TD_NORMAL, b);
-        P.units[DSBFS_K_TD_NORMAL][0] += double(qn);
+    }
+    if (!P.on) {
+      // the level that found the frontier empty ran its previsit
+      ++P.launches[DSBFS_K_PREV_NORMAL];
+      if (d > 0) ++P.launches[DSBFS_K_PREV_DELEG];
+    }
+    if (stats) {
+      DevCtl hc{};
+      HIPCHK(hipMemcpyAsync(&hc, c, sizeof(DevCtl), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      for (int k = 0; k < DSBFS_NUM_KERNELS; ++k) {
+        if (k == DSBFS_K_INIT) continue;
+        for (int j = 0; j < 6; ++j) P.units[k][j] = double(hc.units[k][j]);
       }
-      if (dd_td || dn_td) {
-        b = P.begin();
-        hipLaunchKernelGGL(k_dlen, dim3(grid_for(fdn, kBS, 4096)), dim3(kBS), 0, s,
-                           ws->dlist.as<int32_t>(), cur, g->doff.as<uint64_t>(), int(dd_td),
-                           int(dn_td), ws->dlen.as<int32_t>());
-        HIPCHK(hipGetLastError());
-        scan_excl_i32_to_i64(ws->dlen.as<int32_t>(), ws->dscan.as<int64_t>(), fdn,
-                             ws->scan_tmp.p, s);
-        hipLaunchKernelGGL(k_td_deleg, dim3(SG), dim3(kBS), 0, s, ws->dlist.as<int32_t>(),
-                           ws->dscan.as<int64_t>(), cur, g->doff.as<uint64_t>(),
-                           g->dcol.as<int32_t>(), g->vid_of.as<int32_t>(), int(dd_td), int(dn_td),
-                           out, Vn, Cd, Q[qi ^ 1], cur);
-        HIPCHK(hipGetLastError());
-        P.end(DSBFS_K_TD_DELEG, b);
-        P.units[DSBFS_K_TD_DELEG][0] += double(fdn);
-      }
-      if (dn_bu && nc > 0) {
-        // first pass: every position of the nd source list (dense); later
-        // passes: the positions the previous pass left unvisited
-        const int32_t *cin = cand_state < 0 ? nullptr : C[cand_state];
-        const int nxt = cand_state < 0 ? 0 : (cand_state ^ 1);
-        b = P.begin();
-        hipLaunchKernelGGL(k_bu_normal, dim3(grid_for(nc, kBS, SG)), dim3(kBS), 0, s, cin,
-                           int(cand_state < 0), nc, g->ndsrc.as<int32_t>(),
-                           g->nds_off.as<int64_t>(), g->nds_col.as<int32_t>(), Fd,
-                           g->vid_of.as<int32_t>(), out, Vn, Q[qi ^ 1], C[nxt], cur);
-        HIPCHK(hipGetLastError());
-        P.end(DSBFS_K_BU_NORMAL, b);
-        cand_state = nxt;
-        nc_pending = true;
-      }
-      if (dd_bu || nd_bu) {
-        // candidates: unvisited delegates with an edge in a subgraph scanned
-        // bottom-up; at most U_dd + U_nd of them
-        const int64_t ncand_max = (dd_bu ? U[0] : 0) + (nd_bu ? U[2] : 0);
-        b = P.begin();
-        hipLaunchKernelGGL(k_dcand, dim3(grid_for(g->dwords(), kBS, 4096)), dim3(kBS), 0, s, Cd,
-                           g->ddsrc_mask.as<uint32_t>(), g->dnsrc_mask.as<uint32_t>(),
-                           g->dwords(), int(dd_bu), int(nd_bu), ws->dcand.as<int32_t>(), cur);
-        HIPCHK(hipGetLastError());
-        hipLaunchKernelGGL(k_bu_deleg, dim3(grid_for(std::min<int64_t>(ncand_max, d), kBS, SG)),
-                           dim3(kBS), 0, s, ws->dcand.as<int32_t>(), cur, g->doff.as<uint64_t>(),
-                           g->dcol.as<int32_t>(), Fd, Fn, g->vid_of.as<int32_t>(), int(dd_bu),
-                           int(nd_bu), out, Cd, cur);
-        HIPCHK(hipGetLastError());
-        P.end(DSBFS_K_BU_DELEG, b);
-      }
-      // Large levels clear the normal frontier bitmap with one streaming fill
-      // instead of one scattered store per queue entry.
-      const bool bulk_fn = mark_fn && qn * 16 > int64_t(g->nwords());
-      b = P.begin();
-      if (bulk_fn) HIPCHK(hipMemsetAsync(Fn, 0, size_t(g->nwords()) * 4, s));
-      hipLaunchKernelGGL(k_close,
-                         dim3(grid_for(std::max<int64_t>(bulk_fn ? 0 : qn, g->dwords()), kBS,
-                                       4096)),
-                         dim3(kBS), 0, s, Vd, Fd, Cd, g->dwords(), Fn, Q[qi], prev,
-                         int(mark_fn && !bulk_fn));
-      HIPCHK(hipGetLastError());
-      P.end(DSBFS_K_CLOSE, b);
-      P.units[DSBFS_K_CLOSE][0] += double(bulk_fn ? g->nwords() / 4 : qn);
-      qi ^= 1;
+      deg_sum = double(hc.deg_sum);
     }
   }
 

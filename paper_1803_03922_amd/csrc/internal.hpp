@@ -123,6 +123,12 @@ struct Workspace {
   DevBuf scan_tmp;
   LevelCtr *hctr = nullptr;    // pinned host copy of ctr
   std::vector<hipEvent_t> events;  // profiling event pool
+  // device-side level control of degree-separated DOBFS (bfs.hip)
+  DevBuf dctl;                 // control block of the search in progress
+  DevBuf dtiles;               // tile sums and their scan (delegate-frontier prefix sum)
+  void *hstat = nullptr;       // pinned ring of per-level status records
+  void *lvl = nullptr;         // captured level graphs
+  hipEvent_t lev_ev[3] = {};   // completion of recent levels
   // multi-source lane state
   DevBuf ms_seen, ms_front, ms_next;  // uint64[n]
   void *ms_state = nullptr;           // launch state of multi-source BFS (msbfs.hip)

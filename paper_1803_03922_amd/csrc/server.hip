@@ -72,7 +72,8 @@ size_t workspace_footprint(const Workspace *w) {
          buf_bytes(w->Cd) + buf_bytes(w->q0) + buf_bytes(w->q1) + buf_bytes(w->dlist) +
          buf_bytes(w->dcand) + buf_bytes(w->dlen) + buf_bytes(w->dscan) + buf_bytes(w->c0) +
          buf_bytes(w->c1) + buf_bytes(w->ctr) + buf_bytes(w->scan_tmp) + buf_bytes(w->ms_seen) +
-         buf_bytes(w->ms_front) + buf_bytes(w->ms_next) + size_t(w->g->n) * 5;  // + hub list
+         buf_bytes(w->ms_front) + buf_bytes(w->ms_next) + buf_bytes(w->dctl) +
+         buf_bytes(w->dtiles) + size_t(w->g->n) * 5;  // + hub list
 }
 
 enum QState { Q_PENDING = 0, Q_RUNNING = 1, Q_DONE = 2, Q_RELEASED = 3 };

@@ -59,6 +59,61 @@ def test_rmat_parity(inputs_mod, oracle_mod, scale, TH):
     G.close()
 
 
+def test_profiled_and_captured_levels_agree(inputs_mod, oracle_mod):
+    """The search runs its levels as captured graphs, or (profile = 1) as
+    direct launches timed kernel by kernel; both give the oracle's depths, the
+    same level records and the same counts of kernels that had work."""
+    n, src, dst, O = _rmat(inputs_mod, oracle_mod, 14)
+    label = O.components()
+    G = GpuGraph(src, dst, n, threshold=16)
+    for s in inputs_mod.pick_sources(src, dst, n, 8, seed=77).tolist():
+        want, _ = O.bfs(s, want_parent=False)
+        runs = []
+        for prof in (False, True, False):
+            depth, parent, st = G.bfs(s, want_stats=True, profile=prof)
+            np.testing.assert_array_equal(depth, want)
+            assert O.check(s, depth, parent, label)[0] == 0
+            runs.append(st)
+        a, b = runs[0], runs[1]
+        log(f"profiled vs captured s={s} levels={a['num_levels']}")
+        assert a["num_levels"] == b["num_levels"]
+        assert a["levels"] == b["levels"]
+        assert (a["reached"], a["edges_cc"]) == (b["reached"], b["edges_cc"])
+        for k in a["kernels"]:
+            assert a["kernels"][k]["launches"] == b["kernels"][k]["launches"], k
+            assert a["kernels"][k]["bytes"] == b["kernels"][k]["bytes"], k
+        assert b["kernels"]["prev_normal"]["ms"] > 0
+        assert runs[2]["levels"] == a["levels"]
+    G.close()
+
+
+def test_level_graph_replays_and_recapture(inputs_mod, oracle_mod):
+    """Captured level graphs replayed over many searches with eager work in
+    between, then re-captured for other output buffers: every search matches
+    the oracle."""
+    d = lib()
+    n, src, dst, O = _rmat(inputs_mod, oracle_mod, 12)
+    G = GpuGraph(src, dst, n, threshold=8)
+    torch = G.torch
+    srcs = inputs_mod.pick_sources(src, dst, n, 4, seed=91).tolist()
+    want = {s: O.bfs(s, want_parent=False)[0] for s in srcs}
+    bufs = [(G.depth, G.parent),
+            (torch.empty(n, dtype=torch.int32, device="cuda"),
+             torch.empty(n, dtype=torch.int32, device="cuda"))]
+    junk = torch.zeros(1 << 20, device="cuda")
+    for rnd in range(3):
+        for depth_t, parent_t in bufs:
+            for s in srcs:
+                junk.add_(1.0)                      # eager work between replays
+                d.bfs(G.g, G.ws, s, depth_t, parent_t if rnd != 1 else None,
+                      opts=d.run_opts(want_parent=rnd != 1))
+                torch.cuda.synchronize()
+                np.testing.assert_array_equal(depth_t.cpu().numpy(), want[s],
+                                              err_msg=f"round {rnd} source {s}")
+    assert float(junk[0]) == 3 * 2 * len(srcs)
+    G.close()
+
+
 def test_config1_plain_scale16_64_sources(inputs_mod, oracle_mod):
     """Plain top-down BFS, RMAT scale 16, 64 seeded sources with degree >= 1."""
     n, src, dst, O = _rmat(inputs_mod, oracle_mod, 16)
