@@ -208,7 +208,8 @@ dsbfs_status dsbfs_graph_stats_get(const dsbfs_graph *g, dsbfs_graph_stats *out)
  * 4 normal columns int32[]; 5 delegate row offsets uint64[d+1]; 6 delegate
  * columns int32[]; 7 nd source list int32[n_ndsrc]; 8 dd source mask
  * uint32[ceil(d/32)]; 9 dn source mask uint32[ceil(d/32)]; 10 plain CSR
- * offsets int64[n+1]; 11 plain CSR columns int32[m_dir]; 12 offsets of the
+ * offsets int64[n+1]; 11 plain CSR columns int32[m_dir] (each row ordered
+ * like the dd parts, by neighbour degree); 12 offsets of the
  * nd rows in nd-source-list order int64[n_ndsrc+1]; 13 their columns
  * (delegate IDs) int32[e_nd]; 14 the vertex of each entry of 13 int32[e_nd].
  * Row i of 12/13/14 is the nd part of vertex ndsrc[i]; the bottom-up dn

@@ -354,6 +354,34 @@ __global__ void k_dd_back(const uint64_t *keys, int64_t e_dd, const uint64_t *do
   }
 }
 
+// Keys of every plain-CSR entry: (row, 255 - degree bucket of the
+// neighbour, position in the row). Rows are ascending by neighbour ID, so a
+// stable sort on the row and bucket bits orders each row by neighbour degree,
+// highest first, ties by ascending ID. One wave per row.
+__global__ void k_plain_keys(const int64_t *poff, const int32_t *pcol, const int32_t *deg,
+                             int32_t n, uint64_t *keys) {
+  const int l = lane_id();
+  const int64_t wid = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) / kWave;
+  const int64_t nw = int64_t(gridDim.x) * blockDim.x / kWave;
+  for (int64_t v = wid; v < n; v += nw) {
+    const int64_t beg = poff[v], len = poff[v + 1] - beg;
+    for (int64_t j = l; j < len; j += kWave) {
+      const uint64_t b = 255u - deg_bucket(deg[pcol[beg + j]]);
+      keys[beg + j] = (uint64_t(v) << 32) | (b << 24) | uint64_t(j);
+    }
+  }
+}
+
+// Rebuilds the columns in key order (each row keeps its range).
+__global__ void k_plain_back(const uint64_t *keys, int64_t m, const int64_t *poff,
+                             const int32_t *pcol, int32_t *out) {
+  for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < m;
+       e += int64_t(gridDim.x) * blockDim.x) {
+    const uint64_t key = keys[e];
+    out[e] = pcol[poff[int64_t(key >> 32)] + int64_t(key & 0xffffffu)];
+  }
+}
+
 __global__ void k_dd_len(const uint64_t *doff, int32_t d, int32_t *len) {
   for (int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; k < d;
        k += int64_t(gridDim.x) * blockDim.x)
@@ -659,6 +687,26 @@ Graph *graph_create(const int32_t *src, const int32_t *dst, int64_t g, int32_t n
     if (!o.keep_plain_csr) {
       G->poff.reset();
       G->pcol.reset();
+    } else if (m > 1) {
+      // Plain rows by neighbour degree, highest first: a bottom-up pass over
+      // them (multi-source BFS, the query server) meets hubs first.
+      DevBuf keys, alt, rtmp, col2;
+      keys.alloc(al, size_t(m) * 8, s);
+      alt.alloc(al, size_t(m) * 8, s);
+      rtmp.alloc(al, radix_tmp_bytes(m), s);
+      hipLaunchKernelGGL(k_plain_keys, dim3(8192), dim3(kBS), 0, s, G->poff.as<int64_t>(),
+                         G->pcol.as<int32_t>(), G->deg.as<int32_t>(), n, keys.as<uint64_t>());
+      HIPCHK(hipGetLastError());
+      radix_sort_u64_bits(keys.as<uint64_t>(), alt.as<uint64_t>(), m, 24, 63, rtmp.p, s);
+      alt.reset();
+      rtmp.reset();
+      col2.alloc(al, size_t(m) * 4, s);
+      hipLaunchKernelGGL(k_plain_back, dim3(grid_for(m, kBS, 16384)), dim3(kBS), 0, s,
+                         keys.as<uint64_t>(), m, G->poff.as<int64_t>(), G->pcol.as<int32_t>(),
+                         col2.as<int32_t>());
+      HIPCHK(hipGetLastError());
+      HIPCHK(hipStreamSynchronize(s));
+      std::swap(G->pcol, col2);
     }
     HIPCHK(hipStreamSynchronize(s));
 

@@ -198,6 +198,36 @@ def _deg_bucket(x):
     return min(lg * 8 + frac, 255)
 
 
+def _buckets(deg):
+    """Vectorized _deg_bucket."""
+    deg = np.asarray(deg, dtype=np.int64)
+    out = np.zeros(deg.shape, dtype=np.int64)
+    m = deg > 1
+    lg = np.zeros(deg.shape, dtype=np.int64)
+    lg[m] = np.floor(np.log2(deg[m])).astype(np.int64)
+    hi = m & (lg >= 3)
+    lo = m & (lg < 3)
+    frac = np.zeros(deg.shape, dtype=np.int64)
+    frac[hi] = (deg[hi] >> (lg[hi] - 3)) & 7
+    frac[lo] = (deg[lo] << (3 - lg[lo])) & 7
+    out[m] = np.minimum(lg[m] * 8 + frac[m], 255)
+    return out
+
+
+def _check_degree_ordered_rows(off, col, want_col, deg):
+    """Every row holds the oracle's neighbours, ordered by neighbour degree
+    bucket (highest first), ties by ascending ID."""
+    off = np.asarray(off, dtype=np.int64)
+    n = len(off) - 1
+    row = np.repeat(np.arange(n), np.diff(off))
+    order = np.lexsort((col, row))
+    np.testing.assert_array_equal(col[order], want_col)
+    b = 255 - _buckets(deg[col])
+    same = row[1:] == row[:-1]
+    ok = (b[1:] > b[:-1]) | ((b[1:] == b[:-1]) & (col[1:] > col[:-1]))
+    assert np.all(ok | ~same)
+
+
 def _decode(off):
     off = off.astype(np.uint64)
     start = (off & np.uint64((1 << 40) - 1)).astype(np.int64)
@@ -221,7 +251,7 @@ def test_builder_layout_matches_oracle_split(inputs_mod, oracle_mod, scale, TH):
     np.testing.assert_array_equal(g.export(1, np.int32), r["did"])
     np.testing.assert_array_equal(g.export(2, np.int32), np.nonzero(r["did"] >= 0)[0])
     np.testing.assert_array_equal(g.export(10, np.int64), O.off)
-    np.testing.assert_array_equal(g.export(11, np.int32), O.col)
+    _check_degree_ordered_rows(O.off, g.export(11, np.int32), O.col, O.degrees())
     ns, nf = _decode(g.export(3, np.uint64))
     ncol = g.export(4, np.int32)
     nn_len = np.diff(r["nn_off"])
