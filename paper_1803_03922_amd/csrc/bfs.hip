@@ -403,18 +403,19 @@ __device__ __forceinline__ int64_t seg_search(const int64_t *pre, int64_t cnt, i
 }
 
 // Top-down from the delegate frontier over dd and/or dn. Delegate degrees span
-// a wide range, so the work is balanced over edges: every thread takes runs of
-// consecutive edges of the frontier's concatenated lists, located by a binary
-// search in the prefix sum of their lengths (merge-path style partitioning).
-constexpr int kRun = 4;
-
+// a wide range, so the work is balanced over edges: the frontier's selected
+// row parts, concatenated, are cut into one contiguous range per block, and a
+// block takes 256 consecutive edges per step, one per lane. Lanes of a wave
+// mostly share a row, so the row lookups broadcast and the column reads
+// coalesce. Each wave finds the row of its first edge once by binary search
+// in the prefix sum of the part lengths and walks forward from there.
 __global__ void __launch_bounds__(kBS) k_td_deleg(const int32_t *dlist, const int64_t *dscan,
                                                   const LevelCtr *curc, const uint64_t *doff,
                                                   const int32_t *dcol, const int32_t *vid_of,
                                                   const DevCtl *c, Out out, uint32_t *Vn,
                                                   uint32_t *Cd, int32_t *Qnext, LevelCtr *cur) {
   if (c->done || !(c->dd_td || c->dn_td)) return;
-  const int dd_td = c->dd_td, dn_td = c->dn_td;
+  const int dd_td = c->dd_td;
   out.level1 = c->level1;
   __shared__ int32_t qbuf[kQCap];
   __shared__ int qcount;
@@ -424,44 +425,49 @@ __global__ void __launch_bounds__(kBS) k_td_deleg(const int32_t *dlist, const in
   qa.init();
   const int64_t nd = int64_t(curc->nd_list);
   const int64_t E = dscan[nd];
-  const int64_t nruns = (E + kRun - 1) / kRun;
+  const int w = threadIdx.x / kWave, l = lane_id();
   unsigned long long cl_n = 0, cl_d = 0, edges = 0;
-  const int64_t stride = int64_t(gridDim.x) * blockDim.x;
-  for (int64_t r0 = int64_t(blockIdx.x) * blockDim.x; r0 < nruns; r0 += stride) {
-    const int64_t r = r0 + threadIdx.x;
-    int64_t e = r * kRun;
-    const int64_t eend = min(e + kRun, E);
-    int64_t idx = r < nruns ? seg_search(dscan, nd, e) : 0;
-    for (int t = 0; t < kRun; ++t, ++e) {
-      bool won = false;
-      int32_t v = 0;
-      if (r < nruns && e < eend) {
-        while (dscan[idx + 1] <= e) ++idx;
-        const int32_t k = dlist[idx];
-        const int64_t j = e - dscan[idx];
-        const uint64_t w0 = doff[k];
-        const int64_t beg = row_start(w0), dd = row_first(w0);
-        const int64_t p = dd_td ? beg + j : beg + dd + j;
-        const bool is_dd = dd_td && j < dd;
-        const int32_t x = dcol[p];
-        ++edges;
-        if (is_dd) {
-          if (bit_claim(Cd, uint32_t(x))) {
-            out.put(vid_of[x], vid_of[k]);
-            ++cl_d;
-          }
-        } else {
-          won = bit_claim(Vn, uint32_t(x));
-          if (won) {
-            v = x;
-            out.put(x, vid_of[k]);
-            ++cl_n;
-          }
-        }
-      }
-      qa.push(won, v);
+  // block range [bs, be), a multiple of the block width long
+  const int64_t per = (E + gridDim.x - 1) / gridDim.x;
+  const int64_t bchunk = (per + kBS - 1) / kBS * kBS;
+  const int64_t bs = int64_t(blockIdx.x) * bchunk, be = min(bs + bchunk, E);
+  int64_t idx = 0;  // row of the wave's first edge in the current step
+  if (bs + w * kWave < be) idx = seg_search(dscan, nd, bs + w * kWave);
+  for (int64_t b0 = bs; b0 < be; b0 += kBS) {
+    const int64_t e = b0 + threadIdx.x;
+    const bool valid = e < be;
+    int64_t my = idx;
+    int32_t x = 0, pk = 0;
+    bool is_dd = false;
+    if (valid) {
+      while (dscan[my + 1] <= e) ++my;
+      const int32_t k = dlist[my];
+      const int64_t j = e - dscan[my];
+      const uint64_t w0 = doff[k];
+      const int64_t beg = row_start(w0), dd = row_first(w0);
+      is_dd = dd_td && j < dd;
+      x = dcol[dd_td ? beg + j : beg + dd + j];
+      pk = vid_of[k];
+      ++edges;
     }
-    qa.maybe_flush(kBS * kRun + kBS);
+    // the next step's first edge lies at or after this step's last one
+    idx = lane_read(my, kWave - 1);
+    // claims: a cheap visited test first (most edges lead to vertices already
+    // claimed), then one atomic per run of lanes sharing a bitmap word
+    const bool want_d = valid && is_dd && !bit_test(Cd, uint32_t(x));
+    const bool want_n = valid && !is_dd && !bit_test(Vn, uint32_t(x));
+    const bool won_d = wave_bit_claim(Cd, uint32_t(x), valid && is_dd, want_d);
+    const bool won_n = wave_bit_claim(Vn, uint32_t(x), valid && !is_dd, want_n);
+    if (won_d) {
+      out.put(vid_of[x], pk);
+      ++cl_d;
+    }
+    if (won_n) {
+      out.put(x, pk);
+      ++cl_n;
+    }
+    qa.push(won_n, x);
+    qa.maybe_flush(kBS);
   }
   qa.flush();
   // units: -, edges, normals claimed, delegates claimed
@@ -900,6 +906,9 @@ __global__ void __launch_bounds__(kBS) k_dscan_down(const int32_t *len, int64_t 
 // ---------------------------------------------------------------------------
 // plain top-down (mode 0)
 // ---------------------------------------------------------------------------
+// Runs of consecutive edges per thread in the plain top-down expansion.
+constexpr int kRun = 4;
+
 __global__ void k_plain_len(const int32_t *Q, const LevelCtr *prev, const int64_t *poff,
                             int32_t *len) {
   const int64_t qn = int64_t(prev->qn_next);

@@ -174,6 +174,11 @@ __device__ __forceinline__ uint32_t dpp_u32(uint32_t old, uint32_t v) {
 __device__ __forceinline__ int32_t lane_read(int32_t v, int src) {
   return __builtin_amdgcn_readlane(v, src);
 }
+__device__ __forceinline__ int64_t lane_read(int64_t v, int src) {
+  const uint32_t lo = uint32_t(__builtin_amdgcn_readlane(int(uint32_t(uint64_t(v))), src));
+  const uint32_t hi = uint32_t(__builtin_amdgcn_readlane(int(uint32_t(uint64_t(v) >> 32)), src));
+  return int64_t((static_cast<uint64_t>(hi) << 32) | lo);
+}
 __device__ __forceinline__ unsigned long long lane_read(unsigned long long v, int src) {
   const uint32_t lo = uint32_t(__builtin_amdgcn_readlane(int(uint32_t(v)), src));
   const uint32_t hi = uint32_t(__builtin_amdgcn_readlane(int(uint32_t(v >> 32)), src));
