@@ -2,15 +2,19 @@
 //
 // Several graphs stay resident on the device. Clients submit single-source
 // queries; one scheduler thread serves them:
-//   batched mode: each graph runs a 64-lane multi-source BFS one level at a
-//     time. At every level boundary the lanes whose frontier ran empty
-//     complete their queries, and waiting queries take the free lanes at once
-//     (their lane bits are cleared, their result rows filled with -1, their
-//     sources seeded), so requests that arrive while others are running join
-//     the work already on the GPU. Each graph advances on its own stream and
-//     at its own pace: a graph whose level has finished is relaunched at
-//     once, so the levels of different graphs overlap on the device and a
-//     small graph never waits for a large one.
+//   batched mode: each graph runs a cohort of up to 64 lanes, a multi-source
+//     BFS advanced one level at a time. At every level boundary the lanes
+//     whose frontier ran empty complete their queries, and waiting queries
+//     take free lanes (their lane bits are cleared, their result rows filled
+//     with -1, their sources seeded) while the cohort is in its first
+//     kJoinLevels levels, or start the next cohort once it has drained. So
+//     requests that arrive while others are running join work already on
+//     the GPU, while the lanes of a cohort stay within a few levels of each
+//     other. Each cohort
+//     advances on its own stream and at its own pace: one whose level has
+//     finished is relaunched at once, so the levels of different cohorts and
+//     graphs overlap on the device and a small graph never waits for a
+//     large one.
 //   plain mode: one query at a time, single-source direction-optimized BFS.
 //   adaptive mode: batched, except that a graph with no batch running serves
 //     a short queue one query at a time with single-source DOBFS. A batch is
@@ -88,33 +92,56 @@ struct Query {
   QState state = Q_PENDING;
 };
 
-struct GState {
-  Graph *g = nullptr;
+// One batch of up to 64 lanes on one graph: its lane state, stream and
+// level bookkeeping. Lanes of a cohort start within a few levels of each
+// other, so its bottom-up levels keep their early exit.
+struct Cohort {
   Workspace *ws = nullptr;
   hipStream_t stream = nullptr;
-  hipEvent_t ev = nullptr;
-  std::deque<Query *> pending;
+  hipEvent_t ev = nullptr, ev0 = nullptr;
   Query *lane[64] = {};
   int32_t start_level[64] = {};
-  uint64_t used = 0, live = 0;
+  uint64_t used = 0, live = 0, new_lanes = 0;
   int64_t active = 0;
   int32_t L = 0;
-  std::vector<int32_t *> free_bufs;
+  int32_t batch_start = 0;  // level at which the running batch began
   unsigned long long *ctl_dev = nullptr, *ctl_host = nullptr;
   int32_t *seed_dev = nullptr, *seed_host = nullptr;
-  size_t bytes = 0;
   bool launched = false;
-  uint64_t new_lanes = 0;
+};
+// Cohorts per graph. With two, a query that misses the join window of the
+// running cohort starts the other at once; measured on the served mix (RMAT
+// 18-24 + ER 2^22), two half-full cohorts repeat each other's bottom-up scans
+// and both p50 and p99 latency came out higher than with one.
+constexpr int kCohorts = 1;
+
+struct GState {
+  Graph *g = nullptr;
+  Cohort co[kCohorts];
+  std::deque<Query *> pending;
+  std::vector<int32_t *> free_bufs;
+  size_t bytes = 0;
   // adaptive mode: cost model and the query served alone this round
-  hipEvent_t ev0 = nullptr;
   double t_single_ms = 0, t_level_ms = 0, levels_per_query = 0;
   Query *single = nullptr;
+  bool running() const {
+    for (const Cohort &c : co)
+      if (c.used) return true;
+    return false;
+  }
+  bool in_flight() const {
+    for (const Cohort &c : co)
+      if (c.launched) return true;
+    return false;
+  }
 };
 
 // running average with weight 1/4 for the newest sample (first sample taken as is)
 void ema(double &avg, double x) { avg = avg > 0 ? 0.75 * avg + 0.25 * x : x; }
 
 }  // namespace
+
+constexpr int32_t kJoinLevels = 2;
 
 struct Server {
   dsbfs_server_opts o{};
@@ -167,7 +194,7 @@ struct Server {
 
   bool has_work() const {
     for (const GState *G : graphs)
-      if (G->used || !G->pending.empty()) return true;
+      if (G->running() || !G->pending.empty()) return true;
     return false;
   }
 
@@ -181,12 +208,17 @@ struct Server {
     return double(G->pending.size()) * G->t_single_ms < batch_ms;
   }
 
-  // Admits waiting queries of G at its level boundary (caller holds mu):
-  // in adaptive mode the head query alone when that is cheaper, else into
-  // free lanes.
+  // Admits waiting queries of G (caller holds mu): in adaptive mode the head
+  // query alone when that is cheaper, else into free lanes of a cohort at a
+  // level boundary, preferring a running cohort still within its first
+  // kJoinLevels levels, then an idle one. A query that joined a batch later
+  // would have a tiny frontier while the batch's bottom-up levels cover the
+  // graph, and every unseen vertex would scan its whole row for its bit.
   void admit(GState *G, uint64_t lane_cap, bool adaptive, int64_t t) {
-    G->new_lanes = 0;
-    if (adaptive && !G->used && !G->pending.empty() && serve_alone(G)) {
+    for (Cohort &c : G->co)
+      if (!c.launched) c.new_lanes = 0;
+    if (G->pending.empty()) return;
+    if (adaptive && !G->running() && !G->in_flight() && serve_alone(G)) {
       Query *q = G->pending.front();
       int32_t *row = take_row(G);
       if (!row) return;  // budget: wait for releases
@@ -198,77 +230,91 @@ struct Server {
       G->single = q;
       return;
     }
-    uint64_t free = ~G->used & lane_cap;
-    while (free && !G->pending.empty()) {
-      Query *q = G->pending.front();
-      int32_t *row = take_row(G);
-      if (!row) break;  // budget: wait for releases
-      G->pending.pop_front();
-      const int i = __builtin_ctzll(free);
-      free &= free - 1;
-      q->res = row;
-      q->admit = q->start = t;
-      q->state = Q_RUNNING;
-      q->batched = 1;
-      G->lane[i] = q;
-      G->start_level[i] = G->L;
-      G->seed_host[i] = q->source;
-      G->new_lanes |= 1ull << i;
+    for (int pass = 0; pass < 2 && !G->pending.empty(); ++pass) {
+      for (Cohort &c : G->co) {
+        if (c.launched || G->pending.empty()) continue;
+        const bool joinable = c.used && c.L - c.batch_start < kJoinLevels;
+        if (pass == 0 ? !joinable : c.used != 0) continue;
+        if (!c.used) c.batch_start = c.L;
+        uint64_t free = ~c.used & lane_cap;
+        bool no_budget = false;
+        while (free && !G->pending.empty()) {
+          Query *q = G->pending.front();
+          int32_t *row = take_row(G);
+          if (!row) {  // budget: the rest waits for releases
+            no_budget = true;
+            break;
+          }
+          G->pending.pop_front();
+          const int i = __builtin_ctzll(free);
+          free &= free - 1;
+          q->res = row;
+          q->admit = q->start = t;
+          q->state = Q_RUNNING;
+          q->batched = 1;
+          c.lane[i] = q;
+          c.start_level[i] = c.L;
+          c.seed_host[i] = q->source;
+          c.new_lanes |= 1ull << i;
+        }
+        c.used |= c.new_lanes;  // the lanes admitted so far run in any case
+        if (no_budget) return;
+      }
     }
-    G->used |= G->new_lanes;
   }
 
-  // Enqueues one multi-source level of G on its stream.
-  void launch_level(GState *G) {
+  // Enqueues one multi-source level of cohort c of G on its stream.
+  void launch_level(GState *G, Cohort &c) {
     LaneRows r{};
     for (int i = 0; i < 64; ++i) {
-      r.res[i] = G->lane[i] ? G->lane[i]->res : nullptr;
-      r.dval[i] = G->L + 1 - G->start_level[i];
+      r.res[i] = c.lane[i] ? c.lane[i]->res : nullptr;
+      r.dval[i] = c.L + 1 - c.start_level[i];
     }
-    HIPCHK(hipEventRecord(G->ev0, G->stream));
-    if (G->new_lanes) {
-      HIPCHK(hipMemcpyAsync(G->seed_dev, G->seed_host, 64 * sizeof(int32_t),
-                            hipMemcpyHostToDevice, G->stream));
-      ms_level_recycle(G->g, G->ws, G->new_lanes, G->new_lanes, G->new_lanes, G->seed_dev, r,
-                       G->stream);
-      G->live |= G->new_lanes;
-      G->active += __builtin_popcountll(G->new_lanes);
-      G->new_lanes = 0;
+    HIPCHK(hipEventRecord(c.ev0, c.stream));
+    if (c.new_lanes) {
+      HIPCHK(hipMemcpyAsync(c.seed_dev, c.seed_host, 64 * sizeof(int32_t),
+                            hipMemcpyHostToDevice, c.stream));
+      ms_level_recycle(G->g, c.ws, c.new_lanes, c.new_lanes, c.new_lanes, c.seed_dev, r,
+                       c.stream);
+      c.live |= c.new_lanes;
+      c.active += __builtin_popcountll(c.new_lanes);
+      c.new_lanes = 0;
     }
-    ms_level(G->g, G->ws, G->live, G->active, o.ms.bu_permille, r, G->ctl_dev, G->stream);
-    HIPCHK(hipMemcpyAsync(G->ctl_host, G->ctl_dev, 4 * sizeof(unsigned long long),
-                          hipMemcpyDeviceToHost, G->stream));
-    HIPCHK(hipEventRecord(G->ev, G->stream));
-    G->launched = true;
+    ms_level(G->g, c.ws, c.live, c.active, o.ms.bu_permille, r, c.ctl_dev, c.stream);
+    HIPCHK(hipMemcpyAsync(c.ctl_host, c.ctl_dev, 4 * sizeof(unsigned long long),
+                          hipMemcpyDeviceToHost, c.stream));
+    HIPCHK(hipEventRecord(c.ev, c.stream));
+    c.launched = true;
   }
 
-  // Level of G done on the device: complete the lanes whose frontier ran empty.
-  void complete_level(GState *G) {
+  // Level of cohort c done on the device: complete the lanes whose frontier
+  // ran empty.
+  void complete_level(GState *G, Cohort &c) {
     const int64_t t = now_ns();
     float level_ms = 0;
-    HIPCHK(hipEventElapsedTime(&level_ms, G->ev0, G->ev));
+    HIPCHK(hipEventElapsedTime(&level_ms, c.ev0, c.ev));
     ema(G->t_level_ms, double(level_ms));
-    const uint64_t alive = G->ctl_host[1];
+    const uint64_t alive = c.ctl_host[1];
     std::lock_guard<std::mutex> lk(mu);
-    uint64_t fin = G->used & ~alive;
+    uint64_t fin = c.used & ~alive;
     while (fin) {
       const int i = __builtin_ctzll(fin);
       fin &= fin - 1;
-      Query *q = G->lane[i];
-      q->levels = G->L + 1 - G->start_level[i];
+      Query *q = c.lane[i];
+      q->levels = c.L + 1 - c.start_level[i];
       ema(G->levels_per_query, double(q->levels));
       finish(q, G, t);
-      G->lane[i] = nullptr;
-      G->used &= ~(1ull << i);
+      c.lane[i] = nullptr;
+      c.used &= ~(1ull << i);
     }
-    G->live = alive & G->used;
-    G->active = int64_t(G->ctl_host[0]);
-    G->L += 1;
-    G->launched = false;
+    c.live = alive & c.used;
+    c.active = int64_t(c.ctl_host[0]);
+    c.L += 1;
+    c.launched = false;
   }
 
-  // Every graph advances on its own: a graph whose level finished is admitted
-  // into and relaunched at once, without waiting for the other graphs.
+  // Every cohort of every graph advances on its own: one whose level finished
+  // is admitted into and relaunched at once, without waiting for the others.
   void loop_batched() {
     const uint64_t lane_cap = o.max_lanes >= 64 ? ~0ull : ((1ull << o.max_lanes) - 1ull);
     const bool adaptive = o.batched == 2;
@@ -277,30 +323,33 @@ struct Server {
     ro.want_parent = 0;
     while (true) {
       bool in_flight = false;
-      for (const GState *G : graphs) in_flight = in_flight || G->launched;
+      for (const GState *G : graphs) in_flight = in_flight || G->in_flight();
       {
         std::unique_lock<std::mutex> lk(mu);
         if (!in_flight) cv_work.wait(lk, [&] { return stop || has_work(); });
         if (stop) return;
         const int64_t t = now_ns();
         for (GState *G : graphs)
-          if (!G->launched && !G->single) admit(G, lane_cap, adaptive, t);
+          if (!G->single) admit(G, lane_cap, adaptive, t);
       }
       bool started = false;
       for (GState *G : graphs)
-        if (!G->launched && G->used) {
-          launch_level(G);
-          started = true;
-        }
-      // queries served alone run while the levels of other graphs are in flight
+        for (Cohort &c : G->co)
+          if (!c.launched && c.used) {
+            launch_level(G, c);
+            started = true;
+          }
+      // queries served alone run while the levels of other graphs are in
+      // flight (on the first cohort's workspace, idle when one is chosen)
       bool progressed = false;
       for (GState *G : graphs) {
         Query *q = G->single;
         if (!q) continue;
+        Cohort &c = G->co[0];
         dsbfs_run_stats rs{};
         const int64_t t0 = now_ns();
-        bfs_run(G->g, G->ws, q->source, &ro, q->res, nullptr, &rs, G->stream);
-        HIPCHK(hipStreamSynchronize(G->stream));
+        bfs_run(G->g, c.ws, q->source, &ro, q->res, nullptr, &rs, c.stream);
+        HIPCHK(hipStreamSynchronize(c.stream));
         const int64_t t = now_ns();
         ema(G->t_single_ms, double(t - t0) * 1e-6);
         ema(G->levels_per_query, double(rs.num_levels));
@@ -310,20 +359,21 @@ struct Server {
         G->single = nullptr;
         progressed = true;
       }
-      for (GState *G : graphs) {
-        if (!G->launched) continue;
-        const hipError_t e = hipEventQuery(G->ev);
-        if (e == hipErrorNotReady) continue;
-        HIPCHK(e);
-        complete_level(G);
-        progressed = true;
-      }
+      for (GState *G : graphs)
+        for (Cohort &c : G->co) {
+          if (!c.launched) continue;
+          const hipError_t e = hipEventQuery(c.ev);
+          if (e == hipErrorNotReady) continue;
+          HIPCHK(e);
+          complete_level(G, c);
+          progressed = true;
+        }
       if (progressed) {
         cv_done.notify_all();
         continue;
       }
       in_flight = false;
-      for (const GState *G : graphs) in_flight = in_flight || G->launched;
+      for (const GState *G : graphs) in_flight = in_flight || G->in_flight();
       if (in_flight) {
         if (!started) std::this_thread::sleep_for(std::chrono::microseconds(20));
       } else {
@@ -362,8 +412,8 @@ struct Server {
         q->admit = q->start = now_ns();
         q->state = Q_RUNNING;
       }
-      bfs_run(G->g, G->ws, q->source, &ro, q->res, nullptr, nullptr, G->stream);
-      HIPCHK(hipStreamSynchronize(G->stream));
+      bfs_run(G->g, G->co[0].ws, q->source, &ro, q->res, nullptr, nullptr, G->co[0].stream);
+      HIPCHK(hipStreamSynchronize(G->co[0].stream));
       {
         std::lock_guard<std::mutex> lk(mu);
         finish(q, G, now_ns());
@@ -401,25 +451,52 @@ Server *server_create(const dsbfs_server_opts *o, const dsbfs_allocator *alloc) 
   return S;
 }
 
+namespace {
+
+// Lane state, stream, events and small control buffers of one cohort.
+void cohort_init(Cohort &c, Graph *g, bool batched) {
+  HIPCHK(hipStreamCreateWithFlags(&c.stream, hipStreamNonBlocking));
+  HIPCHK(hipEventCreate(&c.ev));
+  HIPCHK(hipEventCreate(&c.ev0));
+  c.ws = workspace_create(g, 64);
+  if (batched) ms_level_prepare(g, c.ws, c.stream);
+  HIPCHK(hipMalloc(reinterpret_cast<void **>(&c.ctl_dev), 4 * sizeof(unsigned long long)));
+  HIPCHK(hipHostMalloc(reinterpret_cast<void **>(&c.ctl_host), 4 * sizeof(unsigned long long),
+                       hipHostMallocDefault));
+  HIPCHK(hipMalloc(reinterpret_cast<void **>(&c.seed_dev), 64 * sizeof(int32_t)));
+  HIPCHK(hipHostMalloc(reinterpret_cast<void **>(&c.seed_host), 64 * sizeof(int32_t),
+                       hipHostMallocDefault));
+  HIPCHK(hipStreamSynchronize(c.stream));
+}
+
+void cohort_free(Cohort &c) {
+  if (c.stream) (void)hipStreamSynchronize(c.stream);
+  if (c.ws) workspace_destroy(c.ws);
+  if (c.ctl_dev) (void)hipFree(c.ctl_dev);
+  if (c.ctl_host) (void)hipHostFree(c.ctl_host);
+  if (c.seed_dev) (void)hipFree(c.seed_dev);
+  if (c.seed_host) (void)hipHostFree(c.seed_host);
+  if (c.ev) (void)hipEventDestroy(c.ev);
+  if (c.ev0) (void)hipEventDestroy(c.ev0);
+  if (c.stream) (void)hipStreamDestroy(c.stream);
+  c = Cohort();
+}
+
+}  // namespace
+
 void server_add_graph(Server *S, Graph *g, int32_t *id) {
   if (!g->pcol.p && g->m > 0 && S->o.batched)
     fail(DSBFS_ERR_INVALID_ARG, "batched serving needs graphs built with keep_plain_csr");
   GState *G = new GState();
   try {
     G->g = g;
-    HIPCHK(hipStreamCreateWithFlags(&G->stream, hipStreamNonBlocking));
-    HIPCHK(hipEventCreate(&G->ev));
-    HIPCHK(hipEventCreate(&G->ev0));
-    G->ws = workspace_create(g, 64);
-    if (S->o.batched) ms_level_prepare(g, G->ws, G->stream);
-    HIPCHK(hipMalloc(reinterpret_cast<void **>(&G->ctl_dev), 4 * sizeof(unsigned long long)));
-    HIPCHK(hipHostMalloc(reinterpret_cast<void **>(&G->ctl_host), 4 * sizeof(unsigned long long),
-                         hipHostMallocDefault));
-    HIPCHK(hipMalloc(reinterpret_cast<void **>(&G->seed_dev), 64 * sizeof(int32_t)));
-    HIPCHK(hipHostMalloc(reinterpret_cast<void **>(&G->seed_host), 64 * sizeof(int32_t),
-                         hipHostMallocDefault));
-    HIPCHK(hipStreamSynchronize(G->stream));
-    G->bytes = graph_footprint(g) + workspace_footprint(G->ws);
+    // the plain server needs one search workspace; batched modes one per cohort
+    const int nco = S->o.batched ? kCohorts : 1;
+    G->bytes = graph_footprint(g);
+    for (int i = 0; i < nco; ++i) {
+      cohort_init(G->co[i], g, S->o.batched != 0);
+      G->bytes += workspace_footprint(G->co[i].ws);
+    }
     std::lock_guard<std::mutex> lk(S->mu);
     if (S->used_bytes + G->bytes > S->o.hbm_budget_bytes)
       fail(DSBFS_ERR_BUDGET, "graph does not fit the HBM budget");
@@ -427,14 +504,7 @@ void server_add_graph(Server *S, Graph *g, int32_t *id) {
     *id = int32_t(S->graphs.size());
     S->graphs.push_back(G);
   } catch (...) {
-    if (G->ws) workspace_destroy(G->ws);
-    if (G->ctl_dev) (void)hipFree(G->ctl_dev);
-    if (G->ctl_host) (void)hipHostFree(G->ctl_host);
-    if (G->seed_dev) (void)hipFree(G->seed_dev);
-    if (G->seed_host) (void)hipHostFree(G->seed_host);
-    if (G->ev) (void)hipEventDestroy(G->ev);
-    if (G->ev0) (void)hipEventDestroy(G->ev0);
-    if (G->stream) (void)hipStreamDestroy(G->stream);
+    for (Cohort &c : G->co) cohort_free(c);
     delete G;
     throw;
   }
@@ -514,17 +584,9 @@ void server_destroy(Server *S) {
     delete kv.second;
   }
   for (GState *G : S->graphs) {
-    (void)hipStreamSynchronize(G->stream);
+    for (Cohort &c : G->co) cohort_free(c);
     for (int32_t *p : G->free_bufs) (void)hipFree(p);
-    workspace_destroy(G->ws);
     graph_destroy(G->g);
-    (void)hipFree(G->ctl_dev);
-    (void)hipHostFree(G->ctl_host);
-    (void)hipFree(G->seed_dev);
-    (void)hipHostFree(G->seed_host);
-    (void)hipEventDestroy(G->ev);
-    (void)hipEventDestroy(G->ev0);
-    (void)hipStreamDestroy(G->stream);
     delete G;
   }
   delete S;
