@@ -185,6 +185,24 @@ __device__ __forceinline__ unsigned long long lane_read(unsigned long long v, in
   return (static_cast<unsigned long long>(hi) << 32) | lo;
 }
 
+// OR of a 64-bit value over the wave, returned to every lane (DPP inclusive
+// OR-scan of each half, then lane 63 through a scalar register). The whole
+// wave must be active.
+__device__ __forceinline__ uint32_t wave_or_dpp_u32(uint32_t x) {
+  x |= dpp_u32<kDppRowShr + 1>(0u, x);
+  x |= dpp_u32<kDppRowShr + 2>(0u, x);
+  x |= dpp_u32<kDppRowShr + 4>(0u, x);
+  x |= dpp_u32<kDppRowShr + 8>(0u, x);
+  x |= dpp_u32<kDppBcast15, 0xa>(0u, x);
+  x |= dpp_u32<kDppBcast31, 0xc>(0u, x);
+  return uint32_t(__builtin_amdgcn_readlane(int(x), kWave - 1));
+}
+__device__ __forceinline__ uint64_t wave_or_all(uint64_t x) {
+  const uint32_t lo = wave_or_dpp_u32(uint32_t(x));
+  const uint32_t hi = wave_or_dpp_u32(uint32_t(x >> 32));
+  return (uint64_t(hi) << 32) | lo;
+}
+
 // Inclusive prefix sum across the 64 lanes of a wave.
 template <class T> __device__ __forceinline__ T wave_incl_scan(T v) {
   const int l = lane_id();

@@ -111,8 +111,7 @@ __device__ __forceinline__ unsigned long long block_sum_u64(unsigned long long v
 __device__ __forceinline__ void put_lanes(int32_t *depth, int32_t n, int64_t row0, int32_t v,
                                           uint64_t bits, int32_t val, bool valid) {
   const uint64_t mine = valid ? bits : 0ull;
-  uint64_t all = mine;  // lanes present anywhere in the wave
-  for (int o = 32; o > 0; o >>= 1) all |= __shfl_xor(all, o, kWave);
+  uint64_t all = wave_or_all(mine);  // lanes present anywhere in the wave
   while (all) {
     const int i = __ffsll(static_cast<long long>(all)) - 1;
     all &= all - 1;
@@ -122,10 +121,7 @@ __device__ __forceinline__ void put_lanes(int32_t *depth, int32_t n, int64_t row
 
 constexpr int kHub = 64;
 
-__device__ __forceinline__ uint64_t wave_or(uint64_t x) {
-  for (int o = 32; o > 0; o >>= 1) x |= __shfl_xor(x, o, kWave);
-  return x;
-}
+__device__ __forceinline__ uint64_t wave_or(uint64_t x) { return wave_or_all(x); }
 
 // Bottom-up for the 64 vertices of a wave (one per lane; lanes with want = 0
 // take no part): the rows are prefix-summed across the wave and walked 64
@@ -684,8 +680,7 @@ namespace {
 
 __device__ __forceinline__ void put_rows(const LaneRows &r, int32_t v, uint64_t bits, bool valid) {
   const uint64_t mine = valid ? bits : 0ull;
-  uint64_t all = mine;
-  for (int o = 32; o > 0; o >>= 1) all |= __shfl_xor(all, o, kWave);
+  uint64_t all = wave_or_all(mine);
   while (all) {
     const int i = __ffsll(static_cast<long long>(all)) - 1;
     all &= all - 1;
@@ -697,7 +692,7 @@ __device__ __forceinline__ void lv_flush(const MsLevel &a, unsigned long long ac
                                          unsigned long long edges) {
   act = wave_sum(act);
   edges = wave_sum(edges);
-  for (int o = 32; o > 0; o >>= 1) lor |= __shfl_xor(lor, o, kWave);
+  lor = wave_or_all(lor);
   if (lane_id() == 0) {
     if (act) atomicAdd(&a.ctl[0], act);
     if (lor) atomicOr(&a.ctl[1], (unsigned long long)lor);
