@@ -90,14 +90,14 @@ inline size_t dtiles_half(int64_t d) {
   return (nb * 8 + 255) / 256 * 256;
 }
 
-__host__ __device__ inline uint64_t mix64_hd(uint64_t z) {
+__host__ __device__ inline uint64_t mix64(uint64_t z) {
   z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
   z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
   return z ^ (z >> 31);
 }
 
 // Backward workload estimate |U|(q+s)/q (Section IV-B), 0 when q or |U| is 0.
-__host__ __device__ inline double bv_estimate_hd(int64_t U, int64_t q, int64_t s) {
+__host__ __device__ inline double bv_estimate(int64_t U, int64_t q, int64_t s) {
   if (q <= 0 || U <= 0) return 0.0;
   return double(U) * (double(q) + double(s)) / double(q);
 }
@@ -425,7 +425,7 @@ __global__ void __launch_bounds__(kBS) k_td_deleg(const int32_t *dlist, const in
   qa.init();
   const int64_t nd = int64_t(curc->nd_list);
   const int64_t E = dscan[nd];
-  const int w = threadIdx.x / kWave, l = lane_id();
+  const int w = threadIdx.x / kWave;
   unsigned long long cl_n = 0, cl_d = 0, edges = 0;
   // block range [bs, be), a multiple of the block width long
   const int64_t per = (E + gridDim.x - 1) / gridDim.x;
@@ -760,11 +760,11 @@ __global__ void k_decide(DevCtl *c, const LevelCtr *cur, const LevelCtr *prev,
   const int64_t S[3] = {c->rem[0], c->rem[1], c->rem[2]};
   double BV[3];
   for (int k = 0; k < 3; ++k) {
-    BV[k] = bv_estimate_hd(U[k], q[k], S[k]);
+    BV[k] = bv_estimate(U[k], q[k], S[k]);
     int d = c->dir[k];
     if (c->forced == 1) d = 0;
     else if (c->forced == 2) d = L >= 1 ? 1 : 0;
-    else if (c->forced == 3) d = int(mix64_hd(c->forced_seed + uint64_t(L) * 3 + k) & 1);
+    else if (c->forced == 3) d = int(mix64(c->forced_seed + uint64_t(L) * 3 + k) & 1);
     else if (q[k] > 0) {
       if (d == 0 && double(FV[k]) > c->f0[k] * BV[k]) d = 1;
       else if (d == 1 && double(FV[k]) < c->f1[k] * BV[k]) d = 0;
@@ -966,11 +966,6 @@ __global__ void __launch_bounds__(kBS) k_plain_expand(const int32_t *Q, const Le
   block_add4(cur->units[DSBFS_K_PLAIN], entries, edges, claimed, 0, sh);
 }
 
-uint64_t mix64(uint64_t z) {
-  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
-  z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
-  return z ^ (z >> 31);
-}
 
 // Number of resident waves worth of blocks for grid-stride kernels.
 int stride_grid() { return 256 * 8; }
@@ -1039,11 +1034,6 @@ static dsbfs_run_opts default_opts() {
 
 void run_opts_default(dsbfs_run_opts *o) { *o = default_opts(); }
 
-// Backward workload estimate |U|(q+s)/q (Section IV-B), 0 when q or |U| is 0.
-static double bv_estimate(int64_t U, int64_t q, int64_t s) {
-  if (q <= 0 || U <= 0) return 0.0;
-  return double(U) * (double(q) + double(s)) / double(q);
-}
 
 // Per-kernel launch counts, unit totals and (optionally) HIP-event timing.
 struct Prof {
