@@ -211,9 +211,10 @@ dsbfs_status dsbfs_graph_stats_get(const dsbfs_graph *g, dsbfs_graph_stats *out)
  * offsets int64[n+1]; 11 plain CSR columns int32[m_dir] (each row ordered
  * like the dd parts, by neighbour degree); 12 offsets of the
  * nd rows in nd-source-list order int64[n_ndsrc+1]; 13 their columns
- * (delegate IDs) int32[e_nd]; 14 the vertex of each entry of 13 int32[e_nd].
- * Row i of 12/13/14 is the nd part of vertex ndsrc[i]; the bottom-up dn
- * kernel streams it.
+ * (delegate IDs) int32[e_nd]; 14 the first entry of each of those rows as
+ * a pair (delegate ID, its vertex) int32[2 n_ndsrc]. Row i of 12/13 and pair
+ * i of 14 belong to vertex ndsrc[i]; the bottom-up dn kernel probes 14 and
+ * walks 12/13 only on a miss.
  * Row offsets are packed: bits 0..39 = start of the row, bits 40..63 = length
  * of its first part (nn for normal rows, dd for delegate rows); the row ends
  * at the start of the next row. Normal row v holds nn neighbours (vertex IDs)

@@ -485,9 +485,10 @@ __global__ void __launch_bounds__(kBS) k_td_deleg(const int32_t *dlist, const in
 // compacted (as positions) for the next bottom-up level.
 __global__ void __launch_bounds__(kBS) k_bu_normal(const DevCtl *c, int32_t *c0, int32_t *c1,
                                                    const int32_t *ndsrc, const int64_t *nds_off,
-                                                   const int32_t *nds_col, const int32_t *nds_vid,
-                                                   const uint32_t *Fd, Out out, uint32_t *Vn,
-                                                   int32_t *Qnext, LevelCtr *cur) {
+                                                   const int32_t *nds_col, const int2 *nds_first,
+                                                   const int32_t *vid_of, const uint32_t *Fd,
+                                                   Out out, uint32_t *Vn, int32_t *Qnext,
+                                                   LevelCtr *cur) {
   if (c->done || !c->dn_bu) return;
   // first pass: every position of the nd source list (dense); later passes:
   // the positions the previous pass left unvisited
@@ -527,23 +528,26 @@ __global__ void __launch_bounds__(kBS) k_bu_normal(const DevCtl *c, int32_t *c0,
       // visited test, and the parent candidate is fetched beside the
       // frontier test.
       v = ndsrc[pos];
-      beg = nds_off[pos];
-      const int64_t end = nds_off[pos + 1];
       // Rows start with their highest-degree delegate, the likeliest to be in
-      // the frontier: a hit there skips the wave's walk for this row. Its
-      // frontier bit is tested whether or not the candidate turns out to be
-      // visited, so that its loads overlap the visited test instead of
-      // following it; its vertex sits beside it in the row copy.
-      const int32_t k0 = nds_col[beg];
-      pk0 = nds_vid[beg];
+      // the frontier: a hit there skips the wave's walk for this row. The
+      // first entry and its vertex come from a dense array (8 bytes per
+      // candidate, read in list order); its frontier bit is tested whether
+      // or not the candidate turns out to be visited, so that the loads
+      // overlap the visited test instead of following it.
+      const int2 f = nds_first[pos];
+      const int32_t k0 = f.x;
+      pk0 = f.y;
       const bool f0 = bit_test(Fd, uint32_t(k0));
       ++reads;
       visited = bit_test(Vn, uint32_t(v));
-      // selects, not branches: both tests stay on the straight path
       hit0 = (!visited && f0) ? k0 : -1;
-      len = (visited || f0) ? 0 : int32_t(end - beg);
       scanned += !visited;
       edges += !visited;
+      if (!visited && !f0) {
+        // a miss: the rest of the row is walked below
+        beg = nds_off[pos] + 1;
+        len = int32_t(nds_off[pos + 1] - beg);
+      }
     }
     const int32_t incl = wave_incl_scan(len);
     const int32_t T = lane_read(incl, kWave - 1);
@@ -569,7 +573,7 @@ __global__ void __launch_bounds__(kBS) k_bu_normal(const DevCtl *c, int32_t *c0,
     // candidates come in ascending vertex order: claim word by word
     const bool won = wave_bit_claim(Vn, uint32_t(v), ok, found);
     if (won) {
-      out.put(v, hit0 >= 0 ? pk0 : nds_vid[beg + (fe - (incl - len))]);
+      out.put(v, hit0 >= 0 ? pk0 : vid_of[nds_col[beg + (fe - (incl - len))]]);
       ++claimed;
     }
     qa.push(won, v);
@@ -1144,8 +1148,9 @@ struct LevelLaunch {
         b = begin();
         hipLaunchKernelGGL(k_bu_normal, dim3(SG), dim3(kBS), 0, s, static_cast<const DevCtl *>(c),
                            C[0], C[1], g->ndsrc.as<int32_t>(), g->nds_off.as<int64_t>(),
-                           g->nds_col.as<int32_t>(), g->nds_vid.as<int32_t>(),
-                           static_cast<const uint32_t *>(Fd), out, Vn, Q[p ^ 1], cur);
+                           g->nds_col.as<int32_t>(), g->nds_first.as<int2>(),
+                           g->vid_of.as<int32_t>(), static_cast<const uint32_t *>(Fd), out, Vn,
+                           Q[p ^ 1], cur);
         HIPCHK(hipGetLastError());
         end(DSBFS_K_BU_NORMAL, b);
       }

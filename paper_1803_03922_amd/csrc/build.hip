@@ -261,21 +261,21 @@ __global__ void k_nds_len(const int32_t *ndsrc, int64_t cnt, const int32_t *cnt_
 }
 
 // Copies the nd part of row ndsrc[i] to row i of the source-list-ordered copy,
-// with the vertex of each delegate beside it (the parent a hit writes).
+// and its first entry (delegate ID, then that delegate's vertex) to pair i of
+// nds_first, the dense array a bottom-up pass probes first.
 __global__ void k_nds_fill(const int32_t *ndsrc, int64_t cnt, const uint64_t *noff,
                            const int32_t *ncol, const int32_t *vid_of, const int64_t *nds_off,
-                           int32_t *nds_col, int32_t *nds_vid) {
+                           int32_t *nds_col, int32_t *nds_first) {
   for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < cnt;
        i += int64_t(gridDim.x) * blockDim.x) {
     const int32_t v = ndsrc[i];
     const uint64_t w0 = noff[v];
     const int64_t from = row_start(w0) + row_first(w0);
     const int64_t to = nds_off[i], len = nds_off[i + 1] - to;
-    for (int64_t j = 0; j < len; ++j) {
-      const int32_t k = ncol[from + j];
-      nds_col[to + j] = k;
-      nds_vid[to + j] = vid_of[k];
-    }
+    for (int64_t j = 0; j < len; ++j) nds_col[to + j] = ncol[from + j];
+    // rows of the list are never empty
+    nds_first[2 * i] = ncol[from];
+    nds_first[2 * i + 1] = vid_of[ncol[from]];
   }
 }
 
@@ -658,7 +658,7 @@ Graph *graph_create(const int32_t *src, const int32_t *dst, int64_t g, int32_t n
       stmp.alloc(al, scan_tmp_bytes(nsrc), s);
       G->nds_off.alloc(al, size_t(nsrc + 1) * 8, s);
       G->nds_col.alloc(al, size_t(e_nd) * 4, s);
-      G->nds_vid.alloc(al, size_t(e_nd) * 4, s);
+      G->nds_first.alloc(al, size_t(nsrc) * 8, s);
       if (nsrc > 0) {
         hipLaunchKernelGGL(k_nds_len, dim3(grid_for(nsrc, kBS, 8192)), dim3(kBS), 0, s,
                            G->ndsrc.as<int32_t>(), nsrc, cnt_del.as<int32_t>(),
@@ -671,7 +671,7 @@ Graph *graph_create(const int32_t *src, const int32_t *dst, int64_t g, int32_t n
                            G->ndsrc.as<int32_t>(), nsrc, G->noff.as<uint64_t>(),
                            G->ncol.as<int32_t>(), G->vid_of.as<int32_t>(),
                            G->nds_off.as<int64_t>(), G->nds_col.as<int32_t>(),
-                           G->nds_vid.as<int32_t>());
+                           G->nds_first.as<int32_t>());
         HIPCHK(hipGetLastError());
       }
       HIPCHK(hipStreamSynchronize(s));
@@ -750,7 +750,7 @@ void graph_export(const Graph *G, int32_t which, void *host_out, int64_t cap, in
     case 11: b = &G->pcol; nb = G->pcol.p ? G->m * 4 : 0; break;
     case 12: b = &G->nds_off; nb = (G->st.n_ndsrc + 1) * 8; break;
     case 13: b = &G->nds_col; nb = G->st.e_nd * 4; break;
-    case 14: b = &G->nds_vid; nb = G->st.e_nd * 4; break;
+    case 14: b = &G->nds_first; nb = G->st.n_ndsrc * 8; break;
     default: fail(DSBFS_ERR_INVALID_ARG, "unknown array index");
   }
   *bytes = nb;
