@@ -214,7 +214,9 @@ dsbfs_status dsbfs_graph_stats_get(const dsbfs_graph *g, dsbfs_graph_stats *out)
  * (delegate IDs) int32[e_nd]; 14 the first entry of each of those rows as
  * a pair (delegate ID, its vertex) int32[2 n_ndsrc]. Row i of 12/13 and pair
  * i of 14 belong to vertex ndsrc[i]; the bottom-up dn kernel probes 14 and
- * walks 12/13 only on a miss.
+ * walks 12/13 only on a miss; 15 the first entry of each delegate's dd part
+ * as a pair (delegate ID, its vertex), (-1, -1) if the part is empty,
+ * int32[2 d], probed first by the bottom-up dd kernel.
  * Row offsets are packed: bits 0..39 = start of the row, bits 40..63 = length
  * of its first part (nn for normal rows, dd for delegate rows); the row ends
  * at the start of the next row. Normal row v holds nn neighbours (vertex IDs)

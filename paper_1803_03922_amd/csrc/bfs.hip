@@ -600,7 +600,8 @@ __global__ void __launch_bounds__(kBS) k_bu_normal(const DevCtl *c, int32_t *c0,
 // word.
 __global__ void __launch_bounds__(kBS) k_bu_deleg(const int32_t *dcand, const LevelCtr *curc,
                                                   const uint64_t *doff, const int32_t *dcol,
-                                                  const uint32_t *Fd, const uint32_t *Fn,
+                                                  const int2 *dd_first, const uint32_t *Fd,
+                                                  const uint32_t *Fn,
                                                   const int32_t *vid_of, const DevCtl *c,
                                                   Out out, uint32_t *Cd, LevelCtr *cur) {
   if (c->done || !(c->dd_bu || c->nd_bu)) return;
@@ -624,17 +625,18 @@ __global__ void __launch_bounds__(kBS) k_bu_deleg(const int32_t *dcand, const Le
     if (ok) {
       k = dcand[i];
       const uint64_t w0 = doff[k], w1 = doff[k + 1];
-      vk = vid_of[k];  // fetched beside the row bounds
+      vk = vid_of[k];                    // fetched beside the row bounds,
+      const int2 f = dd_first[k];        // as is the dense first dd entry
       const int64_t beg = row_start(w0);
       mid = beg + row_first(w0);
       p = dd_bu ? beg : mid;
       const int64_t hi = nd_bu ? row_start(w1) : mid;
       if (p < hi) {
         ++cands;
-        const int32_t x = dcol[p];
-        ++edges;
         const bool in_dd = p < mid;
-        px = in_dd ? vid_of[x] : x;  // the parent if this entry is a hit
+        const int32_t x = in_dd ? f.x : dcol[p];
+        ++edges;
+        px = in_dd ? f.y : x;  // the parent if this entry is a hit
         if (in_dd ? bit_test(Fd, uint32_t(x)) : bit_test(Fn, uint32_t(x))) hit = p;
         else ++p;
         // delegate degrees are below 2^24, so 64 rows sum below 2^31
@@ -1161,9 +1163,9 @@ struct LevelLaunch {
                          ws->dcand.as<int32_t>(), cur);
       hipLaunchKernelGGL(k_bu_deleg, dim3(SG), dim3(kBS), 0, s, ws->dcand.as<int32_t>(),
                          static_cast<const LevelCtr *>(cur), g->doff.as<uint64_t>(),
-                         g->dcol.as<int32_t>(), static_cast<const uint32_t *>(Fd),
-                         static_cast<const uint32_t *>(Fn), g->vid_of.as<int32_t>(),
-                         static_cast<const DevCtl *>(c), out, Cd, cur);
+                         g->dcol.as<int32_t>(), g->dd_first.as<int2>(),
+                         static_cast<const uint32_t *>(Fd), static_cast<const uint32_t *>(Fn),
+                         g->vid_of.as<int32_t>(), static_cast<const DevCtl *>(c), out, Cd, cur);
       HIPCHK(hipGetLastError());
       end(DSBFS_K_BU_DELEG, b);
     }

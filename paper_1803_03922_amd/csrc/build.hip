@@ -382,6 +382,20 @@ __global__ void k_plain_back(const uint64_t *keys, int64_t m, const int64_t *pof
   }
 }
 
+// First entry of every dd part (its highest-degree neighbour) and that
+// neighbour's vertex, as a dense pair per delegate; (-1, -1) if the part is
+// empty. The bottom-up dd visit probes it before walking the row.
+__global__ void k_dd_first(const uint64_t *doff, const int32_t *dcol, const int32_t *vid_of,
+                           int32_t d, int32_t *out) {
+  for (int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; k < d;
+       k += int64_t(gridDim.x) * blockDim.x) {
+    const uint64_t w = doff[k];
+    const int32_t x = row_first(w) > 0 ? dcol[row_start(w)] : -1;
+    out[2 * k] = x;
+    out[2 * k + 1] = x >= 0 ? vid_of[x] : -1;
+  }
+}
+
 __global__ void k_dd_len(const uint64_t *doff, int32_t d, int32_t *len) {
   for (int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; k < d;
        k += int64_t(gridDim.x) * blockDim.x)
@@ -638,6 +652,13 @@ Graph *graph_create(const int32_t *src, const int32_t *dst, int64_t g, int32_t n
       HIPCHK(hipGetLastError());
       HIPCHK(hipStreamSynchronize(s));
     }
+    G->dd_first.alloc(al, size_t(d) * 8, s);
+    if (d > 0) {
+      hipLaunchKernelGGL(k_dd_first, dim3(grid_for(d, kBS, 4096)), dim3(kBS), 0, s,
+                         G->doff.as<uint64_t>(), G->dcol.as<int32_t>(), G->vid_of.as<int32_t>(),
+                         int32_t(d), G->dd_first.as<int32_t>());
+      HIPCHK(hipGetLastError());
+    }
     if (d > 0 && e_nd > 1) {
       hipLaunchKernelGGL(k_nd_sort, dim3(grid_for(n, kBS, 16384)), dim3(kBS), 0, s,
                          G->noff.as<uint64_t>(), n, G->did.as<int32_t>(), G->ncol.as<int32_t>(),
@@ -751,6 +772,7 @@ void graph_export(const Graph *G, int32_t which, void *host_out, int64_t cap, in
     case 12: b = &G->nds_off; nb = (G->st.n_ndsrc + 1) * 8; break;
     case 13: b = &G->nds_col; nb = G->st.e_nd * 4; break;
     case 14: b = &G->nds_first; nb = G->st.n_ndsrc * 8; break;
+    case 15: b = &G->dd_first; nb = d * 8; break;
     default: fail(DSBFS_ERR_INVALID_ARG, "unknown array index");
   }
   *bytes = nb;

@@ -90,6 +90,7 @@ struct Graph {
   // bottom-up passes over the source list stream them: int64 [n_ndsrc+1],
   // int32 [e_nd] delegate IDs.
   DevBuf nds_off, nds_col, nds_first;
+  DevBuf dd_first;  // per delegate: (first dd neighbour, its vertex), or (-1, -1)
   DevBuf poff, pcol;  // plain CSR: int64 offsets [n+1], int32 columns [m]
   int32_t dwords() const { return (d + 31) / 32; }
   int32_t nwords() const { return (n + 31) / 32; }

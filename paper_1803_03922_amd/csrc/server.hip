@@ -68,7 +68,8 @@ size_t graph_footprint(const Graph *g) {
   return buf_bytes(g->deg) + buf_bytes(g->did) + buf_bytes(g->vid_of) + buf_bytes(g->noff) +
          buf_bytes(g->ncol) + buf_bytes(g->doff) + buf_bytes(g->dcol) + buf_bytes(g->ndsrc) +
          buf_bytes(g->ddsrc_mask) + buf_bytes(g->dnsrc_mask) + buf_bytes(g->nds_off) +
-         buf_bytes(g->nds_col) + buf_bytes(g->nds_first) + buf_bytes(g->poff) +
+         buf_bytes(g->nds_col) + buf_bytes(g->nds_first) + buf_bytes(g->dd_first) +
+         buf_bytes(g->poff) +
          buf_bytes(g->pcol);
 }
 

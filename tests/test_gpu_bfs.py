@@ -288,6 +288,13 @@ def test_builder_layout_matches_oracle_split(inputs_mod, oracle_mod, scale, TH):
     for i, v in enumerate(nd_src.tolist()):   # the row's own nd part, in the same order
         assert nds_col[nds_off[i]:nds_off[i + 1]].tolist() == \
             ncol[ns[v] + nf[v]:ns[v + 1]].tolist()
+    ddf = g.export(15, np.int32).reshape(-1, 2)
+    assert len(ddf) == d
+    for k in range(d):
+        if df[k] > 0:
+            assert ddf[k, 0] == dcol[ds[k]] and ddf[k, 1] == vid[ddf[k, 0]]
+        else:
+            assert ddf[k].tolist() == [-1, -1]
     first = g.export(14, np.int32).reshape(-1, 2)
     assert len(first) == len(nd_src)
     if len(nd_src):
