@@ -148,6 +148,30 @@ def test_config2_do_scale22(inputs_mod, oracle_mod):
     G.close()
 
 
+def test_config3_scale26_sampled(inputs_mod, oracle_mod):
+    """RMAT scale 26 (2.1e9 directed edges, within 2% of 2^31), TH 32,
+    parents, as the bench runs it (captured level graphs): the first of its
+    seeded sources against the oracle, depths bit-exact, parents by the
+    invariants, and the component's size and edge count."""
+    n, src, dst, O = _rmat(inputs_mod, oracle_mod, 26)
+    log("scale 26 oracle graph built")
+    G = GpuGraph(src, dst, n, threshold=32, keep_plain=False)
+    sources = inputs_mod.pick_sources(src, dst, n, 64, seed=1003)
+    del src, dst
+    assert G.stats["m_dir"] == O.m and O.m > 2 * 10 ** 9
+    deg = O.degrees()
+    for s in sources.tolist()[:1]:
+        want, _ = O.bfs(s, want_parent=False)
+        depth, parent, st = G.bfs(s, want_stats=True)
+        log(f"scale 26 s={s} levels={st['num_levels']}")
+        np.testing.assert_array_equal(depth, want)
+        assert O.check(s, depth, parent, None)[0] == 0
+        reached = want >= 0
+        assert st["reached"] == int(reached.sum())
+        assert st["edges_cc"] == int(deg[reached].sum() // 2)
+    G.close()
+
+
 def test_schedule_and_threshold_invariance(inputs_mod, oracle_mod):
     """Direction never changes depths (Section IV-B), nor does TH."""
     n, src, dst, O = _rmat(inputs_mod, oracle_mod, 14)
