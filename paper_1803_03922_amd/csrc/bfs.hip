@@ -730,16 +730,10 @@ __global__ void k_close(uint32_t *Vd, uint32_t *Fd, const uint32_t *Cd, int32_t 
 // ---------------------------------------------------------------------------
 __global__ void k_ctl_init(DevCtl *c, DevCtl init) { *c = init; }
 
-// Direction decision of Section IV-B for dd, dn, nd (indices 0, 1, 2) from
-// this level's previsit counts, in FP64 with the same expression as the
-// oracle's replay, and the plan of the rest of the level. One thread.
-__global__ void k_decide(DevCtl *c, const LevelCtr *cur, const LevelCtr *prev,
-                         LevelStatus *hs) {
-  if (threadIdx.x != 0 || c->done) return;
+// The decision itself (one thread), into the level's status record.
+__device__ void decide_level(DevCtl *__restrict__ c, const LevelCtr *__restrict__ cur,
+                             const LevelCtr *__restrict__ prev, LevelStatus *st) {
   const int32_t L = c->level;
-  // the previous level's kernels are complete: their work units
-  for (int k = 0; k < DSBFS_NUM_KERNELS; ++k)
-    for (int j = 0; j < 4; ++j) c->units[k][j] += prev->units[k][j];
   const int64_t qn = int64_t(prev->qn_next), fdn = int64_t(cur->nd_list);
   c->units[DSBFS_K_PREV_NORMAL][0] += qn;
   c->units[DSBFS_K_PREV_DELEG][0] += fdn;
@@ -750,7 +744,6 @@ __global__ void k_decide(DevCtl *c, const LevelCtr *cur, const LevelCtr *prev,
     c->units[DSBFS_K_BU_NORMAL][4] += prev->nc_next;
     c->nc_pending = 0;
   }
-  LevelStatus *st = hs + (L & (kStatusSlots - 1));
   if (qn == 0 && fdn == 0) {
     c->done = 1;
     st->level = L;
@@ -819,6 +812,30 @@ __global__ void k_decide(DevCtl *c, const LevelCtr *cur, const LevelCtr *prev,
   for (int i = 0; i < 8; ++i) st->plan[i] = plan[i];
   st->level = L;
   st->done = 0;
+}
+
+// Direction decision of Section IV-B for dd, dn, nd (indices 0, 1, 2) from
+// this level's previsit counts, in FP64 with the same expression as the
+// oracle's replay, and the plan of the rest of the level. One wave: the work
+// units are summed by 36 lanes, the decision is made by lane 0 into an LDS
+// record, and the record goes to pinned host memory one word per lane.
+__global__ void k_decide(DevCtl *c, const LevelCtr *cur, const LevelCtr *prev,
+                         LevelStatus *hs) {
+  if (c->done) return;
+  __shared__ LevelStatus rec;
+  __shared__ int32_t slot;
+  const int t = threadIdx.x;
+  // the previous level's kernels are complete: their work units
+  if (t < DSBFS_NUM_KERNELS * 4) c->units[t / 4][t % 4] += prev->units[t / 4][t % 4];
+  __syncthreads();
+  if (t == 0) {
+    decide_level(c, cur, prev, &rec);
+    slot = rec.level & (kStatusSlots - 1);
+  }
+  __syncthreads();
+  const uint32_t *from = reinterpret_cast<const uint32_t *>(&rec);
+  uint32_t *to = reinterpret_cast<uint32_t *>(hs + slot);
+  for (int i = t; i < int(sizeof(LevelStatus) / 4); i += blockDim.x) to[i] = from[i];
 }
 
 // Exclusive prefix sum of the top-down row lengths of the frontier delegates
