@@ -29,9 +29,17 @@ namespace dsbfs {
 
 namespace {
 
+// Arrival counters of the grid barrier, one per 128-byte line so that the
+// groups' atomics do not meet on one address.
+constexpr int kBarGroups = 32;
+struct alignas(128) BarSlot {
+  unsigned long long count;  // 64-bit: never wraps within a launch
+  unsigned long long pad[15];
+};
+
 struct MsCtl {
-  unsigned int bar_count;
-  unsigned int bar_gen;
+  BarSlot grp[kBarGroups];     // arrivals per block group (monotonic)
+  BarSlot top;                 // groups complete (monotonic)
   unsigned int err;            // 1: a barrier wait timed out
   unsigned int pad;
   unsigned long long td_count;   // frontier vertices listed for a top-down level
@@ -60,32 +68,38 @@ struct MsArgs {
 
 __device__ __forceinline__ long long wall_ticks() { return wall_clock64(); }
 
-// Grid-wide barrier: block leaders count arrivals on ctl->bar_count; the last
-// one resets the count and bumps the generation the others wait on. Fences
-// make every plain store before the barrier visible to every block after it.
-// Returns false (everywhere) once any wait has exceeded the bound.
+// Grid-wide barrier in two levels: block b counts its arrival on group
+// b % kBarGroups; the group's last arrival counts on `top`, and everyone waits
+// for `top` to reach the epoch's target. Counters only grow (the launch starts
+// them at zero), so an arrival's ticket names its epoch and nothing is reset.
+// Fences on both sides make every plain store before the barrier visible to
+// every block after it; the wait itself polls with relaxed loads, since an
+// acquiring load per poll would invalidate the L2 under the blocks still at
+// work. Returns false (everywhere) once any wait has exceeded the bound.
 __device__ bool grid_sync(MsCtl *ctl, long long timeout_ticks) {
   __shared__ int ok;
   __syncthreads();
   if (threadIdx.x == 0) {
     __threadfence();
-    const unsigned int g = __hip_atomic_load(&ctl->bar_gen, __ATOMIC_ACQUIRE,
-                                             __HIP_MEMORY_SCOPE_AGENT);
-    const unsigned int arrived = atomicAdd(&ctl->bar_count, 1u) + 1u;
-    if (arrived == gridDim.x) {
-      __hip_atomic_store(&ctl->bar_count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned long long G = gridDim.x;
+    const unsigned long long grp = blockIdx.x % kBarGroups;
+    const unsigned long long gsize = G / kBarGroups + (grp < G % kBarGroups ? 1u : 0u);
+    const unsigned long long ngroups = G < kBarGroups ? G : kBarGroups;
+    const unsigned long long ticket = atomicAdd(&ctl->grp[grp].count, 1ull);
+    const unsigned long long target = (ticket / gsize + 1u) * ngroups;
+    if (ticket % gsize == gsize - 1u) {
       __threadfence();
-      atomicAdd(&ctl->bar_gen, 1u);
-    } else {
-      const long long t0 = wall_ticks();
-      while (__hip_atomic_load(&ctl->bar_gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g) {
-        if (__hip_atomic_load(&ctl->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
-        if (wall_ticks() - t0 > timeout_ticks) {
-          atomicOr(&ctl->err, 1u);
-          break;
-        }
-        __builtin_amdgcn_s_sleep(1);
+      atomicAdd(&ctl->top.count, 1ull);
+    }
+    const long long t0 = wall_ticks();
+    while (__hip_atomic_load(&ctl->top.count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <
+           target) {
+      if (__hip_atomic_load(&ctl->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
+      if (wall_ticks() - t0 > timeout_ticks) {
+        atomicOr(&ctl->err, 1u);
+        break;
       }
+      __builtin_amdgcn_s_sleep(1);
     }
     __threadfence();
     ok = __hip_atomic_load(&ctl->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0;
