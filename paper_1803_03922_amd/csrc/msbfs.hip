@@ -56,7 +56,8 @@ struct MsArgs {
   const int32_t *sources;  // device copy, k entries
   int32_t k;
   int32_t *depth;          // [k][n]
-  uint64_t *seen, *fa, *fb;
+  uint64_t *seen;
+  uint64_t *ring;           // kRing slots of n masks: lanes first reaching each vertex at level j
   int32_t *tdlist;         // frontier vertices of a top-down level, n entries
   int64_t *tdscan;         // prefix of their degrees, n + 1 entries
   const int32_t *hubs;     // vertices of degree > kHub, scanned by whole waves bottom-up
@@ -120,16 +121,55 @@ __device__ __forceinline__ unsigned long long block_sum_u64(unsigned long long v
   return t;
 }
 
-// Writes depth `val` for every lane set in `bits` of vertex v: one masked,
-// row-coalesced store per lane across the wave's consecutive vertices.
-__device__ __forceinline__ void put_lanes(int32_t *depth, int32_t n, int64_t row0, int32_t v,
-                                          uint64_t bits, int32_t val, bool valid) {
-  const uint64_t mine = valid ? bits : 0ull;
-  uint64_t all = wave_or_all(mine);  // lanes present anywhere in the wave
-  while (all) {
-    const int i = __ffsll(static_cast<long long>(all)) - 1;
-    all &= all - 1;
-    if ((mine >> i) & 1ull) depth[(row0 + i) * int64_t(n) + v] = val;
+// Ring of per-level lane masks: slot j % kRing holds, for every vertex, the
+// lanes that first reach it at level j. That array is level j's frontier and
+// also the record from which depths are written, so depths are stored once
+// per batch in one dense pass (or when the ring is about to wrap) instead of
+// one masked store per level.
+constexpr int kRing = 16;
+
+__device__ __forceinline__ uint64_t *ring_slot(const MsArgs &a, int32_t j) {
+  return a.ring + int64_t(j & (kRing - 1)) * a.n;
+}
+
+// Writes depth j for the lanes of ring levels [f, t) (t - f < kRing) and, when
+// `final`, -1 for the lanes that never reached the vertex. A wave takes 64
+// consecutive vertices and stores one 256-byte row segment per batch lane.
+__device__ void flush_depth(const MsArgs &a, int64_t row0, uint64_t lanemask, int32_t f,
+                            int32_t t, bool final, int64_t tid, int64_t nthreads,
+                            int64_t nv_iter) {
+  const int32_t n = a.n;
+  for (int64_t it = 0; it < nv_iter; ++it) {
+    const int64_t v = tid + it * nthreads;
+    const bool valid = v < n;
+    // bit b of a lane's level offset j - f, as four lane masks
+    uint64_t q0 = 0, q1 = 0, q2 = 0, q3 = 0, got = 0, miss = 0;
+    if (valid) {
+      for (int32_t j = f; j < t; ++j) {
+        const uint64_t m = ring_slot(a, j)[v];
+        const int32_t o = j - f;
+        got |= m;
+        q0 |= (o & 1) ? m : 0ull;
+        q1 |= (o & 2) ? m : 0ull;
+        q2 |= (o & 4) ? m : 0ull;
+        q3 |= (o & 8) ? m : 0ull;
+      }
+      if (final) miss = ~a.seen[v] & lanemask;
+    }
+    const uint64_t wr = got | miss;
+    uint64_t all = wave_or_all(wr);
+    while (all) {
+      const int i = __ffsll(static_cast<long long>(all)) - 1;
+      all &= all - 1;
+      if ((wr >> i) & 1ull) {
+        const int32_t d = ((miss >> i) & 1ull)
+                              ? -1
+                              : f + int32_t((q0 >> i) & 1ull) + (int32_t((q1 >> i) & 1ull) << 1) +
+                                    (int32_t((q2 >> i) & 1ull) << 2) +
+                                    (int32_t((q3 >> i) & 1ull) << 3);
+        a.depth[(row0 + i) * int64_t(n) + v] = d;
+      }
+    }
   }
 }
 
@@ -203,11 +243,13 @@ __global__ void __launch_bounds__(1024) k_msbfs(MsArgs a) {
     const int lanes = min(64, a.k - b * 64);
     const uint64_t lanemask = lanes == 64 ? ~0ull : ((1ull << lanes) - 1ull);
     const int64_t row0 = int64_t(b) * 64;
-    // reset lane state
+    // reset lane state: seen, level 0 (the sources) and level 1 (a top-down
+    // first level ORs into it)
+    uint64_t *const lv0 = ring_slot(a, 0), *const lv1 = ring_slot(a, 1);
     for (int64_t v = tid; v < n; v += nthreads) {
       a.seen[v] = 0;
-      a.fa[v] = 0;
-      a.fb[v] = 0;
+      lv0[v] = 0;
+      lv1[v] = 0;
     }
     if (blockIdx.x == 0 && threadIdx.x < 3) {
       a.ctl->active[threadIdx.x] = 0;
@@ -218,19 +260,32 @@ __global__ void __launch_bounds__(1024) k_msbfs(MsArgs a) {
     if (tid < lanes) {
       const int32_t s = a.sources[row0 + tid];
       atomicOr(reinterpret_cast<unsigned long long *>(&a.seen[s]), 1ull << tid);
-      atomicOr(reinterpret_cast<unsigned long long *>(&a.fa[s]), 1ull << tid);
-      a.depth[(row0 + tid) * int64_t(n) + s] = 0;
+      atomicOr(reinterpret_cast<unsigned long long *>(&lv0[s]), 1ull << tid);
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) a.ctl->active[0] = (unsigned long long)lanes;
     if (!grid_sync(a.ctl, a.timeout_ticks)) return;
-    uint64_t *fcur = a.fa, *fnext = a.fb;
     int64_t active = lanes;
+    int32_t flushed = 0;  // levels [0, flushed) have their depths written
     // Lanes whose frontier is empty are finished: no vertex waits for them.
     uint64_t live = lanemask;
     const int64_t wid = tid / kWave, nwaves = nthreads / kWave;
     const int l = lane_id();
-    for (int32_t L = 0;; ++L) {
-      const int32_t val = L + 1;
+    int32_t L = 0;
+    for (;; ++L) {
+      // slot L + 2 is cleared at the end of this level and slot L + 1 written
+      // during it: the levels they held must have their depths out first
+      if (L + 2 - kRing >= flushed) {
+        flush_depth(a, row0, lanemask, flushed, L + 1, false, tid, nthreads, nv_iter);
+        flushed = L + 1;
+        if (!grid_sync(a.ctl, a.timeout_ticks)) return;
+      }
+      uint64_t *const fcur = ring_slot(a, L), *const fnext = ring_slot(a, L + 1);
+      // the rolling count slot level L + 1 adds into; every block read it
+      // (for level L - 2) before the barrier that ended level L - 1
+      if (blockIdx.x == 0 && threadIdx.x == 0) {
+        a.ctl->active[(L + 2) % 3] = 0;
+        a.ctl->alive[(L + 2) % 3] = 0;
+      }
       unsigned long long act = 0;
       uint64_t lor = 0;
       if (active <= a.bu_threshold) {
@@ -286,21 +341,14 @@ __global__ void __launch_bounds__(1024) k_msbfs(MsArgs a) {
         }
         if (!grid_sync(a.ctl, a.timeout_ticks)) return;
         if (blockIdx.x == 0 && threadIdx.x == 0) a.ctl->td_count = 0;
-        // close: fold next into seen, write depths, clear the old frontier
-        for (int64_t it = 0; it < nv_iter; ++it) {
-          const int64_t v = tid + it * nthreads;
-          const bool valid = v < n;
-          uint64_t nw = 0;
-          if (valid) {
-            const uint64_t s0 = a.seen[v];
-            nw = fnext[v] & ~s0;
-            fnext[v] = nw;
-            a.seen[v] = s0 | nw;
-            fcur[v] = 0;
-            act += nw != 0;
-            lor |= nw;
-          }
-          put_lanes(a.depth, n, row0, int32_t(valid ? v : 0), nw, val, valid);
+        // close: fold next into seen
+        for (int64_t v = tid; v < n; v += nthreads) {
+          const uint64_t s0 = a.seen[v];
+          const uint64_t nw = fnext[v] & ~s0;
+          fnext[v] = nw;
+          if (nw) a.seen[v] = s0 | nw;
+          act += nw != 0;
+          lor |= nw;
         }
       } else {
         // bottom-up with the close fused in: w is only written by the thread
@@ -327,7 +375,6 @@ __global__ void __launch_bounds__(1024) k_msbfs(MsArgs a) {
             act += nw != 0;
             lor |= nw;
           }
-          put_lanes(a.depth, n, row0, int32_t(valid ? w : 0), nw, val, valid);
         }
         for (int64_t h = wid; h < a.nhubs; h += nwaves) {
           const int32_t w = a.hubs[h];
@@ -351,7 +398,6 @@ __global__ void __launch_bounds__(1024) k_msbfs(MsArgs a) {
             act += nw != 0;
             lor |= nw;
           }
-          if ((nw >> l) & 1ull) a.depth[(row0 + l) * int64_t(n) + w] = val;
         }
       }
       const unsigned long long bact = block_sum_u64(act, sh);
@@ -363,29 +409,18 @@ __global__ void __launch_bounds__(1024) k_msbfs(MsArgs a) {
                                          __HIP_MEMORY_SCOPE_AGENT));
       live = __hip_atomic_load(&a.ctl->alive[(L + 1) % 3], __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_AGENT);
-      if (blockIdx.x == 0 && threadIdx.x == 0) {
-        a.ctl->active[(L + 2) % 3] = 0;
-        a.ctl->alive[(L + 2) % 3] = 0;
-        atomicAdd(&a.ctl->levels, 1ull);
-      }
-      uint64_t *t = fcur;
-      fcur = fnext;
-      fnext = t;
+      if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(&a.ctl->levels, 1ull);
       if (active == 0) break;
-      // the bottom-up pass overwrote every fnext entry; a top-down pass next
-      // needs its target cleared
+      // a top-down level L + 1 ORs into slot L + 2, which must start at zero
+      // (its scatter comes two barriers after this); a bottom-up level
+      // overwrites every entry itself
       if (active <= a.bu_threshold) {
-        for (int64_t v = tid; v < n; v += nthreads) fnext[v] = 0;
+        uint64_t *const after = ring_slot(a, L + 2);
+        for (int64_t v = tid; v < n; v += nthreads) after[v] = 0;
       }
-      if (!grid_sync(a.ctl, a.timeout_ticks)) return;
     }
-    // unreached: -1 for every lane never seen
-    for (int64_t it = 0; it < nv_iter; ++it) {
-      const int64_t v = tid + it * nthreads;
-      const bool valid = v < n;
-      const uint64_t miss = valid ? (~a.seen[v] & lanemask) : 0ull;
-      put_lanes(a.depth, n, row0, int32_t(valid ? v : 0), miss, -1, valid);
-    }
+    // depths of the levels not yet written, and -1 for lanes never seen
+    flush_depth(a, row0, lanemask, flushed, L + 1, true, tid, nthreads, nv_iter);
     if (!grid_sync(a.ctl, a.timeout_ticks)) return;
   }
   const unsigned long long be = block_sum_u64(edges, sh);
@@ -439,6 +474,7 @@ struct MsGraph {
 
 struct MsState {
   DevBuf ctl, srcs, hubs;
+  DevBuf ring;  // kRing x n lane masks
   int64_t nhubs = -1;  // -1: hub list not built yet
   int32_t cap_k = 0;
   std::map<std::string, MsGraph> graphs;
@@ -471,6 +507,7 @@ static void msbfs_launch(const Graph *g, Workspace *ws, const int32_t *sources, 
   MsState *st = reinterpret_cast<MsState *>(ws->ms_state);
   const Alloc *al = &g->al;
   if (!st->ctl.p) st->ctl.alloc(al, sizeof(MsCtl), s);
+  if (!st->ring.p) st->ring.alloc(al, size_t(kRing) * size_t(g->n) * 8, s);
   if (st->cap_k < k) {
     st->srcs.alloc(al, size_t(k) * 4, s);
     st->cap_k = k;
@@ -511,8 +548,7 @@ static void msbfs_launch(const Graph *g, Workspace *ws, const int32_t *sources, 
   a.k = k;
   a.depth = depth;
   a.seen = ws->ms_seen.as<uint64_t>();
-  a.fa = ws->ms_front.as<uint64_t>();
-  a.fb = ws->ms_next.as<uint64_t>();
+  a.ring = st->ring.as<uint64_t>();
   a.tdlist = ws->dlen.as<int32_t>();    // int32[max(n, d)]
   a.tdscan = ws->dscan.as<int64_t>();   // int64[max(n, d) + 1]
   a.hubs = st->hubs.as<int32_t>();
