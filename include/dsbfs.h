@@ -266,11 +266,14 @@ typedef struct dsbfs_ms_opts {
   int32_t bu_permille;    /* bottom-up when active frontier vertices exceed this
                              many per mille of n (0..1000) */
   int32_t use_graph;      /* 1: capture the launch in a hipGraph and replay it */
+  int32_t lanes_per_batch; /* sources per batch: 64, 128 or 256; 0 = automatic
+                              (the narrowest that holds k, at most 256) */
 } dsbfs_ms_opts;
 
 /*
  * Multi-source BFS from k sources (host int32[k], each in [0, n)), bit-parallel
- * in batches of 64 lanes, all batches in one persistent launch. depth is a
+ * in batches of 64, 128 or 256 lanes, all batches in one persistent launch.
+ * Device memory held by the workspace for it: 17 x n x (lanes / 8) bytes. depth is a
  * device int32[k][n] array: row i gets the hop distances from sources[i]
  * (-1 unreachable), exactly as k single-source searches would. Uses the plain
  * CSR (graph built with keep_plain_csr = 1). opts NULL = tuned/cached

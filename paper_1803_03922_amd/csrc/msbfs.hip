@@ -1,5 +1,7 @@
-// Bit-parallel multi-source BFS: 64 sources per batch as the lanes of a 64-bit
-// mask per vertex (seen, frontier, next), all batches in one persistent launch.
+// Bit-parallel multi-source BFS: 64 x W sources per batch (W = 1, 2 or 4) as
+// the lanes of W 64-bit words per vertex (seen, and a ring of per-level lane
+// sets that serves as frontier and as depth record), all batches in one
+// persistent launch.
 //
 // Not in the paper: the batched form follows the bit-parallel multi-source
 // BFS of Then et al., "The More the Merrier" (PVLDB 8(4), 2014). Each lane's
@@ -8,14 +10,16 @@
 // Per level of a batch:
 //   top-down  (few frontier vertices): every vertex v with frontier[v] != 0
 //             ORs frontier[v] & ~seen[w] into next[w] of each neighbour w,
-//             then a close pass folds next into seen and writes depths;
+//             then a close pass folds next into seen;
 //   bottom-up (otherwise): every vertex w with unseen lanes ORs frontier[v]
 //             of its neighbours until all of its unseen lanes are covered,
-//             and closes itself on the spot (writes next[w], seen[w], depths).
-// Levels and batches are separated by a grid barrier inside one kernel whose
-// grid fits the chip (occupancy-checked); the barrier's wait is bounded, so a
-// grid that is not fully resident ends with an error flag instead of a hang.
-// The launch can be captured once into a hipGraph and replayed.
+//             and closes itself on the spot (writes next[w], seen[w]).
+// Depths are written from the ring once per batch (earlier only if the search
+// runs longer than the ring holds). Levels and batches are separated by a grid
+// barrier inside one kernel whose grid fits the chip (occupancy-checked); the
+// barrier's wait is bounded, so a grid that is not fully resident ends with an
+// error flag instead of a hang. The launch can be captured once into a
+// hipGraph and replayed.
 #include <algorithm>
 #include <chrono>
 #include <cstdio>
@@ -37,6 +41,9 @@ struct alignas(128) BarSlot {
   unsigned long long pad[15];
 };
 
+// A batch runs 64 x W sources as the bits of W 64-bit words per vertex.
+constexpr int kMaxWords = 4;
+
 struct MsCtl {
   BarSlot grp[kBarGroups];     // arrivals per block group (monotonic)
   BarSlot top;                 // groups complete (monotonic)
@@ -44,7 +51,7 @@ struct MsCtl {
   unsigned int pad;
   unsigned long long td_count;   // frontier vertices listed for a top-down level
   unsigned long long active[3];  // vertices with a non-empty next mask, per level (rolling)
-  unsigned long long alive[3];   // lanes with a non-empty next frontier, per level (rolling)
+  unsigned long long alive[3][kMaxWords];  // lanes with a non-empty next frontier (rolling)
   unsigned long long levels;     // levels run, summed over batches
   unsigned long long edges;      // adjacency entries read, summed over batches
 };
@@ -56,8 +63,8 @@ struct MsArgs {
   const int32_t *sources;  // device copy, k entries
   int32_t k;
   int32_t *depth;          // [k][n]
-  uint64_t *seen;
-  uint64_t *ring;           // kRing slots of n masks: lanes first reaching each vertex at level j
+  void *seen;              // LaneSet<W>[n]
+  void *ring;              // kRing slots of LaneSet<W>[n]: lanes first reaching each vertex at level j
   int32_t *tdlist;         // frontier vertices of a top-down level, n entries
   int64_t *tdscan;         // prefix of their degrees, n + 1 entries
   const int32_t *hubs;     // vertices of degree > kHub, scanned by whole waves bottom-up
@@ -121,53 +128,82 @@ __device__ __forceinline__ unsigned long long block_sum_u64(unsigned long long v
   return t;
 }
 
-// Ring of per-level lane masks: slot j % kRing holds, for every vertex, the
+// The lanes of one vertex: W 64-bit words, lane i in bit i % 64 of word i / 64.
+template <int W>
+struct alignas(W == 1 ? 8 : 16) LaneSet {
+  uint64_t w[W];
+};
+
+template <int W>
+__device__ __forceinline__ bool lanes_any(const LaneSet<W> &x) {
+  uint64_t o = 0;
+#pragma unroll
+  for (int j = 0; j < W; ++j) o |= x.w[j];
+  return o != 0;
+}
+
+// Ring of per-level lane sets: slot j % kRing holds, for every vertex, the
 // lanes that first reach it at level j. That array is level j's frontier and
 // also the record from which depths are written, so depths are stored once
 // per batch in one dense pass (or when the ring is about to wrap) instead of
 // one masked store per level.
 constexpr int kRing = 16;
 
-__device__ __forceinline__ uint64_t *ring_slot(const MsArgs &a, int32_t j) {
-  return a.ring + int64_t(j & (kRing - 1)) * a.n;
+template <int W>
+__device__ __forceinline__ LaneSet<W> *ring_slot(const MsArgs &a, int32_t j) {
+  return static_cast<LaneSet<W> *>(a.ring) + int64_t(j & (kRing - 1)) * a.n;
 }
 
 // Writes depth j for the lanes of ring levels [f, t) (t - f < kRing) and, when
 // `final`, -1 for the lanes that never reached the vertex. A wave takes 64
 // consecutive vertices and stores one 256-byte row segment per batch lane.
-__device__ void flush_depth(const MsArgs &a, int64_t row0, uint64_t lanemask, int32_t f,
+// mask[j]: the batch's lanes in word j.
+template <int W>
+__device__ void flush_depth(const MsArgs &a, int64_t row0, const uint64_t *mask, int32_t f,
                             int32_t t, bool final, int64_t tid, int64_t nthreads,
                             int64_t nv_iter) {
   const int32_t n = a.n;
+  const LaneSet<W> *seen = static_cast<const LaneSet<W> *>(a.seen);
   for (int64_t it = 0; it < nv_iter; ++it) {
     const int64_t v = tid + it * nthreads;
     const bool valid = v < n;
-    // bit b of a lane's level offset j - f, as four lane masks
-    uint64_t q0 = 0, q1 = 0, q2 = 0, q3 = 0, got = 0, miss = 0;
+    // bit b of a lane's level offset j - f, as four lane sets
+    LaneSet<W> q0{}, q1{}, q2{}, q3{}, got{}, miss{};
     if (valid) {
       for (int32_t j = f; j < t; ++j) {
-        const uint64_t m = ring_slot(a, j)[v];
+        const LaneSet<W> m = ring_slot<W>(a, j)[v];
         const int32_t o = j - f;
-        got |= m;
-        q0 |= (o & 1) ? m : 0ull;
-        q1 |= (o & 2) ? m : 0ull;
-        q2 |= (o & 4) ? m : 0ull;
-        q3 |= (o & 8) ? m : 0ull;
+#pragma unroll
+        for (int x = 0; x < W; ++x) {
+          got.w[x] |= m.w[x];
+          q0.w[x] |= (o & 1) ? m.w[x] : 0ull;
+          q1.w[x] |= (o & 2) ? m.w[x] : 0ull;
+          q2.w[x] |= (o & 4) ? m.w[x] : 0ull;
+          q3.w[x] |= (o & 8) ? m.w[x] : 0ull;
+        }
       }
-      if (final) miss = ~a.seen[v] & lanemask;
+      if (final) {
+        const LaneSet<W> sv = seen[v];
+#pragma unroll
+        for (int x = 0; x < W; ++x) miss.w[x] = ~sv.w[x] & mask[x];
+      }
     }
-    const uint64_t wr = got | miss;
-    uint64_t all = wave_or_all(wr);
-    while (all) {
-      const int i = __ffsll(static_cast<long long>(all)) - 1;
-      all &= all - 1;
-      if ((wr >> i) & 1ull) {
-        const int32_t d = ((miss >> i) & 1ull)
-                              ? -1
-                              : f + int32_t((q0 >> i) & 1ull) + (int32_t((q1 >> i) & 1ull) << 1) +
-                                    (int32_t((q2 >> i) & 1ull) << 2) +
-                                    (int32_t((q3 >> i) & 1ull) << 3);
-        a.depth[(row0 + i) * int64_t(n) + v] = d;
+#pragma unroll
+    for (int x = 0; x < W; ++x) {
+      const uint64_t wr = got.w[x] | miss.w[x];
+      uint64_t all = wave_or_all(wr);
+      while (all) {
+        const int i = __ffsll(static_cast<long long>(all)) - 1;
+        all &= all - 1;
+        if ((wr >> i) & 1ull) {
+          const int32_t d = ((miss.w[x] >> i) & 1ull)
+                                ? -1
+                                : f + int32_t((q0.w[x] >> i) & 1ull) +
+                                      (int32_t((q1.w[x] >> i) & 1ull) << 1) +
+                                      (int32_t((q2.w[x] >> i) & 1ull) << 2) +
+                                      (int32_t((q3.w[x] >> i) & 1ull) << 3);
+          a.depth[(row0 + 64 * x + i) * int64_t(n) + v] = d;
+        }
       }
     }
   }
@@ -177,124 +213,156 @@ constexpr int kHub = 64;
 
 __device__ __forceinline__ uint64_t wave_or(uint64_t x) { return wave_or_all(x); }
 
-// Bottom-up for the 64 vertices of a wave (one per lane; lanes with want = 0
-// take no part): the rows are prefix-summed across the wave and walked 64
-// entries at a time, so consecutive vertices' rows are read coalesced and 64
-// frontier words are in flight per step. Each vertex's frontier OR collects in
-// an LDS slot; the walk stops once every vertex's wanted lanes are covered.
-// Called by every lane of the wave; returns the lanes found for this lane's
-// vertex. LDS rows are per wave (64 entries each).
-__device__ uint64_t bu_wave(const int64_t *off, const int32_t *col, const uint64_t *fcur,
-                            int64_t w, uint64_t want, int32_t *s_ex, int64_t *s_beg,
-                            unsigned long long *s_want, unsigned long long *s_acc,
-                            unsigned long long &edges) {
+// LDS rows of one wave for the bottom-up walk (64 vertices).
+template <int W>
+struct BuRows {
+  int32_t ex[kWave];           // exclusive prefix of the row lengths
+  int64_t beg[kWave];          // row starts
+  LaneSet<W> want[kWave];      // lanes each vertex still needs
+  unsigned long long acc[kWave][W];  // lanes found so far
+};
+
+// Bottom-up for the 64 vertices of a wave (one per lane; lanes with nothing
+// wanted take no part): the rows are prefix-summed across the wave and walked
+// 64 entries at a time, so consecutive vertices' rows are read coalesced and
+// 64 frontier sets are in flight per step. Each vertex's frontier OR collects
+// in LDS; the walk stops once every vertex's wanted lanes are covered. Called
+// by every lane of the wave; returns the lanes found for this lane's vertex.
+template <int W>
+__device__ LaneSet<W> bu_wave(const int64_t *off, const int32_t *col, const LaneSet<W> *fcur,
+                              int64_t w, const LaneSet<W> &want, BuRows<W> &r,
+                              unsigned long long &edges) {
   const int l = lane_id();
   int32_t len = 0;
   int64_t beg = 0;
-  if (want) {
+  if (lanes_any(want)) {
     beg = off[w];
     len = int32_t(off[w + 1] - beg);
   }
   const int32_t incl = wave_incl_scan(len);
   const int32_t T = lane_read(incl, kWave - 1);
   wave_sync();
-  s_ex[l] = incl - len;
-  s_beg[l] = beg;
-  s_want[l] = want;
-  s_acc[l] = 0;
+  r.ex[l] = incl - len;
+  r.beg[l] = beg;
+  r.want[l] = want;
+#pragma unroll
+  for (int x = 0; x < W; ++x) r.acc[l][x] = 0;
   wave_sync();
+  auto covered = [&](int o, const LaneSet<W> &wl) {
+    bool c = true;
+#pragma unroll
+    for (int x = 0; x < W; ++x) c = c && (r.acc[o][x] & wl.w[x]) == wl.w[x];
+    return c;
+  };
   uint64_t pend = __ballot(len > 0);
   for (int32_t e0 = 0; e0 < T && pend; e0 += kWave) {
     const int32_t e = e0 + l;
     if (e < T) {
-      int lo = 0;
+      int o = 0;
 #pragma unroll
       for (int step = 32; step > 0; step >>= 1) {
-        const int c = lo + step;
-        if (s_ex[c] <= e) lo = c;
+        const int c = o + step;
+        if (r.ex[c] <= e) o = c;
       }
-      const uint64_t wl = s_want[lo];
-      if ((s_acc[lo] & wl) != wl) {
-        const uint64_t m = fcur[col[s_beg[lo] + (e - s_ex[lo])]] & wl;
+      const LaneSet<W> wl = r.want[o];
+      if (!covered(o, wl)) {
+        const LaneSet<W> m = fcur[col[r.beg[o] + (e - r.ex[o])]];
         ++edges;
-        if (m) atomicOr(&s_acc[lo], (unsigned long long)m);
+#pragma unroll
+        for (int x = 0; x < W; ++x) {
+          const uint64_t y = m.w[x] & wl.w[x];
+          if (y) atomicOr(&r.acc[o][x], (unsigned long long)y);
+        }
       }
     }
     wave_sync();
-    pend = __ballot(len > 0 && (s_acc[l] & want) != want);
+    pend = __ballot(len > 0 && !covered(l, want));
   }
-  const uint64_t r = s_acc[l] & want;
+  LaneSet<W> res;
+#pragma unroll
+  for (int x = 0; x < W; ++x) res.w[x] = r.acc[l][x] & want.w[x];
   wave_sync();
-  return r;
+  return res;
 }
 
+template <int W>
 __global__ void __launch_bounds__(1024) k_msbfs(MsArgs a) {
-  __shared__ int32_t s_ex[16][kWave];
-  __shared__ int64_t s_beg[16][kWave];
-  __shared__ unsigned long long s_want[16][kWave], s_acc[16][kWave];
+  __shared__ BuRows<W> s_rows[16];
   __shared__ unsigned long long sh[16];
+  constexpr int kLanes = 64 * W;
   const int32_t n = a.n;
+  LaneSet<W> *const seen = static_cast<LaneSet<W> *>(a.seen);
   const int64_t tid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   const int64_t nthreads = int64_t(gridDim.x) * blockDim.x;
   const int64_t nv_iter = (int64_t(n) + nthreads - 1) / nthreads;
-  const int nbatch = (a.k + 63) / 64;
+  const int nbatch = (a.k + kLanes - 1) / kLanes;
+  const int64_t wid = tid / kWave, nwaves = nthreads / kWave;
+  const int l = lane_id();
   unsigned long long edges = 0;
   for (int b = 0; b < nbatch; ++b) {
-    const int lanes = min(64, a.k - b * 64);
-    const uint64_t lanemask = lanes == 64 ? ~0ull : ((1ull << lanes) - 1ull);
-    const int64_t row0 = int64_t(b) * 64;
+    const int lanes = min(kLanes, a.k - b * kLanes);
+    uint64_t mask[W];
+#pragma unroll
+    for (int x = 0; x < W; ++x) {
+      const int in = lanes - 64 * x;
+      mask[x] = in >= 64 ? ~0ull : (in > 0 ? (1ull << in) - 1ull : 0ull);
+    }
+    const int64_t row0 = int64_t(b) * kLanes;
     // reset lane state: seen, level 0 (the sources) and level 1 (a top-down
     // first level ORs into it)
-    uint64_t *const lv0 = ring_slot(a, 0), *const lv1 = ring_slot(a, 1);
+    LaneSet<W> *const lv0 = ring_slot<W>(a, 0), *const lv1 = ring_slot<W>(a, 1);
     for (int64_t v = tid; v < n; v += nthreads) {
-      a.seen[v] = 0;
-      lv0[v] = 0;
-      lv1[v] = 0;
+      seen[v] = LaneSet<W>{};
+      lv0[v] = LaneSet<W>{};
+      lv1[v] = LaneSet<W>{};
     }
     if (blockIdx.x == 0 && threadIdx.x < 3) {
       a.ctl->active[threadIdx.x] = 0;
-      a.ctl->alive[threadIdx.x] = 0;
+#pragma unroll
+      for (int x = 0; x < kMaxWords; ++x) a.ctl->alive[threadIdx.x][x] = 0;
     }
     if (!grid_sync(a.ctl, a.timeout_ticks)) return;
     // seed the sources of this batch (duplicates share a vertex: OR the lanes)
     if (tid < lanes) {
       const int32_t s = a.sources[row0 + tid];
-      atomicOr(reinterpret_cast<unsigned long long *>(&a.seen[s]), 1ull << tid);
-      atomicOr(reinterpret_cast<unsigned long long *>(&lv0[s]), 1ull << tid);
+      const int x = int(tid) >> 6;
+      const unsigned long long bit = 1ull << (tid & 63);
+      atomicOr(reinterpret_cast<unsigned long long *>(&seen[s].w[x]), bit);
+      atomicOr(reinterpret_cast<unsigned long long *>(&lv0[s].w[x]), bit);
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) a.ctl->active[0] = (unsigned long long)lanes;
     if (!grid_sync(a.ctl, a.timeout_ticks)) return;
     int64_t active = lanes;
     int32_t flushed = 0;  // levels [0, flushed) have their depths written
     // Lanes whose frontier is empty are finished: no vertex waits for them.
-    uint64_t live = lanemask;
-    const int64_t wid = tid / kWave, nwaves = nthreads / kWave;
-    const int l = lane_id();
+    LaneSet<W> live;
+#pragma unroll
+    for (int x = 0; x < W; ++x) live.w[x] = mask[x];
     int32_t L = 0;
     for (;; ++L) {
       // slot L + 2 is cleared at the end of this level and slot L + 1 written
       // during it: the levels they held must have their depths out first
       if (L + 2 - kRing >= flushed) {
-        flush_depth(a, row0, lanemask, flushed, L + 1, false, tid, nthreads, nv_iter);
+        flush_depth<W>(a, row0, mask, flushed, L + 1, false, tid, nthreads, nv_iter);
         flushed = L + 1;
         if (!grid_sync(a.ctl, a.timeout_ticks)) return;
       }
-      uint64_t *const fcur = ring_slot(a, L), *const fnext = ring_slot(a, L + 1);
+      LaneSet<W> *const fcur = ring_slot<W>(a, L), *const fnext = ring_slot<W>(a, L + 1);
       // the rolling count slot level L + 1 adds into; every block read it
       // (for level L - 2) before the barrier that ended level L - 1
       if (blockIdx.x == 0 && threadIdx.x == 0) {
         a.ctl->active[(L + 2) % 3] = 0;
-        a.ctl->alive[(L + 2) % 3] = 0;
+#pragma unroll
+        for (int x = 0; x < W; ++x) a.ctl->alive[(L + 2) % 3][x] = 0;
       }
       unsigned long long act = 0;
-      uint64_t lor = 0;
+      LaneSet<W> lor{};
       if (active <= a.bu_threshold) {
         // top-down, edge-parallel: (1) list the frontier vertices, (2) one
         // block prefix-sums their degrees, (3) every thread takes edges of the
         // concatenated rows. fnext is all zero here.
         for (int64_t v0 = int64_t(blockIdx.x) * blockDim.x; v0 < n; v0 += nthreads) {
           const int64_t v = v0 + threadIdx.x;
-          const bool f = v < n && fcur[v] != 0;
+          const bool f = v < n && lanes_any(fcur[v]);
           const int64_t pos = wave_append(f, &a.ctl->td_count);
           if (f) a.tdlist[pos] = int32_t(v);
         }
@@ -336,91 +404,128 @@ __global__ void __launch_bounds__(1024) k_msbfs(MsArgs a) {
           const int32_t v = a.tdlist[lo];
           const int32_t w = a.col[a.off[v] + (e - a.tdscan[lo])];
           ++edges;
-          const uint64_t m = fcur[v] & ~a.seen[w];
-          if (m) atomicOr(reinterpret_cast<unsigned long long *>(&fnext[w]), m);
+          const LaneSet<W> fv = fcur[v], sw = seen[w];
+#pragma unroll
+          for (int x = 0; x < W; ++x) {
+            const uint64_t m = fv.w[x] & ~sw.w[x];
+            if (m) atomicOr(reinterpret_cast<unsigned long long *>(&fnext[w].w[x]), m);
+          }
         }
         if (!grid_sync(a.ctl, a.timeout_ticks)) return;
         if (blockIdx.x == 0 && threadIdx.x == 0) a.ctl->td_count = 0;
         // close: fold next into seen
         for (int64_t v = tid; v < n; v += nthreads) {
-          const uint64_t s0 = a.seen[v];
-          const uint64_t nw = fnext[v] & ~s0;
+          const LaneSet<W> s0 = seen[v], fx = fnext[v];
+          LaneSet<W> nw, s1;
+#pragma unroll
+          for (int x = 0; x < W; ++x) {
+            nw.w[x] = fx.w[x] & ~s0.w[x];
+            s1.w[x] = s0.w[x] | nw.w[x];
+            lor.w[x] |= nw.w[x];
+          }
           fnext[v] = nw;
-          if (nw) a.seen[v] = s0 | nw;
-          act += nw != 0;
-          lor |= nw;
+          const bool any = lanes_any(nw);
+          if (any) seen[v] = s1;
+          act += any;
         }
       } else {
         // bottom-up with the close fused in: w is only written by the thread
         // (or, for a hub, the wave) that scans it. Vertices of degree <= kHub:
         // one thread each; hubs: one wave each, 64 neighbours per step.
-        const int wv = threadIdx.x / kWave;
+        BuRows<W> &rows = s_rows[threadIdx.x / kWave];
         for (int64_t it = 0; it < nv_iter; ++it) {
           const int64_t w = tid + it * nthreads;
           bool valid = w < n;
-          uint64_t s0 = 0, want = 0;
+          LaneSet<W> s0{}, want{};
           if (valid) {
             if (a.off[w + 1] - a.off[w] > kHub) {
               valid = false;  // the hub pass below owns it
             } else {
-              s0 = a.seen[w];
-              want = ~s0 & live;
+              s0 = seen[w];
+#pragma unroll
+              for (int x = 0; x < W; ++x) want.w[x] = ~s0.w[x] & live.w[x];
             }
           }
-          const uint64_t nw = bu_wave(a.off, a.col, fcur, w, want, s_ex[wv], s_beg[wv],
-                                      s_want[wv], s_acc[wv], edges);
+          const LaneSet<W> nw = bu_wave<W>(a.off, a.col, fcur, w, want, rows, edges);
           if (valid) {
-            if (nw) a.seen[w] = s0 | nw;
+            const bool any = lanes_any(nw);
+            if (any) {
+              LaneSet<W> s1;
+#pragma unroll
+              for (int x = 0; x < W; ++x) s1.w[x] = s0.w[x] | nw.w[x];
+              seen[w] = s1;
+            }
             fnext[w] = nw;
-            act += nw != 0;
-            lor |= nw;
+            act += any;
+#pragma unroll
+            for (int x = 0; x < W; ++x) lor.w[x] |= nw.w[x];
           }
         }
         for (int64_t h = wid; h < a.nhubs; h += nwaves) {
           const int32_t w = a.hubs[h];
-          const uint64_t s0 = a.seen[w];
-          const uint64_t want = ~s0 & live;
-          uint64_t nw = 0;
-          if (want) {
+          const LaneSet<W> s0 = seen[w];
+          LaneSet<W> want, acc{};
+#pragma unroll
+          for (int x = 0; x < W; ++x) want.w[x] = ~s0.w[x] & live.w[x];
+          if (lanes_any(want)) {
             const int64_t p1 = a.off[w + 1];
-            uint64_t acc = 0;
             for (int64_t p = a.off[w]; p < p1; p += kWave) {
-              const uint64_t x = p + l < p1 ? fcur[a.col[p + l]] : 0ull;
-              acc |= wave_or(x);
+              LaneSet<W> y{};
+              if (p + l < p1) y = fcur[a.col[p + l]];
+              bool done = true;
+#pragma unroll
+              for (int x = 0; x < W; ++x) {
+                acc.w[x] |= wave_or(y.w[x]);
+                done = done && (acc.w[x] & want.w[x]) == want.w[x];
+              }
               if (l == 0) edges += uint64_t(min<int64_t>(kWave, p1 - p));
-              if ((acc & want) == want) break;
+              if (done) break;
             }
-            nw = acc & want;
           }
+          LaneSet<W> nw;
+#pragma unroll
+          for (int x = 0; x < W; ++x) nw.w[x] = acc.w[x] & want.w[x];
           if (l == 0) {
-            if (nw) a.seen[w] = s0 | nw;
+            const bool any = lanes_any(nw);
+            if (any) {
+              LaneSet<W> s1;
+#pragma unroll
+              for (int x = 0; x < W; ++x) s1.w[x] = s0.w[x] | nw.w[x];
+              seen[w] = s1;
+            }
             fnext[w] = nw;
-            act += nw != 0;
-            lor |= nw;
+            act += any;
+#pragma unroll
+            for (int x = 0; x < W; ++x) lor.w[x] |= nw.w[x];
           }
         }
       }
       const unsigned long long bact = block_sum_u64(act, sh);
       if (threadIdx.x == 0 && bact) atomicAdd(&a.ctl->active[(L + 1) % 3], bact);
-      lor = wave_or(lor);
-      if (l == 0 && lor) atomicOr(&a.ctl->alive[(L + 1) % 3], (unsigned long long)lor);
+#pragma unroll
+      for (int x = 0; x < W; ++x) {
+        const uint64_t o = wave_or(lor.w[x]);
+        if (l == 0 && o) atomicOr(&a.ctl->alive[(L + 1) % 3][x], (unsigned long long)o);
+      }
       if (!grid_sync(a.ctl, a.timeout_ticks)) return;
       active = int64_t(__hip_atomic_load(&a.ctl->active[(L + 1) % 3], __ATOMIC_RELAXED,
                                          __HIP_MEMORY_SCOPE_AGENT));
-      live = __hip_atomic_load(&a.ctl->alive[(L + 1) % 3], __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT);
+#pragma unroll
+      for (int x = 0; x < W; ++x)
+        live.w[x] = __hip_atomic_load(&a.ctl->alive[(L + 1) % 3][x], __ATOMIC_RELAXED,
+                                      __HIP_MEMORY_SCOPE_AGENT);
       if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(&a.ctl->levels, 1ull);
       if (active == 0) break;
       // a top-down level L + 1 ORs into slot L + 2, which must start at zero
       // (its scatter comes two barriers after this); a bottom-up level
       // overwrites every entry itself
       if (active <= a.bu_threshold) {
-        uint64_t *const after = ring_slot(a, L + 2);
-        for (int64_t v = tid; v < n; v += nthreads) after[v] = 0;
+        LaneSet<W> *const after = ring_slot<W>(a, L + 2);
+        for (int64_t v = tid; v < n; v += nthreads) after[v] = LaneSet<W>{};
       }
     }
     // depths of the levels not yet written, and -1 for lanes never seen
-    flush_depth(a, row0, lanemask, flushed, L + 1, true, tid, nthreads, nv_iter);
+    flush_depth<W>(a, row0, mask, flushed, L + 1, true, tid, nthreads, nv_iter);
     if (!grid_sync(a.ctl, a.timeout_ticks)) return;
   }
   const unsigned long long be = block_sum_u64(edges, sh);
@@ -450,11 +555,28 @@ std::string device_name() {
 
 dsbfs_ms_opts default_ms_opts() {
   dsbfs_ms_opts o{};
-  o.block = 256;
-  o.blocks_per_cu = 4;
+  o.block = 1024;
+  o.blocks_per_cu = 1;
   o.bu_permille = 2;
   o.use_graph = 1;
+  o.lanes_per_batch = 0;
   return o;
+}
+
+// 64-bit words per vertex for k sources: the narrowest batch that holds them
+// all, at most kMaxWords (the frontier set of a vertex is read whole per edge,
+// so a wider batch costs little more per edge and needs fewer batches).
+int ms_words(const dsbfs_ms_opts &o, int32_t k) {
+  if (o.lanes_per_batch) return o.lanes_per_batch / 64;
+  return k <= 64 ? 1 : (k <= 128 ? 2 : kMaxWords);
+}
+
+const void *ms_kernel(int words) {
+  switch (words) {
+    case 1: return reinterpret_cast<const void *>(&k_msbfs<1>);
+    case 2: return reinterpret_cast<const void *>(&k_msbfs<2>);
+    default: return reinterpret_cast<const void *>(&k_msbfs<4>);
+  }
 }
 
 void check_ms_opts(const dsbfs_ms_opts &o) {
@@ -464,6 +586,9 @@ void check_ms_opts(const dsbfs_ms_opts &o) {
     fail(DSBFS_ERR_INVALID_ARG, "ms blocks_per_cu must be in [1, 32]");
   if (o.bu_permille < 0 || o.bu_permille > 1000)
     fail(DSBFS_ERR_INVALID_ARG, "ms bu_permille must be in [0, 1000]");
+  if (o.lanes_per_batch != 0 && o.lanes_per_batch != 64 && o.lanes_per_batch != 128 &&
+      o.lanes_per_batch != 256)
+    fail(DSBFS_ERR_INVALID_ARG, "ms lanes_per_batch must be 0 (automatic), 64, 128 or 256");
 }
 
 // The graph captured for one (workspace, launch configuration, k, depth).
@@ -474,7 +599,8 @@ struct MsGraph {
 
 struct MsState {
   DevBuf ctl, srcs, hubs;
-  DevBuf ring;  // kRing x n lane masks
+  DevBuf ring, seen;  // kRing x n and n lane sets of `words` words each
+  int words = 0;
   int64_t nhubs = -1;  // -1: hub list not built yet
   int32_t cap_k = 0;
   std::map<std::string, MsGraph> graphs;
@@ -507,10 +633,16 @@ static void msbfs_launch(const Graph *g, Workspace *ws, const int32_t *sources, 
   MsState *st = reinterpret_cast<MsState *>(ws->ms_state);
   const Alloc *al = &g->al;
   if (!st->ctl.p) st->ctl.alloc(al, sizeof(MsCtl), s);
-  if (!st->ring.p) st->ring.alloc(al, size_t(kRing) * size_t(g->n) * 8, s);
-  if (st->cap_k < k) {
-    st->srcs.alloc(al, size_t(k) * 4, s);
-    st->cap_k = k;
+  const int words = ms_words(o, k);
+  const bool grow_lanes = st->words < words;
+  if (grow_lanes) {
+    st->ring.alloc(al, size_t(kRing) * size_t(g->n) * 8 * words, s);
+    st->seen.alloc(al, size_t(g->n) * 8 * words, s);
+    st->words = words;
+  }
+  if (st->cap_k < k || grow_lanes) {
+    if (st->cap_k < k) st->srcs.alloc(al, size_t(k) * 4, s);
+    st->cap_k = std::max(st->cap_k, k);
     // captured graphs hold the old pointer
     for (auto &kv : st->graphs) {
       if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
@@ -534,8 +666,9 @@ static void msbfs_launch(const Graph *g, Workspace *ws, const int32_t *sources, 
     st->nhubs = d2h_scalar(cnt.as<int64_t>(), s);
   }
 
+  const void *kern = ms_kernel(words);
   int occ = 0;
-  HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_msbfs, o.block, 0));
+  HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, o.block, 0));
   if (occ < 1) fail(DSBFS_ERR_INVALID_ARG, "ms block size does not fit a compute unit");
   const int per_cu = std::min(o.blocks_per_cu, occ);
   const int grid = device_cus() * per_cu;
@@ -547,8 +680,8 @@ static void msbfs_launch(const Graph *g, Workspace *ws, const int32_t *sources, 
   a.sources = st->srcs.as<int32_t>();
   a.k = k;
   a.depth = depth;
-  a.seen = ws->ms_seen.as<uint64_t>();
-  a.ring = st->ring.as<uint64_t>();
+  a.seen = st->seen.p;
+  a.ring = st->ring.p;
   a.tdlist = ws->dlen.as<int32_t>();    // int32[max(n, d)]
   a.tdscan = ws->dscan.as<int64_t>();   // int64[max(n, d) + 1]
   a.hubs = st->hubs.as<int32_t>();
@@ -562,7 +695,7 @@ static void msbfs_launch(const Graph *g, Workspace *ws, const int32_t *sources, 
   HIPCHK(hipMemcpyAsync(st->ctl.p, &zero, sizeof(MsCtl), hipMemcpyHostToDevice, s));
   if (o.use_graph) {
     char key[160];
-    std::snprintf(key, sizeof(key), "%d/%d/%d/%d/%p", o.block, grid, k, o.bu_permille,
+    std::snprintf(key, sizeof(key), "%d/%d/%d/%d/%d/%p", o.block, grid, k, o.bu_permille, words,
                   static_cast<void *>(depth));
     MsGraph &mg = st->graphs[key];
     if (!mg.exec) {
@@ -573,8 +706,7 @@ static void msbfs_launch(const Graph *g, Workspace *ws, const int32_t *sources, 
         // captured as a cooperative launch, so the runtime still checks that
         // the whole grid is co-resident when the graph is replayed
         void *args[] = {&a};
-        e = hipLaunchCooperativeKernel(reinterpret_cast<const void *>(&k_msbfs), dim3(grid),
-                                       dim3(o.block), args, 0, cs);
+        e = hipLaunchCooperativeKernel(kern, dim3(grid), dim3(o.block), args, 0, cs);
         hipGraph_t gr = nullptr;
         hipError_t e2 = hipStreamEndCapture(cs, &gr);
         if (e == hipSuccess) e = e2;
@@ -591,8 +723,7 @@ static void msbfs_launch(const Graph *g, Workspace *ws, const int32_t *sources, 
     HIPCHK(hipGraphLaunch(mg.exec, s));
   } else {
     void *args[] = {&a};
-    HIPCHK(hipLaunchCooperativeKernel(reinterpret_cast<const void *>(&k_msbfs), dim3(grid),
-                                      dim3(o.block), args, 0, s));
+    HIPCHK(hipLaunchCooperativeKernel(kern, dim3(grid), dim3(o.block), args, 0, s));
   }
   MsCtl h{};
   HIPCHK(hipMemcpyAsync(&h, st->ctl.p, sizeof(MsCtl), hipMemcpyDeviceToHost, s));
@@ -668,7 +799,9 @@ void msbfs_tune(const Graph *g, Workspace *ws, const int32_t *sources, int32_t k
   const std::string key = tune_key(g);
   if (cache_lookup(cache_path, key, best)) return;
   if (k < 1) fail(DSBFS_ERR_INVALID_ARG, "tuning needs at least one source");
-  const int32_t kt = std::min<int32_t>(k, 64);
+  // up to one full batch of the widest lane set, so the candidates run at the
+  // lane width the full launch will use
+  const int32_t kt = std::min<int32_t>(k, 64 * kMaxWords);
   DevBuf out;
   out.alloc(&g->al, size_t(kt) * size_t(g->n) * 4, s);
   double best_ms = 1e30;
@@ -679,7 +812,8 @@ void msbfs_tune(const Graph *g, Workspace *ws, const int32_t *sources, int32_t k
   for (int b : blocks)
     for (int c : percu) {
       int occ = 0;
-      HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_msbfs, b, 0));
+      HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          &occ, ms_kernel(ms_words(default_ms_opts(), kt)), b, 0));
       if (c > occ || b * c > 2048) continue;
       for (int t : thr) {
         dsbfs_ms_opts o{};
@@ -868,9 +1002,7 @@ __global__ void k_lv_td_close(MsLevel a, LaneRows r) {
 }
 
 __global__ void __launch_bounds__(256) k_lv_bu(MsLevel a, LaneRows r) {
-  __shared__ int32_t s_ex[4][kWave];
-  __shared__ int64_t s_beg[4][kWave];
-  __shared__ unsigned long long s_want[4][kWave], s_acc[4][kWave];
+  __shared__ BuRows<1> s_rows[4];
   const int64_t nthreads = int64_t(gridDim.x) * blockDim.x;
   const int64_t tid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   const int64_t iters = (int64_t(a.n) + nthreads - 1) / nthreads;
@@ -889,8 +1021,10 @@ __global__ void __launch_bounds__(256) k_lv_bu(MsLevel a, LaneRows r) {
         want = ~s0 & a.live;
       }
     }
-    const uint64_t nw = bu_wave(a.off, a.col, a.fcur, w, want, s_ex[wv], s_beg[wv], s_want[wv],
-                                s_acc[wv], edges);
+    const uint64_t nw =
+        bu_wave<1>(a.off, a.col, reinterpret_cast<const LaneSet<1> *>(a.fcur), w,
+                   LaneSet<1>{{want}}, s_rows[wv], edges)
+            .w[0];
     if (valid) {
       if (nw) a.seen[w] = s0 | nw;
       a.fnext[w] = nw;

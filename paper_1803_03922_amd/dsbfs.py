@@ -91,7 +91,8 @@ class dsbfs_run_stats(ctypes.Structure):
 
 
 class dsbfs_ms_opts(ctypes.Structure):
-    _fields_ = [("block", i32), ("blocks_per_cu", i32), ("bu_permille", i32), ("use_graph", i32)]
+    _fields_ = [("block", i32), ("blocks_per_cu", i32), ("bu_permille", i32), ("use_graph", i32),
+                ("lanes_per_batch", i32)]
 
     def as_dict(self):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}

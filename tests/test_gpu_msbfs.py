@@ -15,9 +15,9 @@ from gpu_helpers import lib, log, torch_cuda
 pytestmark = pytest.mark.gpu
 
 
-def _opts(block=256, per_cu=4, permille=2, graph=1):
+def _opts(block=256, per_cu=4, permille=2, graph=1, lanes=0):
     d = lib()
-    return d.dsbfs_ms_opts(block, per_cu, permille, graph)
+    return d.dsbfs_ms_opts(block, per_cu, permille, graph, lanes)
 
 
 def _setup(src, dst, n):
@@ -52,6 +52,25 @@ def test_msbfs_rmat12_all_lanes(inputs_mod, oracle_mod, permille, graph):
         np.testing.assert_array_equal(depth[i], want, err_msg=f"lane {i} source {s}")
 
 
+@pytest.mark.parametrize("lanes", [64, 128, 256, 0])
+def test_msbfs_lane_widths_rmat12(inputs_mod, oracle_mod, lanes):
+    """300 sources: full and partial batches at every lane width (64: 5
+    batches, 128: 3, 256: 2; 0 picks 256)."""
+    scale = 12
+    n = 1 << scale
+    src, dst = inputs_mod.rmat_edges(scale)
+    O = oracle_mod.Graph(src, dst, n)
+    g, ws = _setup(src, dst, n)
+    sources = inputs_mod.pick_sources(src, dst, n, 300, seed=77)
+    for permille in (0, 2, 1000):
+        depth = _run(g, ws, n, sources, _opts(block=1024, per_cu=1, permille=permille,
+                                              lanes=lanes)).cpu().numpy()
+        for i, s in enumerate(sources.tolist()):
+            want, _ = O.bfs(s, want_parent=False)
+            np.testing.assert_array_equal(depth[i], want,
+                                          err_msg=f"lanes {lanes} permille {permille} row {i}")
+
+
 def test_msbfs_closed_forms_and_duplicates(oracle_mod):
     # the paths run far more levels than the kernel's ring of level masks
     # holds, so their depths are written in several passes, and the disjoint
@@ -61,9 +80,11 @@ def test_msbfs_closed_forms_and_duplicates(oracle_mod):
         g, ws = _setup(src, dst, n)
         sources = np.array([0, 1, 0, n - 1, 5, 5, 5], dtype=np.int32)   # repeated sources
         for permille in (0, 1000):
-            depth = _run(g, ws, n, sources, _opts(permille=permille)).cpu().numpy()
-            for i, s in enumerate(sources.tolist()):
-                np.testing.assert_array_equal(depth[i], dist(s), err_msg=f"n={n} lane {i}")
+            for lanes in (0, 256):
+                depth = _run(g, ws, n, sources, _opts(permille=permille, lanes=lanes)).cpu().numpy()
+                for i, s in enumerate(sources.tolist()):
+                    np.testing.assert_array_equal(depth[i], dist(s),
+                                                  err_msg=f"n={n} lanes {lanes} lane {i}")
 
 
 def test_msbfs_launch_shapes(inputs_mod, oracle_mod):
@@ -161,6 +182,9 @@ def test_msbfs_errors(inputs_mod):
     assert e.value.status == d.ERR_INVALID_ARG
     with pytest.raises(d.DsbfsError) as e:
         d.msbfs(g, ws, np.array([1, 2], np.int32), depth, _opts(block=96))
+    assert e.value.status == d.ERR_INVALID_ARG
+    with pytest.raises(d.DsbfsError) as e:
+        d.msbfs(g, ws, np.array([1, 2], np.int32), depth, _opts(lanes=96))
     assert e.value.status == d.ERR_INVALID_ARG
     with pytest.raises(d.DsbfsError) as e:
         d.Workspace(g, max_lanes=32)
