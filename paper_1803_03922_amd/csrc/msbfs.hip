@@ -287,7 +287,11 @@ __device__ LaneSet<W> bu_wave(const int64_t *off, const int32_t *col, const Lane
 
 template <int W>
 __global__ void __launch_bounds__(1024) k_msbfs(MsArgs a) {
-  __shared__ BuRows<W> s_rows[16];
+  // per wave: bottom-up rows, or a top-down level's window of the degree scan
+  __shared__ union {
+    BuRows<W> rows[16];
+    int64_t win[16][kWave + 1];
+  } s_u;
   __shared__ unsigned long long sh[16];
   constexpr int kLanes = 64 * W;
   const int32_t n = a.n;
@@ -357,12 +361,12 @@ __global__ void __launch_bounds__(1024) k_msbfs(MsArgs a) {
       unsigned long long act = 0;
       LaneSet<W> lor{};
       if (active <= a.bu_threshold) {
-        // top-down, edge-parallel: (1) list the frontier vertices, (2) one
-        // block prefix-sums their degrees, (3) every thread takes edges of the
-        // concatenated rows. fnext is all zero here.
+        // top-down, edge-parallel: (1) list the frontier vertices that have
+        // edges, (2) one block prefix-sums their degrees, (3) every wave takes
+        // a contiguous share of the concatenated rows. fnext is all zero here.
         for (int64_t v0 = int64_t(blockIdx.x) * blockDim.x; v0 < n; v0 += nthreads) {
           const int64_t v = v0 + threadIdx.x;
-          const bool f = v < n && lanes_any(fcur[v]);
+          const bool f = v < n && lanes_any(fcur[v]) && a.off[v + 1] > a.off[v];
           const int64_t pos = wave_append(f, &a.ctl->td_count);
           if (f) a.tdlist[pos] = int32_t(v);
         }
@@ -394,45 +398,73 @@ __global__ void __launch_bounds__(1024) k_msbfs(MsArgs a) {
         }
         if (!grid_sync(a.ctl, a.timeout_ticks)) return;
         const int64_t E = a.tdscan[cnt];
-        for (int64_t e = tid; e < E; e += nthreads) {
-          int64_t lo = 0, hi = cnt - 1;
-          while (lo < hi) {
-            const int64_t mid = (lo + hi + 1) >> 1;
-            if (a.tdscan[mid] <= e) lo = mid;
+        // wave share: [eb, ee), a multiple of 64 edges. Every listed row has
+        // an edge, so 64 consecutive edges belong to at most 64 consecutive
+        // list entries: a step stages the scan values of the 65 entries from
+        // its first edge's owner in LDS, finds each edge's owner among the
+        // first 64, and the first edge of the next step's owner with the 65th.
+        const int64_t share = ((E + nwaves - 1) / nwaves + kWave - 1) / kWave * kWave;
+        const int64_t eb = wid * share, ee = min(E, eb + share);
+        if (eb < ee) {
+          int64_t own = 0, hi = cnt - 1;  // owner of eb: last i with tdscan[i] <= eb
+          while (own < hi) {
+            const int64_t mid = (own + hi + 1) >> 1;
+            if (a.tdscan[mid] <= eb) own = mid;
             else hi = mid - 1;
           }
-          const int32_t v = a.tdlist[lo];
-          const int32_t w = a.col[a.off[v] + (e - a.tdscan[lo])];
-          ++edges;
-          const LaneSet<W> fv = fcur[v], sw = seen[w];
+          int64_t *const win = s_u.win[threadIdx.x / kWave];
+          for (int64_t e0 = eb; e0 < ee; e0 += kWave) {
+            win[l] = own + l < cnt ? a.tdscan[own + l] : INT64_MAX;
+            if (l == 0) win[kWave] = own + kWave < cnt ? a.tdscan[own + kWave] : INT64_MAX;
+            wave_sync();
+            const int64_t e = e0 + l;
+            int o = 0;
+            if (e < ee) {
 #pragma unroll
-          for (int x = 0; x < W; ++x) {
-            const uint64_t m = fv.w[x] & ~sw.w[x];
-            if (m) atomicOr(reinterpret_cast<unsigned long long *>(&fnext[w].w[x]), m);
+              for (int step = 32; step > 0; step >>= 1) {
+                const int c = o + step;
+                if (win[c] <= e) o = c;
+              }
+              const int32_t v = a.tdlist[own + o];
+              const int32_t w = a.col[a.off[v] + (e - win[o])];
+              ++edges;
+              const LaneSet<W> fv = fcur[v], sw = seen[w];
+#pragma unroll
+              for (int x = 0; x < W; ++x) {
+                const uint64_t m = fv.w[x] & ~sw.w[x];
+                if (m) atomicOr(reinterpret_cast<unsigned long long *>(&fnext[w].w[x]), m);
+              }
+            }
+            // owner of e0 + 64: the owner of this step's last edge, or the
+            // entry after it when that row ended at e0 + 63 (a partial step
+            // is the last one)
+            const int o63 = lane_read(o, kWave - 1);
+            own += o63 + (e0 + kWave >= win[o63 + 1] ? 1 : 0);
+            wave_sync();
           }
         }
         if (!grid_sync(a.ctl, a.timeout_ticks)) return;
         if (blockIdx.x == 0 && threadIdx.x == 0) a.ctl->td_count = 0;
-        // close: fold next into seen
+        // close: fold next into seen (the scatter only set lanes that were
+        // unseen, and seen did not change during it, so next is all new)
         for (int64_t v = tid; v < n; v += nthreads) {
-          const LaneSet<W> s0 = seen[v], fx = fnext[v];
-          LaneSet<W> nw, s1;
+          const LaneSet<W> nw = fnext[v];
+          if (lanes_any(nw)) {
+            LaneSet<W> s1 = seen[v];
 #pragma unroll
-          for (int x = 0; x < W; ++x) {
-            nw.w[x] = fx.w[x] & ~s0.w[x];
-            s1.w[x] = s0.w[x] | nw.w[x];
-            lor.w[x] |= nw.w[x];
+            for (int x = 0; x < W; ++x) {
+              s1.w[x] |= nw.w[x];
+              lor.w[x] |= nw.w[x];
+            }
+            seen[v] = s1;
+            ++act;
           }
-          fnext[v] = nw;
-          const bool any = lanes_any(nw);
-          if (any) seen[v] = s1;
-          act += any;
         }
       } else {
         // bottom-up with the close fused in: w is only written by the thread
         // (or, for a hub, the wave) that scans it. Vertices of degree <= kHub:
         // one thread each; hubs: one wave each, 64 neighbours per step.
-        BuRows<W> &rows = s_rows[threadIdx.x / kWave];
+        BuRows<W> &rows = s_u.rows[threadIdx.x / kWave];
         for (int64_t it = 0; it < nv_iter; ++it) {
           const int64_t w = tid + it * nthreads;
           bool valid = w < n;
