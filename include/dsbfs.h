@@ -273,7 +273,9 @@ typedef struct dsbfs_ms_opts {
 /*
  * Multi-source BFS from k sources (host int32[k], each in [0, n)), bit-parallel
  * in batches of 64, 128 or 256 lanes, all batches in one persistent launch.
- * Device memory held by the workspace for it: 17 x n x (lanes / 8) bytes. depth is a
+ * Device memory held by the workspace for it: 17 x n x (lanes / 8) bytes of
+ * lane state, plus, once per graph, a copy of the plain CSR's columns with
+ * hub neighbours renumbered (4 x m_dir bytes) and a hub index (4 x n). depth is a
  * device int32[k][n] array: row i gets the hop distances from sources[i]
  * (-1 unreachable), exactly as k single-source searches would. Uses the plain
  * CSR (graph built with keep_plain_csr = 1). opts NULL = tuned/cached

@@ -69,6 +69,13 @@ struct MsArgs {
   int64_t *tdscan;         // prefix of their degrees, n + 1 entries
   const int32_t *hubs;     // vertices of degree > kHub, scanned by whole waves bottom-up
   int64_t nhubs;
+  // Hub frontier cache (bottom-up reads): col2 is col with every hub
+  // neighbour h replaced by n + (its index in hubs); hot holds two slots of
+  // nhubs lane sets, slot L & 1 a copy of level L's frontier of the hubs.
+  // col2 == col and hot == nullptr when the cache is off.
+  const int32_t *col2;
+  const int32_t *hub_idx;  // index in hubs of each vertex, -1 if not a hub
+  void *hot;
   MsCtl *ctl;
   int64_t bu_threshold;    // bottom-up when active vertices exceed this
   long long timeout_ticks; // bound of one barrier wait (wall clock ticks)
@@ -228,9 +235,18 @@ struct BuRows {
 // 64 frontier sets are in flight per step. Each vertex's frontier OR collects
 // in LDS; the walk stops once every vertex's wanted lanes are covered. Called
 // by every lane of the wave; returns the lanes found for this lane's vertex.
+// The frontier set of neighbour entry c: fcur[c], or hcur[c - nlim] for an
+// entry that names a hub slot (c >= nlim).
+template <int W>
+__device__ __forceinline__ LaneSet<W> front_of(const LaneSet<W> *fcur, const LaneSet<W> *hcur,
+                                               int32_t nlim, int32_t c) {
+  return c >= nlim ? hcur[c - nlim] : fcur[c];
+}
+
 template <int W>
 __device__ LaneSet<W> bu_wave(const int64_t *off, const int32_t *col, const LaneSet<W> *fcur,
-                              int64_t w, const LaneSet<W> &want, BuRows<W> &r,
+                              const LaneSet<W> *hcur, int32_t nlim, int64_t w,
+                              const LaneSet<W> &want, BuRows<W> &r,
                               unsigned long long &edges) {
   const int l = lane_id();
   int32_t len = 0;
@@ -266,7 +282,7 @@ __device__ LaneSet<W> bu_wave(const int64_t *off, const int32_t *col, const Lane
       }
       const LaneSet<W> wl = r.want[o];
       if (!covered(o, wl)) {
-        const LaneSet<W> m = fcur[col[r.beg[o] + (e - r.ex[o])]];
+        const LaneSet<W> m = front_of<W>(fcur, hcur, nlim, col[r.beg[o] + (e - r.ex[o])]);
         ++edges;
 #pragma unroll
         for (int x = 0; x < W; ++x) {
@@ -296,6 +312,8 @@ __global__ void __launch_bounds__(1024) k_msbfs(MsArgs a) {
   constexpr int kLanes = 64 * W;
   const int32_t n = a.n;
   LaneSet<W> *const seen = static_cast<LaneSet<W> *>(a.seen);
+  LaneSet<W> *const hot = static_cast<LaneSet<W> *>(a.hot);
+  const int32_t nlim = hot ? n : INT32_MAX;  // col2 entries >= nlim name hub slots
   const int64_t tid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   const int64_t nthreads = int64_t(gridDim.x) * blockDim.x;
   const int64_t nv_iter = (int64_t(n) + nthreads - 1) / nthreads;
@@ -320,6 +338,8 @@ __global__ void __launch_bounds__(1024) k_msbfs(MsArgs a) {
       lv0[v] = LaneSet<W>{};
       lv1[v] = LaneSet<W>{};
     }
+    if (hot)
+      for (int64_t h = tid; h < a.nhubs; h += nthreads) hot[h] = LaneSet<W>{};
     if (blockIdx.x == 0 && threadIdx.x < 3) {
       a.ctl->active[threadIdx.x] = 0;
 #pragma unroll
@@ -333,6 +353,8 @@ __global__ void __launch_bounds__(1024) k_msbfs(MsArgs a) {
       const unsigned long long bit = 1ull << (tid & 63);
       atomicOr(reinterpret_cast<unsigned long long *>(&seen[s].w[x]), bit);
       atomicOr(reinterpret_cast<unsigned long long *>(&lv0[s].w[x]), bit);
+      if (hot && a.hub_idx[s] >= 0)
+        atomicOr(reinterpret_cast<unsigned long long *>(&hot[a.hub_idx[s]].w[x]), bit);
     }
     if (!grid_sync(a.ctl, a.timeout_ticks)) return;
     int64_t active = lanes;
@@ -351,6 +373,9 @@ __global__ void __launch_bounds__(1024) k_msbfs(MsArgs a) {
         if (!grid_sync(a.ctl, a.timeout_ticks)) return;
       }
       LaneSet<W> *const fcur = ring_slot<W>(a, L), *const fnext = ring_slot<W>(a, L + 1);
+      // hub copies of this level's frontier (read) and of the next (written)
+      LaneSet<W> *const hcur = hot ? hot + (L & 1) * a.nhubs : nullptr;
+      LaneSet<W> *const hnext = hot ? hot + ((L + 1) & 1) * a.nhubs : nullptr;
       // the rolling count slot level L + 1 adds into; every block read it
       // (for level L - 2) before the barrier that ended level L - 1
       if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -460,6 +485,8 @@ __global__ void __launch_bounds__(1024) k_msbfs(MsArgs a) {
             ++act;
           }
         }
+        if (hot)
+          for (int64_t h = tid; h < a.nhubs; h += nthreads) hnext[h] = fnext[a.hubs[h]];
       } else {
         // bottom-up with the close fused in: w is only written by the thread
         // (or, for a hub, the wave) that scans it. Vertices of degree <= kHub:
@@ -478,7 +505,7 @@ __global__ void __launch_bounds__(1024) k_msbfs(MsArgs a) {
               for (int x = 0; x < W; ++x) want.w[x] = ~s0.w[x] & live.w[x];
             }
           }
-          const LaneSet<W> nw = bu_wave<W>(a.off, a.col, fcur, w, want, rows, edges);
+          const LaneSet<W> nw = bu_wave<W>(a.off, a.col2, fcur, hcur, nlim, w, want, rows, edges);
           if (valid) {
             const bool any = lanes_any(nw);
             if (any) {
@@ -503,7 +530,7 @@ __global__ void __launch_bounds__(1024) k_msbfs(MsArgs a) {
             const int64_t p1 = a.off[w + 1];
             for (int64_t p = a.off[w]; p < p1; p += kWave) {
               LaneSet<W> y{};
-              if (p + l < p1) y = fcur[a.col[p + l]];
+              if (p + l < p1) y = front_of<W>(fcur, hcur, nlim, a.col2[p + l]);
               bool done = true;
 #pragma unroll
               for (int x = 0; x < W; ++x) {
@@ -526,6 +553,7 @@ __global__ void __launch_bounds__(1024) k_msbfs(MsArgs a) {
               seen[w] = s1;
             }
             fnext[w] = nw;
+            if (hot) hnext[h] = nw;
             act += any;
 #pragma unroll
             for (int x = 0; x < W; ++x) lor.w[x] |= nw.w[x];
@@ -562,6 +590,22 @@ __global__ void __launch_bounds__(1024) k_msbfs(MsArgs a) {
   }
   const unsigned long long be = block_sum_u64(edges, sh);
   if (threadIdx.x == 0 && be) atomicAdd(&a.ctl->edges, be);
+}
+
+__global__ void k_hub_index(const int32_t *hubs, int64_t nhubs, int32_t *hub_idx) {
+  for (int64_t h = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; h < nhubs;
+       h += int64_t(gridDim.x) * blockDim.x)
+    hub_idx[hubs[h]] = int32_t(h);
+}
+
+__global__ void k_col_remap(const int32_t *col, int64_t m, const int32_t *hub_idx, int32_t n,
+                            int32_t *col2) {
+  for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < m;
+       e += int64_t(gridDim.x) * blockDim.x) {
+    const int32_t c = col[e];
+    const int32_t h = hub_idx[c];
+    col2[e] = h >= 0 ? n + h : c;
+  }
 }
 
 __global__ void k_flag_hub(const int64_t *off, int32_t n, uint8_t *flag) {
@@ -632,6 +676,7 @@ struct MsGraph {
 struct MsState {
   DevBuf ctl, srcs, hubs;
   DevBuf ring, seen;  // kRing x n and n lane sets of `words` words each
+  DevBuf hub_idx, col2, hot;  // hub frontier cache (see MsArgs)
   int words = 0;
   int64_t nhubs = -1;  // -1: hub list not built yet
   int32_t cap_k = 0;
@@ -665,24 +710,6 @@ static void msbfs_launch(const Graph *g, Workspace *ws, const int32_t *sources, 
   MsState *st = reinterpret_cast<MsState *>(ws->ms_state);
   const Alloc *al = &g->al;
   if (!st->ctl.p) st->ctl.alloc(al, sizeof(MsCtl), s);
-  const int words = ms_words(o, k);
-  const bool grow_lanes = st->words < words;
-  if (grow_lanes) {
-    st->ring.alloc(al, size_t(kRing) * size_t(g->n) * 8 * words, s);
-    st->seen.alloc(al, size_t(g->n) * 8 * words, s);
-    st->words = words;
-  }
-  if (st->cap_k < k || grow_lanes) {
-    if (st->cap_k < k) st->srcs.alloc(al, size_t(k) * 4, s);
-    st->cap_k = std::max(st->cap_k, k);
-    // captured graphs hold the old pointer
-    for (auto &kv : st->graphs) {
-      if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
-      if (kv.second.graph) (void)hipGraphDestroy(kv.second.graph);
-    }
-    st->graphs.clear();
-  }
-  HIPCHK(hipMemcpyAsync(st->srcs.p, sources, size_t(k) * 4, hipMemcpyHostToDevice, s));
   if (st->nhubs < 0) {
     // vertices whose rows a whole wave scans in bottom-up levels
     DevBuf flag, tmp, cnt;
@@ -697,7 +724,38 @@ static void msbfs_launch(const Graph *g, Workspace *ws, const int32_t *sources, 
                      s);
     st->nhubs = d2h_scalar(cnt.as<int64_t>(), s);
   }
-
+  // hub frontier cache: the remapped columns once per graph (while hub slot
+  // numbers n + h fit int32)
+  if (st->nhubs > 0 && !st->col2.p && int64_t(g->n) + st->nhubs < int64_t(INT32_MAX)) {
+    st->hub_idx.alloc(al, size_t(g->n) * 4, s);
+    HIPCHK(hipMemsetAsync(st->hub_idx.p, 0xff, size_t(g->n) * 4, s));
+    hipLaunchKernelGGL(k_hub_index, dim3(grid_for(st->nhubs, 256, 8192)), dim3(256), 0, s,
+                       st->hubs.as<int32_t>(), st->nhubs, st->hub_idx.as<int32_t>());
+    st->col2.alloc(al, size_t(g->m) * 4, s);
+    hipLaunchKernelGGL(k_col_remap, dim3(grid_for(g->m, 256, 8192)), dim3(256), 0, s,
+                       g->pcol.as<int32_t>(), g->m, st->hub_idx.as<int32_t>(), g->n,
+                       st->col2.as<int32_t>());
+    HIPCHK(hipGetLastError());
+  }
+  const int words = ms_words(o, k);
+  const bool grow_lanes = st->words < words;
+  if (grow_lanes) {
+    st->ring.alloc(al, size_t(kRing) * size_t(g->n) * 8 * words, s);
+    st->seen.alloc(al, size_t(g->n) * 8 * words, s);
+    if (st->col2.p) st->hot.alloc(al, size_t(2) * size_t(st->nhubs) * 8 * words, s);
+    st->words = words;
+  }
+  if (st->cap_k < k || grow_lanes) {
+    if (st->cap_k < k) st->srcs.alloc(al, size_t(k) * 4, s);
+    st->cap_k = std::max(st->cap_k, k);
+    // captured graphs hold the old pointer
+    for (auto &kv : st->graphs) {
+      if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
+      if (kv.second.graph) (void)hipGraphDestroy(kv.second.graph);
+    }
+    st->graphs.clear();
+  }
+  HIPCHK(hipMemcpyAsync(st->srcs.p, sources, size_t(k) * 4, hipMemcpyHostToDevice, s));
   const void *kern = ms_kernel(words);
   int occ = 0;
   HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, o.block, 0));
@@ -718,6 +776,9 @@ static void msbfs_launch(const Graph *g, Workspace *ws, const int32_t *sources, 
   a.tdscan = ws->dscan.as<int64_t>();   // int64[max(n, d) + 1]
   a.hubs = st->hubs.as<int32_t>();
   a.nhubs = st->nhubs;
+  a.col2 = st->col2.p ? st->col2.as<int32_t>() : a.col;
+  a.hub_idx = st->col2.p ? st->hub_idx.as<int32_t>() : nullptr;
+  a.hot = st->col2.p ? st->hot.p : nullptr;
   a.ctl = st->ctl.as<MsCtl>();
   a.bu_threshold = int64_t(g->n) * o.bu_permille / 1000;
   a.timeout_ticks = 100000000ll * 20;  // 20 s of the 100 MHz wall clock per barrier wait
@@ -1054,8 +1115,8 @@ __global__ void __launch_bounds__(256) k_lv_bu(MsLevel a, LaneRows r) {
       }
     }
     const uint64_t nw =
-        bu_wave<1>(a.off, a.col, reinterpret_cast<const LaneSet<1> *>(a.fcur), w,
-                   LaneSet<1>{{want}}, s_rows[wv], edges)
+        bu_wave<1>(a.off, a.col, reinterpret_cast<const LaneSet<1> *>(a.fcur), nullptr,
+                   INT32_MAX, w, LaneSet<1>{{want}}, s_rows[wv], edges)
             .w[0];
     if (valid) {
       if (nw) a.seen[w] = s0 | nw;
