@@ -137,9 +137,14 @@ struct Workspace {
 };
 
 // Per-lane result rows of a level-at-a-time multi-source step (server).
-struct LaneRows {
-  int32_t *res[64];   // result row of each lane (int32[n]) or NULL if the lane is idle
-  int32_t dval[64];   // depth this level writes for each lane
+// Rows written by one flush of the server's level ring (see k_lv_flush).
+struct LaneFlush {
+  int32_t *res[64];    // result row of each lane (int32[n]) or NULL if the lane is idle
+  int32_t start[64];   // level at which each lane's source had depth 0
+  uint64_t valid[16];  // per level jlo + o: the lanes whose unwritten levels include it
+  uint64_t lanes;      // lanes considered
+  int32_t jlo, jhi;    // levels [jlo, jhi], jhi - jlo < 16
+  int32_t final;       // 1: only lanes whose frontier ran empty; write -1 where unreached
 };
 
 // ---------------------------------------------------------------------------

@@ -677,6 +677,7 @@ struct MsState {
   DevBuf ctl, srcs, hubs;
   DevBuf ring, seen;  // kRing x n and n lane sets of `words` words each
   DevBuf hub_idx, col2, hot;  // hub frontier cache (see MsArgs)
+  DevBuf lvring;               // level-at-a-time use: kRing x n lane masks
   int words = 0;
   int64_t nhubs = -1;  // -1: hub list not built yet
   int32_t cap_k = 0;
@@ -936,7 +937,11 @@ void msbfs_tune(const Graph *g, Workspace *ws, const int32_t *sources, int32_t k
 // ---------------------------------------------------------------------------
 // Level-at-a-time multi-source BFS for the query server: lanes join and leave
 // at level boundaries (continuous batching), so each lane has its own result
-// row and its own depth offset, and the host decides between levels.
+// row and its own start level, and the host decides between levels. As in the
+// persistent kernel, a ring of kRing per-level lane masks is the frontier and
+// the depth record: a lane's row is written in one dense pass when its
+// frontier runs empty (or, for the levels about to be overwritten, when the
+// ring wraps).
 // ---------------------------------------------------------------------------
 namespace dsbfs {
 
@@ -945,6 +950,7 @@ struct MsLevel {
   const int32_t *col;
   int32_t n;
   uint64_t *seen, *fcur, *fnext;
+  uint64_t *ring;           // kRing slots of n masks; fcur / fnext are two of them
   int32_t *tdlist;
   int64_t *tdscan;
   const int32_t *hubs;
@@ -954,16 +960,6 @@ struct MsLevel {
 };
 
 namespace {
-
-__device__ __forceinline__ void put_rows(const LaneRows &r, int32_t v, uint64_t bits, bool valid) {
-  const uint64_t mine = valid ? bits : 0ull;
-  uint64_t all = wave_or_all(mine);
-  while (all) {
-    const int i = __ffsll(static_cast<long long>(all)) - 1;
-    all &= all - 1;
-    if ((mine >> i) & 1ull) r.res[i][v] = r.dval[i];
-  }
-}
 
 __device__ __forceinline__ void lv_flush(const MsLevel &a, unsigned long long act, uint64_t lor,
                                          unsigned long long edges) {
@@ -977,33 +973,74 @@ __device__ __forceinline__ void lv_flush(const MsLevel &a, unsigned long long ac
   }
 }
 
-// Clears the lanes in `clear` everywhere (recycled lanes) and fills the
-// result rows of the lanes in `fill` with -1.
-__global__ void k_lv_recycle(MsLevel a, uint64_t clear, uint64_t fill, LaneRows r) {
+// Clears the lanes in `clear` (recycled lanes) from seen and from the current
+// and next frontier. Their bits in older ring slots stay: a lane's rows only
+// ever read levels from its start on.
+__global__ void k_lv_recycle(MsLevel a, uint64_t clear) {
   const int64_t stride = int64_t(gridDim.x) * blockDim.x;
   for (int64_t v = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; v < a.n; v += stride) {
-    if (clear) {
-      a.seen[v] &= ~clear;
-      a.fcur[v] &= ~clear;
-      a.fnext[v] &= ~clear;
-    }
-    uint64_t f = fill;
-    while (f) {
-      const int i = __ffsll(static_cast<long long>(f)) - 1;
-      f &= f - 1;
-      r.res[i][v] = -1;
-    }
+    a.seen[v] &= ~clear;
+    a.fcur[v] &= ~clear;
+    a.fnext[v] &= ~clear;
   }
 }
 
-// Seeds lane i at source src[i] for every lane in `mask`.
-__global__ void k_lv_seed(MsLevel a, uint64_t mask, const int32_t *src, LaneRows r) {
+// Seeds lane i at source src[i] for every lane in `mask` (its depth 0 is
+// written from the ring with the rest of its row).
+__global__ void k_lv_seed(MsLevel a, uint64_t mask, const int32_t *src) {
   const int i = threadIdx.x;
   if (i < 64 && ((mask >> i) & 1ull)) {
     const int32_t s = src[i];
     atomicOr(reinterpret_cast<unsigned long long *>(&a.seen[s]), 1ull << i);
     atomicOr(reinterpret_cast<unsigned long long *>(&a.fcur[s]), 1ull << i);
-    r.res[i][s] = 0;
+  }
+}
+
+// Writes the result rows of a set of lanes from ring levels [f.jlo, f.jhi]
+// (fewer than kRing): depth j - start[i] where lane i's bit is in level j's
+// mask and f.valid[j - jlo] admits lane i (levels before a lane's start or
+// already written are excluded), and, when `final`, -1 where the lane never
+// arrived. final: the set is f.lanes minus the lanes still alive after the
+// level just run (ctl[1]), i.e. the lanes that completed; else f.lanes.
+__global__ void k_lv_flush(MsLevel a, LaneFlush f) {
+  uint64_t set = f.lanes;
+  if (f.final) set &= ~a.ctl[1];
+  if (!set) return;
+  const int64_t nthreads = int64_t(gridDim.x) * blockDim.x;
+  const int64_t tid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int64_t iters = (int64_t(a.n) + nthreads - 1) / nthreads;
+  const int32_t nlev = f.jhi - f.jlo + 1;
+  for (int64_t it = 0; it < iters; ++it) {
+    const int64_t v = tid + it * nthreads;
+    const bool valid = v < a.n;
+    uint64_t q0 = 0, q1 = 0, q2 = 0, q3 = 0, got = 0, miss = 0;
+    if (valid) {
+      for (int32_t o = 0; o < nlev; ++o) {
+        const int32_t j = f.jlo + o;
+        const uint64_t m = a.ring[int64_t(j & (kRing - 1)) * a.n + v] & f.valid[o] & set;
+        got |= m;
+        q0 |= (o & 1) ? m : 0ull;
+        q1 |= (o & 2) ? m : 0ull;
+        q2 |= (o & 4) ? m : 0ull;
+        q3 |= (o & 8) ? m : 0ull;
+      }
+      if (f.final) miss = ~a.seen[v] & set;
+    }
+    const uint64_t wr = got | miss;
+    uint64_t all = wave_or_all(wr);
+    while (all) {
+      const int i = __ffsll(static_cast<long long>(all)) - 1;
+      all &= all - 1;
+      if ((wr >> i) & 1ull) {
+        const int32_t d = ((miss >> i) & 1ull)
+                              ? -1
+                              : f.jlo + int32_t((q0 >> i) & 1ull) +
+                                    (int32_t((q1 >> i) & 1ull) << 1) +
+                                    (int32_t((q2 >> i) & 1ull) << 2) +
+                                    (int32_t((q3 >> i) & 1ull) << 3) - f.start[i];
+        f.res[i][v] = d;
+      }
+    }
   }
 }
 
@@ -1070,7 +1107,9 @@ __global__ void k_lv_td_expand(MsLevel a) {
   lv_flush(a, 0, 0, edges);
 }
 
-__global__ void k_lv_td_close(MsLevel a, LaneRows r) {
+// Close of a top-down level: fold next into seen (the scatter only set lanes
+// that were unseen, and seen did not change during it, so next is all new).
+__global__ void k_lv_td_close(MsLevel a) {
   const int64_t nthreads = int64_t(gridDim.x) * blockDim.x;
   const int64_t tid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   const int64_t iters = (int64_t(a.n) + nthreads - 1) / nthreads;
@@ -1078,23 +1117,19 @@ __global__ void k_lv_td_close(MsLevel a, LaneRows r) {
   uint64_t lor = 0;
   for (int64_t it = 0; it < iters; ++it) {
     const int64_t v = tid + it * nthreads;
-    const bool valid = v < a.n;
-    uint64_t nw = 0;
-    if (valid) {
-      const uint64_t s0 = a.seen[v];
-      nw = a.fnext[v] & ~s0;
-      a.fnext[v] = nw;
-      a.seen[v] = s0 | nw;
-      a.fcur[v] = 0;
-      act += nw != 0;
-      lor |= nw;
+    if (v < a.n) {
+      const uint64_t nw = a.fnext[v];
+      if (nw) {
+        a.seen[v] |= nw;
+        ++act;
+        lor |= nw;
+      }
     }
-    put_rows(r, int32_t(valid ? v : 0), nw, valid);
   }
   lv_flush(a, act, lor, 0);
 }
 
-__global__ void __launch_bounds__(256) k_lv_bu(MsLevel a, LaneRows r) {
+__global__ void __launch_bounds__(256) k_lv_bu(MsLevel a) {
   __shared__ BuRows<1> s_rows[4];
   const int64_t nthreads = int64_t(gridDim.x) * blockDim.x;
   const int64_t tid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -1124,7 +1159,6 @@ __global__ void __launch_bounds__(256) k_lv_bu(MsLevel a, LaneRows r) {
       act += nw != 0;
       lor |= nw;
     }
-    put_rows(r, int32_t(valid ? w : 0), nw, valid);
   }
   const int64_t wid = tid / kWave, nwaves = nthreads / kWave;
   for (int64_t h = wid; h < a.nhubs; h += nwaves) {
@@ -1149,7 +1183,6 @@ __global__ void __launch_bounds__(256) k_lv_bu(MsLevel a, LaneRows r) {
       act += nw != 0;
       lor |= nw;
     }
-    if ((nw >> l) & 1ull) r.res[l][w] = r.dval[l];
   }
   lv_flush(a, act, lor, edges);
 }
@@ -1157,24 +1190,31 @@ __global__ void __launch_bounds__(256) k_lv_bu(MsLevel a, LaneRows r) {
 }  // namespace
 
 // Host side of one level for the server. ws must have 64 lanes. `live` are
-// the lanes with a non-empty frontier; results go to r.res / r.dval. After
-// the call (asynchronous on s) ctl[0] holds the next frontier's vertex
-// count, ctl[1] its lanes. Returns the direction used (0 top-down, 1 up).
-int ms_level(const Graph *g, Workspace *ws, uint64_t live, int64_t active, int32_t bu_permille,
-             const LaneRows &r, unsigned long long *ctl, hipStream_t s) {
+// the lanes with a non-empty frontier; L is the level (ring slot L is its
+// frontier, slot L + 1 receives the next). After the call (asynchronous on s)
+// ctl[0] holds the next frontier's vertex count, ctl[1] its lanes. Returns
+// the direction used (0 top-down, 1 up).
+static MsLevel level_args(const Graph *g, Workspace *ws, int32_t L, unsigned long long *ctl) {
   MsState *st = reinterpret_cast<MsState *>(ws->ms_state);
   MsLevel a{};
   a.off = g->poff.as<int64_t>();
   a.col = g->pcol.as<int32_t>();
   a.n = g->n;
   a.seen = ws->ms_seen.as<uint64_t>();
-  a.fcur = ws->ms_front.as<uint64_t>();
-  a.fnext = ws->ms_next.as<uint64_t>();
+  a.ring = st->lvring.as<uint64_t>();
+  a.fcur = a.ring + int64_t(L & (kRing - 1)) * g->n;
+  a.fnext = a.ring + int64_t((L + 1) & (kRing - 1)) * g->n;
   a.tdlist = ws->dlen.as<int32_t>();
   a.tdscan = ws->dscan.as<int64_t>();
   a.hubs = st->hubs.as<int32_t>();
   a.nhubs = st->nhubs;
   a.ctl = ctl;
+  return a;
+}
+
+int ms_level(const Graph *g, Workspace *ws, uint64_t live, int64_t active, int32_t bu_permille,
+             int32_t L, unsigned long long *ctl, hipStream_t s) {
+  MsLevel a = level_args(g, ws, L, ctl);
   a.live = live;
   const int SG = device_cus() * 8;
   HIPCHK(hipMemsetAsync(ctl, 0, 4 * sizeof(unsigned long long), s));
@@ -1184,14 +1224,39 @@ int ms_level(const Graph *g, Workspace *ws, uint64_t live, int64_t active, int32
     hipLaunchKernelGGL(k_lv_td_list, dim3(grid_for(g->n, 256, SG)), dim3(256), 0, s, a);
     hipLaunchKernelGGL(k_lv_td_scan, dim3(1), dim3(1024), 0, s, a);
     hipLaunchKernelGGL(k_lv_td_expand, dim3(SG), dim3(256), 0, s, a);
-    hipLaunchKernelGGL(k_lv_td_close, dim3(grid_for(g->n, 256, SG)), dim3(256), 0, s, a, r);
+    hipLaunchKernelGGL(k_lv_td_close, dim3(grid_for(g->n, 256, SG)), dim3(256), 0, s, a);
   } else {
-    hipLaunchKernelGGL(k_lv_bu, dim3(grid_for(g->n, 256, SG)), dim3(256), 0, s, a, r);
+    hipLaunchKernelGGL(k_lv_bu, dim3(grid_for(g->n, 256, SG)), dim3(256), 0, s, a);
   }
   HIPCHK(hipGetLastError());
-  // the next frontier becomes the current one
-  std::swap(ws->ms_front, ws->ms_next);
   return td ? 0 : 1;
+}
+
+// Writes result rows from the level ring (k_lv_flush); ctl is the level's
+// control block (read for `final`).
+void ms_level_flush(const Graph *g, Workspace *ws, const LaneFlush &f, unsigned long long *ctl,
+                    hipStream_t s) {
+  if (f.jhi - f.jlo >= kRing || f.jhi < f.jlo)
+    fail(DSBFS_ERR_DEVICE, "server level flush window outside the ring");
+  MsLevel a = level_args(g, ws, f.jhi, ctl);
+  const int SG = device_cus() * 8;
+  hipLaunchKernelGGL(k_lv_flush, dim3(grid_for(g->n, 256, SG)), dim3(256), 0, s, a, f);
+  HIPCHK(hipGetLastError());
+}
+
+// Levels a lane may keep unwritten in the ring before its rows must be
+// flushed (the ring holds kRing levels; one slot receives the next level).
+int ms_level_ring() { return kRing; }
+
+// Device bytes held by the multi-source state of a workspace.
+size_t ms_state_bytes(const Workspace *ws) {
+  const MsState *st = reinterpret_cast<const MsState *>(ws->ms_state);
+  if (!st) return 0;
+  const DevBuf *b[] = {&st->ctl, &st->srcs, &st->hubs, &st->ring, &st->seen,
+                       &st->hub_idx, &st->col2, &st->hot, &st->lvring};
+  size_t t = 0;
+  for (const DevBuf *x : b) t += x->p ? x->bytes : 0;
+  return t;
 }
 
 // Prepares a 64-lane workspace for level-at-a-time use (hub list, state).
@@ -1200,8 +1265,8 @@ void ms_level_prepare(const Graph *g, Workspace *ws, hipStream_t s) {
   if (!g->pcol.p && g->m > 0) fail(DSBFS_ERR_INVALID_ARG, "batched serving needs the plain CSR");
   if (!ws->ms_state) ws->ms_state = new MsState();
   MsState *st = reinterpret_cast<MsState *>(ws->ms_state);
+  const Alloc *al = &g->al;
   if (st->nhubs < 0) {
-    const Alloc *al = &g->al;
     DevBuf flag, tmp, cnt;
     flag.alloc(al, size_t(g->n), s);
     tmp.alloc(al, compact_tmp_bytes(g->n), s);
@@ -1215,25 +1280,21 @@ void ms_level_prepare(const Graph *g, Workspace *ws, hipStream_t s) {
     st->nhubs = d2h_scalar(cnt.as<int64_t>(), s);
   }
   const int64_t n = g->n;
+  if (!st->lvring.p) st->lvring.alloc(al, size_t(kRing) * size_t(n) * 8, s);
   HIPCHK(hipMemsetAsync(ws->ms_seen.p, 0, size_t(n) * 8, s));
-  HIPCHK(hipMemsetAsync(ws->ms_front.p, 0, size_t(n) * 8, s));
-  HIPCHK(hipMemsetAsync(ws->ms_next.p, 0, size_t(n) * 8, s));
+  HIPCHK(hipMemsetAsync(st->lvring.p, 0, size_t(kRing) * size_t(n) * 8, s));
 }
 
-void ms_level_recycle(const Graph *g, Workspace *ws, uint64_t clear, uint64_t fill,
-                      uint64_t seed_mask, const int32_t *seed_src_dev, const LaneRows &r,
-                      hipStream_t s) {
-  MsLevel a{};
-  a.n = g->n;
-  a.seen = ws->ms_seen.as<uint64_t>();
-  a.fcur = ws->ms_front.as<uint64_t>();
-  a.fnext = ws->ms_next.as<uint64_t>();
+// Admission at level L: clears the lanes in `clear` and seeds the lanes in
+// seed_mask at seed_src_dev[i].
+void ms_level_recycle(const Graph *g, Workspace *ws, int32_t L, uint64_t clear, uint64_t seed_mask,
+                      const int32_t *seed_src_dev, hipStream_t s) {
+  MsLevel a = level_args(g, ws, L, nullptr);
   const int SG = device_cus() * 8;
-  if (clear || fill)
-    hipLaunchKernelGGL(k_lv_recycle, dim3(grid_for(g->n, 256, SG)), dim3(256), 0, s, a, clear,
-                       fill, r);
+  if (clear)
+    hipLaunchKernelGGL(k_lv_recycle, dim3(grid_for(g->n, 256, SG)), dim3(256), 0, s, a, clear);
   if (seed_mask) hipLaunchKernelGGL(k_lv_seed, dim3(1), dim3(64), 0, s, a, seed_mask,
-                                    seed_src_dev, r);
+                                    seed_src_dev);
   HIPCHK(hipGetLastError());
 }
 

@@ -42,11 +42,14 @@
 namespace dsbfs {
 
 int ms_level(const Graph *g, Workspace *ws, uint64_t live, int64_t active, int32_t bu_permille,
-             const LaneRows &r, unsigned long long *ctl, hipStream_t s);
+             int32_t L, unsigned long long *ctl, hipStream_t s);
+void ms_level_flush(const Graph *g, Workspace *ws, const LaneFlush &f, unsigned long long *ctl,
+                    hipStream_t s);
+int ms_level_ring();
+size_t ms_state_bytes(const Workspace *ws);
 void ms_level_prepare(const Graph *g, Workspace *ws, hipStream_t s);
-void ms_level_recycle(const Graph *g, Workspace *ws, uint64_t clear, uint64_t fill,
-                      uint64_t seed_mask, const int32_t *seed_src_dev, const LaneRows &r,
-                      hipStream_t s);
+void ms_level_recycle(const Graph *g, Workspace *ws, int32_t L, uint64_t clear, uint64_t seed_mask,
+                      const int32_t *seed_src_dev, hipStream_t s);
 Workspace *workspace_create(const Graph *g, int32_t max_lanes);
 void workspace_destroy(Workspace *ws);
 void graph_destroy(Graph *G);
@@ -79,7 +82,7 @@ size_t workspace_footprint(const Workspace *w) {
          buf_bytes(w->dcand) + buf_bytes(w->dlen) + buf_bytes(w->dscan) + buf_bytes(w->c0) +
          buf_bytes(w->c1) + buf_bytes(w->ctr) + buf_bytes(w->scan_tmp) + buf_bytes(w->ms_seen) +
          buf_bytes(w->ms_front) + buf_bytes(w->ms_next) + buf_bytes(w->dctl) +
-         buf_bytes(w->dtiles) + size_t(w->g->n) * 5;  // + hub list
+         buf_bytes(w->dtiles) + ms_state_bytes(w);
 }
 
 enum QState { Q_PENDING = 0, Q_RUNNING = 1, Q_DONE = 2, Q_RELEASED = 3 };
@@ -102,6 +105,7 @@ struct Cohort {
   hipEvent_t ev = nullptr, ev0 = nullptr;
   Query *lane[64] = {};
   int32_t start_level[64] = {};
+  int32_t from[64] = {};  // first level of each lane whose depths are not yet written
   uint64_t used = 0, live = 0, new_lanes = 0;
   int64_t active = 0;
   int32_t L = 0;
@@ -255,6 +259,7 @@ struct Server {
           q->batched = 1;
           c.lane[i] = q;
           c.start_level[i] = c.L;
+          c.from[i] = c.L;
           c.seed_host[i] = q->source;
           c.new_lanes |= 1ull << i;
         }
@@ -264,24 +269,52 @@ struct Server {
     }
   }
 
-  // Enqueues one multi-source level of cohort c of G on its stream.
-  void launch_level(GState *G, Cohort &c) {
-    LaneRows r{};
+  // Rows of the lanes in `lanes` from their first unwritten level up to the
+  // current level c.L (final: only those whose frontier ran empty this level).
+  static LaneFlush lane_flush(const Cohort &c, uint64_t lanes, int final) {
+    LaneFlush f{};
+    f.lanes = lanes;
+    f.final = final;
+    f.jhi = c.L;
+    f.jlo = c.L;
+    for (uint64_t m = lanes; m; m &= m - 1) f.jlo = std::min(f.jlo, c.from[__builtin_ctzll(m)]);
     for (int i = 0; i < 64; ++i) {
-      r.res[i] = c.lane[i] ? c.lane[i]->res : nullptr;
-      r.dval[i] = c.L + 1 - c.start_level[i];
+      f.res[i] = c.lane[i] ? c.lane[i]->res : nullptr;
+      f.start[i] = c.start_level[i];
     }
+    for (int o = 0; o <= f.jhi - f.jlo; ++o)
+      for (uint64_t m = lanes; m; m &= m - 1) {
+        const int i = __builtin_ctzll(m);
+        if (c.from[i] <= f.jlo + o) f.valid[o] |= 1ull << i;
+      }
+    return f;
+  }
+
+  // Enqueues one multi-source level of cohort c of G on its stream, then the
+  // rows of the lanes it completes.
+  void launch_level(GState *G, Cohort &c) {
     HIPCHK(hipEventRecord(c.ev0, c.stream));
+    // this level's next frontier overwrites ring level L + 1 - ring: lanes
+    // whose rows still need it are written up to level L first
+    uint64_t wrap = 0;
+    for (uint64_t m = c.used & ~c.new_lanes; m; m &= m - 1) {
+      const int i = __builtin_ctzll(m);
+      if (c.from[i] <= c.L + 1 - ms_level_ring()) wrap |= 1ull << i;
+    }
+    if (wrap) {
+      ms_level_flush(G->g, c.ws, lane_flush(c, wrap, 0), c.ctl_dev, c.stream);
+      for (uint64_t m = wrap; m; m &= m - 1) c.from[__builtin_ctzll(m)] = c.L + 1;
+    }
     if (c.new_lanes) {
       HIPCHK(hipMemcpyAsync(c.seed_dev, c.seed_host, 64 * sizeof(int32_t),
                             hipMemcpyHostToDevice, c.stream));
-      ms_level_recycle(G->g, c.ws, c.new_lanes, c.new_lanes, c.new_lanes, c.seed_dev, r,
-                       c.stream);
+      ms_level_recycle(G->g, c.ws, c.L, c.new_lanes, c.new_lanes, c.seed_dev, c.stream);
       c.live |= c.new_lanes;
       c.active += __builtin_popcountll(c.new_lanes);
       c.new_lanes = 0;
     }
-    ms_level(G->g, c.ws, c.live, c.active, o.ms.bu_permille, r, c.ctl_dev, c.stream);
+    ms_level(G->g, c.ws, c.live, c.active, o.ms.bu_permille, c.L, c.ctl_dev, c.stream);
+    ms_level_flush(G->g, c.ws, lane_flush(c, c.used, 1), c.ctl_dev, c.stream);
     HIPCHK(hipMemcpyAsync(c.ctl_host, c.ctl_dev, 4 * sizeof(unsigned long long),
                           hipMemcpyDeviceToHost, c.stream));
     HIPCHK(hipEventRecord(c.ev, c.stream));

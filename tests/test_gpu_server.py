@@ -7,6 +7,7 @@ import time
 import numpy as np
 import pytest
 
+from closed_forms import disjoint_paths, path
 from gpu_helpers import lib, log, torch_cuda
 
 pytestmark = pytest.mark.gpu
@@ -64,6 +65,31 @@ def test_server_mix_matches_oracle(inputs_mod, oracle_mod, batched):
         np.testing.assert_array_equal(row, want, err_msg=f"graph {k} source {s}")
         assert st["done_ns"] >= st["start_ns"] >= st["admit_ns"] >= st["arrival_ns"] > 0
         assert st["batched"] == int(batched) or (batched == 2 and st["batched"] in (0, 1))
+    S.destroy()
+
+
+def test_server_long_paths(oracle_mod):
+    """Searches far longer than the kernel's ring of level masks (a path of
+    150 vertices, and two disjoint paths so that rows also hold -1), with
+    queries joining at different levels: rows are written in several passes
+    per lane, each lane from its own start level."""
+    forms = [path(150), disjoint_paths(60, 50)]
+    specs = [(n, s, t, None) for n, s, t, _ in forms]
+    S, gids = _server(specs, 1)
+    rng = np.random.default_rng(11)
+    jobs = []
+    for i in range(60):
+        k = i % 2
+        n = forms[k][0]
+        src = int(rng.integers(0, n))
+        jobs.append((k, src, S.submit(gids[k], src)))
+        if i % 6 == 5:
+            time.sleep(0.003)
+    for k, src, t in jobs:
+        n, _, _, dist = forms[k]
+        row, st = _fetch(S, t, n)
+        np.testing.assert_array_equal(row, dist(src), err_msg=f"graph {k} source {src}")
+        assert st["batched"] == 1
     S.destroy()
 
 
