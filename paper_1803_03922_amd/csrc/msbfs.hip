@@ -453,10 +453,12 @@ __global__ void __launch_bounds__(1024) k_msbfs(MsArgs a) {
               const int32_t v = a.tdlist[own + o];
               const int32_t w = a.col[a.off[v] + (e - win[o])];
               ++edges;
-              const LaneSet<W> fv = fcur[v], sw = seen[w];
+              // lanes already in next (a possibly stale read: the atomic
+              // decides) need no atomic
+              const LaneSet<W> fv = fcur[v], sw = seen[w], nx = fnext[w];
 #pragma unroll
               for (int x = 0; x < W; ++x) {
-                const uint64_t m = fv.w[x] & ~sw.w[x];
+                const uint64_t m = fv.w[x] & ~sw.w[x] & ~nx.w[x];
                 if (m) atomicOr(reinterpret_cast<unsigned long long *>(&fnext[w].w[x]), m);
               }
             }
@@ -1101,7 +1103,9 @@ __global__ void k_lv_td_expand(MsLevel a) {
     const int32_t v = a.tdlist[lo];
     const int32_t w = a.col[a.off[v] + (e - a.tdscan[lo])];
     ++edges;
-    const uint64_t m = a.fcur[v] & ~a.seen[w];
+    // lanes already in next (a possibly stale read: the atomic decides) need
+    // no atomic
+    const uint64_t m = a.fcur[v] & ~a.seen[w] & ~a.fnext[w];
     if (m) atomicOr(reinterpret_cast<unsigned long long *>(&a.fnext[w]), m);
   }
   lv_flush(a, 0, 0, edges);
