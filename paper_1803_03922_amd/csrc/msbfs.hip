@@ -522,43 +522,63 @@ __global__ void __launch_bounds__(1024) k_msbfs(MsArgs a) {
             for (int x = 0; x < W; ++x) lor.w[x] |= nw.w[x];
           }
         }
-        for (int64_t h = wid; h < a.nhubs; h += nwaves) {
-          const int32_t w = a.hubs[h];
-          const LaneSet<W> s0 = seen[w];
-          LaneSet<W> want, acc{};
+        // hubs, 64 per wave step: each lane screens one and closes it if it
+        // wants nothing (most hubs in late levels); the wave then scans the
+        // rows of the others one at a time
+        for (int64_t h0 = wid * kWave; h0 < a.nhubs; h0 += nwaves * kWave) {
+          const int64_t hl = h0 + l;
+          bool need = false;
+          if (hl < a.nhubs) {
+            const int32_t wl = a.hubs[hl];
+            const LaneSet<W> sl = seen[wl];
+            LaneSet<W> wantl;
 #pragma unroll
-          for (int x = 0; x < W; ++x) want.w[x] = ~s0.w[x] & live.w[x];
-          if (lanes_any(want)) {
-            const int64_t p1 = a.off[w + 1];
-            for (int64_t p = a.off[w]; p < p1; p += kWave) {
-              LaneSet<W> y{};
-              if (p + l < p1) y = front_of<W>(fcur, hcur, nlim, a.col2[p + l]);
-              bool done = true;
-#pragma unroll
-              for (int x = 0; x < W; ++x) {
-                acc.w[x] |= wave_or(y.w[x]);
-                done = done && (acc.w[x] & want.w[x]) == want.w[x];
-              }
-              if (l == 0) edges += uint64_t(min<int64_t>(kWave, p1 - p));
-              if (done) break;
+            for (int x = 0; x < W; ++x) wantl.w[x] = ~sl.w[x] & live.w[x];
+            need = lanes_any(wantl);
+            if (!need) {
+              fnext[wl] = LaneSet<W>{};
+              if (hot) hnext[hl] = LaneSet<W>{};
             }
           }
-          LaneSet<W> nw;
+          for (uint64_t todo = __ballot(need); todo; todo &= todo - 1) {
+            const int64_t h = h0 + __builtin_ctzll(todo);
+            const int32_t w = a.hubs[h];
+            const LaneSet<W> s0 = seen[w];
+            LaneSet<W> want, acc{};
 #pragma unroll
-          for (int x = 0; x < W; ++x) nw.w[x] = acc.w[x] & want.w[x];
-          if (l == 0) {
-            const bool any = lanes_any(nw);
-            if (any) {
-              LaneSet<W> s1;
+            for (int x = 0; x < W; ++x) want.w[x] = ~s0.w[x] & live.w[x];
+            {
+              const int64_t p1 = a.off[w + 1];
+              for (int64_t p = a.off[w]; p < p1; p += kWave) {
+                LaneSet<W> y{};
+                if (p + l < p1) y = front_of<W>(fcur, hcur, nlim, a.col2[p + l]);
+                bool done = true;
 #pragma unroll
-              for (int x = 0; x < W; ++x) s1.w[x] = s0.w[x] | nw.w[x];
-              seen[w] = s1;
+                for (int x = 0; x < W; ++x) {
+                  acc.w[x] |= wave_or(y.w[x]);
+                  done = done && (acc.w[x] & want.w[x]) == want.w[x];
+                }
+                if (l == 0) edges += uint64_t(min<int64_t>(kWave, p1 - p));
+                if (done) break;
+              }
             }
-            fnext[w] = nw;
-            if (hot) hnext[h] = nw;
-            act += any;
+            LaneSet<W> nw;
 #pragma unroll
-            for (int x = 0; x < W; ++x) lor.w[x] |= nw.w[x];
+            for (int x = 0; x < W; ++x) nw.w[x] = acc.w[x] & want.w[x];
+            if (l == 0) {
+              const bool any = lanes_any(nw);
+              if (any) {
+                LaneSet<W> s1;
+#pragma unroll
+                for (int x = 0; x < W; ++x) s1.w[x] = s0.w[x] | nw.w[x];
+                seen[w] = s1;
+              }
+              fnext[w] = nw;
+              if (hot) hnext[h] = nw;
+              act += any;
+#pragma unroll
+              for (int x = 0; x < W; ++x) lor.w[x] |= nw.w[x];
+            }
           }
         }
       }
@@ -1165,27 +1185,38 @@ __global__ void __launch_bounds__(256) k_lv_bu(MsLevel a) {
     }
   }
   const int64_t wid = tid / kWave, nwaves = nthreads / kWave;
-  for (int64_t h = wid; h < a.nhubs; h += nwaves) {
-    const int32_t w = a.hubs[h];
-    const uint64_t s0 = a.seen[w];
-    const uint64_t want = ~s0 & a.live;
-    uint64_t nw = 0;
-    if (want) {
-      const int64_t p1 = a.off[w + 1];
-      uint64_t acc = 0;
-      for (int64_t p = a.off[w]; p < p1; p += kWave) {
-        const uint64_t x = p + l < p1 ? a.fcur[a.col[p + l]] : 0ull;
-        acc |= wave_or(x);
-        if (l == 0) edges += uint64_t(min<int64_t>(kWave, p1 - p));
-        if ((acc & want) == want) break;
-      }
-      nw = acc & want;
+  // hubs, 64 per wave step: lanes close those that want nothing, the wave
+  // scans the rows of the others one at a time
+  for (int64_t h0 = wid * kWave; h0 < a.nhubs; h0 += nwaves * kWave) {
+    const int64_t hl = h0 + l;
+    bool need = false;
+    if (hl < a.nhubs) {
+      const int32_t wl = a.hubs[hl];
+      need = (~a.seen[wl] & a.live) != 0;
+      if (!need) a.fnext[wl] = 0;
     }
-    if (l == 0) {
-      if (nw) a.seen[w] = s0 | nw;
-      a.fnext[w] = nw;
-      act += nw != 0;
-      lor |= nw;
+    for (uint64_t todo = __ballot(need); todo; todo &= todo - 1) {
+      const int32_t w = a.hubs[h0 + __builtin_ctzll(todo)];
+      const uint64_t s0 = a.seen[w];
+      const uint64_t want = ~s0 & a.live;
+      uint64_t nw = 0;
+      {
+        const int64_t p1 = a.off[w + 1];
+        uint64_t acc = 0;
+        for (int64_t p = a.off[w]; p < p1; p += kWave) {
+          const uint64_t x = p + l < p1 ? a.fcur[a.col[p + l]] : 0ull;
+          acc |= wave_or(x);
+          if (l == 0) edges += uint64_t(min<int64_t>(kWave, p1 - p));
+          if ((acc & want) == want) break;
+        }
+        nw = acc & want;
+      }
+      if (l == 0) {
+        if (nw) a.seen[w] = s0 | nw;
+        a.fnext[w] = nw;
+        act += nw != 0;
+        lor |= nw;
+      }
     }
   }
   lv_flush(a, act, lor, edges);
