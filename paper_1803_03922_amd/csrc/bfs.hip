@@ -316,6 +316,10 @@ __global__ void __launch_bounds__(kBS) k_normal_level(const int32_t *Q, const Le
                                                       const DevCtl *c, int32_t *Qnext,
                                                       LevelCtr *cur) {
   if (c->done) return;
+  const int64_t qn = int64_t(prev->qn_next);
+  // blocks past the queue have nothing to add (a short queue leaves most of
+  // the grid idle: skip its LDS set-up and block reductions)
+  if (int64_t(blockIdx.x) * blockDim.x >= qn) return;
   const int mark_fn = c->mark_fn;
   out.level1 = c->level1;
   __shared__ int32_t s_excl[kNW][kWave];
@@ -328,7 +332,6 @@ __global__ void __launch_bounds__(kBS) k_normal_level(const int32_t *Q, const Le
   BlockAppend qa{qbuf, &qcount, &qbase, kQCap, &cur->qn_next, Qnext};
   qa.init();
   const int w = threadIdx.x / kWave;
-  const int64_t qn = int64_t(prev->qn_next);
   unsigned long long fv_nn = 0, q_nn = 0, fv_nd = 0, q_nd = 0, edges = 0, claimed = 0;
   for (int64_t b0 = int64_t(blockIdx.x) * blockDim.x; b0 < qn;
        b0 += int64_t(gridDim.x) * blockDim.x) {
