@@ -236,8 +236,9 @@ dsbfs_status dsbfs_graph_destroy(dsbfs_graph *g);
 
 /*
  * Per-call scratch for searches on graph g: bitmaps, queues and counters of
- * single-source search, and lane state for up to max_lanes (0 or 64)
- * simultaneous multi-source lanes. Memory from the graph's allocator.
+ * single-source search. max_lanes (0 or 64) = 64 enables multi-source use,
+ * whose lane state is allocated at its first call (see dsbfs_msbfs). Memory
+ * from the graph's allocator.
  */
 dsbfs_status dsbfs_workspace_create(const dsbfs_graph *g, int32_t max_lanes,
                                     dsbfs_workspace **out);

@@ -1030,11 +1030,6 @@ Workspace *workspace_create(const Graph *g, int32_t max_lanes) {
     HIPCHK(hipHostMalloc(&ws->hstat, kStatusSlots * sizeof(LevelStatus), hipHostMallocDefault));
     std::memset(ws->hstat, 0, kStatusSlots * sizeof(LevelStatus));
     for (hipEvent_t &e : ws->lev_ev) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-    if (max_lanes == 64) {
-      ws->ms_seen.alloc(al, size_t(n) * 8, s);
-      ws->ms_front.alloc(al, size_t(n) * 8, s);
-      ws->ms_next.alloc(al, size_t(n) * 8, s);
-    }
     return ws;
   } catch (...) {
     delete ws;

@@ -131,7 +131,6 @@ struct Workspace {
   void *lvl = nullptr;         // captured level graphs
   hipEvent_t lev_ev[3] = {};   // completion of recent levels
   // multi-source lane state
-  DevBuf ms_seen, ms_front, ms_next;  // uint64[n]
   void *ms_state = nullptr;           // launch state of multi-source BFS (msbfs.hip)
   ~Workspace();
 };

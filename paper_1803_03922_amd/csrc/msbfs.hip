@@ -699,7 +699,7 @@ struct MsState {
   DevBuf ctl, srcs, hubs;
   DevBuf ring, seen;  // kRing x n and n lane sets of `words` words each
   DevBuf hub_idx, col2, hot;  // hub frontier cache (see MsArgs)
-  DevBuf lvring;               // level-at-a-time use: kRing x n lane masks
+  DevBuf lvring, lvseen;       // level-at-a-time use: kRing x n and n lane masks
   int words = 0;
   int64_t nhubs = -1;  // -1: hub list not built yet
   int32_t cap_k = 0;
@@ -1235,7 +1235,7 @@ static MsLevel level_args(const Graph *g, Workspace *ws, int32_t L, unsigned lon
   a.off = g->poff.as<int64_t>();
   a.col = g->pcol.as<int32_t>();
   a.n = g->n;
-  a.seen = ws->ms_seen.as<uint64_t>();
+  a.seen = st->lvseen.as<uint64_t>();
   a.ring = st->lvring.as<uint64_t>();
   a.fcur = a.ring + int64_t(L & (kRing - 1)) * g->n;
   a.fnext = a.ring + int64_t((L + 1) & (kRing - 1)) * g->n;
@@ -1288,7 +1288,7 @@ size_t ms_state_bytes(const Workspace *ws) {
   const MsState *st = reinterpret_cast<const MsState *>(ws->ms_state);
   if (!st) return 0;
   const DevBuf *b[] = {&st->ctl, &st->srcs, &st->hubs, &st->ring, &st->seen,
-                       &st->hub_idx, &st->col2, &st->hot, &st->lvring};
+                       &st->hub_idx, &st->col2, &st->hot, &st->lvring, &st->lvseen};
   size_t t = 0;
   for (const DevBuf *x : b) t += x->p ? x->bytes : 0;
   return t;
@@ -1316,7 +1316,8 @@ void ms_level_prepare(const Graph *g, Workspace *ws, hipStream_t s) {
   }
   const int64_t n = g->n;
   if (!st->lvring.p) st->lvring.alloc(al, size_t(kRing) * size_t(n) * 8, s);
-  HIPCHK(hipMemsetAsync(ws->ms_seen.p, 0, size_t(n) * 8, s));
+  if (!st->lvseen.p) st->lvseen.alloc(al, size_t(n) * 8, s);
+  HIPCHK(hipMemsetAsync(st->lvseen.p, 0, size_t(n) * 8, s));
   HIPCHK(hipMemsetAsync(st->lvring.p, 0, size_t(kRing) * size_t(n) * 8, s));
 }
 

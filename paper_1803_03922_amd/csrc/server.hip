@@ -80,8 +80,7 @@ size_t workspace_footprint(const Workspace *w) {
   return buf_bytes(w->Vn) + buf_bytes(w->Fn) + buf_bytes(w->Vd) + buf_bytes(w->Fd) +
          buf_bytes(w->Cd) + buf_bytes(w->q0) + buf_bytes(w->q1) + buf_bytes(w->dlist) +
          buf_bytes(w->dcand) + buf_bytes(w->dlen) + buf_bytes(w->dscan) + buf_bytes(w->c0) +
-         buf_bytes(w->c1) + buf_bytes(w->ctr) + buf_bytes(w->scan_tmp) + buf_bytes(w->ms_seen) +
-         buf_bytes(w->ms_front) + buf_bytes(w->ms_next) + buf_bytes(w->dctl) +
+         buf_bytes(w->c1) + buf_bytes(w->ctr) + buf_bytes(w->scan_tmp) + buf_bytes(w->dctl) +
          buf_bytes(w->dtiles) + ms_state_bytes(w);
 }
 
