@@ -114,7 +114,7 @@ def test_level_graph_replays_and_recapture(inputs_mod, oracle_mod):
     G.close()
 
 
-def test_config1_plain_scale16_64_sources(inputs_mod, oracle_mod):
+def test_plain_rmat16_64_sources(inputs_mod, oracle_mod):
     """Plain top-down BFS, RMAT scale 16, 64 seeded sources with degree >= 1."""
     n, src, dst, O = _rmat(inputs_mod, oracle_mod, 16)
     label = O.components()
@@ -129,7 +129,7 @@ def test_config1_plain_scale16_64_sources(inputs_mod, oracle_mod):
     G.close()
 
 
-def test_config2_do_scale22(inputs_mod, oracle_mod):
+def test_do_rmat22_64_sources(inputs_mod, oracle_mod):
     """Degree-separated DOBFS, TH = 32, RMAT scale 22, seeded sources."""
     n, src, dst, O = _rmat(inputs_mod, oracle_mod, 22)
     log("scale 22 oracle graph built")
@@ -148,7 +148,7 @@ def test_config2_do_scale22(inputs_mod, oracle_mod):
     G.close()
 
 
-def test_config3_scale26_sampled(inputs_mod, oracle_mod):
+def test_do_rmat26_sampled_source(inputs_mod, oracle_mod):
     """RMAT scale 26 (2.1e9 directed edges, within 2% of 2^31), TH 32,
     parents, as the bench runs it (captured level graphs): the first of its
     seeded sources against the oracle, depths bit-exact, parents by the

@@ -111,8 +111,9 @@ def test_msbfs_launch_shapes(inputs_mod, oracle_mod):
             np.testing.assert_array_equal(got[i], wants[i], err_msg=f"replay {rep} lane {i}")
 
 
-def test_msbfs_config4_scale24_1024_sources(inputs_mod, oracle_mod):
-    """RMAT scale 24, 1024 sources = 16 batches in one launch; 16 sampled rows
+def test_msbfs_rmat24_1024_sources(inputs_mod, oracle_mod):
+    """RMAT scale 24, 1024 sources = 4 batches of 256 lanes in one launch, with
+    the tuner's launch configuration as the benchmark uses it; 16 sampled rows
     against the oracle, and on every row: depth 0 at its source only, and the
     reached count equals the size of the source's component."""
     torch = torch_cuda()
@@ -126,7 +127,10 @@ def test_msbfs_config4_scale24_1024_sources(inputs_mod, oracle_mod):
     g, ws = _setup(src, dst, n)
     sources = inputs_mod.pick_sources(src, dst, n, 1024, seed=1004)
     assert len(sources) == 1024
-    depth = _run(g, ws, n, sources, None)
+    # the launch configuration the benchmark times: the tuner's choice
+    opts = lib().msbfs_tune(g, ws, sources)
+    log(f"tuned {opts.as_dict()}")
+    depth = _run(g, ws, n, sources, opts)
     log("scale 24 multi-source BFS done")
     reached = (depth >= 0).sum(dim=1).cpu().numpy()
     np.testing.assert_array_equal(reached, comp_size[label[sources]])
