@@ -9,7 +9,7 @@ import tempfile
 import numpy as np
 import pytest
 
-from closed_forms import disjoint_paths, grid, hypercube, path, star
+from closed_forms import disjoint_paths, grid, hypercube, path, star, two_cliques_path
 from gpu_helpers import lib, log, torch_cuda
 
 pytestmark = pytest.mark.gpu
@@ -69,6 +69,24 @@ def test_msbfs_lane_widths_rmat12(inputs_mod, oracle_mod, lanes):
             want, _ = O.bfs(s, want_parent=False)
             np.testing.assert_array_equal(depth[i], want,
                                           err_msg=f"lanes {lanes} permille {permille} row {i}")
+
+
+def test_msbfs_hubs_and_long_searches(oracle_mod):
+    """Two 70-cliques joined by a 30-vertex path: clique vertices are hubs
+    (degree 69 > 64: whole-wave scans and the hub frontier cache) and
+    searches run past the ring of level masks; every vertex as a source."""
+    n, src, dst, _ = two_cliques_path(70, 30)
+    O = oracle_mod.Graph(src, dst, n)
+    g, ws = _setup(src, dst, n)
+    sources = np.arange(n, dtype=np.int32)
+    wants = [O.bfs(int(s), want_parent=False)[0] for s in sources.tolist()]
+    for lanes in (64, 0):
+        for permille in (0, 2, 1000):
+            depth = _run(g, ws, n, sources, _opts(block=1024, per_cu=1, permille=permille,
+                                                  lanes=lanes)).cpu().numpy()
+            for i in range(n):
+                np.testing.assert_array_equal(depth[i], wants[i],
+                                              err_msg=f"lanes {lanes} permille {permille} row {i}")
 
 
 def test_msbfs_closed_forms_and_duplicates(oracle_mod):
