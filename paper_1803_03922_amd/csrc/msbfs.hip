@@ -1018,13 +1018,22 @@ __global__ void k_lv_seed(MsLevel a, uint64_t mask, const int32_t *src) {
   }
 }
 
+// Also, when publish is set (once per level, after the level's kernels):
+// block 0 copies the level's control block to host_ctl (pinned host memory,
+// read by the host once the stream passes this kernel) and clears
+// next_ctl, the control block of the next level.
 // Writes the result rows of a set of lanes from ring levels [f.jlo, f.jhi]
 // (fewer than kRing): depth j - start[i] where lane i's bit is in level j's
 // mask and f.valid[j - jlo] admits lane i (levels before a lane's start or
 // already written are excluded), and, when `final`, -1 where the lane never
 // arrived. final: the set is f.lanes minus the lanes still alive after the
 // level just run (ctl[1]), i.e. the lanes that completed; else f.lanes.
-__global__ void k_lv_flush(MsLevel a, LaneFlush f) {
+__global__ void k_lv_flush(MsLevel a, LaneFlush f, unsigned long long *next_ctl,
+                           unsigned long long *host_ctl) {
+  if (host_ctl && blockIdx.x == 0 && threadIdx.x < 4) {
+    host_ctl[threadIdx.x] = a.ctl[threadIdx.x];
+    next_ctl[threadIdx.x] = 0;
+  }
   uint64_t set = f.lanes;
   if (f.final) set &= ~a.ctl[1];
   if (!set) return;
@@ -1252,7 +1261,8 @@ int ms_level(const Graph *g, Workspace *ws, uint64_t live, int64_t active, int32
   MsLevel a = level_args(g, ws, L, ctl);
   a.live = live;
   const int SG = device_cus() * 8;
-  HIPCHK(hipMemsetAsync(ctl, 0, 4 * sizeof(unsigned long long), s));
+  // ctl starts at zero: cleared by the previous level's publishing flush (or
+  // at set-up)
   const bool td = active <= int64_t(g->n) * bu_permille / 1000;
   if (td) {
     hipLaunchKernelGGL(k_lv_zero, dim3(grid_for(g->n, 256, SG)), dim3(256), 0, s, a.fnext, g->n);
@@ -1268,14 +1278,16 @@ int ms_level(const Graph *g, Workspace *ws, uint64_t live, int64_t active, int32
 }
 
 // Writes result rows from the level ring (k_lv_flush); ctl is the level's
-// control block (read for `final`).
+// control block (read for `final`). With host_ctl, also publishes ctl there
+// and clears next_ctl (see k_lv_flush).
 void ms_level_flush(const Graph *g, Workspace *ws, const LaneFlush &f, unsigned long long *ctl,
-                    hipStream_t s) {
+                    unsigned long long *next_ctl, unsigned long long *host_ctl, hipStream_t s) {
   if (f.jhi - f.jlo >= kRing || f.jhi < f.jlo)
     fail(DSBFS_ERR_DEVICE, "server level flush window outside the ring");
   MsLevel a = level_args(g, ws, f.jhi, ctl);
   const int SG = device_cus() * 8;
-  hipLaunchKernelGGL(k_lv_flush, dim3(grid_for(g->n, 256, SG)), dim3(256), 0, s, a, f);
+  hipLaunchKernelGGL(k_lv_flush, dim3(grid_for(g->n, 256, SG)), dim3(256), 0, s, a, f, next_ctl,
+                     host_ctl);
   HIPCHK(hipGetLastError());
 }
 

@@ -44,7 +44,7 @@ namespace dsbfs {
 int ms_level(const Graph *g, Workspace *ws, uint64_t live, int64_t active, int32_t bu_permille,
              int32_t L, unsigned long long *ctl, hipStream_t s);
 void ms_level_flush(const Graph *g, Workspace *ws, const LaneFlush &f, unsigned long long *ctl,
-                    hipStream_t s);
+                    unsigned long long *next_ctl, unsigned long long *host_ctl, hipStream_t s);
 int ms_level_ring();
 size_t ms_state_bytes(const Workspace *ws);
 void ms_level_prepare(const Graph *g, Workspace *ws, hipStream_t s);
@@ -109,6 +109,8 @@ struct Cohort {
   int64_t active = 0;
   int32_t L = 0;
   int32_t batch_start = 0;  // level at which the running batch began
+  // control blocks of the levels, alternating by level parity (4 words each),
+  // and the host copy of the last finished level's
   unsigned long long *ctl_dev = nullptr, *ctl_host = nullptr;
   int32_t *seed_dev = nullptr, *seed_host = nullptr;
   bool launched = false;
@@ -292,6 +294,8 @@ struct Server {
   // Enqueues one multi-source level of cohort c of G on its stream, then the
   // rows of the lanes it completes.
   void launch_level(GState *G, Cohort &c) {
+    unsigned long long *const ctl = c.ctl_dev + 4 * (c.L & 1);
+    unsigned long long *const next_ctl = c.ctl_dev + 4 * ((c.L + 1) & 1);
     HIPCHK(hipEventRecord(c.ev0, c.stream));
     // this level's next frontier overwrites ring level L + 1 - ring: lanes
     // whose rows still need it are written up to level L first
@@ -301,7 +305,7 @@ struct Server {
       if (c.from[i] <= c.L + 1 - ms_level_ring()) wrap |= 1ull << i;
     }
     if (wrap) {
-      ms_level_flush(G->g, c.ws, lane_flush(c, wrap, 0), c.ctl_dev, c.stream);
+      ms_level_flush(G->g, c.ws, lane_flush(c, wrap, 0), ctl, nullptr, nullptr, c.stream);
       for (uint64_t m = wrap; m; m &= m - 1) c.from[__builtin_ctzll(m)] = c.L + 1;
     }
     if (c.new_lanes) {
@@ -312,10 +316,10 @@ struct Server {
       c.active += __builtin_popcountll(c.new_lanes);
       c.new_lanes = 0;
     }
-    ms_level(G->g, c.ws, c.live, c.active, o.ms.bu_permille, c.L, c.ctl_dev, c.stream);
-    ms_level_flush(G->g, c.ws, lane_flush(c, c.used, 1), c.ctl_dev, c.stream);
-    HIPCHK(hipMemcpyAsync(c.ctl_host, c.ctl_dev, 4 * sizeof(unsigned long long),
-                          hipMemcpyDeviceToHost, c.stream));
+    ms_level(G->g, c.ws, c.live, c.active, o.ms.bu_permille, c.L, ctl, c.stream);
+    // rows of the lanes this level completes; publishes the level's counts to
+    // c.ctl_host and clears the next level's control block
+    ms_level_flush(G->g, c.ws, lane_flush(c, c.used, 1), ctl, next_ctl, c.ctl_host, c.stream);
     HIPCHK(hipEventRecord(c.ev, c.stream));
     c.launched = true;
   }
@@ -493,7 +497,8 @@ void cohort_init(Cohort &c, Graph *g, bool batched) {
   HIPCHK(hipEventCreate(&c.ev0));
   c.ws = workspace_create(g, 64);
   if (batched) ms_level_prepare(g, c.ws, c.stream);
-  HIPCHK(hipMalloc(reinterpret_cast<void **>(&c.ctl_dev), 4 * sizeof(unsigned long long)));
+  HIPCHK(hipMalloc(reinterpret_cast<void **>(&c.ctl_dev), 8 * sizeof(unsigned long long)));
+  HIPCHK(hipMemsetAsync(c.ctl_dev, 0, 8 * sizeof(unsigned long long), c.stream));
   HIPCHK(hipHostMalloc(reinterpret_cast<void **>(&c.ctl_host), 4 * sizeof(unsigned long long),
                        hipHostMallocDefault));
   HIPCHK(hipMalloc(reinterpret_cast<void **>(&c.seed_dev), 64 * sizeof(int32_t)));
