@@ -136,6 +136,11 @@ struct Workspace {
 };
 
 // Per-lane result rows of a level-at-a-time multi-source step (server).
+// Sources of the lanes admitted at one level (by value: no copy per level).
+struct SeedList {
+  int32_t src[64];
+};
+
 // Rows written by one flush of the server's level ring (see k_lv_flush).
 struct LaneFlush {
   int32_t *res[64];    // result row of each lane (int32[n]) or NULL if the lane is idle

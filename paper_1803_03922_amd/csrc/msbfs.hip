@@ -1007,12 +1007,12 @@ __global__ void k_lv_recycle(MsLevel a, uint64_t clear) {
   }
 }
 
-// Seeds lane i at source src[i] for every lane in `mask` (its depth 0 is
+// Seeds lane i at source src.src[i] for every lane in `mask` (its depth 0 is
 // written from the ring with the rest of its row).
-__global__ void k_lv_seed(MsLevel a, uint64_t mask, const int32_t *src) {
+__global__ void k_lv_seed(MsLevel a, uint64_t mask, SeedList src) {
   const int i = threadIdx.x;
   if (i < 64 && ((mask >> i) & 1ull)) {
-    const int32_t s = src[i];
+    const int32_t s = src.src[i];
     atomicOr(reinterpret_cast<unsigned long long *>(&a.seen[s]), 1ull << i);
     atomicOr(reinterpret_cast<unsigned long long *>(&a.fcur[s]), 1ull << i);
   }
@@ -1334,15 +1334,14 @@ void ms_level_prepare(const Graph *g, Workspace *ws, hipStream_t s) {
 }
 
 // Admission at level L: clears the lanes in `clear` and seeds the lanes in
-// seed_mask at seed_src_dev[i].
+// seed_mask at seeds.src[i].
 void ms_level_recycle(const Graph *g, Workspace *ws, int32_t L, uint64_t clear, uint64_t seed_mask,
-                      const int32_t *seed_src_dev, hipStream_t s) {
+                      const SeedList &seeds, hipStream_t s) {
   MsLevel a = level_args(g, ws, L, nullptr);
   const int SG = device_cus() * 8;
   if (clear)
     hipLaunchKernelGGL(k_lv_recycle, dim3(grid_for(g->n, 256, SG)), dim3(256), 0, s, a, clear);
-  if (seed_mask) hipLaunchKernelGGL(k_lv_seed, dim3(1), dim3(64), 0, s, a, seed_mask,
-                                    seed_src_dev);
+  if (seed_mask) hipLaunchKernelGGL(k_lv_seed, dim3(1), dim3(64), 0, s, a, seed_mask, seeds);
   HIPCHK(hipGetLastError());
 }
 

@@ -49,7 +49,7 @@ int ms_level_ring();
 size_t ms_state_bytes(const Workspace *ws);
 void ms_level_prepare(const Graph *g, Workspace *ws, hipStream_t s);
 void ms_level_recycle(const Graph *g, Workspace *ws, int32_t L, uint64_t clear, uint64_t seed_mask,
-                      const int32_t *seed_src_dev, hipStream_t s);
+                      const SeedList &seeds, hipStream_t s);
 Workspace *workspace_create(const Graph *g, int32_t max_lanes);
 void workspace_destroy(Workspace *ws);
 void graph_destroy(Graph *G);
@@ -112,7 +112,7 @@ struct Cohort {
   // control blocks of the levels, alternating by level parity (4 words each),
   // and the host copy of the last finished level's
   unsigned long long *ctl_dev = nullptr, *ctl_host = nullptr;
-  int32_t *seed_dev = nullptr, *seed_host = nullptr;
+  SeedList seeds{};  // sources of the lanes admitted for the next level
   bool launched = false;
 };
 // Cohorts per graph. With two, a query that misses the join window of the
@@ -261,7 +261,7 @@ struct Server {
           c.lane[i] = q;
           c.start_level[i] = c.L;
           c.from[i] = c.L;
-          c.seed_host[i] = q->source;
+          c.seeds.src[i] = q->source;
           c.new_lanes |= 1ull << i;
         }
         c.used |= c.new_lanes;  // the lanes admitted so far run in any case
@@ -309,9 +309,7 @@ struct Server {
       for (uint64_t m = wrap; m; m &= m - 1) c.from[__builtin_ctzll(m)] = c.L + 1;
     }
     if (c.new_lanes) {
-      HIPCHK(hipMemcpyAsync(c.seed_dev, c.seed_host, 64 * sizeof(int32_t),
-                            hipMemcpyHostToDevice, c.stream));
-      ms_level_recycle(G->g, c.ws, c.L, c.new_lanes, c.new_lanes, c.seed_dev, c.stream);
+      ms_level_recycle(G->g, c.ws, c.L, c.new_lanes, c.new_lanes, c.seeds, c.stream);
       c.live |= c.new_lanes;
       c.active += __builtin_popcountll(c.new_lanes);
       c.new_lanes = 0;
@@ -501,9 +499,6 @@ void cohort_init(Cohort &c, Graph *g, bool batched) {
   HIPCHK(hipMemsetAsync(c.ctl_dev, 0, 8 * sizeof(unsigned long long), c.stream));
   HIPCHK(hipHostMalloc(reinterpret_cast<void **>(&c.ctl_host), 4 * sizeof(unsigned long long),
                        hipHostMallocDefault));
-  HIPCHK(hipMalloc(reinterpret_cast<void **>(&c.seed_dev), 64 * sizeof(int32_t)));
-  HIPCHK(hipHostMalloc(reinterpret_cast<void **>(&c.seed_host), 64 * sizeof(int32_t),
-                       hipHostMallocDefault));
   HIPCHK(hipStreamSynchronize(c.stream));
 }
 
@@ -512,8 +507,6 @@ void cohort_free(Cohort &c) {
   if (c.ws) workspace_destroy(c.ws);
   if (c.ctl_dev) (void)hipFree(c.ctl_dev);
   if (c.ctl_host) (void)hipHostFree(c.ctl_host);
-  if (c.seed_dev) (void)hipFree(c.seed_dev);
-  if (c.seed_host) (void)hipHostFree(c.seed_host);
   if (c.ev) (void)hipEventDestroy(c.ev);
   if (c.ev0) (void)hipEventDestroy(c.ev0);
   if (c.stream) (void)hipStreamDestroy(c.stream);
