@@ -1075,17 +1075,14 @@ __global__ void k_lv_flush(MsLevel a, LaneFlush f, unsigned long long *next_ctl,
   }
 }
 
-__global__ void k_lv_zero(uint64_t *p, int32_t n) {
-  for (int64_t v = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; v < n;
-       v += int64_t(gridDim.x) * blockDim.x)
-    p[v] = 0;
-}
-
+// Lists the frontier vertices of a top-down level and clears next (the
+// scatter ORs into it; a later kernel, so the clear is complete by then).
 __global__ void k_lv_td_list(MsLevel a) {
   for (int64_t v0 = int64_t(blockIdx.x) * blockDim.x; v0 < a.n;
        v0 += int64_t(gridDim.x) * blockDim.x) {
     const int64_t v = v0 + threadIdx.x;
     const bool f = v < a.n && a.fcur[v] != 0;
+    if (v < a.n) a.fnext[v] = 0;
     const int64_t pos = wave_append(f, &a.ctl[2]);
     if (f) a.tdlist[pos] = int32_t(v);
   }
@@ -1265,7 +1262,6 @@ int ms_level(const Graph *g, Workspace *ws, uint64_t live, int64_t active, int32
   // at set-up)
   const bool td = active <= int64_t(g->n) * bu_permille / 1000;
   if (td) {
-    hipLaunchKernelGGL(k_lv_zero, dim3(grid_for(g->n, 256, SG)), dim3(256), 0, s, a.fnext, g->n);
     hipLaunchKernelGGL(k_lv_td_list, dim3(grid_for(g->n, 256, SG)), dim3(256), 0, s, a);
     hipLaunchKernelGGL(k_lv_td_scan, dim3(1), dim3(1024), 0, s, a);
     hipLaunchKernelGGL(k_lv_td_expand, dim3(SG), dim3(256), 0, s, a);
