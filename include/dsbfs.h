@@ -135,6 +135,9 @@ typedef struct dsbfs_level_stats {
   int32_t reserved;
   int64_t FV_nn, q_nn;               /* nn is always forward */
   int64_t frontier_normal, frontier_delegate;
+  double kernel_ms[9];  /* profile = 1 only: HIP-event time of each kernel of
+                           this level (indexed DSBFS_K_*), 0 when it had no
+                           work; all 0 without profiling */
 } dsbfs_level_stats;
 
 /* Kernels of a search, for per-kernel profiles. */

@@ -564,9 +564,13 @@ __global__ void __launch_bounds__(kBS) k_bu_normal(const DevCtl *c, int32_t *c0,
       const int32_t e = e0 + l;
       if (e < T) {
         const int lo = owner64(s_excl[w], e);
-        const int32_t x = nds_col[s_beg[w][lo] + (e - s_excl[w][lo])];
-        ++edges;
-        if (bit_test(Fd, uint32_t(x))) atomicMin(&s_found[w][lo], e);
+        // a row whose parent an earlier step found is not read further: a
+        // scan stops at its first frontier neighbour (Section IV-B)
+        if (s_found[w][lo] == kNone) {
+          const int32_t x = nds_col[s_beg[w][lo] + (e - s_excl[w][lo])];
+          ++edges;
+          if (bit_test(Fd, uint32_t(x))) atomicMin(&s_found[w][lo], e);
+        }
       }
       wave_sync();
       remaining = __ballot(len > 0 && s_found[w][l] == kNone);
@@ -1062,7 +1066,8 @@ struct Prof {
   hipStream_t s = nullptr;
   Workspace *ws = nullptr;
   size_t next = 0;
-  struct Span { int k, b, e; };
+  struct Span { int k, b, e, level; };
+  int level = -1;  // level whose kernels are being launched (-1: init)
   std::vector<Span> spans;
   int64_t launches[DSBFS_NUM_KERNELS] = {};
   double units[DSBFS_NUM_KERNELS][6] = {};
@@ -1086,7 +1091,7 @@ struct Prof {
     if (!on) return;
     const int i = int(next);
     HIPCHK(hipEventRecord(ev(), s));
-    spans.push_back({k, b, i});
+    spans.push_back({k, b, i, level});
   }
   void add_level(const LevelCtr &c) {
     for (int k = 0; k < DSBFS_NUM_KERNELS; ++k)
@@ -1372,6 +1377,7 @@ void bfs_run(const Graph *g, Workspace *ws, int32_t source, const dsbfs_run_opts
       // synchronization per level, so that only kernels with work are counted
       for (int32_t L = 0;; ++L) {
         const size_t sp0 = P.spans.size();
+        P.level = L;
         ll.enqueue(L & 1, s, &P);
         HIPCHK(hipStreamSynchronize(s));
         const LevelStatus st = hs[L & (kStatusSlots - 1)];
@@ -1437,8 +1443,10 @@ void bfs_run(const Graph *g, Workspace *ws, int32_t source, const dsbfs_run_opts
   if (stats) {
     HIPCHK(hipStreamSynchronize(s));
     stats->num_levels = int32_t(rec.size());
-    for (int32_t i = 0; i < stats->num_levels && i < stats->capacity && stats->levels; ++i)
+    for (int32_t i = 0; i < stats->num_levels && i < stats->capacity && stats->levels; ++i) {
       stats->levels[i] = rec[i];
+      for (double &t : stats->levels[i].kernel_ms) t = 0.0;  // filled from the spans below
+    }
     // Every reached vertex sits in exactly one level's frontier, whose previsit
     // (or plain expansion) summed its full degree; each vertex but the source
     // was claimed exactly once. So the component's size and edge count come
@@ -1487,6 +1495,9 @@ void bfs_run(const Graph *g, Workspace *ws, int32_t source, const dsbfs_run_opts
       float t = 0.f;
       HIPCHK(hipEventElapsedTime(&t, ws->events[sp.b], ws->events[sp.e]));
       ms[sp.k] += double(t);
+      if (sp.level >= 0 && sp.level < stats->num_levels && sp.level < stats->capacity &&
+          stats->levels)
+        stats->levels[sp.level].kernel_ms[sp.k] += double(t);
     }
     for (int k = 0; k < DSBFS_NUM_KERNELS; ++k) {
       stats->kernels[k].ms = ms[k];

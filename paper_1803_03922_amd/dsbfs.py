@@ -67,7 +67,7 @@ class dsbfs_level_stats(ctypes.Structure):
     _fields_ = [("q", i64 * 3), ("s", i64 * 3), ("U", i64 * 3), ("FV", i64 * 3),
                 ("BV", ctypes.c_double * 3), ("dir", i32 * 3), ("reserved", i32),
                 ("FV_nn", i64), ("q_nn", i64), ("frontier_normal", i64),
-                ("frontier_delegate", i64)]
+                ("frontier_delegate", i64), ("kernel_ms", ctypes.c_double * 9)]
 
     def as_dict(self):
         return {"q": list(self.q), "s": list(self.s), "U": list(self.U), "FV": list(self.FV),
@@ -159,6 +159,43 @@ def check(st: int, where: str):
 
 
 # ---------------------------------------------------------------------------
+# Teardown order: every live library object (servers, workspaces, graphs) is
+# destroyed explicitly before the interpreter shuts down, while the HIP
+# runtime and PyTorch's allocator (which the library frees into) still work.
+# Finalizers that run during interpreter shutdown call nothing in the library.
+# ---------------------------------------------------------------------------
+import atexit  # noqa: E402
+import sys  # noqa: E402
+import weakref  # noqa: E402
+
+_live = weakref.WeakValueDictionary()   # creation number -> object
+_serial = [0]
+
+
+def _track(obj):
+    _serial[0] += 1
+    _live[_serial[0]] = obj
+
+
+def shutdown():
+    """Destroys every live server, workspace and graph, newest first (servers
+    own their graphs, and a workspace is destroyed before its graph). Called
+    at interpreter exit, before PyTorch and the HIP runtime are torn down; a
+    program may call it earlier itself."""
+    objs = [o for _, o in sorted(_live.items(), reverse=True)]
+    for kind in (Server, Workspace, Graph):
+        for o in objs:
+            if isinstance(o, kind):
+                try:
+                    o.destroy()
+                except Exception:
+                    pass
+
+
+atexit.register(shutdown)
+
+
+# ---------------------------------------------------------------------------
 # torch plumbing: device memory and streams
 # ---------------------------------------------------------------------------
 def _torch():
@@ -211,7 +248,10 @@ def _dev_ptr(t) -> int:
     return 0 if t is None else int(t.data_ptr())
 
 
-DEFAULT_FACTOR0 = (0.5, 0.05, 1e-7)
+# The paper's direction-switch factors for (dd, dn, nd) (Section VI-B), the
+# header's DSBFS_PAPER_FACTOR0_* constants. The library's defaults differ:
+# run_opts() without factor0 takes them from dsbfs_run_opts_default.
+PAPER_FACTOR0 = (0.5, 0.05, 1e-7)
 
 
 def run_opts(mode: int = 1, want_parent: bool = True, factor0=None, factor1=None,
@@ -257,6 +297,7 @@ class Graph:
         st = dsbfs_graph_stats()
         check(dsbfs_graph_stats_get(self.h, ctypes.byref(st)), "dsbfs_graph_stats_get")
         self.stats = st.as_dict()
+        _track(self)
 
     def export(self, which: int, dtype) -> np.ndarray:
         nbytes = ctypes.c_int64(0)
@@ -276,7 +317,9 @@ class Graph:
         """Forget the handle (after moving it to a server)."""
         self.h = None
 
-    def __del__(self):
+    def __del__(self, _finalizing=sys.is_finalizing):
+        if _finalizing():
+            return
         try:
             self.destroy()
         except Exception:
@@ -289,13 +332,16 @@ class Workspace:
         check(dsbfs_workspace_create(graph.h, max_lanes, ctypes.byref(h)), "dsbfs_workspace_create")
         self.h = h
         self.graph = graph
+        _track(self)
 
     def destroy(self):
         if self.h:
             check(dsbfs_workspace_destroy(self.h), "dsbfs_workspace_destroy")
             self.h = None
 
-    def __del__(self):
+    def __del__(self, _finalizing=sys.is_finalizing):
+        if _finalizing():
+            return
         try:
             self.destroy()
         except Exception:
@@ -325,6 +371,9 @@ def bfs(graph: Graph, ws: Workspace, source: int, depth, parent=None, opts=None,
             for i, name in enumerate(KERNEL_NAMES)}
     return {"num_levels": nl, "reached": int(st.reached), "edges_cc": int(st.edges_cc),
             "levels": [levels[i].as_dict() for i in range(min(nl, capacity))],
+            "level_kernel_ms": [{name: float(levels[i].kernel_ms[j])
+                                 for j, name in enumerate(KERNEL_NAMES)}
+                                for i in range(min(nl, capacity))],
             "kernels": kern}
 
 
@@ -384,6 +433,7 @@ class Server:
         check(dsbfs_server_create(ctypes.byref(o), None, ctypes.byref(h)), "dsbfs_server_create")
         self.h = h
         self.n_of = {}
+        _track(self)
 
     def add_graph(self, graph: Graph) -> int:
         gid = ctypes.c_int32(0)
@@ -414,7 +464,9 @@ class Server:
             check(dsbfs_server_destroy(self.h), "dsbfs_server_destroy")
             self.h = None
 
-    def __del__(self):
+    def __del__(self, _finalizing=sys.is_finalizing):
+        if _finalizing():
+            return
         try:
             self.destroy()
         except Exception:

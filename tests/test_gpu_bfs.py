@@ -129,47 +129,106 @@ def test_plain_rmat16_64_sources(inputs_mod, oracle_mod):
     G.close()
 
 
-def test_do_rmat22_64_sources(inputs_mod, oracle_mod):
-    """Degree-separated DOBFS, TH = 32, RMAT scale 22, seeded sources."""
+def _oracle_row_report(inputs_mod, oracle_mod, scale, bad, rows):
+    """Message for digest mismatches: recomputes the oracle row of each bad
+    source (at most 3) and names the first differing vertex."""
+    from digests import first_difference
+    n = 1 << scale
+    src, dst = inputs_mod.rmat_edges(scale)
+    O = oracle_mod.Graph(src, dst, n)
+    msgs = []
+    for key, got, want in bad[:3]:
+        s = key[-1] if isinstance(key, tuple) else key
+        ref, _ = O.bfs(int(s), want_parent=False)
+        msgs.append(f"{key}: {first_difference(rows[key], ref)}")
+    return f"{len(bad)} rows differ from the oracle: " + "; ".join(msgs)
+
+
+def test_do_rmat22_all_64_sources(inputs_mod, oracle_mod):
+    """Degree-separated DOBFS, TH = 32, RMAT scale 22, all 64 seeded sources:
+    every depth row bit-exact against the oracle's digest, every parent array
+    through the oracle's invariant checker, and the component's size and edge
+    count per source."""
+    import concurrent.futures as cf
+    from digests import RowChecker, load, sources_of, threads
+    want = load("rmat22")
+    sources = sources_of("rmat22")
     n, src, dst, O = _rmat(inputs_mod, oracle_mod, 22)
+    assert sources == inputs_mod.pick_sources(src, dst, n, 64, seed=1002).tolist()
     log("scale 22 oracle graph built")
     G = GpuGraph(src, dst, n, threshold=32)
     st = O.split_stats(32)
     for k in ("d", "e_nn", "e_nd", "e_dn", "e_dd", "n_ndsrc", "n_ddsrc", "n_dnsrc"):
         assert G.stats[k] == st[k], k
     assert G.stats["m_dir"] == O.m
-    sources = inputs_mod.pick_sources(src, dst, n, 64, seed=1002)
-    for i, s in enumerate(sources.tolist()[:16]):
-        want, _ = O.bfs(s, want_parent=False)
-        depth, parent, _ = G.bfs(s, mode=1)
-        log(f"scale 22 source {i} s={s}")
-        np.testing.assert_array_equal(depth, want)
-        assert O.check(s, depth, parent, None)[0] == 0
+    chk = RowChecker(want)
+    pool = cf.ThreadPoolExecutor(max_workers=threads())
+    checks, rows = [], {}
+    for i, s in enumerate(sources):
+        depth, parent, rs = G.bfs(s, mode=1, want_stats=True)
+        assert rs["reached"] == want[s]["reached"] and rs["edges_cc"] == want[s]["edges_cc"], s
+        assert rs["num_levels"] == want[s]["max_depth"] + 1, s
+        rows[s] = depth
+        chk.submit(s, depth)
+        checks.append((s, pool.submit(O.check, s, depth, parent, None)))
+        if i % 16 == 15:
+            log(f"scale 22: {i + 1} of 64 sources searched")
+    bad = chk.mismatches()
+    assert not bad, _oracle_row_report(inputs_mod, oracle_mod, 22, bad, rows)
+    for s, f in checks:
+        assert f.result()[0] == 0, f"parent invariants fail from source {s}: {f.result()}"
+    pool.shutdown()
+    log(f"scale 22: {chk.checked} rows equal the oracle's")
     G.close()
 
 
-def test_do_rmat26_sampled_source(inputs_mod, oracle_mod):
-    """RMAT scale 26 (2.1e9 directed edges, within 2% of 2^31), TH 32,
-    parents, as the bench runs it (captured level graphs): the first of its
-    seeded sources against the oracle, depths bit-exact, parents by the
-    invariants, and the component's size and edge count."""
-    n, src, dst, O = _rmat(inputs_mod, oracle_mod, 26)
+def test_do_rmat26_64_sources_each_threshold(inputs_mod, oracle_mod):
+    """RMAT scale 26 (2.1e9 directed edges, within 2% of 2^31), the bench's
+    configuration (captured level graphs, parents on): at TH 16, 32, 64 and
+    128, all 64 seeded sources, every depth row bit-exact against the oracle's
+    digest and the component size and edge count per source; at TH 32 every
+    parent array also passes the oracle's invariant checker."""
+    import concurrent.futures as cf
+    from digests import RowChecker, load, sources_of, threads
+    want = load("rmat26")
+    sources = sources_of("rmat26")
+    scale = 26
+    n = 1 << scale
+    src, dst = inputs_mod.rmat_edges(scale)
+    assert sources == inputs_mod.pick_sources(src, dst, n, 64, seed=1003).tolist()
+    O = oracle_mod.Graph(src, dst, n)
     log("scale 26 oracle graph built")
-    G = GpuGraph(src, dst, n, threshold=32, keep_plain=False)
-    sources = inputs_mod.pick_sources(src, dst, n, 64, seed=1003)
-    del src, dst
-    assert G.stats["m_dir"] == O.m and O.m > 2 * 10 ** 9
-    deg = O.degrees()
-    for s in sources.tolist()[:1]:
-        want, _ = O.bfs(s, want_parent=False)
-        depth, parent, st = G.bfs(s, want_stats=True)
-        log(f"scale 26 s={s} levels={st['num_levels']}")
-        np.testing.assert_array_equal(depth, want)
-        assert O.check(s, depth, parent, None)[0] == 0
-        reached = want >= 0
-        assert st["reached"] == int(reached.sum())
-        assert st["edges_cc"] == int(deg[reached].sum() // 2)
-    G.close()
+    for TH in (32, 16, 64, 128):
+        G = GpuGraph(src, dst, n, threshold=TH, keep_plain=False)
+        assert G.stats["m_dir"] == O.m and O.m > 2 * 10 ** 9
+        chk = RowChecker(want, pending=8)
+        pool = cf.ThreadPoolExecutor(max_workers=threads()) if TH == 32 else None
+        checks, rows = [], {}
+        for i, s in enumerate(sources):
+            depth, parent, rs = G.bfs(s, want_stats=True, want_parent=TH == 32)
+            assert rs["reached"] == want[s]["reached"], (TH, s)
+            assert rs["edges_cc"] == want[s]["edges_cc"], (TH, s)
+            chk.submit(s, depth)
+            if pool is not None:
+                checks.append((s, pool.submit(O.check, s, depth, parent, None)))
+                if len(checks) >= 16:   # bound the rows held for checking
+                    s0, f0 = checks.pop(0)
+                    assert f0.result()[0] == 0, f"parent invariants fail from {s0}: {f0.result()}"
+            if i % 16 == 15:
+                log(f"scale 26 TH {TH}: {i + 1} of 64 sources searched")
+        bad = chk.mismatches()
+        if bad:
+            rows = {k: G.bfs(k, want_parent=False)[0] for k, _, _ in bad[:3]}
+            G.close()
+            del src, dst
+            raise AssertionError(f"TH {TH}: " +
+                                 _oracle_row_report(inputs_mod, oracle_mod, 26, bad, rows))
+        for s, f in checks:
+            assert f.result()[0] == 0, f"parent invariants fail from source {s}: {f.result()}"
+        if pool is not None:
+            pool.shutdown()
+        log(f"scale 26 TH {TH}: {chk.checked} rows equal the oracle's")
+        G.close()
 
 
 def test_schedule_and_threshold_invariance(inputs_mod, oracle_mod):

@@ -1,8 +1,8 @@
 """GPU parity of bit-parallel multi-source BFS: every lane's depths equal the
 oracle's single-source depths, for partial batches, duplicate sources, forced
 top-down-only / bottom-up-only schedules, captured-graph and cooperative
-launches, and at full size (RMAT scale 24, 1024 sources) on sampled rows plus
-component-size checks on every row."""
+launches, and at full size (RMAT scale 24, 1024 sources: every row against
+the oracle's digest)."""
 import os
 import tempfile
 
@@ -129,40 +129,47 @@ def test_msbfs_launch_shapes(inputs_mod, oracle_mod):
             np.testing.assert_array_equal(got[i], wants[i], err_msg=f"replay {rep} lane {i}")
 
 
-def test_msbfs_rmat24_1024_sources(inputs_mod, oracle_mod):
-    """RMAT scale 24, 1024 sources = 4 batches of 256 lanes in one launch, with
-    the tuner's launch configuration as the benchmark uses it; 16 sampled rows
-    against the oracle, and on every row: depth 0 at its source only, and the
-    reached count equals the size of the source's component."""
+@pytest.mark.parametrize("shape", ["64x16", "tuned"])
+def test_msbfs_rmat24_1024_sources_all_rows(inputs_mod, oracle_mod, shape):
+    """RMAT scale 24, 1024 seeded sources in one persistent launch, every one
+    of the 1024 depth rows bit-exact against the oracle's digest: as 16
+    batches of 64 lanes (one 64-bit lane mask per vertex), and with the
+    tuner's launch configuration as the benchmark uses it."""
+    from digests import RowChecker, first_difference, load, sources_of
     torch = torch_cuda()
+    want = load("rmat24")
+    sources = np.array(sources_of("rmat24"), dtype=np.int32)
+    assert len(sources) == 1024
     scale = 24
     n = 1 << scale
     src, dst = inputs_mod.rmat_edges(scale)
-    O = oracle_mod.Graph(src, dst, n)
-    log("scale 24 oracle built")
-    label = O.components()
-    comp_size = np.bincount(label, minlength=n)
+    assert sources.tolist() == inputs_mod.pick_sources(src, dst, n, 1024, seed=1004).tolist()
     g, ws = _setup(src, dst, n)
-    sources = inputs_mod.pick_sources(src, dst, n, 1024, seed=1004)
-    assert len(sources) == 1024
-    # the launch configuration the benchmark times: the tuner's choice
-    opts = lib().msbfs_tune(g, ws, sources)
-    log(f"tuned {opts.as_dict()}")
+    if shape == "64x16":
+        opts = _opts(block=1024, per_cu=1, permille=1, graph=1, lanes=64)
+    else:
+        opts = lib().msbfs_tune(g, ws, sources)
+    log(f"scale 24 multi-source BFS, {shape}: {opts.as_dict()}")
     depth = _run(g, ws, n, sources, opts)
     log("scale 24 multi-source BFS done")
-    reached = (depth >= 0).sum(dim=1).cpu().numpy()
-    np.testing.assert_array_equal(reached, comp_size[label[sources]])
-    zeros = (depth == 0).sum(dim=1).cpu().numpy()
-    assert (zeros == 1).all()
-    at_src = depth[torch.arange(1024, device="cuda"),
-                   torch.as_tensor(sources, device="cuda").long()].cpu().numpy()
-    assert (at_src == 0).all()
-    assert int((depth < -1).sum().item()) == 0
-    rng = np.random.default_rng(1)
-    for i in sorted(rng.choice(1024, size=16, replace=False).tolist()):
-        want, _ = O.bfs(int(sources[i]), want_parent=False)
-        np.testing.assert_array_equal(depth[i].cpu().numpy(), want, err_msg=f"row {i}")
-        log(f"row {i} ok")
+    chk = RowChecker({i: want[int(s)] for i, s in enumerate(sources.tolist())}, pending=64)
+    for c0 in range(0, 1024, 64):
+        block = depth[c0:c0 + 64].cpu().numpy()
+        for i in range(block.shape[0]):
+            chk.submit(c0 + i, block[i])
+        log(f"rows {c0}..{c0 + 63} copied")
+    bad = chk.mismatches()
+    if bad:
+        O = oracle_mod.Graph(src, dst, n)
+        msgs = []
+        for i, _, _ in bad[:3]:
+            ref, _ = O.bfs(int(sources[i]), want_parent=False)
+            msgs.append(f"row {i} (source {int(sources[i])}): "
+                        f"{first_difference(depth[i].cpu().numpy(), ref)}")
+        raise AssertionError(f"{len(bad)} of 1024 rows differ: " + "; ".join(msgs))
+    assert chk.checked == 1024
+    del depth
+    torch.cuda.empty_cache()
 
 
 def test_msbfs_tuner_cache(inputs_mod, oracle_mod):

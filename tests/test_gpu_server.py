@@ -232,3 +232,69 @@ def test_server_errors(inputs_mod, oracle_mod):
         d.Server(1 << 30, max_lanes=65)
     assert e.value.status == d.ERR_INVALID_ARG
     S.destroy()
+
+
+@pytest.mark.parametrize("batched", [1, 2])
+def test_server_real_mix_rows_match_digests(inputs_mod, batched):
+    """The served mix at its real sizes: RMAT scales 18, 20, 22, 24 and an
+    Erdos-Renyi graph with 2^22 vertices and 8n pairs, TH 32, all resident.
+    The 320 digest queries (64 sources per graph) arrive shuffled as a
+    Poisson stream at 1500 queries/s; every returned row must equal the
+    oracle's depth row (SHA-256 digest), for continuous batching (1) and the
+    adaptive mode (2)."""
+    import threading
+    from digests import load, row_digest
+    d = lib()
+    torch_cuda()
+    want = load("served")
+    specs = [("rmat", 18), ("rmat", 20), ("rmat", 22), ("rmat", 24), ("er", 22)]
+    S = d.Server(BIG, max_lanes=64, batched=batched)
+    gids, ns = [], []
+    for kind, sc in specs:
+        n = 1 << sc
+        if kind == "rmat":
+            src, dst = inputs_mod.rmat_edges(sc)
+        else:
+            src, dst = inputs_mod.er_edges(n, 8 * n, seed=0x22)
+        gi = len(gids)
+        picked = inputs_mod.pick_sources(src, dst, n, 64, seed=6000 + gi).tolist()
+        assert sorted(picked) == sorted(s for g, s in want if g == gi)
+        gids.append(S.add_graph(d.Graph(src, dst, n, threshold=32, keep_plain_csr=True)))
+        ns.append(n)
+        log(f"served graph {gi} ({kind} {sc}) resident")
+    keys = sorted(want)
+    rng = np.random.default_rng(5100 + batched)
+    order = rng.permutation(len(keys))
+    gaps = rng.exponential(1.0 / 1500.0, size=len(keys))
+    tickets = [None] * len(keys)
+    ready = threading.Semaphore(0)
+    bad, done = [], []
+
+    def collect():
+        for j in range(len(keys)):
+            ready.acquire()
+            gi, s = keys[order[j]]
+            ptr, st = S.wait(tickets[j])
+            row = d.device_row(ptr, ns[gi]).cpu().numpy()
+            S.release(tickets[j])
+            if row_digest(row) != want[(gi, s)]["sha256"]:
+                bad.append((gi, s))
+            done.append(st["batched"])
+
+    th = threading.Thread(target=collect)
+    th.start()
+    at = d.now_ns() + 1_000_000
+    for j in range(len(keys)):
+        at += int(gaps[j] * 1e9)
+        while d.now_ns() < at:
+            time.sleep(50e-6)
+        gi, s = keys[order[j]]
+        tickets[j] = S.submit(gids[gi], s, at)
+        ready.release()
+    th.join()
+    S.destroy()
+    log(f"served {len(done)} queries, {sum(done)} as lanes, {len(bad)} rows differ")
+    assert len(done) == len(keys)
+    assert not bad, f"served rows differ from the oracle for (graph, source) {bad[:5]}"
+    if batched == 1:
+        assert sum(done) == len(keys)

@@ -301,13 +301,132 @@ def test_do_replay_two_hubs_strict_comparison(oracle_mod):
     assert L2[1]["dir"][1] == (0 if L2[1]["q"][1] > 0 else 1)
 
 
+def _table1_total(p, n, d, e_nn, e_nd, e_dn, e_dd):
+    """Sum of Table I's per-subgraph rows over p GPUs: offsets n/p*4 (nn),
+    n/p*4 (nd), d*4 (dn), d*4 (dd); columns |E_nn|/p*8, |E_nd|/p*4,
+    |E_dn|/p*4, |E_dd|/p*4."""
+    per_gpu = (n / p * 4 + e_nn / p * 8) + (n / p * 4 + e_nd / p * 4) \
+        + (d * 4 + e_dn / p * 4) + (d * 4 + e_dd / p * 4)
+    return per_gpu * p
+
+
 def test_table1_totals():
-    """Table I: per-subgraph rows summed over p GPUs give 8n + 8dp + 4m + 4|E_nn|."""
+    """Table I's rows, summed over p GPUs, give 8n + 8dp + 4m + 4|E_nn| (the
+    paper's total) on the fixture's symbolic rows."""
     with open(os.path.join(GOLD, "table1_memory.txt")) as f:
         rows = [list(map(int, l.split())) for l in f if l.strip() and not l.startswith("#")]
     for p, n, d, e_nn, e_nd, e_dn, e_dd, want in rows:
-        per_gpu = (n / p * 4 + e_nn / p * 8) + (n / p * 4 + e_nd / p * 4) \
-            + (d * 4 + e_dn / p * 4) + (d * 4 + e_dd / p * 4)
-        assert per_gpu * p == want
+        assert _table1_total(p, n, d, e_nn, e_nd, e_dn, e_dd) == want
         m = e_nn + e_nd + e_dn + e_dd
         assert 8 * n + 8 * d * p + 4 * m + 4 * e_nn == want
+
+
+def test_table1_memory_of_split_graphs(oracle_mod):
+    """Table I at p = 1 applied to the oracle's split of small graphs whose
+    four edge classes are counted by hand (fixture table1_graphs.txt)."""
+    k = 12
+    graphs = {}
+    n, s, t, _ = star(k)
+    graphs["star12"] = (n, s, t)
+    pairs = [(0, 1)] + [(0, 2 + i) for i in range(10)] + [(1, 12 + i) for i in range(10)]
+    graphs["two_hubs10"] = (22, np.array([a for a, _ in pairs], np.int32),
+                            np.array([b for _, b in pairs], np.int32))
+    n, s, t, _ = complete(4)
+    graphs["k4"] = (n, s, t)
+    n, s, t, _ = path(5)
+    graphs["path5"] = (n, s, t)
+    with open(os.path.join(GOLD, "table1_graphs.txt")) as f:
+        rows = [l.split() for l in f if l.strip() and not l.startswith("#")]
+    assert len(rows) == 4
+    for name, TH, d, e_nn, e_nd, e_dn, e_dd, want in rows:
+        n, s, t = graphs[name]
+        st = _graph(oracle_mod, n, s, t).split_stats(int(TH))
+        got = (st["d"], st["e_nn"], st["e_nd"], st["e_dn"], st["e_dd"])
+        assert got == tuple(int(x) for x in (d, e_nn, e_nd, e_dn, e_dd)), name
+        assert _table1_total(1, n, st["d"], st["e_nn"], st["e_nd"], st["e_dn"],
+                             st["e_dd"]) == int(want), name
+
+
+def _expected_checks_brute(a, od):
+    """Expected number of potential parents a bottom-up scan checks, stopping
+    at the first one in the frontier, when each of od potential parents is in
+    the frontier independently with probability a: enumerates every frontier
+    subset (no closed form)."""
+    total = 0.0
+    for mask in range(1 << od):
+        pr = 1.0
+        for i in range(od):
+            pr *= a if (mask >> i) & 1 else (1 - a)
+        checks = od
+        for i in range(od):
+            if (mask >> i) & 1:
+                checks = i + 1
+                break
+        total += pr * checks
+    return total
+
+
+def test_do_replay_exact_bv_star_brute_force(oracle_mod):
+    """Exact BV (Section IV-B's expected checks summed over U) on the star of
+    test_do_replay_star_hand_derived: level 0, nd kernel, U = {hub}, whose
+    reversed-subgraph degree is k (its dn edges) and a = q/(q+s) = 1/k; level
+    1, dn kernel, U = the k-1 unvisited leaves, each with one delegate
+    neighbour, a = 1/(1+0) = 1. Each term is checked against the brute-force
+    expectation over frontier subsets."""
+    k = 12
+    n, src, dst, _ = star(k)
+    G = _graph(oracle_mod, n, src, dst)
+    f0, f1 = _factors()
+    depth, _ = G.bfs(1)
+    L = G.do_replay(2, depth, f0, f1, bv_exact=True)
+    assert len(L) == 3
+    assert L[0]["BV"][2] == pytest.approx(_expected_checks_brute(1.0 / k, k), rel=1e-12)
+    assert L[0]["BV"][0] == 0.0 and L[0]["BV"][1] == 0.0      # q = 0: not evaluated
+    assert L[1]["BV"][1] == pytest.approx((k - 1) * _expected_checks_brute(1.0, 1), rel=1e-12)
+    assert L[2]["BV"] == [0.0, 0.0, 0.0]                     # U empty
+    assert [x["dir"] for x in L] == [[0, 0, 1], [0, 1, 1], [0, 1, 1]]
+
+
+def test_do_replay_exact_bv_changes_the_decision(oracle_mod):
+    """Two hubs A=0, B=1 joined, each with k leaves, TH=2, source A. With the
+    exact sum, level 0's dd term is U = {B} with one dd edge and a = 1/2: one
+    check, BV_dd = 1, so FV_dd = 1 > 0.5*1 and dd goes backward, where the
+    paper's approximation (BV_dd = 2) keeps it forward. dn: U = the 2k
+    leaves, one delegate each: BV_dn = 2k (approximation 4k)."""
+    k = 10
+    pairs = [(0, 1)] + [(0, 2 + i) for i in range(k)] + [(1, 2 + k + i) for i in range(k)]
+    src = np.array([a for a, _ in pairs], np.int32)
+    dst = np.array([b for _, b in pairs], np.int32)
+    G = _graph(oracle_mod, 2 + 2 * k, src, dst)
+    f0, f1 = _factors()
+    depth, _ = G.bfs(0)
+    ex = G.do_replay(2, depth, f0, f1, bv_exact=True)
+    ap = G.do_replay(2, depth, f0, f1, bv_exact=False)
+    assert ex[0]["BV"][0] == pytest.approx(_expected_checks_brute(0.5, 1))
+    assert ex[0]["BV"][1] == pytest.approx(2 * k * _expected_checks_brute(0.5, 1))
+    assert ap[0]["BV"][:2] == [pytest.approx(2.0), pytest.approx(4.0 * k)]
+    assert ex[0]["dir"][0] == 1 and ap[0]["dir"][0] == 0
+    # level 1: nd frontier = A's k leaves, a = k/(k+k); U = unvisited delegates
+    # with dn edges = {} (B is visited) -> 0
+    assert ex[1]["q"][2] == k and ex[1]["s"][2] == k and ex[1]["BV"][2] == 0.0
+
+
+def test_do_replay_exact_bv_two_delegate_neighbours(oracle_mod):
+    """Hubs 0, 1, 2 (degree > TH = 2); normals 3..8 adjacent to hubs 0 and 1,
+    normals 9..11 to hub 2, and the dd edge 0-2; source hub 0. Level 0, dn:
+    q = 1, s = |{1, 2}| = 2 (delegates with dn edges, unvisited), a = 1/3;
+    U = normals 3..11: six with two delegate neighbours, three with one.
+    BV_dn = 6 E(1/3, 2) + 3 E(1/3, 1). dd: q = 1, s = |{2}| = 1, a = 1/2,
+    U = {2} with one dd edge: BV_dd = E(1/2, 1)."""
+    pairs = [(h, v) for v in range(3, 9) for h in (0, 1)] + [(2, v) for v in (9, 10, 11)]
+    pairs += [(0, 2)]
+    src = np.array([a for a, _ in pairs], np.int32)
+    dst = np.array([b for _, b in pairs], np.int32)
+    G = _graph(oracle_mod, 12, src, dst)
+    assert G.split_stats(2)["d"] == 3
+    depth, _ = G.bfs(0)
+    L = G.do_replay(2, depth, (10.0, 10.0, 10.0), (0.0, 0.0, 0.0), bv_exact=True)
+    want_dn = 6 * _expected_checks_brute(1 / 3, 2) + 3 * _expected_checks_brute(1 / 3, 1)
+    assert L[0]["q"][:2] == [1, 1] and L[0]["s"][:2] == [1, 2]
+    assert L[0]["BV"][1] == pytest.approx(want_dn, rel=1e-12)
+    assert L[0]["BV"][0] == pytest.approx(_expected_checks_brute(0.5, 1), rel=1e-12)
