@@ -12,6 +12,13 @@ import os
 
 import numpy as np
 
+# PyTorch first: its HIP runtime (libamdhip64.so.7, bundled with torch) is
+# then already in the process when libdsbfs.so is loaded, and the library's
+# dependency on that soname binds to it. Loaded the other way round, the
+# process would hold two HIP runtimes, and device memory and streams from
+# torch would not be valid in the library's.
+import torch  # noqa: F401,E402
+
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libdsbfs.so")
 
