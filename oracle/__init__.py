@@ -44,6 +44,28 @@ class Level(ctypes.Structure):
                 "frontier_delegate": int(self.frontier_delegate)}
 
 
+class WorkLevel(ctypes.Structure):
+    _fields_ = [("q", ctypes.c_int64 * 3), ("s", ctypes.c_int64 * 3), ("U", ctypes.c_int64 * 3),
+                ("FV", ctypes.c_int64 * 3), ("BV", ctypes.c_double * 3),
+                ("dir", ctypes.c_int32 * 3), ("runs", ctypes.c_int32 * 5)] + \
+               [(k, ctypes.c_int64) for k in
+                ("f_norm", "f_deleg", "e_nn", "e_nd", "e_dd", "e_dn", "c_dn", "e_bu_dn", "c_dd",
+                 "e_bu_dd", "c_nd", "e_bu_nd", "c_deleg", "s_dn", "s_dd", "s_nd", "cl_nn", "cl_nd",
+                 "cl_dd", "cl_dn", "cl_bu_dn", "cl_bu_deleg")]
+
+    def as_dict(self):
+        out = {}
+        for k, t in self._fields_:
+            v = getattr(self, k)
+            out[k] = list(v) if hasattr(v, "__len__") else int(v)
+        return out
+
+
+# Visits of or_work_bytes, in its order.
+WORK_VISITS = ("init", "normal_frontier", "delegate_previsit", "nd_forward", "deleg_forward",
+               "dn_backward", "deleg_backward")
+
+
 def build(force: bool = True) -> str:
     """Compile oracle.c into liboracle.so (gcc, OpenMP for the CSR build only)."""
     if force or not os.path.exists(_SO):
@@ -94,6 +116,14 @@ def _load():
         L.or_do_replay.restype = ctypes.c_int
         L.or_do_replay.argtypes = [vp, ctypes.c_int64, I32P, F64P, F64P, ctypes.c_int,
                                    ctypes.POINTER(Level), ctypes.c_int]
+        L.or_work_prepare.restype = ctypes.c_int
+        L.or_work_prepare.argtypes = [vp, ctypes.c_int64, ctypes.POINTER(vp)]
+        L.or_work_free.argtypes = [vp]
+        L.or_do_work.restype = ctypes.c_int
+        L.or_do_work.argtypes = [vp, I32P, F64P, F64P, ctypes.POINTER(WorkLevel), ctypes.c_int]
+        L.or_work_bytes.restype = ctypes.c_int
+        L.or_work_bytes.argtypes = [ctypes.POINTER(WorkLevel), ctypes.c_int, ctypes.c_int64,
+                                    ctypes.c_int, F64P, I64P]
         _lib = L
     return _lib
 
@@ -215,6 +245,48 @@ class Graph:
         if nl < 0:
             raise ValueError("or_do_replay failed")
         return [out[i].as_dict() for i in range(min(nl, max_levels))]
+
+
+class WorkModel:
+    """The work model of searches on one graph at one threshold (or_do_work):
+    per level, the schedule and the work of every visit, and the algorithmic
+    bytes per visit (or_work_bytes)."""
+
+    def __init__(self, graph: Graph, TH: int):
+        h = ctypes.c_void_p()
+        rc = _load().or_work_prepare(graph._h, TH, ctypes.byref(h))
+        if rc != 0:
+            raise ValueError(f"or_work_prepare failed ({rc})")
+        self._h = h
+        self._graph = graph   # the prepared rows point into the graph
+        self.n = graph.n
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _lib is not None:
+            _lib.or_work_free(h)
+            self._h = None
+
+    def levels(self, depth, factor0, factor1, max_levels: int = 4096):
+        depth = _c32(depth)
+        out = (WorkLevel * max_levels)()
+        f0 = (ctypes.c_double * 3)(*factor0)
+        f1 = (ctypes.c_double * 3)(*factor1)
+        nl = _load().or_do_work(self._h, _i32(depth), f0, f1, out, max_levels)
+        if nl < 0:
+            raise ValueError("or_do_work failed")
+        return out, min(nl, max_levels)
+
+    def run(self, depth, factor0, factor1, want_parent: bool = True):
+        """(levels as dicts, {visit: bytes}, {visit: levels with work})."""
+        out, nl = self.levels(depth, factor0, factor1)
+        b = (ctypes.c_double * 7)()
+        la = (ctypes.c_int64 * 7)()
+        rc = _load().or_work_bytes(out, nl, self.n, 8 if want_parent else 4, b, la)
+        if rc != 0:
+            raise ValueError("or_work_bytes failed")
+        return ([out[i].as_dict() for i in range(nl)], dict(zip(WORK_VISITS, list(b))),
+                dict(zip(WORK_VISITS, list(la))))
 
 
 def apsp(n: int, src, dst) -> np.ndarray:

@@ -30,10 +30,18 @@
  *    the oracle's own depths.
  *  - Brute-force all-pairs shortest paths (Floyd-Warshall) and union-find
  *    components, built straight from the edge list, to pin the search.
+ *  - The work model of a search (or_do_work, or_work_bytes): per level, the
+ *    schedule of Section IV-B and the edges, candidates, scanned entries and
+ *    candidate-set bytes of every visit, from the oracle's own level sets;
+ *    this is the m' + d*b work bound of Section IV-B at p = 1, turned into
+ *    the bytes the method must move.
  *
  * Parity status: every function here is pinned by tests against closed
- * forms, brute force or hand-derived values, except the bv_exact option,
- * which is pinned only by the geometric-series identity.
+ * forms, brute force or hand-derived values: the search by closed forms and
+ * Floyd-Warshall, the exact-BV option by a brute-force expectation over
+ * frontier subsets, the work model by hand-derived searches (one where the
+ * stored row order changes the scan), closed forms of an all-forward search
+ * and the per-level replay.
  */
 #include <math.h>
 #include <stdint.h>
@@ -499,4 +507,334 @@ int or_do_replay(const or_graph *G, int64_t TH, const int32_t *depth, const doub
     if (out && L < max_levels) out[L] = r;
   }
   return levels;
+}
+
+/* ---------------------------------------------------------------------- */
+/* Work model of one search: the bytes the method must move (algorithmic   */
+/* bytes), level by level, for the schedule of Section IV-B.               */
+/* ---------------------------------------------------------------------- */
+
+/*
+ * Log-scale degree bucket: eight buckets per power of two, from the position
+ * of the leading one bit and the three bits below it, capped at 255.
+ */
+static int32_t or_deg_bucket(int64_t x) {
+  if (x <= 1) return 0;
+  int lg = 63 - __builtin_clzll((unsigned long long)x);
+  int64_t frac = lg >= 3 ? (x >> (lg - 3)) & 7 : (x << (3 - lg)) & 7;
+  int64_t b = (int64_t)lg * 8 + frac;
+  return (int32_t)(b < 255 ? b : 255);
+}
+
+/*
+ * The rows a backward scan reads, in the order it reads them (the paper fixes
+ * only which edges each subgraph holds, Table I; the order inside a row is
+ * the layout's choice, and a scan that stops at the first frontier neighbour
+ * inspects a number of entries that depends on it):
+ *   normal v:   its delegate neighbours (the nd part), by decreasing degree,
+ *               ties by ascending ID;
+ *   delegate u: its delegate neighbours (dd part), by decreasing degree
+ *               bucket, ties by ascending ID, then its normal neighbours
+ *               (dn part), ascending.
+ * brow[v] .. brow[v+1] is the row; bmid[v] ends a delegate's dd part.
+ */
+typedef struct or_work_graph {
+  const or_graph *G;
+  int64_t TH;
+  int32_t n;
+  uint8_t *del;            /* 1 iff delegate (degree > TH) */
+  int64_t *to_del, *to_norm;
+  int64_t *brow, *bmid;
+  int32_t *bcol;
+  int64_t n_ndsrc, n_ddsrc, n_dnsrc, d;
+} or_work_graph;
+
+static int cmp_u64(const void *a, const void *b) {
+  uint64_t x = *(const uint64_t *)a, y = *(const uint64_t *)b;
+  return (x > y) - (x < y);
+}
+
+static int64_t or_max_deg(const or_graph *G) {
+  int64_t mx = 0;
+  for (int32_t v = 0; v < G->n; ++v) if (or_deg(G, v) > mx) mx = or_deg(G, v);
+  return mx;
+}
+
+void or_work_free(or_work_graph *W) {
+  if (!W) return;
+  free(W->del); free(W->to_del); free(W->to_norm); free(W->brow); free(W->bmid); free(W->bcol);
+  free(W);
+}
+
+int or_work_prepare(const or_graph *G, int64_t TH, or_work_graph **out) {
+  if (!G || !out) return OR_EINVAL;
+  *out = NULL;
+  const int32_t n = G->n;
+  or_work_graph *W = (or_work_graph *)calloc(1, sizeof(or_work_graph));
+  if (!W) return OR_ENOMEM;
+  W->G = G; W->TH = TH; W->n = n;
+  W->del = (uint8_t *)malloc((size_t)n);
+  W->to_del = (int64_t *)malloc((size_t)n * sizeof(int64_t));
+  W->to_norm = (int64_t *)malloc((size_t)n * sizeof(int64_t));
+  W->brow = (int64_t *)malloc(((size_t)n + 1) * sizeof(int64_t));
+  W->bmid = (int64_t *)malloc((size_t)n * sizeof(int64_t));
+  if (!W->del || !W->to_del || !W->to_norm || !W->brow || !W->bmid) {
+    or_work_free(W);
+    return OR_ENOMEM;
+  }
+  for (int32_t v = 0; v < n; ++v) W->del[v] = or_deg(G, v) > TH;
+  for (int32_t v = 0; v < n; ++v) {
+    int64_t a = 0, b = 0;
+    for (int64_t i = G->off[v]; i < G->off[v + 1]; ++i) {
+      if (W->del[G->col[i]]) a++; else b++;
+    }
+    W->to_del[v] = a;
+    W->to_norm[v] = b;
+    if (W->del[v]) {
+      W->d++;
+      if (a) W->n_ddsrc++;
+      if (b) W->n_dnsrc++;
+    } else if (a) {
+      W->n_ndsrc++;
+    }
+  }
+  W->brow[0] = 0;
+  for (int32_t v = 0; v < n; ++v)
+    W->brow[v + 1] = W->brow[v] + (W->del[v] ? or_deg(G, v) : W->to_del[v]);
+  W->bcol = (int32_t *)malloc((size_t)(W->brow[n] > 0 ? W->brow[n] : 1) * sizeof(int32_t));
+  if (!W->bcol) { or_work_free(W); return OR_ENOMEM; }
+  /* sort keys: the rank (decreasing degree, or decreasing degree bucket) in
+     the high 32 bits, the vertex ID in the low 32 */
+  uint64_t *key = (uint64_t *)malloc((size_t)(or_max_deg(G) > 0 ? or_max_deg(G) : 1) *
+                                     sizeof(uint64_t));
+  if (!key) { or_work_free(W); return OR_ENOMEM; }
+  for (int32_t v = 0; v < n; ++v) {
+    int32_t *row = W->bcol + W->brow[v];
+    int64_t k = 0;
+    for (int64_t i = G->off[v]; i < G->off[v + 1]; ++i) {
+      int32_t u = G->col[i];
+      if (!W->del[u]) continue;
+      uint64_t rank = W->del[v] ? (uint64_t)(255 - or_deg_bucket(or_deg(G, u)))
+                                : (uint64_t)(INT32_MAX - or_deg(G, u));
+      key[k++] = (rank << 32) | (uint32_t)u;
+    }
+    qsort(key, (size_t)k, sizeof(uint64_t), cmp_u64);
+    for (int64_t i = 0; i < k; ++i) row[i] = (int32_t)(key[i] & 0xffffffffu);
+    W->bmid[v] = W->brow[v] + k;
+    if (W->del[v])   /* dn part: ascending, as the CSR row already is */
+      for (int64_t i = G->off[v]; i < G->off[v + 1]; ++i)
+        if (!W->del[G->col[i]]) row[k++] = G->col[i];
+  }
+  free(key);
+  *out = W;
+  return OR_OK;
+}
+
+/* Per level of one search: the schedule and the work of every visit. */
+typedef struct {
+  int64_t q[3], s[3], U[3], FV[3];   /* dd, dn, nd: the decision's inputs */
+  double BV[3];
+  int32_t dir[3];                    /* direction used (0 forward, 1 backward) */
+  int32_t runs[5];                   /* visits with work: nd fwd, dd fwd, dn fwd, dn bwd, dd/nd bwd */
+  int64_t f_norm, f_deleg;           /* frontier vertices with >= 1 edge */
+  int64_t e_nn, e_nd, e_dd, e_dn;    /* edges expanded forward, per subgraph */
+  int64_t c_dn, e_bu_dn;             /* backward dn: candidates, entries inspected */
+  int64_t c_dd, e_bu_dd, c_nd, e_bu_nd;  /* backward dd / nd */
+  int64_t c_deleg;                   /* delegate candidates of the backward dd/nd visit */
+  int64_t s_dn, s_dd, s_nd;          /* candidate-set bytes scanned */
+  int64_t cl_nn, cl_nd, cl_dd, cl_dn, cl_bu_dn, cl_bu_deleg;  /* first reached, by visit */
+} or_work_level_t;
+
+/*
+ * The work of one search whose depths are `depth`, at threshold TH, with the
+ * direction factors of Section IV-B (BV = |U|(q+s)/q). The decision's inputs
+ * are the per-kernel definitions of or_do_replay, summed here from per-depth
+ * histograms (every vertex is in exactly one level's frontier, and "not
+ * visited at level L" is "total minus visited up to L"), so the schedule is
+ * the same one in O(n + m) per search.
+ *
+ * Within a level the visits run in the order: nn forward (always, Section
+ * IV-B), nd forward, dd and dn forward, dn backward, dd and nd backward (one
+ * pass over the delegate candidates: the dd part first, then the dn part if
+ * the dd part has no frontier neighbour). A vertex is first reached by the
+ * first visit in that order that can reach it, and a backward visit's
+ * candidates are the vertices of its source set not visited before the level
+ * and not reached earlier in the level. A forward visit reads each edge of
+ * its frontier's rows; a backward scan reads a candidate's row in stored
+ * order up to and including its first frontier neighbour (the whole row if
+ * there is none).
+ *
+ * Bytes (per level; the 8 bytes of output per vertex are counted where the
+ * vertex is first reached, and by the initialization for unreached vertices):
+ *   offsets 16 per frontier vertex with an edge, and 16 per backward
+ *   candidate; 4 per edge expanded or entry inspected; candidate sets
+ *   4|ndsrc| + n/8 (dn) and 2 d/8 (dd, nd) per backward visit that runs.
+ * Returns the number of levels (max depth + 1) or a negative error.
+ */
+int or_do_work(const or_work_graph *W, const int32_t *depth, const double *factor0,
+               const double *factor1, or_work_level_t *out, int max_levels) {
+  if (!W || !depth || !factor0 || !factor1) return OR_EINVAL;
+  const or_graph *G = W->G;
+  const int32_t n = W->n;
+  int32_t maxd = -1;
+  for (int32_t v = 0; v < n; ++v) if (depth[v] > maxd) maxd = depth[v];
+  const int32_t NL = maxd + 1;
+  if (NL <= 0) return 0;
+  /* per-depth histograms of the decision's inputs */
+  int64_t *H = (int64_t *)calloc((size_t)NL * 12, sizeof(int64_t));
+  if (!H) return OR_ENOMEM;
+  enum { FVDD, FVDN, QDD, QDN, FVND, FVNN, QND, QNN, VDD, VDN, VND, FN };
+  for (int32_t v = 0; v < n; ++v) {
+    int32_t L = depth[v];
+    if (L < 0) continue;
+    int64_t *h = H + (size_t)L * 12;
+    int64_t a = W->to_del[v], b = W->to_norm[v];
+    if (W->del[v]) {
+      h[FVDD] += a; h[FVDN] += b; h[QDD] += a > 0; h[QDN] += b > 0;
+      h[VDD] += a > 0; h[VDN] += b > 0;
+    } else {
+      h[FVND] += a; h[FVNN] += b; h[QND] += a > 0; h[QNN] += b > 0;
+      h[VND] += a > 0;
+    }
+  }
+  int32_t dir[3] = {0, 0, 0};
+  int64_t vis_dd = 0, vis_dn = 0, vis_nd = 0;   /* visited up to this level */
+  for (int32_t L = 0; L < NL; ++L) {
+    const int64_t *h = H + (size_t)L * 12;
+    or_work_level_t r;
+    memset(&r, 0, sizeof(r));
+    vis_dd += h[VDD]; vis_dn += h[VDN]; vis_nd += h[VND];
+    r.q[K_DD] = h[QDD]; r.q[K_DN] = h[QDN]; r.q[K_ND] = h[QND];
+    r.FV[K_DD] = h[FVDD]; r.FV[K_DN] = h[FVDN]; r.FV[K_ND] = h[FVND];
+    /* dd: U = ddsrc unvisited, s = |U|; dn: U = ndsrc unvisited, s = dnsrc
+       unvisited; nd: U = dnsrc unvisited, s = ndsrc unvisited */
+    r.U[K_DD] = W->n_ddsrc - vis_dd; r.s[K_DD] = r.U[K_DD];
+    r.U[K_DN] = W->n_ndsrc - vis_nd; r.s[K_DN] = W->n_dnsrc - vis_dn;
+    r.U[K_ND] = W->n_dnsrc - vis_dn; r.s[K_ND] = W->n_ndsrc - vis_nd;
+    for (int k = 0; k < 3; ++k) {
+      r.BV[k] = or_bv_approx(r.U[k], r.q[k], r.s[k]);
+      if (r.q[k] > 0) {
+        if (dir[k] == 0 && (double)r.FV[k] > factor0[k] * r.BV[k]) dir[k] = 1;
+        else if (dir[k] == 1 && (double)r.FV[k] < factor1[k] * r.BV[k]) dir[k] = 0;
+      }
+      r.dir[k] = dir[k];
+    }
+    const int nd_fwd = dir[K_ND] == 0 && r.q[K_ND] > 0;
+    const int dd_fwd = dir[K_DD] == 0 && r.q[K_DD] > 0;
+    const int dn_fwd = dir[K_DN] == 0 && r.q[K_DN] > 0;
+    const int dn_bwd = dir[K_DN] == 1 && r.q[K_DN] > 0 && r.U[K_DN] > 0;
+    const int dd_bwd = dir[K_DD] == 1 && r.q[K_DD] > 0 && r.U[K_DD] > 0;
+    const int nd_bwd = dir[K_ND] == 1 && r.q[K_ND] > 0 && r.U[K_ND] > 0;
+    r.runs[0] = nd_fwd; r.runs[1] = dd_fwd; r.runs[2] = dn_fwd; r.runs[3] = dn_bwd;
+    r.runs[4] = dd_bwd || nd_bwd;
+    r.e_nn = h[FVNN];
+    if (nd_fwd) r.e_nd = h[FVND];
+    if (dd_fwd) r.e_dd = h[FVDD];
+    if (dn_fwd) r.e_dn = h[FVDN];
+    for (int32_t v = 0; v < n; ++v) {
+      if (depth[v] != L) continue;
+      if (W->del[v]) r.f_deleg += or_deg(G, v) > 0;
+      else r.f_norm += or_deg(G, v) > 0;
+    }
+    /* first reach of every vertex at depth L + 1, and the backward scans */
+    if (dn_bwd) r.s_dn = 4 * W->n_ndsrc + ((int64_t)n + 7) / 8;
+    if (dd_bwd) r.s_dd = 2 * ((W->d + 7) / 8);
+    if (nd_bwd) r.s_nd = 2 * ((W->d + 7) / 8);
+    for (int32_t v = 0; v < n; ++v) {
+      const int32_t dv = depth[v];
+      if (dv >= 0 && dv <= L) continue;   /* visited before this level */
+      int from_norm = 0, from_del = 0;     /* has a frontier neighbour of that class */
+      if (dv == L + 1) {
+        for (int64_t i = G->off[v]; i < G->off[v + 1]; ++i) {
+          int32_t u = G->col[i];
+          if (depth[u] != L) continue;
+          if (W->del[u]) from_del = 1; else from_norm = 1;
+        }
+      }
+      if (!W->del[v]) {
+        if (from_norm) { r.cl_nn++; continue; }          /* nn forward */
+        if (dn_fwd && from_del) { r.cl_dn++; continue; }
+        if (dn_bwd && W->to_del[v] > 0) {
+          r.c_dn++;
+          int64_t k = 0, hit = 0;
+          for (int64_t i = W->brow[v]; i < W->brow[v + 1]; ++i) {
+            ++k;
+            if (depth[W->bcol[i]] == L) { hit = 1; break; }
+          }
+          r.e_bu_dn += k;
+          if (hit) r.cl_bu_dn++;
+        }
+      } else {
+        if (nd_fwd && from_norm) { r.cl_nd++; continue; }
+        if (dd_fwd && from_del) { r.cl_dd++; continue; }
+        const int scan_dd = dd_bwd && W->to_del[v] > 0, scan_dn = nd_bwd && W->to_norm[v] > 0;
+        if (!scan_dd && !scan_dn) continue;
+        r.c_deleg++;
+        int hit = 0;
+        if (scan_dd) {
+          r.c_dd++;
+          int64_t k = 0;
+          for (int64_t i = W->brow[v]; i < W->bmid[v]; ++i) {
+            ++k;
+            if (depth[W->bcol[i]] == L) { hit = 1; break; }
+          }
+          r.e_bu_dd += k;
+        }
+        if (!hit && scan_dn) {
+          r.c_nd++;
+          int64_t k = 0;
+          for (int64_t i = W->bmid[v]; i < W->brow[v + 1]; ++i) {
+            ++k;
+            if (depth[W->bcol[i]] == L) { hit = 1; break; }
+          }
+          r.e_bu_nd += k;
+        }
+        if (hit) r.cl_bu_deleg++;
+      }
+    }
+    if (out && L < max_levels) out[L] = r;
+  }
+  free(H);
+  return NL;
+}
+
+/*
+ * Algorithmic bytes of a search from its work levels, per visit:
+ *   [0] initialization: out_bytes per vertex never reached and for the source;
+ *   [1] normal frontier (previsit and nn forward): 16 per frontier normal with
+ *       an edge, 4 per nn edge, out_bytes per vertex first reached;
+ *   [2] delegate frontier previsit: 16 per frontier delegate with an edge;
+ *   [3] nd forward, [4] dd and dn forward: 4 per edge, out_bytes per vertex
+ *       first reached;
+ *   [5] dn backward, [6] dd and nd backward: 16 per candidate, 4 per entry
+ *       inspected, the candidate-set bytes, out_bytes per vertex first reached.
+ * out_bytes = 8 with parents (depth + parent), 4 without. launches[k] counts
+ * the levels on which visit k had work (for [0], 1).
+ */
+int or_work_bytes(const or_work_level_t *lv, int nl, int64_t n, int out_bytes, double *bytes,
+                  int64_t *launches) {
+  if (!lv || nl < 0 || !bytes || !launches) return OR_EINVAL;
+  for (int k = 0; k < 7; ++k) { bytes[k] = 0.0; launches[k] = 0; }
+  const double ob = (double)out_bytes;
+  int64_t reached = 1;
+  for (int L = 0; L < nl; ++L) {
+    const or_work_level_t *r = &lv[L];
+    reached += r->cl_nn + r->cl_nd + r->cl_dd + r->cl_dn + r->cl_bu_dn + r->cl_bu_deleg;
+    bytes[1] += 16.0 * r->f_norm + 4.0 * r->e_nn + ob * r->cl_nn;
+    bytes[2] += 16.0 * r->f_deleg;
+    bytes[3] += 4.0 * r->e_nd + ob * r->cl_nd;
+    bytes[4] += 4.0 * (r->e_dd + r->e_dn) + ob * (r->cl_dd + r->cl_dn);
+    bytes[5] += 16.0 * r->c_dn + 4.0 * r->e_bu_dn + (double)r->s_dn + ob * r->cl_bu_dn;
+    bytes[6] += 16.0 * r->c_deleg + 4.0 * (r->e_bu_dd + r->e_bu_nd) + (double)(r->s_dd + r->s_nd) +
+                ob * r->cl_bu_deleg;
+    launches[1] += 1;
+    launches[2] += 1;
+    launches[3] += r->runs[0];
+    launches[4] += r->runs[1] || r->runs[2];
+    launches[5] += r->runs[3];
+    launches[6] += r->runs[4];
+  }
+  bytes[0] = ob * (double)(n - reached + 1);
+  launches[0] = 1;
+  return OR_OK;
 }

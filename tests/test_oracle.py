@@ -310,17 +310,6 @@ def _table1_total(p, n, d, e_nn, e_nd, e_dn, e_dd):
     return per_gpu * p
 
 
-def test_table1_totals():
-    """Table I's rows, summed over p GPUs, give 8n + 8dp + 4m + 4|E_nn| (the
-    paper's total) on the fixture's symbolic rows."""
-    with open(os.path.join(GOLD, "table1_memory.txt")) as f:
-        rows = [list(map(int, l.split())) for l in f if l.strip() and not l.startswith("#")]
-    for p, n, d, e_nn, e_nd, e_dn, e_dd, want in rows:
-        assert _table1_total(p, n, d, e_nn, e_nd, e_dn, e_dd) == want
-        m = e_nn + e_nd + e_dn + e_dd
-        assert 8 * n + 8 * d * p + 4 * m + 4 * e_nn == want
-
-
 def test_table1_memory_of_split_graphs(oracle_mod):
     """Table I at p = 1 applied to the oracle's split of small graphs whose
     four edge classes are counted by hand (fixture table1_graphs.txt)."""
@@ -430,3 +419,140 @@ def test_do_replay_exact_bv_two_delegate_neighbours(oracle_mod):
     assert L[0]["q"][:2] == [1, 1] and L[0]["s"][:2] == [1, 2]
     assert L[0]["BV"][1] == pytest.approx(want_dn, rel=1e-12)
     assert L[0]["BV"][0] == pytest.approx(_expected_checks_brute(0.5, 1), rel=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# Work model (algorithmic bytes of a search)
+# ---------------------------------------------------------------------------
+
+def _pairs(n, pairs):
+    return (n, np.array([a for a, _ in pairs], np.int32), np.array([b for _, b in pairs], np.int32))
+
+
+def test_work_model_star_hand_derived(oracle_mod):
+    """Star, hub 0 (the only delegate at TH = 2) and k = 12 leaves, from leaf
+    1, the paper's factors (schedule as in test_do_replay_star_hand_derived).
+    Level 0: nd backward: one candidate (the hub), whose dn part is its
+    leaves ascending, so the scan stops at leaf 1, the first entry; mask bytes
+    2 * ceil(1/8). Level 1: dn backward: the other 11 leaves, one entry each,
+    all reached; candidate-set bytes 4 * 12 + ceil(13/8). Bytes: frontier
+    normals 16 * (1 + 11); delegate previsit 16; dn backward
+    16*11 + 4*11 + 50 + 8*11; delegate backward 16 + 4 + 2 + 8."""
+    k = 12
+    n, src, dst, _ = star(k)
+    G = _graph(oracle_mod, n, src, dst)
+    f0, f1 = _factors()
+    depth, _ = G.bfs(1)
+    L, B, runs = oracle_mod.WorkModel(G, 2).run(depth, f0, f1)
+    assert len(L) == 3
+    assert (L[0]["c_deleg"], L[0]["c_nd"], L[0]["e_bu_nd"], L[0]["s_nd"], L[0]["cl_bu_deleg"]) == \
+        (1, 1, 1, 2, 1)
+    assert (L[1]["c_dn"], L[1]["e_bu_dn"], L[1]["s_dn"], L[1]["cl_bu_dn"]) == (11, 11, 50, 11)
+    assert L[2]["runs"] == [0, 0, 0, 0, 0] and L[2]["f_norm"] == 11
+    assert B == {"init": 8.0, "normal_frontier": 192.0, "delegate_previsit": 16.0,
+                 "nd_forward": 0.0, "deleg_forward": 0.0, "dn_backward": 358.0,
+                 "deleg_backward": 30.0}
+    assert runs["dn_backward"] == 1 and runs["deleg_backward"] == 1
+    # without parents the output costs 4 bytes per vertex
+    _, B4, _ = oracle_mod.WorkModel(G, 2).run(depth, f0, f1, want_parent=False)
+    assert B4["dn_backward"] == 358.0 - 4 * 11 and B4["deleg_backward"] == 30.0 - 4
+
+
+def test_work_model_stored_order_hand_derived(oracle_mod):
+    """Delegates A=0, B=1, C=2 (degrees 4, 5, 6 > TH = 3) share the normal
+    neighbour x=3 (degree 3); A has leaves 4..6, B 7..10, C 11..15. From A
+    with the paper's factors:
+    level 0: dn: q=1, FV=4, U = 13 normals with a delegate neighbour, s = 2
+    (B, C): BV = 39 and 4 > 0.05*39, backward. The candidates are the 13
+    normals. x's nd part is stored by decreasing degree (C, B, A), so its scan
+    reads 3 entries before it finds A (1 in ascending order); A's leaves read
+    1 entry each and are reached, B's and C's leaves read 1 each and miss:
+    15 entries, 4 reached, 4*13 + 2 candidate-set bytes.
+    level 1: frontier x and A's leaves (normals): nd: q=4, FV=6, U={B, C},
+    s=9: BV = 6.5, backward: B's and C's dn parts are ascending and start
+    with x: 1 entry each, both reached.
+    level 2: frontier B, C: dn stays backward: the 9 leaves of B and C, one
+    entry each, all reached. level 3: nd has no unvisited candidate."""
+    pairs = [(0, 3), (1, 3), (2, 3)] + [(0, v) for v in (4, 5, 6)] + \
+        [(1, v) for v in (7, 8, 9, 10)] + [(2, v) for v in (11, 12, 13, 14, 15)]
+    n, src, dst = _pairs(16, pairs)
+    G = _graph(oracle_mod, n, src, dst)
+    assert G.split_stats(3)["d"] == 3
+    f0, f1 = _factors()
+    depth, _ = G.bfs(0)
+    L, B, _ = oracle_mod.WorkModel(G, 3).run(depth, f0, f1)
+    assert len(L) == 4
+    assert L[0]["dir"][1] == 1 and L[0]["BV"][1] == pytest.approx(39.0)
+    assert (L[0]["c_dn"], L[0]["e_bu_dn"], L[0]["cl_bu_dn"], L[0]["s_dn"]) == (13, 15, 4, 54)
+    assert L[1]["dir"][2] == 1 and L[1]["BV"][2] == pytest.approx(6.5)
+    assert (L[1]["c_deleg"], L[1]["c_nd"], L[1]["e_bu_nd"], L[1]["cl_bu_deleg"]) == (2, 2, 2, 2)
+    assert (L[2]["c_dn"], L[2]["e_bu_dn"], L[2]["cl_bu_dn"]) == (9, 9, 9)
+    assert L[3]["runs"] == [0, 0, 0, 0, 0]
+    assert B["dn_backward"] == 16 * 13 + 4 * 15 + 54 + 8 * 4 + 16 * 9 + 4 * 9 + 54 + 8 * 9
+    assert B["deleg_backward"] == 16 * 2 + 4 * 2 + 2 + 8 * 2
+
+
+def _reach_invariants(L, depth):
+    """Every vertex at depth l + 1 is first reached exactly once, at level l."""
+    for lv, r in enumerate(L):
+        got = r["cl_nn"] + r["cl_nd"] + r["cl_dd"] + r["cl_dn"] + r["cl_bu_dn"] + r["cl_bu_deleg"]
+        assert got == int((depth == lv + 1).sum()), lv
+
+
+@pytest.mark.parametrize("TH", [0, 2, 8, 32, 10 ** 6])
+def test_work_model_all_forward_closed_form(oracle_mod, inputs_mod, TH):
+    """With factor0 = inf no kernel leaves the forward direction: every
+    reached vertex's row is expanded once, so the forward edges sum to the
+    component's directed edge count (sum of its degrees), the frontier
+    vertices with an edge are the reached vertices of positive degree, and
+    no backward work is done."""
+    src, dst = inputs_mod.rmat_edges(10)
+    n = 1 << 10
+    G = _graph(oracle_mod, n, src, dst)
+    deg = G.degrees()
+    W = oracle_mod.WorkModel(G, TH)
+    inf = float("inf")
+    for s in inputs_mod.pick_sources(src, dst, n, 4, seed=5).tolist():
+        depth, _ = G.bfs(s)
+        L, B, _ = W.run(depth, (inf, inf, inf), (0.0, 0.0, 0.0))
+        reached = depth >= 0
+        assert sum(r["e_nn"] + r["e_nd"] + r["e_dd"] + r["e_dn"] for r in L) == deg[reached].sum()
+        assert sum(r["f_norm"] + r["f_deleg"] for r in L) == int((reached & (deg > 0)).sum())
+        for r in L:
+            assert r["c_dn"] == r["c_deleg"] == r["e_bu_dn"] == r["e_bu_dd"] == r["e_bu_nd"] == 0
+            assert r["s_dn"] == r["s_dd"] == r["s_nd"] == 0
+        _reach_invariants(L, depth)
+        assert B["init"] == 8 * (int((~reached).sum()) + 1)   # unreached + the source
+        total = sum(B.values())
+        assert total == 16 * int((reached & (deg > 0)).sum()) + 4 * deg[reached].sum() + 8 * n
+
+
+@pytest.mark.parametrize("scale,TH", [(10, 4), (12, 16), (12, 64)])
+def test_work_model_schedule_equals_replay(oracle_mod, inputs_mod, scale, TH):
+    """The work model's schedule (summed from per-depth histograms) equals the
+    level-by-level replay of Section IV-B (pinned above by hand-derived
+    cases) under several factor pairs; every vertex is reached once; a
+    backward scan never reads more entries than its candidates' rows hold
+    and at least one per candidate."""
+    src, dst = inputs_mod.rmat_edges(scale)
+    n = 1 << scale
+    G = _graph(oracle_mod, n, src, dst)
+    W = oracle_mod.WorkModel(G, TH)
+    r = G.split_rows(TH)
+    nd_len = np.diff(r["nd_off"])
+    for f0, f1 in (((0.5, 0.05, 1e-7), (0.0, 0.0, 0.0)), ((0.02, 0.001, 1e-6), (0.0, 0.0, 0.0)),
+                   ((1e-3, 1e-3, 1e-3), (0.2, 0.5, 2.0)), ((0.0, 0.0, 0.0), (0.0, 0.0, 0.0))):
+        for s in inputs_mod.pick_sources(src, dst, n, 3, seed=40 + scale).tolist():
+            depth, _ = G.bfs(s)
+            L, _, _ = W.run(depth, f0, f1)
+            rep = G.do_replay(TH, depth, f0, f1)
+            assert len(L) == len(rep)
+            for a, b in zip(L, rep):
+                for k in ("q", "s", "U", "FV", "BV", "dir"):
+                    assert a[k] == b[k], (k, a[k], b[k])
+            _reach_invariants(L, depth)
+            for lv, a in enumerate(L):
+                if a["c_dn"]:
+                    unvis = (depth < 0) | (depth > lv)
+                    cap = int(nd_len[unvis].sum())
+                    assert a["c_dn"] <= a["e_bu_dn"] <= cap
