@@ -61,6 +61,11 @@ class WorkLevel(ctypes.Structure):
         return out
 
 
+class MsLevel(ctypes.Structure):
+    _fields_ = [("active", ctypes.c_int64), ("e", ctypes.c_int64), ("v", ctypes.c_int64),
+                ("bottom_up", ctypes.c_int32), ("pad", ctypes.c_int32)]
+
+
 # Visits of or_work_bytes, in its order.
 WORK_VISITS = ("init", "normal_frontier", "delegate_previsit", "nd_forward", "deleg_forward",
                "dn_backward", "deleg_backward")
@@ -124,6 +129,9 @@ def _load():
         L.or_work_bytes.restype = ctypes.c_int
         L.or_work_bytes.argtypes = [ctypes.POINTER(WorkLevel), ctypes.c_int, ctypes.c_int64,
                                     ctypes.c_int, F64P, I64P]
+        L.or_ms_work.restype = ctypes.c_int
+        L.or_ms_work.argtypes = [vp, I32P, ctypes.c_int32, ctypes.c_int32, I32P,
+                                 ctypes.POINTER(MsLevel), ctypes.c_int, F64P]
         _lib = L
     return _lib
 
@@ -233,6 +241,24 @@ class Graph:
             arrs[k + "_col"] = arrs[k + "_col"][:st["e_" + k]]
         arrs["did"] = did
         return arrs
+
+    def ms_work(self, sources, permille: int, want_depth: bool = False,
+                max_levels: int = 4096):
+        """Work model of one bit-parallel multi-source batch (or_ms_work):
+        (levels as dicts, algorithmic bytes, depth rows [k][n] or None)."""
+        srcs = _c32(sources)
+        k = len(srcs)
+        depth = np.empty((k, self.n), dtype=np.int32) if want_depth else None
+        out = (MsLevel * max_levels)()
+        b = ctypes.c_double(0.0)
+        nl = _load().or_ms_work(self._h, _i32(srcs), k, permille,
+                                _i32(depth) if want_depth else None, out, max_levels,
+                                ctypes.byref(b))
+        if nl < 0:
+            raise ValueError(f"or_ms_work failed ({nl})")
+        levels = [{"active": int(out[i].active), "e": int(out[i].e), "v": int(out[i].v),
+                   "bottom_up": int(out[i].bottom_up)} for i in range(min(nl, max_levels))]
+        return levels, float(b.value), depth
 
     def do_replay(self, TH: int, depth, factor0=(0.5, 0.05, 1e-7), factor1=(0.0, 0.0, 0.0),
                   bv_exact: bool = False, max_levels: int = 4096):

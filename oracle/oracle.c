@@ -583,6 +583,7 @@ int or_work_prepare(const or_graph *G, int64_t TH, or_work_graph **out) {
     return OR_ENOMEM;
   }
   for (int32_t v = 0; v < n; ++v) W->del[v] = or_deg(G, v) > TH;
+#pragma omp parallel for schedule(dynamic, 4096)
   for (int32_t v = 0; v < n; ++v) {
     int64_t a = 0, b = 0;
     for (int64_t i = G->off[v]; i < G->off[v + 1]; ++i) {
@@ -590,11 +591,13 @@ int or_work_prepare(const or_graph *G, int64_t TH, or_work_graph **out) {
     }
     W->to_del[v] = a;
     W->to_norm[v] = b;
+  }
+  for (int32_t v = 0; v < n; ++v) {
     if (W->del[v]) {
       W->d++;
-      if (a) W->n_ddsrc++;
-      if (b) W->n_dnsrc++;
-    } else if (a) {
+      if (W->to_del[v]) W->n_ddsrc++;
+      if (W->to_norm[v]) W->n_dnsrc++;
+    } else if (W->to_del[v]) {
       W->n_ndsrc++;
     }
   }
@@ -605,27 +608,37 @@ int or_work_prepare(const or_graph *G, int64_t TH, or_work_graph **out) {
   if (!W->bcol) { or_work_free(W); return OR_ENOMEM; }
   /* sort keys: the rank (decreasing degree, or decreasing degree bucket) in
      the high 32 bits, the vertex ID in the low 32 */
-  uint64_t *key = (uint64_t *)malloc((size_t)(or_max_deg(G) > 0 ? or_max_deg(G) : 1) *
-                                     sizeof(uint64_t));
-  if (!key) { or_work_free(W); return OR_ENOMEM; }
-  for (int32_t v = 0; v < n; ++v) {
-    int32_t *row = W->bcol + W->brow[v];
-    int64_t k = 0;
-    for (int64_t i = G->off[v]; i < G->off[v + 1]; ++i) {
-      int32_t u = G->col[i];
-      if (!W->del[u]) continue;
-      uint64_t rank = W->del[v] ? (uint64_t)(255 - or_deg_bucket(or_deg(G, u)))
-                                : (uint64_t)(INT32_MAX - or_deg(G, u));
-      key[k++] = (rank << 32) | (uint32_t)u;
+  const int64_t maxdeg = or_max_deg(G);
+  int failed = 0;
+#pragma omp parallel
+  {
+    uint64_t *key = (uint64_t *)malloc((size_t)(maxdeg > 0 ? maxdeg : 1) * sizeof(uint64_t));
+    if (!key) {
+#pragma omp atomic write
+      failed = 1;
     }
-    qsort(key, (size_t)k, sizeof(uint64_t), cmp_u64);
-    for (int64_t i = 0; i < k; ++i) row[i] = (int32_t)(key[i] & 0xffffffffu);
-    W->bmid[v] = W->brow[v] + k;
-    if (W->del[v])   /* dn part: ascending, as the CSR row already is */
-      for (int64_t i = G->off[v]; i < G->off[v + 1]; ++i)
-        if (!W->del[G->col[i]]) row[k++] = G->col[i];
+#pragma omp for schedule(dynamic, 4096)
+    for (int32_t v = 0; v < n; ++v) {
+      if (!key) continue;
+      int32_t *row = W->bcol + W->brow[v];
+      int64_t k = 0;
+      for (int64_t i = G->off[v]; i < G->off[v + 1]; ++i) {
+        int32_t u = G->col[i];
+        if (!W->del[u]) continue;
+        uint64_t rank = W->del[v] ? (uint64_t)(255 - or_deg_bucket(or_deg(G, u)))
+                                  : (uint64_t)(INT32_MAX - or_deg(G, u));
+        key[k++] = (rank << 32) | (uint32_t)u;
+      }
+      qsort(key, (size_t)k, sizeof(uint64_t), cmp_u64);
+      for (int64_t i = 0; i < k; ++i) row[i] = (int32_t)(key[i] & 0xffffffffu);
+      W->bmid[v] = W->brow[v] + k;
+      if (W->del[v])   /* dn part: ascending, as the CSR row already is */
+        for (int64_t i = G->off[v]; i < G->off[v + 1]; ++i)
+          if (!W->del[G->col[i]]) row[k++] = G->col[i];
+    }
+    free(key);
   }
-  free(key);
+  if (failed) { or_work_free(W); return OR_ENOMEM; }
   *out = W;
   return OR_OK;
 }
@@ -837,4 +850,163 @@ int or_work_bytes(const or_work_level_t *lv, int nl, int64_t n, int out_bytes, d
   bytes[0] = ob * (double)(n - reached + 1);
   launches[0] = 1;
   return OR_OK;
+}
+
+/* ---------------------------------------------------------------------- */
+/* Work model of bit-parallel multi-source BFS (one batch).                */
+/* ---------------------------------------------------------------------- */
+
+/*
+ * Bit-parallel multi-source BFS (Then et al., "The More the Merrier", PVLDB
+ * 8(4), 2014; not in the paper): k <= 64 W sources are the lanes of W 64-bit
+ * words per vertex. At level L, F[v] = the lanes first reaching v at depth L,
+ * seen[v] = the lanes reaching v at depth <= L, live = the lanes with a
+ * non-empty F. The next level is next[w] = (OR of F[u] over neighbours u)
+ * and not seen[w]. A level runs top-down when its active vertices (F != 0)
+ * number at most n * permille / 1000 (integer division), else bottom-up:
+ *   top-down:  each active vertex reads its row: E = sum of their degrees,
+ *              V = active vertices;
+ *   bottom-up: each vertex with wanted = live and not seen[w] non-empty reads
+ *              its row in stored order, ORing F of the entries, until the
+ *              OR covers wanted (the whole row if it never does):
+ *              E = entries read, V = such vertices.
+ * Rows are read in stored order: neighbours by decreasing degree bucket,
+ * ties by ascending ID (or_deg_bucket). Bytes of a level: 4 E (columns) +
+ * 8 W E (lane sets of the entries) + 24 W V (seen, frontier and next of the
+ * vertices) + 16 V (their row offsets); of the batch: the levels plus
+ * 4 k n for the depth rows. depth (k x n, may be NULL) receives every lane's
+ * hop distances (-1 unreached). Returns the number of levels run, or a
+ * negative error.
+ */
+typedef struct {
+  int64_t active, e, v;   /* active vertices; entries read; vertices processed */
+  int32_t bottom_up;
+  int32_t pad;
+} or_ms_level_t;
+
+int or_ms_work(const or_graph *G, const int32_t *sources, int32_t k, int32_t permille,
+               int32_t *depth, or_ms_level_t *out, int max_levels, double *bytes) {
+  if (!G || !sources || k < 1 || k > 256 || permille < 0 || permille > 1000 || !bytes)
+    return OR_EINVAL;
+  const int32_t n = G->n;
+  const int W = (k + 63) / 64;
+  for (int32_t i = 0; i < k; ++i)
+    if (sources[i] < 0 || sources[i] >= n) return OR_EINVAL;
+  uint64_t *seen = (uint64_t *)calloc((size_t)n * W, sizeof(uint64_t));
+  uint64_t *F = (uint64_t *)calloc((size_t)n * W, sizeof(uint64_t));
+  uint64_t *nx = (uint64_t *)calloc((size_t)n * W, sizeof(uint64_t));
+  int64_t *row = (int64_t *)malloc(((size_t)n + 1) * sizeof(int64_t));
+  int32_t *col = (int32_t *)malloc((size_t)(G->m > 0 ? G->m : 1) * sizeof(int32_t));
+  if (!seen || !F || !nx || !row || !col) {
+    free(seen); free(F); free(nx); free(row); free(col);
+    return OR_ENOMEM;
+  }
+  /* rows in stored order */
+  for (int32_t v = 0; v <= n; ++v) row[v] = G->off[v];
+  int64_t maxdeg = or_max_deg(G);
+  int failed = 0;
+#pragma omp parallel
+  {
+    uint64_t *key = (uint64_t *)malloc((size_t)(maxdeg > 0 ? maxdeg : 1) * sizeof(uint64_t));
+    if (!key) {
+#pragma omp atomic write
+      failed = 1;
+    }
+#pragma omp for schedule(dynamic, 4096)
+    for (int32_t v = 0; v < n; ++v) {
+      if (!key) continue;
+      int64_t len = G->off[v + 1] - G->off[v];
+      for (int64_t i = 0; i < len; ++i) {
+        int32_t u = G->col[G->off[v] + i];
+        key[i] = ((uint64_t)(255 - or_deg_bucket(or_deg(G, u))) << 32) | (uint32_t)u;
+      }
+      qsort(key, (size_t)len, sizeof(uint64_t), cmp_u64);
+      for (int64_t i = 0; i < len; ++i) col[G->off[v] + i] = (int32_t)(key[i] & 0xffffffffu);
+    }
+    free(key);
+  }
+  if (failed) {
+    free(seen); free(F); free(nx); free(row); free(col);
+    return OR_ENOMEM;
+  }
+  if (depth)
+    for (int64_t i = 0; i < (int64_t)k * n; ++i) depth[i] = -1;
+  for (int32_t i = 0; i < k; ++i) {
+    int32_t s = sources[i];
+    F[(size_t)s * W + i / 64] |= 1ull << (i % 64);
+    seen[(size_t)s * W + i / 64] |= 1ull << (i % 64);
+    if (depth) depth[(size_t)i * n + s] = 0;
+  }
+  const int64_t threshold = (int64_t)n * permille / 1000;
+  double total = 4.0 * k * n;
+  int L = 0;
+  while (1) {
+    uint64_t live[4] = {0, 0, 0, 0};
+    int64_t active = 0;
+    for (int32_t v = 0; v < n; ++v) {
+      int any = 0;
+      for (int w = 0; w < W; ++w) {
+        live[w] |= F[(size_t)v * W + w];
+        any |= F[(size_t)v * W + w] != 0;
+      }
+      active += any;
+    }
+    if (active == 0) break;
+    const int bu = active > threshold;
+    int64_t E = 0, V = 0;
+#pragma omp parallel for schedule(dynamic, 4096) reduction(+ : E, V)
+    for (int32_t x = 0; x < n; ++x) {
+      uint64_t want[4], acc[4] = {0, 0, 0, 0};
+      int wanted = 0;
+      for (int w = 0; w < W; ++w) {
+        want[w] = live[w] & ~seen[(size_t)x * W + w];
+        wanted |= want[w] != 0;
+      }
+      /* top-down: an active vertex reads its whole row */
+      if (!bu) {
+        int act = 0;
+        for (int w = 0; w < W; ++w) act |= F[(size_t)x * W + w] != 0;
+        if (act) { E += row[x + 1] - row[x]; V += 1; }
+      }
+      int64_t read = 0;
+      if (wanted) {
+        for (int64_t i = row[x]; i < row[x + 1]; ++i) {
+          int32_t u = col[i];
+          int covered = 1;
+          for (int w = 0; w < W; ++w) {
+            acc[w] |= F[(size_t)u * W + w];
+            covered &= (acc[w] & want[w]) == want[w];
+          }
+          ++read;
+          if (covered) break;
+        }
+        if (bu) { E += read; V += 1; }
+      }
+      for (int w = 0; w < W; ++w) nx[(size_t)x * W + w] = acc[w] & want[w];
+    }
+    if (out && L < max_levels) {
+      out[L].active = active;
+      out[L].e = E;
+      out[L].v = V;
+      out[L].bottom_up = bu;
+      out[L].pad = 0;
+    }
+    total += 4.0 * E + 8.0 * W * E + 24.0 * W * V + 16.0 * V;
+    for (int32_t v = 0; v < n; ++v)
+      for (int w = 0; w < W; ++w) {
+        uint64_t b = nx[(size_t)v * W + w];
+        seen[(size_t)v * W + w] |= b;
+        F[(size_t)v * W + w] = b;
+        if (depth)
+          while (b) {
+            int lane = w * 64 + __builtin_ctzll(b);
+            b &= b - 1;
+            depth[(size_t)lane * n + v] = L + 1;
+          }
+      }
+    ++L;
+  }
+  *bytes = total;
+  free(seen); free(F); free(nx); free(row); free(col);
+  return L;
 }

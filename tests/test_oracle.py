@@ -556,3 +556,68 @@ def test_work_model_schedule_equals_replay(oracle_mod, inputs_mod, scale, TH):
                     unvis = (depth < 0) | (depth > lv)
                     cap = int(nd_len[unvis].sum())
                     assert a["c_dn"] <= a["e_bu_dn"] <= cap
+
+
+# ---------------------------------------------------------------------------
+# Work model of bit-parallel multi-source BFS
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("k,permille", [(5, 0), (64, 2), (100, 50), (256, 1000), (200, 10)])
+def test_ms_work_lanes_equal_single_source(oracle_mod, inputs_mod, k, permille):
+    """Every lane of the simulated batch (1, 2 or 4 words of lanes) has the
+    depths of a single-source search from its source, whatever the mix of
+    top-down and bottom-up levels."""
+    src, dst = inputs_mod.rmat_edges(10)
+    n = 1 << 10
+    G = _graph(oracle_mod, n, src, dst)
+    rng = np.random.default_rng(k)
+    sources = rng.integers(0, n, size=k).astype(np.int32)   # repeats allowed
+    levels, _, depth = G.ms_work(sources, permille, want_depth=True)
+    for i, s in enumerate(sources.tolist()):
+        np.testing.assert_array_equal(depth[i], G.bfs(s, want_parent=False)[0], err_msg=str(i))
+    assert len(levels) == int(depth.max()) + 1
+
+
+def test_ms_work_top_down_closed_form(oracle_mod, inputs_mod):
+    """All levels top-down (permille 1000): vertex v is active once per
+    distinct depth it has over the lanes, and each time its whole row is
+    read, so E = sum over v of deg(v) * #distinct depths and V = sum of
+    #distinct depths; bytes = 4 k n + 4 E + 8 W E + 24 W V + 16 V."""
+    src, dst = inputs_mod.rmat_edges(9)
+    n = 1 << 9
+    G = _graph(oracle_mod, n, src, dst)
+    deg = G.degrees()
+    for k in (3, 64, 130):
+        sources = inputs_mod.pick_sources(src, dst, n, k, seed=k)
+        D = np.stack([G.bfs(int(s), want_parent=False)[0] for s in sources])
+        distinct = np.array([len(set(D[:, v][D[:, v] >= 0].tolist())) for v in range(n)])
+        levels, b, _ = G.ms_work(sources, 1000)
+        E = sum(x["e"] for x in levels)
+        V = sum(x["v"] for x in levels)
+        assert not any(x["bottom_up"] for x in levels)
+        assert E == int((deg * distinct).sum()) and V == int(distinct.sum())
+        W = (k + 63) // 64
+        assert b == 4 * k * n + 4 * E + 8 * W * E + 24 * W * V + 16 * V
+
+
+def test_ms_work_bottom_up_path_hand_derived(oracle_mod):
+    """Path 0-1-...-(n-1), one lane from 0, every level bottom-up
+    (permille 0). Rows are stored by decreasing degree bucket, so vertex 1
+    reads 2 (degree 2) before 0 (degree 1). Level 0: vertex 1 reads 2
+    entries and finds 0; 2..n-2 read both entries and miss; n-1 reads its
+    one entry: E = 2n - 3, V = n - 1. Level L in 1..n-3: L+1 finds L at once,
+    L+2..n-2 read 2 each, n-1 reads 1: E = 2n - 4 - 2L, V = n - 1 - L.
+    Level n-2: only n-1 is unseen and finds n-2: E = V = 1. Level n-1: the
+    frontier is n-1 and nothing is unseen: E = V = 0."""
+    n = 12
+    _, src, dst, _ = path(n)
+    G = _graph(oracle_mod, n, src, dst)
+    levels, b, depth = G.ms_work(np.array([0], np.int32), 0, want_depth=True)
+    assert depth[0].tolist() == list(range(n))
+    want = [(2 * n - 3, n - 1)] + [(2 * n - 4 - 2 * L, n - 1 - L) for L in range(1, n - 2)] + \
+        [(1, 1), (0, 0)]
+    assert [(x["e"], x["v"]) for x in levels] == want
+    assert all(x["bottom_up"] == 1 for x in levels) and [x["active"] for x in levels] == [1] * n
+    E = sum(e for e, _ in want)
+    V = sum(v for _, v in want)
+    assert b == 4 * n + 4 * E + 8 * E + 24 * V + 16 * V
