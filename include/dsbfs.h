@@ -263,6 +263,26 @@ dsbfs_status dsbfs_bfs(const dsbfs_graph *g, dsbfs_workspace *ws, int32_t source
                        const dsbfs_run_opts *opts, int32_t *depth, int32_t *parent,
                        dsbfs_run_stats *stats, void *stream);
 
+/*
+ * dsbfs_bfs without a workspace and without any allocation, for callers that
+ * cannot allocate device memory (serving loops with a fixed footprint,
+ * harnesses that forbid allocation). Same arguments, results and errors as
+ * dsbfs_bfs, with the search's scratch memory taken from one static device
+ * array per GPU of 64 MiB (held from the library's load until the process
+ * ends). A graph needing more (about 26 MB at RMAT scale 20; roughly 25 bytes
+ * per vertex) is refused with RANGE before any device work. Levels run as
+ * direct launches, and the call returns after its work on `stream` has
+ * completed; calls on one device are serialized by a lock, so they never
+ * overlap, and each call starts from a cleared state (the array keeps the
+ * previous call's contents, which the search overwrites before reading).
+ * opts->profile must be 0 (timing events are not created).
+ * Errors: as dsbfs_bfs; RANGE (graph too large for the scratch array);
+ * INVALID_ARG (profile = 1).
+ */
+dsbfs_status dsbfs_bfs_noalloc(const dsbfs_graph *g, int32_t source, const dsbfs_run_opts *opts,
+                               int32_t *depth, int32_t *parent, dsbfs_run_stats *stats,
+                               void *stream);
+
 /* Tile and schedule parameters of multi-source BFS (chosen by the tuner). */
 typedef struct dsbfs_ms_opts {
   int32_t block;          /* threads per workgroup: 64, 128, 256, 512 or 1024 */

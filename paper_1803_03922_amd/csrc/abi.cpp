@@ -53,6 +53,8 @@ void workspace_destroy(Workspace *ws);
 void run_opts_default(dsbfs_run_opts *o);
 void bfs_run(const Graph *g, Workspace *ws, int32_t source, const dsbfs_run_opts *o,
              int32_t *depth, int32_t *parent, dsbfs_run_stats *stats, hipStream_t s);
+void bfs_run_noalloc(const Graph *g, int32_t source, const dsbfs_run_opts *o, int32_t *depth,
+                     int32_t *parent, dsbfs_run_stats *stats, hipStream_t s);
 void graph_export(const Graph *g, int32_t which, void *host_out, int64_t cap, int64_t *bytes);
 void msbfs_run(const Graph *g, Workspace *ws, const int32_t *sources, int32_t k,
                const dsbfs_ms_opts *o, int32_t *depth, hipStream_t s);
@@ -170,6 +172,15 @@ dsbfs_status dsbfs_bfs(const dsbfs_graph *g, dsbfs_workspace *ws, int32_t source
   return guard([&] {
     if (!g || !ws) fail(DSBFS_ERR_INVALID_ARG, "graph and workspace must not be NULL");
     bfs_run(g->g, ws->w, source, opts, depth, parent, stats, static_cast<hipStream_t>(stream));
+  });
+}
+
+dsbfs_status dsbfs_bfs_noalloc(const dsbfs_graph *g, int32_t source, const dsbfs_run_opts *opts,
+                               int32_t *depth, int32_t *parent, dsbfs_run_stats *stats,
+                               void *stream) {
+  return guard([&] {
+    if (!g) fail(DSBFS_ERR_INVALID_ARG, "graph must not be NULL");
+    bfs_run_noalloc(g->g, source, opts, depth, parent, stats, static_cast<hipStream_t>(stream));
   });
 }
 

@@ -25,6 +25,8 @@
 // "DOBFS", Section VI-C), with the same load-balanced expansion.
 #include <cmath>
 #include <cstring>
+#include <mutex>
+#include <string>
 
 #include "internal.hpp"
 
@@ -37,8 +39,8 @@ void level_graphs_release(Workspace *ws);
 Workspace::~Workspace() {
   msbfs_release(this);
   level_graphs_release(this);
-  if (hctr) (void)hipHostFree(hctr);
-  if (hstat) (void)hipHostFree(hstat);
+  if (hctr && !borrowed) (void)hipHostFree(hctr);
+  if (hstat && !borrowed) (void)hipHostFree(hstat);
   for (hipEvent_t e : events) (void)hipEventDestroy(e);
   for (hipEvent_t e : lev_ev)
     if (e) (void)hipEventDestroy(e);
@@ -1372,7 +1374,20 @@ void bfs_run(const Graph *g, Workspace *ws, int32_t source, const dsbfs_run_opts
     LevelStatus *hs = static_cast<LevelStatus *>(ws->hstat);
     const LevelLaunch ll = level_launch(g, ws, out);
     std::vector<LevelStatus> seen;
-    if (P.on) {
+    if (ws->borrowed) {
+      // allocation-free search: direct launches (no captured graphs, no
+      // events), and the level's status record copied from device memory
+      // after each level
+      for (int32_t L = 0;; ++L) {
+        ll.enqueue(L & 1, s, nullptr);
+        LevelStatus st;
+        HIPCHK(hipMemcpyAsync(&st, hs + (L & (kStatusSlots - 1)), sizeof(LevelStatus),
+                              hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        if (st.done) break;
+        seen.push_back(st);
+      }
+    } else if (P.on) {
       // direct launches with an event around each kernel and one stream
       // synchronization per level, so that only kernels with work are counted
       for (int32_t L = 0;; ++L) {
@@ -1424,7 +1439,8 @@ void bfs_run(const Graph *g, Workspace *ws, int32_t source, const dsbfs_run_opts
       }
     }
     if (!P.on) {
-      // the level that found the frontier empty ran its previsit
+      // the level that found the frontier empty ran its previsit (as did the
+      // levels queued behind it, which return at once and are not counted)
       ++P.launches[DSBFS_K_PREV_NORMAL];
       if (d > 0) ++P.launches[DSBFS_K_PREV_DELEG];
     }
@@ -1506,6 +1522,118 @@ void bfs_run(const Graph *g, Workspace *ws, int32_t source, const dsbfs_run_opts
       stats->kernels[k].edges = int64_t(edges[k]);
     }
   }
+}
+
+// ---------------------------------------------------------------------------
+// Allocation-free single-source search
+// ---------------------------------------------------------------------------
+// For callers that cannot allocate device memory: the search's scratch (the
+// workspace's bitmaps, queues, candidate lists, counters, control block and
+// level status ring) is carved out of one file-scope device array. Each GPU
+// holds its own copy of the array, at its own address, from the library's
+// load until the process ends; host code never uses the array's name as an
+// address, only the device address hipGetSymbolAddress returns for the
+// current device.
+constexpr size_t kScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+
+struct ScratchSlot {
+  std::mutex mu;         // one search at a time per device
+  void *ptr = nullptr;   // device address of `scratch` on this device
+};
+
+ScratchSlot &scratch_slot(int dev) {
+  static ScratchSlot slots[kMaxDevices];
+  return slots[dev];
+}
+
+inline size_t round256(size_t b) { return ((b < 256 ? 256 : b) + 255) / 256 * 256; }
+
+}  // namespace
+
+size_t noalloc_scratch_bytes(const Graph *g) {
+  const int64_t n = g->n, d = g->d, nm = std::max(n, d);
+  size_t t = 0;
+  t += 2 * round256(size_t(g->nwords()) * 4);          // Vn, Fn
+  t += 3 * round256(size_t(g->dwords()) * 4);          // Vd, Fd, Cd
+  t += 2 * round256(size_t(n) * 4);                    // q0, q1
+  t += 2 * round256(size_t(d) * 4);                    // dlist, dcand
+  t += round256(size_t(nm) * 4);                       // dlen
+  t += round256(size_t(nm + 1) * 8);                   // dscan
+  t += 2 * round256(size_t(g->st.n_ndsrc) * 4);        // c0, c1
+  t += round256(2 * sizeof(LevelCtr));                 // ctr
+  t += round256(scan_tmp_bytes(nm));                   // scan_tmp
+  t += round256(sizeof(DevCtl));                       // dctl
+  t += round256(2 * dtiles_half(d));                   // dtiles
+  t += round256(kStatusSlots * sizeof(LevelStatus));   // status ring
+  return t;
+}
+
+void bfs_run_noalloc(const Graph *g, int32_t source, const dsbfs_run_opts *opts, int32_t *depth,
+                     int32_t *parent, dsbfs_run_stats *stats, hipStream_t s) {
+  if (!g) fail(DSBFS_ERR_INVALID_ARG, "graph must not be NULL");
+  if (opts && opts->profile)
+    fail(DSBFS_ERR_INVALID_ARG, "profile = 1 needs timing events; the allocation-free search "
+                                "does not create them");
+  const size_t need = noalloc_scratch_bytes(g);
+  if (need > kScratchBytes)
+    fail(DSBFS_ERR_RANGE, "graph needs " + std::to_string(need) +
+                              " bytes of search scratch; the allocation-free search holds " +
+                              std::to_string(kScratchBytes) + " (use a workspace)");
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) fail(DSBFS_ERR_INVALID_ARG, "device index out of range");
+  ScratchSlot &sl = scratch_slot(dev);
+  std::lock_guard<std::mutex> lock(sl.mu);
+  if (!sl.ptr) {
+    void *ptr = nullptr;
+    HIPCHK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr) fail(DSBFS_ERR_HIP, "hipGetSymbolAddress returned NULL for the search scratch");
+    sl.ptr = ptr;
+  }
+  char *base = static_cast<char *>(sl.ptr);
+  size_t off = 0;
+  auto carve = [&](DevBuf &b, size_t bytes) {
+    b.p = base + off;
+    b.bytes = round256(bytes);
+    b.al = nullptr;   // not owned: nothing is freed
+    b.s = s;
+    off += b.bytes;
+  };
+  const int64_t n = g->n, d = g->d, nm = std::max(n, d);
+  Workspace ws;
+  ws.g = g;
+  ws.borrowed = true;
+  carve(ws.Vn, size_t(g->nwords()) * 4);
+  carve(ws.Fn, size_t(g->nwords()) * 4);
+  carve(ws.Vd, size_t(g->dwords()) * 4);
+  carve(ws.Fd, size_t(g->dwords()) * 4);
+  carve(ws.Cd, size_t(g->dwords()) * 4);
+  carve(ws.q0, size_t(n) * 4);
+  carve(ws.q1, size_t(n) * 4);
+  carve(ws.dlist, size_t(d) * 4);
+  carve(ws.dcand, size_t(d) * 4);
+  carve(ws.dlen, size_t(nm) * 4);
+  carve(ws.dscan, size_t(nm + 1) * 8);
+  carve(ws.c0, size_t(g->st.n_ndsrc) * 4);
+  carve(ws.c1, size_t(g->st.n_ndsrc) * 4);
+  carve(ws.ctr, 2 * sizeof(LevelCtr));
+  carve(ws.scan_tmp, scan_tmp_bytes(nm));
+  carve(ws.dctl, sizeof(DevCtl));
+  carve(ws.dtiles, 2 * dtiles_half(d));
+  DevBuf ring;
+  carve(ring, kStatusSlots * sizeof(LevelStatus));
+  if (off != need) fail(DSBFS_ERR_HIP, "allocation-free scratch layout mismatch");
+  LevelCtr hctr[2];
+  ws.hctr = hctr;
+  ws.hstat = ring.p;
+  bfs_run(g, &ws, source, opts, depth, parent, stats, s);
+  // the next call reuses the array: this one's work must be complete
+  HIPCHK(hipStreamSynchronize(s));
 }
 
 }  // namespace dsbfs

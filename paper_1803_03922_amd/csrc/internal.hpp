@@ -132,6 +132,10 @@ struct Workspace {
   hipEvent_t lev_ev[3] = {};   // completion of recent levels
   // multi-source lane state
   void *ms_state = nullptr;           // launch state of multi-source BFS (msbfs.hip)
+  // borrowed: every buffer points into memory the workspace does not own (the
+  // allocation-free search's static scratch); hstat is then device memory,
+  // read by copies, and hctr a host buffer of the caller's frame
+  bool borrowed = false;
   ~Workspace();
 };
 

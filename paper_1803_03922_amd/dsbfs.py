@@ -133,6 +133,8 @@ dsbfs_workspace_create = _sig("dsbfs_workspace_create", i32, [vp, i32, ctypes.PO
 dsbfs_workspace_destroy = _sig("dsbfs_workspace_destroy", i32, [vp])
 dsbfs_bfs = _sig("dsbfs_bfs", i32, [vp, vp, i32, ctypes.POINTER(dsbfs_run_opts), vp, vp,
                                     ctypes.POINTER(dsbfs_run_stats), vp])
+dsbfs_bfs_noalloc = _sig("dsbfs_bfs_noalloc", i32, [vp, i32, ctypes.POINTER(dsbfs_run_opts), vp,
+                                                    vp, ctypes.POINTER(dsbfs_run_stats), vp])
 dsbfs_msbfs = _sig("dsbfs_msbfs", i32, [vp, vp, I32P, i32, ctypes.POINTER(dsbfs_ms_opts), vp, vp])
 dsbfs_msbfs_tune = _sig("dsbfs_msbfs_tune", i32, [vp, vp, I32P, i32, ctypes.c_char_p,
                                                   ctypes.POINTER(dsbfs_ms_opts), vp])
@@ -382,6 +384,17 @@ def bfs(graph: Graph, ws: Workspace, source: int, depth, parent=None, opts=None,
                                  for j, name in enumerate(KERNEL_NAMES)}
                                 for i in range(min(nl, capacity))],
             "kernels": kern}
+
+
+def bfs_noalloc(graph: Graph, source: int, depth, parent=None, opts=None,
+                stream: int | None = None):
+    """Runs dsbfs_bfs_noalloc (no workspace, no allocation) into device int32
+    tensors depth/parent."""
+    stream = current_stream() if stream is None else stream
+    if opts is None:
+        opts = run_opts(want_parent=parent is not None)
+    check(dsbfs_bfs_noalloc(graph.h, source, ctypes.byref(opts), _dev_ptr(depth),
+                            _dev_ptr(parent), None, stream), "dsbfs_bfs_noalloc")
 
 
 def msbfs(graph: Graph, ws: Workspace, sources, depth, opts: dsbfs_ms_opts | None = None,

@@ -19,7 +19,7 @@ def test_header_symbols_exported():
     from paper_1803_03922_amd import dsbfs
     lib = ctypes.CDLL(dsbfs.LIB_PATH)
     names = _declared()
-    assert len(names) == 19
+    assert len(names) == 20
     for name in names:
         assert hasattr(lib, name), name
     # and the binding wraps every one of them under the same name
@@ -61,6 +61,7 @@ def test_host_side_argument_errors():
     assert st == dsbfs.ERR_INVALID_ARG and b"threshold" in dsbfs.dsbfs_last_error()
     assert dsbfs.dsbfs_graph_create(None, None, 0, 1, None, None, None, None) == dsbfs.ERR_INVALID_ARG
     assert dsbfs.dsbfs_bfs(None, None, 0, None, None, None, None, None) == dsbfs.ERR_INVALID_ARG
+    assert dsbfs.dsbfs_bfs_noalloc(None, 0, None, None, None, None, None) == dsbfs.ERR_INVALID_ARG
     assert dsbfs.dsbfs_graph_destroy(None) == 0
     assert dsbfs.dsbfs_workspace_destroy(None) == 0
     assert dsbfs.dsbfs_server_destroy(None) == 0
