@@ -44,6 +44,19 @@ class Level(ctypes.Structure):
                 "frontier_delegate": int(self.frontier_delegate)}
 
 
+class Level4(ctypes.Structure):
+    _fields_ = [("q", ctypes.c_int64 * 4), ("s", ctypes.c_int64 * 4), ("U", ctypes.c_int64 * 4),
+                ("FV", ctypes.c_int64 * 4), ("BV", ctypes.c_double * 4),
+                ("dir", ctypes.c_int32 * 4), ("frontier_normal", ctypes.c_int64),
+                ("frontier_delegate", ctypes.c_int64)]
+
+    def as_dict(self):
+        return {"q": list(self.q), "s": list(self.s), "U": list(self.U), "FV": list(self.FV),
+                "BV": list(self.BV), "dir": list(self.dir),
+                "frontier_normal": int(self.frontier_normal),
+                "frontier_delegate": int(self.frontier_delegate)}
+
+
 class WorkLevel(ctypes.Structure):
     _fields_ = [("q", ctypes.c_int64 * 3), ("s", ctypes.c_int64 * 3), ("U", ctypes.c_int64 * 3),
                 ("FV", ctypes.c_int64 * 3), ("BV", ctypes.c_double * 3),
@@ -121,6 +134,11 @@ def _load():
         L.or_do_replay.restype = ctypes.c_int
         L.or_do_replay.argtypes = [vp, ctypes.c_int64, I32P, F64P, F64P, ctypes.c_int,
                                    ctypes.POINTER(Level), ctypes.c_int]
+        L.or_do_replay4.restype = ctypes.c_int
+        L.or_do_replay4.argtypes = [vp, ctypes.c_int64, I32P, F64P, F64P, ctypes.c_int,
+                                    ctypes.POINTER(Level4), ctypes.c_int]
+        L.or_pagerank.restype = ctypes.c_int
+        L.or_pagerank.argtypes = [vp, ctypes.c_double, ctypes.c_int32, F64P]
         L.or_work_prepare.restype = ctypes.c_int
         L.or_work_prepare.argtypes = [vp, ctypes.c_int64, ctypes.POINTER(vp)]
         L.or_work_free.argtypes = [vp]
@@ -242,6 +260,14 @@ class Graph:
         arrs["did"] = did
         return arrs
 
+    def pagerank(self, alpha: float, iterations: int) -> np.ndarray:
+        """FP64 power iteration from the uniform vector (or_pagerank)."""
+        r = np.empty(self.n, dtype=np.float64)
+        rc = _load().or_pagerank(self._h, alpha, iterations, r.ctypes.data_as(F64P))
+        if rc != 0:
+            raise ValueError(f"or_pagerank failed ({rc})")
+        return r
+
     def ms_work(self, sources, permille: int, want_depth: bool = False,
                 max_levels: int = 4096):
         """Work model of one bit-parallel multi-source batch (or_ms_work):
@@ -313,6 +339,23 @@ class WorkModel:
             raise ValueError("or_work_bytes failed")
         return ([out[i].as_dict() for i in range(nl)], dict(zip(WORK_VISITS, list(b))),
                 dict(zip(WORK_VISITS, list(la))))
+
+
+def _replay4(graph, TH, depth, factor0, factor1, bv_exact=False, max_levels=4096):
+    depth = _c32(depth)
+    out = (Level4 * max_levels)()
+    f0 = (ctypes.c_double * 4)(*factor0)
+    f1 = (ctypes.c_double * 4)(*factor1)
+    nl = _load().or_do_replay4(graph._h, TH, _i32(depth), f0, f1, int(bv_exact), out, max_levels)
+    if nl < 0:
+        raise ValueError("or_do_replay4 failed")
+    return [out[i].as_dict() for i in range(min(nl, max_levels))]
+
+
+Graph.do_replay4 = lambda self, TH, depth, factor0, factor1, bv_exact=False: \
+    _replay4(self, TH, depth, factor0, factor1, bv_exact)
+Graph.do_replay4.__doc__ = """Schedule with nn under the direction decision too (or_do_replay4):
+per level, q, s, U, FV, BV and dir for (dd, dn, nd, nn)."""
 
 
 def apsp(n: int, src, dst) -> np.ndarray:

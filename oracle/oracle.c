@@ -407,7 +407,7 @@ double or_bv_approx(int64_t U, int64_t q, int64_t s) {
   return (double)U * ((double)q + (double)s) / (double)q;
 }
 
-enum { K_DD = 0, K_DN = 1, K_ND = 2 };
+enum { K_DD = 0, K_DN = 1, K_ND = 2, K_NN = 3 };
 
 typedef struct {
   int64_t q[3], s[3], U[3], FV[3];   /* per DO kernel dd, dn, nd */
@@ -417,34 +417,48 @@ typedef struct {
   int64_t frontier_normal, frontier_delegate;
 } or_level_t;
 
+/* One level of the schedule with nn under the direction decision too. */
+typedef struct {
+  int64_t q[4], s[4], U[4], FV[4];   /* dd, dn, nd, nn */
+  double BV[4];
+  int32_t dir[4];
+  int64_t frontier_normal, frontier_delegate;
+} or_level4_t;
+
 /*
- * Replays the direction schedule of one search from the oracle's own depths.
- * At level L (frontier = vertices at depth L; visited = depth in [0, L]):
+ * Replays the direction schedule of one search from the oracle's own depths,
+ * for the kernels dd, dn, nd and nn. At level L (frontier = vertices at depth
+ * L; visited = depth in [0, L]):
  *   dd: FV = sum of dd degrees of frontier delegates, q = frontier delegates
  *       with a dd edge, U = ddsrc minus visited, s = |U|;
  *   dn: FV = sum of dn degrees of frontier delegates, q = frontier delegates
  *       with a dn edge, U = ndsrc minus visited, s = |dnsrc minus visited|;
  *   nd: FV = sum of nd degrees of frontier normals, q = frontier normals
- *       with an nd edge, U = dnsrc minus visited, s = |ndsrc minus visited|.
- * If q == 0 the kernel has nothing to do and keeps its direction; otherwise
- * forward switches to backward when FV > factor0*BV and backward switches to
- * forward when FV < factor1*BV. BV is |U|(q+s)/q (bv_exact == 0) or the sum
- * of or_bv_term over U with od = the degree in the reversed subgraph
- * (bv_exact == 1). Writes at most max_levels records; returns the number of
- * levels with a non-empty frontier, or a negative error.
+ *       with an nd edge, U = dnsrc minus visited, s = |ndsrc minus visited|;
+ *   nn: FV = sum of nn degrees of frontier normals, q = frontier normals
+ *       with an nn edge, U = normals with an nn edge minus visited, s = |U|
+ *       (nn is symmetric at one GPU, like dd).
+ * Section IV-B keeps nn forward (across GPUs nn is not symmetric); a factor0
+ * of +infinity for nn reproduces that. If q == 0 the kernel has nothing to
+ * do and keeps its direction; otherwise forward switches to backward when
+ * FV > factor0*BV and backward switches to forward when FV < factor1*BV. BV
+ * is |U|(q+s)/q (bv_exact == 0) or the sum of or_bv_term over U with od = the
+ * degree in the reversed subgraph (bv_exact == 1). Writes at most max_levels
+ * records; returns the number of levels with a non-empty frontier, or a
+ * negative error.
  */
-int or_do_replay(const or_graph *G, int64_t TH, const int32_t *depth, const double *factor0,
-                 const double *factor1, int bv_exact, or_level_t *out, int max_levels) {
+int or_do_replay4(const or_graph *G, int64_t TH, const int32_t *depth, const double *factor0,
+                  const double *factor1, int bv_exact, or_level4_t *out, int max_levels) {
   if (!G || !depth || !factor0 || !factor1) return OR_EINVAL;
   const int32_t n = G->n;
   int32_t maxd = -1;
   for (int32_t v = 0; v < n; ++v) if (depth[v] > maxd) maxd = depth[v];
-  int32_t dir[3] = {0, 0, 0};
+  int32_t dir[4] = {0, 0, 0, 0};
   int levels = maxd + 1;
   for (int32_t L = 0; L <= maxd; ++L) {
-    or_level_t r;
+    or_level4_t r;
     memset(&r, 0, sizeof(r));
-    double bvx[3] = {0, 0, 0};
+    double bvx[4] = {0, 0, 0, 0};
     for (int32_t v = 0; v < n; ++v) {
       int64_t dv = or_deg(G, v);
       int del = dv > TH;
@@ -470,15 +484,16 @@ int or_do_replay(const or_graph *G, int64_t TH, const int32_t *depth, const doub
         if (in_frontier) {
           r.frontier_normal++;
           r.FV[K_ND] += to_del;
-          r.FV_nn += to_norm;
+          r.FV[K_NN] += to_norm;
           if (to_del) r.q[K_ND]++;
-          if (to_norm) r.q_nn++;
+          if (to_norm) r.q[K_NN]++;
         }
         if (unvisited && to_del) { r.U[K_DN]++; r.s[K_ND]++; }
+        if (unvisited && to_norm) { r.U[K_NN]++; r.s[K_NN]++; }
       }
     }
     if (bv_exact) {
-      for (int k = 0; k < 3; ++k) {
+      for (int k = 0; k < 4; ++k) {
         if (r.q[k] == 0) continue;
         double a = (double)r.q[k] / ((double)r.q[k] + (double)r.s[k]);
         for (int32_t v = 0; v < n; ++v) {
@@ -493,10 +508,11 @@ int or_do_replay(const or_graph *G, int64_t TH, const int32_t *depth, const doub
           if (k == K_DD && del && to_del) bvx[k] += or_bv_term(a, to_del);
           if (k == K_DN && !del && to_del) bvx[k] += or_bv_term(a, to_del);
           if (k == K_ND && del && to_norm) bvx[k] += or_bv_term(a, to_norm);
+          if (k == K_NN && !del && to_norm) bvx[k] += or_bv_term(a, to_norm);
         }
       }
     }
-    for (int k = 0; k < 3; ++k) {
+    for (int k = 0; k < 4; ++k) {
       r.BV[k] = bv_exact ? bvx[k] : or_bv_approx(r.U[k], r.q[k], r.s[k]);
       if (r.q[k] > 0) {
         if (dir[k] == 0 && (double)r.FV[k] > factor0[k] * r.BV[k]) dir[k] = 1;
@@ -507,6 +523,36 @@ int or_do_replay(const or_graph *G, int64_t TH, const int32_t *depth, const doub
     if (out && L < max_levels) out[L] = r;
   }
   return levels;
+}
+
+/*
+ * The schedule of Section IV-B itself: dd, dn and nd under the decision, nn
+ * always forward (or_do_replay4 with nn's factor0 at +infinity).
+ */
+int or_do_replay(const or_graph *G, int64_t TH, const int32_t *depth, const double *factor0,
+                 const double *factor1, int bv_exact, or_level_t *out, int max_levels) {
+  if (!G || !depth || !factor0 || !factor1) return OR_EINVAL;
+  const double f0[4] = {factor0[0], factor0[1], factor0[2], INFINITY};
+  const double f1[4] = {factor1[0], factor1[1], factor1[2], 0.0};
+  or_level4_t *r4 = NULL;
+  if (out && max_levels > 0) {
+    r4 = (or_level4_t *)malloc((size_t)max_levels * sizeof(or_level4_t));
+    if (!r4) return OR_ENOMEM;
+  }
+  int nl = or_do_replay4(G, TH, depth, f0, f1, bv_exact, r4, out ? max_levels : 0);
+  for (int L = 0; r4 && L < nl && L < max_levels; ++L) {
+    or_level_t *o = &out[L];
+    for (int k = 0; k < 3; ++k) {
+      o->q[k] = r4[L].q[k]; o->s[k] = r4[L].s[k]; o->U[k] = r4[L].U[k];
+      o->FV[k] = r4[L].FV[k]; o->BV[k] = r4[L].BV[k]; o->dir[k] = r4[L].dir[k];
+    }
+    o->FV_nn = r4[L].FV[K_NN];
+    o->q_nn = r4[L].q[K_NN];
+    o->frontier_normal = r4[L].frontier_normal;
+    o->frontier_delegate = r4[L].frontier_delegate;
+  }
+  free(r4);
+  return nl;
 }
 
 /* ---------------------------------------------------------------------- */
@@ -1009,4 +1055,45 @@ int or_ms_work(const or_graph *G, const int32_t *sources, int32_t k, int32_t per
   *bytes = total;
   free(seen); free(F); free(nx); free(row); free(col);
   return L;
+}
+
+/* ---------------------------------------------------------------------- */
+/* PageRank on the simple symmetric graph (another algorithm on the        */
+/* degree-separated layout: delegates then hold multi-bit state, the       */
+/* paper's future work, Sections VI-D and VII).                            */
+/* ---------------------------------------------------------------------- */
+
+/*
+ * Power iteration in FP64, `iterations` steps from the uniform vector:
+ *   D_t = sum of r_t[u] over vertices of degree 0 (their rank is spread
+ *         uniformly);
+ *   r_{t+1}[v] = (1 - alpha) / n + alpha * (D_t / n + sum over neighbours u
+ *                of r_t[u] / deg(u)).
+ * The sum over a vertex's neighbours is taken in ascending neighbour order.
+ * rank receives r after the last step. Returns 0 or a negative error.
+ */
+int or_pagerank(const or_graph *G, double alpha, int32_t iterations, double *rank) {
+  if (!G || !rank || iterations < 0 || !(alpha >= 0.0 && alpha <= 1.0)) return OR_EINVAL;
+  const int32_t n = G->n;
+  double *r = (double *)malloc((size_t)n * sizeof(double));
+  double *c = (double *)malloc((size_t)n * sizeof(double));
+  if (!r || !c) { free(r); free(c); return OR_ENOMEM; }
+  for (int32_t v = 0; v < n; ++v) r[v] = 1.0 / (double)n;
+  for (int32_t t = 0; t < iterations; ++t) {
+    double D = 0.0;
+    for (int32_t u = 0; u < n; ++u) {
+      int64_t du = or_deg(G, u);
+      if (du == 0) { D += r[u]; c[u] = 0.0; }
+      else c[u] = r[u] / (double)du;
+    }
+    for (int32_t v = 0; v < n; ++v) {
+      double s = 0.0;
+      for (int64_t i = G->off[v]; i < G->off[v + 1]; ++i) s += c[G->col[i]];
+      r[v] = (1.0 - alpha) / (double)n + alpha * (D / (double)n + s);
+    }
+  }
+  memcpy(rank, r, (size_t)n * sizeof(double));
+  free(r);
+  free(c);
+  return OR_OK;
 }

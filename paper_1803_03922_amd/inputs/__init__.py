@@ -64,6 +64,9 @@ def _load():
         lib.inp_pick_sources.restype = ctypes.c_int64
         lib.inp_pick_sources.argtypes = [i32p, i32p, ctypes.c_int64, ctypes.c_int32,
                                          ctypes.c_int64, ctypes.c_uint64, i32p]
+        lib.inp_pick_sources_deg.restype = ctypes.c_int64
+        lib.inp_pick_sources_deg.argtypes = [i32p, ctypes.c_int32, ctypes.c_int64,
+                                             ctypes.c_uint64, i32p]
         _lib = lib
     return _lib
 
@@ -128,4 +131,15 @@ def pick_sources(src: np.ndarray, dst: np.ndarray, n: int, k: int, seed: int) ->
     got = lib.inp_pick_sources(_p(src), _p(dst), len(src), n, k, seed, _p(out))
     if got < 0:
         raise ValueError("inp_pick_sources: bad arguments")
+    return out[:got].copy()
+
+
+def pick_sources_deg(deg: np.ndarray, k: int, seed: int) -> np.ndarray:
+    """pick_sources from a degree array (same sources: eligible iff degree > 0)."""
+    lib = _load()
+    deg = np.ascontiguousarray(deg, dtype=np.int32)
+    out = np.empty(max(k, 1), dtype=np.int32)
+    got = lib.inp_pick_sources_deg(_p(deg), len(deg), k, seed, _p(out))
+    if got < 0:
+        raise ValueError("inp_pick_sources_deg: bad arguments")
     return out[:got].copy()

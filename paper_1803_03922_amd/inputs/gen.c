@@ -239,3 +239,29 @@ int64_t inp_pick_sources(const int32_t *src, const int32_t *dst, int64_t num_edg
   free(ok);
   return got;
 }
+
+/*
+ * The same picker from a degree array: vertex v is eligible iff deg[v] > 0,
+ * which for the simple symmetric graph of an edge list is exactly "endpoint
+ * of a pair u != v", so both pickers return the same sources.
+ */
+int64_t inp_pick_sources_deg(const int32_t *deg, int32_t n, int64_t k, uint64_t seed,
+                             int32_t *out) {
+  if (n < 1 || k < 0 || !deg || !out) return -1;
+  uint8_t *ok = (uint8_t *)calloc((size_t)n, 1);
+  if (!ok) return -1;
+  int64_t eligible = 0;
+  for (int32_t v = 0; v < n; ++v)
+    if (deg[v] > 0) { ok[v] = 1; ++eligible; }
+  int64_t want = k < eligible ? k : eligible, got = 0;
+  const uint64_t max_draws = 64ULL * (uint64_t)n + 4096ULL;
+  for (uint64_t j = 0; got < want && j < max_draws; ++j) {
+    uint64_t r = inp_splitmix64_at(seed, j) >> 32;
+    int32_t v = (int32_t)((r * (uint64_t)n) >> 32);
+    if (ok[v] == 1) { ok[v] = 2; out[got++] = v; }
+  }
+  for (int32_t v = 0; got < want && v < n; ++v)
+    if (ok[v] == 1) { ok[v] = 2; out[got++] = v; }
+  free(ok);
+  return got;
+}

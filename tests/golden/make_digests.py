@@ -19,6 +19,8 @@ self-loops and duplicates dropped):
   rmat22  RMAT scale 22, 64 sources picked with seed 1002
   rmat26  RMAT scale 26, 64 sources picked with seed 1003
   rmat24  RMAT scale 24, 1024 sources picked with seed 1004
+  rmat28  RMAT scale 28, 8 sources picked with seed 1005 (needs about 120 GB
+          of host memory; written on a host with that much)
   served  RMAT 18, 20, 22, 24 and Erdos-Renyi n = 2^22 with 8n pairs
           (seed 0x22), 64 sources each picked with seed 6000 + graph index
 """
@@ -39,6 +41,8 @@ sys.path.insert(0, ROOT)
 
 import oracle  # noqa: E402
 from paper_1803_03922_amd import inputs  # noqa: E402
+
+OUT = [HERE]   # directory the digest files are written to (--out)
 
 SERVED = (("rmat", 18), ("rmat", 20), ("rmat", 22), ("rmat", 24), ("er", 22))
 
@@ -90,7 +94,7 @@ def make_rmat(scale, k, seed, threads, name):
     deg = O.degrees()
     print(f"{name}: oracle CSR of scale {scale} in {time.time() - t0:.1f}s", flush=True)
     out = rows(O, deg, sources, threads)
-    write(os.path.join(HERE, f"depth_digests_{name}.txt"),
+    write(os.path.join(OUT[0], f"depth_digests_{name}.txt"),
           [f"Oracle depth rows: RMAT scale {scale}, edge factor 16, A,B,C,D = .57/.19/.19/.05,",
            f"graph seed 0x1803039220000000 + {scale}, relabelled, symmetrized, deduplicated;",
            f"n = {n}, m_dir = {O.m}; {len(sources)} sources from pick_sources(k={k}, "
@@ -112,7 +116,7 @@ def make_served(threads):
             out.append((gi,) + r)
         print(f"served graph {gi} ({kind} {scale}, m_dir {O.m}) done at {time.time() - t0:.1f}s",
               flush=True)
-    path = os.path.join(HERE, "depth_digests_served.txt")
+    path = os.path.join(OUT[0], "depth_digests_served.txt")
     tmp = path + ".tmp"
     with open(tmp, "w") as f:
         f.write("# Oracle depth rows of the served mix: graph 0..3 = RMAT scale 18, 20, 22, 24\n"
@@ -130,8 +134,11 @@ def make_served(threads):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--which", default="rmat22,served,rmat26,rmat24")
+    ap.add_argument("--out", default=HERE, help="directory of the digest files")
     ap.add_argument("--threads", type=int, default=8)
     a = ap.parse_args()
+    OUT[0] = a.out
+    os.makedirs(OUT[0], exist_ok=True)
     oracle.build(force=False)
     inputs.build(force=False)
     for w in a.which.split(","):
@@ -141,6 +148,8 @@ def main():
             make_rmat(26, 64, 1003, a.threads, "rmat26")
         elif w == "rmat24":
             make_rmat(24, 1024, 1004, a.threads, "rmat24")
+        elif w == "rmat28":
+            make_rmat(28, 8, 1005, a.threads, "rmat28")
         elif w == "served":
             make_served(a.threads)
         elif w:

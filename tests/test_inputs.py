@@ -58,3 +58,14 @@ def test_pick_sources(inputs_mod):
     ok[d[m]] = True
     assert ok[out].all()
     assert np.array_equal(out, inputs_mod.pick_sources(s, d, 1024, 64, seed=1001))
+
+
+def test_pick_sources_from_degrees_equals_edge_list_picker(inputs_mod, oracle_mod):
+    """The degree-array picker returns the edge-list picker's sources (a vertex
+    has degree > 0 in the simple graph iff it ends a non-loop pair)."""
+    for scale, k, seed in ((10, 64, 1), (12, 300, 7), (8, 10 ** 4, 3)):
+        n = 1 << scale
+        src, dst = inputs_mod.rmat_edges(scale)
+        deg = oracle_mod.Graph(src, dst, n).degrees()
+        np.testing.assert_array_equal(inputs_mod.pick_sources_deg(deg, k, seed),
+                                      inputs_mod.pick_sources(src, dst, n, k, seed))

@@ -621,3 +621,103 @@ def test_ms_work_bottom_up_path_hand_derived(oracle_mod):
     E = sum(e for e, _ in want)
     V = sum(v for _, v in want)
     assert b == 4 * n + 4 * E + 8 * E + 24 * V + 16 * V
+
+
+# ---------------------------------------------------------------------------
+# Direction decision with nn included (the DO-on-nn variant)
+# ---------------------------------------------------------------------------
+
+def test_do_replay4_path_nn_hand_derived(oracle_mod):
+    """Path 0-1-...-9 at TH = 5 (every vertex normal, every edge nn), from 0,
+    nn factors 0.02 forward->backward and 0.5 backward->forward.
+    Level 0: q=1, FV=1, U = the 9 unvisited vertices (all have nn edges),
+    s = 9: BV = 9*(1+9)/1 = 90; 1 > 0.02*90 = 1.8 is false: forward.
+    Level 1: frontier {1}: FV=2, U = s = 8: BV = 72; 2 > 1.44: backward.
+    Level 2: frontier {2}: FV=2, U = s = 7: BV = 56; 2 < 0.5*56: forward
+    again. The other kernels have no frontier (q = 0) and stay forward."""
+    n, src, dst, _ = path(10)
+    G = _graph(oracle_mod, n, src, dst)
+    depth, _ = G.bfs(0)
+    inf = float("inf")
+    L = G.do_replay4(5, depth, (inf, inf, inf, 0.02), (0.0, 0.0, 0.0, 0.5))
+    assert len(L) == 10
+    assert [x["q"][3] for x in L] == [1] * 10
+    assert [x["FV"][3] for x in L] == [1] + [2] * 8 + [1]
+    assert [x["U"][3] for x in L[:3]] == [9, 8, 7] and [x["s"][3] for x in L[:3]] == [9, 8, 7]
+    assert [x["BV"][3] for x in L[:3]] == [pytest.approx(90.0), pytest.approx(72.0),
+                                             pytest.approx(56.0)]
+    assert [x["dir"][3] for x in L[:3]] == [0, 1, 0]
+    assert all(x["q"][:3] == [0, 0, 0] and x["dir"][:3] == [0, 0, 0] for x in L)
+
+
+def test_do_replay4_reduces_to_replay_when_nn_forward(oracle_mod, inputs_mod):
+    """With nn's factor0 at +infinity the four-kernel schedule is the
+    three-kernel one of Section IV-B (nn columns: FV_nn and q_nn)."""
+    src, dst = inputs_mod.rmat_edges(11)
+    n = 1 << 11
+    G = _graph(oracle_mod, n, src, dst)
+    for s in inputs_mod.pick_sources(src, dst, n, 3, seed=17).tolist():
+        depth, _ = G.bfs(s)
+        for f0 in ((0.5, 0.05, 1e-7), (1e-3, 1e-3, 1e-3)):
+            a = G.do_replay(16, depth, f0, (0.0, 0.1, 0.0))
+            b = G.do_replay4(16, depth, f0 + (float("inf"),), (0.0, 0.1, 0.0, 0.0))
+            assert len(a) == len(b)
+            for x, y in zip(a, b):
+                for k in ("q", "s", "U", "FV", "BV", "dir"):
+                    assert x[k] == y[k][:3]
+                assert (x["FV_nn"], x["q_nn"]) == (y["FV"][3], y["q"][3])
+                assert y["dir"][3] == 0
+
+
+# ---------------------------------------------------------------------------
+# PageRank
+# ---------------------------------------------------------------------------
+
+def test_pagerank_regular_graphs_stay_uniform(oracle_mod):
+    """On a regular graph every vertex receives exactly what it gives: the
+    uniform vector is fixed at every step."""
+    from closed_forms import hypercube
+    for n, src, dst, _ in (cycle(17), complete(9), hypercube(6)):
+        G = _graph(oracle_mod, n, src, dst)
+        for it in (1, 5, 40):
+            r = G.pagerank(0.85, it)
+            np.testing.assert_allclose(r, 1.0 / n, rtol=1e-13, atol=0)
+
+
+def test_pagerank_star_closed_form(oracle_mod):
+    """Star, hub 0 with k leaves (n = k + 1), no dangling vertex. The fixed
+    point solves h = (1-a)/n + a k l and l = (1-a)/n + a h / k, so
+    h = (1 + a k) / (n (1 + a)) and l = (1-a)/n + a h / k; the iteration
+    contracts by a per step."""
+    a = 0.85
+    for k in (1, 5, 40):
+        n, src, dst, _ = star(k)
+        r = _graph(oracle_mod, n, src, dst).pagerank(a, 400)
+        h = (1 + a * k) / (n * (1 + a))
+        l = (1 - a) / n + a * h / k
+        np.testing.assert_allclose(r[0], h, rtol=1e-12)
+        np.testing.assert_allclose(r[1:], l, rtol=1e-12)
+
+
+@pytest.mark.parametrize("n,k,seed", [(40, 60, 1), (90, 200, 2), (120, 90, 3)])
+def test_pagerank_matches_dense_solve(oracle_mod, n, k, seed):
+    """Random graphs with isolated vertices (dangling): the iteration's limit
+    equals the solution of (I - a M) r = (1 - a)/n, M[v, u] = 1/deg(u) for
+    each edge {u, v} and 1/n in the column of a degree-0 vertex, solved by
+    numpy's dense LU; every step keeps the ranks summing to 1."""
+    rng = np.random.default_rng(seed)
+    src, dst = _random_pairs(rng, n, k)
+    G = _graph(oracle_mod, n, src, dst)
+    a = 0.85
+    deg = G.degrees()
+    M = np.zeros((n, n))
+    off, col = G.off, G.col
+    for u in range(n):
+        if deg[u] == 0:
+            M[:, u] = 1.0 / n
+        for i in range(off[u], off[u + 1]):
+            M[col[i], u] = 1.0 / deg[u]
+    want = np.linalg.solve(np.eye(n) - a * M, np.full(n, (1 - a) / n))
+    np.testing.assert_allclose(G.pagerank(a, 400), want, rtol=1e-11, atol=1e-15)
+    for it in (1, 2, 7):
+        assert abs(G.pagerank(a, it).sum() - 1.0) < 1e-13
