@@ -86,6 +86,7 @@ typedef struct dsbfs_graph_stats {
   int64_t bytes_plain;  /* device bytes of the plain CSR (0 if not kept) */
   int32_t threshold;
   int32_t reserved;
+  int64_t n_nnsrc;      /* normal vertices with a normal neighbour */
 } dsbfs_graph_stats;
 
 /*
@@ -117,6 +118,14 @@ typedef struct dsbfs_run_opts {
   int32_t profile;      /* 1: time every kernel launch with HIP events on the
                            call's stream and report per-kernel totals in stats */
   uint64_t forced_seed; /* seed of schedule 3 */
+  int32_t nn_do;        /* 1: nn under the direction decision too, with its own
+                           bottom-up visit (a variant: Section IV-B keeps nn
+                           forward because across GPUs nn is not symmetric; at
+                           one GPU it is). The normal previsit then only counts
+                           and a separate pass expands nn forward. Default 0. */
+  int32_t reserved;
+  double factor0_nn;    /* nn's forward->backward factor when nn_do (default 1e-3) */
+  double factor1_nn;    /* nn's backward->forward factor when nn_do (default 0) */
 } dsbfs_run_opts;
 
 /* Fills *o with the defaults listed above (mode 1, parents on). */
@@ -133,18 +142,22 @@ typedef struct dsbfs_level_stats {
   double BV[3];      /* backward workload |U|(q+s)/q */
   int32_t dir[3];    /* direction taken: 0 forward, 1 backward */
   int32_t reserved;
-  int64_t FV_nn, q_nn;               /* nn is always forward */
+  int64_t FV_nn, q_nn;               /* nn's workload and frontier */
   int64_t frontier_normal, frontier_delegate;
-  double kernel_ms[9];  /* profile = 1 only: HIP-event time of each kernel of
+  double kernel_ms[11]; /* profile = 1 only: HIP-event time of each kernel of
                            this level (indexed DSBFS_K_*), 0 when it had no
                            work; all 0 without profiling */
+  int64_t U_nn, s_nn;   /* nn_do: unvisited normals with an nn edge (both) */
+  double BV_nn;         /* nn_do: nn's backward workload */
+  int32_t dir_nn;       /* direction nn took (always 0 without nn_do) */
+  int32_t reserved2;
 } dsbfs_level_stats;
 
 /* Kernels of a search, for per-kernel profiles. */
 enum {
   DSBFS_K_INIT = 0,        /* depth/parent fill and bitmap clear */
   DSBFS_K_PREV_NORMAL = 1, /* previsit of the normal queue fused with its
-                              top-down nn visit (nn is always top-down) */
+                              top-down nn visit (with nn_do: previsit only) */
   DSBFS_K_PREV_DELEG = 2,  /* previsit of the delegate frontier mask */
   DSBFS_K_TD_NORMAL = 3,   /* top-down nd from the normal queue */
   DSBFS_K_TD_DELEG = 4,    /* top-down dd and/or dn from the delegate frontier */
@@ -152,7 +165,9 @@ enum {
   DSBFS_K_BU_DELEG = 6,    /* bottom-up dd and/or nd over unvisited delegates */
   DSBFS_K_CLOSE = 7,       /* level close */
   DSBFS_K_PLAIN = 8,       /* mode 0: length, scan and expansion of one level */
-  DSBFS_NUM_KERNELS = 9
+  DSBFS_K_TD_NN = 9,       /* nn_do: top-down nn from the normal queue */
+  DSBFS_K_BU_NN = 10,      /* nn_do: bottom-up nn over normals with an nn edge */
+  DSBFS_NUM_KERNELS = 11
 };
 
 /* Per-kernel totals of one search. bytes is the algorithmic HBM traffic of the
@@ -219,7 +234,11 @@ dsbfs_status dsbfs_graph_stats_get(const dsbfs_graph *g, dsbfs_graph_stats *out)
  * i of 14 belong to vertex ndsrc[i]; the bottom-up dn kernel probes 14 and
  * walks 12/13 only on a miss; 15 the first entry of each delegate's dd part
  * as a pair (delegate ID, its vertex), (-1, -1) if the part is empty,
- * int32[2 d], probed first by the bottom-up dd kernel.
+ * int32[2 d], probed first by the bottom-up dd kernel; 16 the part lengths
+ * of every normal row, uint16[n]: nn length | nd length << 8, 0xFFFF when
+ * either is 255 or more, 0 for a delegate (read by the normal previsit);
+ * 17 the normal vertices with a normal neighbour, ascending, int32[n_nnsrc]
+ * (candidates of the bottom-up nn visit when nn_do is set).
  * Row offsets are packed: bits 0..39 = start of the row, bits 40..63 = length
  * of its first part (nn for normal rows, dd for delegate rows); the row ends
  * at the start of the next row. Normal row v holds nn neighbours (vertex IDs)
@@ -233,6 +252,50 @@ dsbfs_status dsbfs_graph_stats_get(const dsbfs_graph *g, dsbfs_graph_stats *out)
  */
 dsbfs_status dsbfs_graph_export(const dsbfs_graph *g, int32_t which, void *host_out,
                                 int64_t capacity_bytes, int64_t *bytes);
+
+/*
+ * RMAT workload on the device (Section VI-A "Reporting": the graphs are
+ * generated on the GPUs, vertex IDs relabelled by a deterministic hash).
+ * Edge e takes one quadrant per level i < scale from the high 32 bits of the
+ * (64 e + i)-th output of the SplitMix64 stream with initial state `seed`
+ * (the stream's k-th output is the published finaliser of
+ * seed + (k + 1) * 0x9E3779B97F4A7C15), against thresholds floor(p * 2^32)
+ * of a, a + b, a + b + c (row bit set from a + b on, column bit in [a, a + b)
+ * and from a + b + c on); with `permute`, both endpoints then pass through a
+ * bijection of scale-bit integers: four rounds of x = x * mul_r, x ^= x >> (scale / 2),
+ * x = x + add_r (mod 2^scale), with mul_r = (output 2r | 1) and add_r = output
+ * 2r + 1 of the stream seeded with perm_seed, masked to scale bits. The
+ * same definition as the host generator of the test inputs; results are
+ * equal bit for bit.
+ */
+typedef struct dsbfs_rmat_spec {
+  int32_t scale;        /* 2^scale vertices, 1..31 */
+  int32_t permute;      /* 1: relabel vertex IDs through the seeded bijection */
+  int64_t num_edges;    /* generated pairs (the paper's edge factor 16: 16 * 2^scale) */
+  double a, b, c;       /* quadrant probabilities; d = 1 - a - b - c */
+  uint64_t seed;        /* graph seed */
+  uint64_t perm_seed;   /* relabelling seed */
+} dsbfs_rmat_spec;
+
+/*
+ * Writes the RMAT edge list of *spec to device arrays src, dst
+ * (int32[num_edges] each, caller-owned), ordered on `stream` (not
+ * synchronized). Errors: INVALID_ARG (bad spec, NULL arrays), HIP.
+ */
+dsbfs_status dsbfs_rmat_generate(const dsbfs_rmat_spec *spec, int32_t *src, int32_t *dst,
+                                 void *stream);
+
+/*
+ * dsbfs_graph_create for the RMAT graph of *spec (n = 2^scale) without an
+ * edge list anywhere: the generator writes both directions of every
+ * non-loop edge straight into the builder's sort keys on the device, so the
+ * largest graph that fits is bounded by device memory alone (two 8-byte keys
+ * per directed edge during the sort). Same layout, options, ownership and
+ * errors as dsbfs_graph_create.
+ */
+dsbfs_status dsbfs_graph_create_rmat(const dsbfs_rmat_spec *spec, const dsbfs_build_opts *opts,
+                                     const dsbfs_allocator *alloc, void *stream,
+                                     dsbfs_graph **out);
 
 /* Frees the graph's device memory. NULL is accepted. */
 dsbfs_status dsbfs_graph_destroy(dsbfs_graph *g);
@@ -283,6 +346,25 @@ dsbfs_status dsbfs_bfs_noalloc(const dsbfs_graph *g, int32_t source, const dsbfs
                                int32_t *depth, int32_t *parent, dsbfs_run_stats *stats,
                                void *stream);
 
+/*
+ * PageRank on the degree-separated layout (another primitive on degree-
+ * separated graphs with multi-bit delegate state, the paper's future work,
+ * Sections VI-D and VII): FP64 power iteration from the uniform vector,
+ *   r'[v] = (1 - alpha)/n + alpha * (D/n + sum over neighbours u of r[u]/deg(u)),
+ * D = rank held by degree-0 vertices. Delegates keep their contributions in a
+ * compact array by delegate ID, normal vertices by vertex ID. Runs
+ * max_iterations steps, or stops after the first step whose L1 change is
+ * below tolerance (tolerance > 0: one host synchronization per step). rank:
+ * device double[n], caller-owned. *iterations_done and *last_delta (host,
+ * either may be NULL) receive the steps run and the last L1 change. Scratch
+ * (3 n + d doubles) comes from the graph's allocator for the call.
+ * Synchronizes the stream. Errors: INVALID_ARG (alpha outside [0, 1],
+ * negative max_iterations, NULL rank), OUT_OF_MEMORY, HIP.
+ */
+dsbfs_status dsbfs_pagerank(const dsbfs_graph *g, double alpha, int32_t max_iterations,
+                            double tolerance, double *rank, int32_t *iterations_done,
+                            double *last_delta, void *stream);
+
 /* Tile and schedule parameters of multi-source BFS (chosen by the tuner). */
 typedef struct dsbfs_ms_opts {
   int32_t block;          /* threads per workgroup: 64, 128, 256, 512 or 1024 */
@@ -322,7 +404,18 @@ dsbfs_status dsbfs_msbfs_tune(const dsbfs_graph *g, dsbfs_workspace *ws, const i
 typedef struct dsbfs_query_stats {
   int64_t arrival_ns, admit_ns, start_ns, done_ns;
   int32_t graph_id, source, levels, batched; /* batched: 1 = ran as a lane */
+  int32_t waited_budget;  /* 1: admission waited at least once for HBM budget */
+  int32_t loaded_graph;   /* 1: its graph was loaded from host memory for it */
 } dsbfs_query_stats;
+
+/* Server totals (dsbfs_server_stats_get). */
+typedef struct dsbfs_server_stats {
+  int64_t budget_bytes, used_bytes;   /* budget and what is charged now */
+  int64_t graphs, resident_graphs;    /* added / on the device now */
+  int64_t loads, evictions;           /* graph moves host -> device, device -> host */
+  int64_t budget_waits;               /* queries whose admission waited for budget */
+  int64_t queries_done;
+} dsbfs_server_stats;
 
 /* Server configuration. */
 typedef struct dsbfs_server_opts {
@@ -335,18 +428,32 @@ typedef struct dsbfs_server_opts {
                                  cheaper than one batch (measured per graph),
                                  else batches as in 1 */
   dsbfs_ms_opts ms;        /* kernel parameters of the batched path */
+  int32_t join_levels;     /* batched: waiting queries join a running batch only
+                              during its first join_levels levels (<= 0: 2); a
+                              large value admits at every level boundary */
+  int32_t reserved;
 } dsbfs_server_opts;
 
 /*
  * Query server (continuous batching). create starts one scheduler thread on
- * the current device; add_graph moves a graph under the server (admitted only
- * if it fits the budget: else BUDGET and the caller keeps it); submit queues a
- * single-source query (arrival_ns: caller's steady-clock timestamp, 0 = now)
- * and returns a ticket; wait blocks until that query's depth array is on the
- * device (timeout_ns < 0: forever; NOT_READY on timeout) and returns its
- * device pointer (int32[n_graph], owned by the server until release);
- * release returns the result buffer to the budget. Results stay device
- * resident. destroy stops the thread and frees everything.
+ * the current device; result rows come from `alloc` when given (called from
+ * the scheduler thread, so it must be callable from any thread), else from
+ * hipMalloc. add_graph moves a graph under the server: BUDGET (and the caller
+ * keeps the graph) if the graph plus one result row can never fit; a graph
+ * that does not fit now is kept in host memory until a query needs it, and
+ * idle graphs (no query waiting or running) are evicted to host memory, least
+ * recently used first, to make room (Section III-C's per-GPU memory bound
+ * applied to several resident graphs). submit queues a single-source query
+ * (arrival_ns: caller's steady-clock timestamp, 0 = now) and returns a
+ * ticket; wait blocks until that query's depth array is on the device
+ * (timeout_ns < 0: forever; NOT_READY on timeout) and returns its device
+ * pointer (int32[n_graph], owned by the server until release); release
+ * returns the result buffer to the budget. Results stay device resident.
+ * stats_get reports the budget, residency and admission totals. destroy
+ * stops the thread and frees everything. Every call may come from any
+ * thread at any time, including add_graph while queries run. Rows count
+ * against the budget until released: a client that holds results while it
+ * waits for a query whose graph needs that room waits for ever.
  */
 dsbfs_status dsbfs_server_create(const dsbfs_server_opts *opts, const dsbfs_allocator *alloc,
                                  dsbfs_server **out);
@@ -356,6 +463,7 @@ dsbfs_status dsbfs_server_submit(dsbfs_server *s, int32_t graph_id, int32_t sour
 dsbfs_status dsbfs_server_wait(dsbfs_server *s, int64_t ticket, int64_t timeout_ns,
                                const int32_t **depth_dev, dsbfs_query_stats *stats);
 dsbfs_status dsbfs_server_release(dsbfs_server *s, int64_t ticket);
+dsbfs_status dsbfs_server_stats_get(dsbfs_server *s, dsbfs_server_stats *out);
 dsbfs_status dsbfs_server_destroy(dsbfs_server *s);
 
 /* Host steady-clock now, in nanoseconds (the server's time base). */

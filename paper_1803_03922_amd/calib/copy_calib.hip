@@ -1,7 +1,14 @@
-// Plain copy kernel of known size: 1 GiB read and 1 GiB written per
-// dispatch. Profiling it with the FETCH_SIZE and WRITE_SIZE counters gives
-// the factor that turns those counters into bytes on this device; the same
-// factor then scales the counters of the search kernels.
+// Kernels of known traffic for calibrating the HBM counters (FETCH_SIZE,
+// WRITE_SIZE) on this device:
+//   copy_calib_kernel:    1 GiB read and 1 GiB written per dispatch, streaming;
+//   gather_calib_kernel:  2^24 reads of 4 bytes, each in its own 128-byte line
+//                         of a 4 GiB array (lines visited in a scattered
+//                         order), plus 4 bytes written per thread;
+//   scatter_calib_kernel: 2^24 writes of 4 bytes, each in its own 128-byte
+//                         line, scattered the same way.
+// Profiling each with one counter per run gives the factor that turns the
+// counters into bytes for streaming traffic, and what one scattered 4-byte
+// access costs in counted traffic.
 #include <hip/hip_runtime.h>
 #include <cstdio>
 
@@ -15,6 +22,26 @@ __global__ void fill_calib_kernel(int4 *a, size_t n, int v) {
   for (size_t i = blockIdx.x * size_t(blockDim.x) + threadIdx.x; i < n;
        i += size_t(gridDim.x) * blockDim.x)
     a[i] = make_int4(v, v, v, v);
+}
+
+// Line of access i: an odd multiplier mod 2^lines_log2 is a bijection, so the
+// 2^24 accesses of a dispatch touch 2^24 distinct lines.
+__device__ __forceinline__ size_t scattered_line(size_t i, int lines_log2) {
+  return (i * 0x9E3779B1ull) & ((size_t(1) << lines_log2) - 1);
+}
+
+__global__ void gather_calib_kernel(const int *a, int *out, size_t reads, int lines_log2) {
+  int s = 0;
+  for (size_t i = blockIdx.x * size_t(blockDim.x) + threadIdx.x; i < reads;
+       i += size_t(gridDim.x) * blockDim.x)
+    s += a[scattered_line(i, lines_log2) * 32];   // 32 ints = one 128-byte line
+  out[blockIdx.x * size_t(blockDim.x) + threadIdx.x] = s;
+}
+
+__global__ void scatter_calib_kernel(int *a, size_t writes, int lines_log2, int v) {
+  for (size_t i = blockIdx.x * size_t(blockDim.x) + threadIdx.x; i < writes;
+       i += size_t(gridDim.x) * blockDim.x)
+    a[scattered_line(i, lines_log2) * 32] = v;
 }
 
 static int check(hipError_t e, const char *what) {
@@ -41,5 +68,34 @@ int main() {
   std::printf("copy_calib: 3 dispatches of %zu bytes read + %zu bytes written\n", bytes, bytes);
   (void)hipFree(a);
   (void)hipFree(b);
+
+  // scattered accesses over a 4 GiB array: 2^25 lines of 128 bytes
+  const int lines_log2 = 25;
+  const size_t big = (size_t(1) << lines_log2) * 128;
+  const size_t accesses = size_t(1) << 24;
+  const int grid = 4096, block = 256;
+  int *g = nullptr, *out = nullptr;
+  if (check(hipMalloc(&g, big), "hipMalloc") ||
+      check(hipMalloc(&out, size_t(grid) * block * sizeof(int)), "hipMalloc"))
+    return 1;
+  hipLaunchKernelGGL(fill_calib_kernel, dim3(4096), dim3(256), 0, 0, reinterpret_cast<int4 *>(g),
+                     big / sizeof(int4), 2);
+  if (check(hipGetLastError(), "fill")) return 1;
+  for (int r = 0; r < 3; ++r) {
+    hipLaunchKernelGGL(gather_calib_kernel, dim3(grid), dim3(block), 0, 0, g, out, accesses,
+                       lines_log2);
+    if (check(hipGetLastError(), "gather")) return 1;
+  }
+  for (int r = 0; r < 3; ++r) {
+    hipLaunchKernelGGL(scatter_calib_kernel, dim3(grid), dim3(block), 0, 0, g, accesses,
+                       lines_log2, r);
+    if (check(hipGetLastError(), "scatter")) return 1;
+  }
+  if (check(hipDeviceSynchronize(), "sync")) return 1;
+  std::printf("gather_calib: 3 dispatches of %zu scattered 4-byte reads (+ %zu bytes written)\n",
+              accesses, size_t(grid) * block * sizeof(int));
+  std::printf("scatter_calib: 3 dispatches of %zu scattered 4-byte writes\n", accesses);
+  (void)hipFree(g);
+  (void)hipFree(out);
   return 0;
 }

@@ -46,7 +46,11 @@ void Alloc::put(void *p, hipStream_t s) const {
 
 // defined in the other translation units
 Graph *graph_create(const int32_t *src, const int32_t *dst, int64_t g, int32_t n,
-                    const dsbfs_build_opts *opts, const dsbfs_allocator *alloc, hipStream_t s);
+                    const dsbfs_build_opts *opts, const dsbfs_allocator *alloc, hipStream_t s,
+                    const dsbfs_rmat_spec *rmat);
+void rmat_generate(const dsbfs_rmat_spec *sp, int32_t *src, int32_t *dst, hipStream_t s);
+void pagerank_run(const Graph *g, double alpha, int32_t max_iter, double tol, double *rank,
+                  int32_t *iters_done, double *last_delta, hipStream_t s);
 void graph_destroy(Graph *G);
 Workspace *workspace_create(const Graph *g, int32_t max_lanes);
 void workspace_destroy(Workspace *ws);
@@ -67,6 +71,7 @@ void server_submit(Server *S, int32_t gid, int32_t source, int64_t arrival, int6
 dsbfs_status server_wait(Server *S, int64_t ticket, int64_t timeout_ns, const int32_t **depth,
                          dsbfs_query_stats *st);
 void server_release(Server *S, int64_t ticket);
+void server_stats(Server *S, dsbfs_server_stats *st);
 void server_destroy(Server *S);
 int64_t now_ns();
 
@@ -120,9 +125,26 @@ dsbfs_status dsbfs_graph_create(const int32_t *src, const int32_t *dst, int64_t 
     if (!out) fail(DSBFS_ERR_INVALID_ARG, "out must not be NULL");
     *out = nullptr;
     Graph *g = graph_create(src, dst, num_edges, num_vertices, opts, alloc,
-                            static_cast<hipStream_t>(stream));
+                            static_cast<hipStream_t>(stream), nullptr);
     *out = new dsbfs_graph{g};
   });
+}
+
+dsbfs_status dsbfs_graph_create_rmat(const dsbfs_rmat_spec *spec, const dsbfs_build_opts *opts,
+                                     const dsbfs_allocator *alloc, void *stream,
+                                     dsbfs_graph **out) {
+  return guard([&] {
+    if (!out || !spec) fail(DSBFS_ERR_INVALID_ARG, "spec and out must not be NULL");
+    *out = nullptr;
+    Graph *g = graph_create(nullptr, nullptr, 0, 0, opts, alloc,
+                            static_cast<hipStream_t>(stream), spec);
+    *out = new dsbfs_graph{g};
+  });
+}
+
+dsbfs_status dsbfs_rmat_generate(const dsbfs_rmat_spec *spec, int32_t *src, int32_t *dst,
+                                 void *stream) {
+  return guard([&] { rmat_generate(spec, src, dst, static_cast<hipStream_t>(stream)); });
 }
 
 dsbfs_status dsbfs_graph_stats_get(const dsbfs_graph *g, dsbfs_graph_stats *out) {
@@ -184,6 +206,16 @@ dsbfs_status dsbfs_bfs_noalloc(const dsbfs_graph *g, int32_t source, const dsbfs
   });
 }
 
+dsbfs_status dsbfs_pagerank(const dsbfs_graph *g, double alpha, int32_t max_iterations,
+                            double tolerance, double *rank, int32_t *iterations_done,
+                            double *last_delta, void *stream) {
+  return guard([&] {
+    if (!g) fail(DSBFS_ERR_INVALID_ARG, "graph must not be NULL");
+    pagerank_run(g->g, alpha, max_iterations, tolerance, rank, iterations_done, last_delta,
+                 static_cast<hipStream_t>(stream));
+  });
+}
+
 dsbfs_status dsbfs_msbfs(const dsbfs_graph *g, dsbfs_workspace *ws, const int32_t *sources,
                          int32_t k, const dsbfs_ms_opts *opts, int32_t *depth, void *stream) {
   return guard([&] {
@@ -242,6 +274,13 @@ dsbfs_status dsbfs_server_release(dsbfs_server *s, int64_t ticket) {
   return guard([&] {
     if (!s) fail(DSBFS_ERR_INVALID_ARG, "server must not be NULL");
     server_release(s->s, ticket);
+  });
+}
+
+dsbfs_status dsbfs_server_stats_get(dsbfs_server *s, dsbfs_server_stats *out) {
+  return guard([&] {
+    if (!s || !out) fail(DSBFS_ERR_INVALID_ARG, "server and out must not be NULL");
+    server_stats(s->s, out);
   });
 }
 

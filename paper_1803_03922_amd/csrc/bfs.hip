@@ -57,20 +57,23 @@ constexpr int kNW = kBS / kWave;
 // when it has no work, so the levels run back to back without a host round
 // trip (the host only learns, a level or two later, that the search ended).
 struct DevCtl {
-  double f0[3], f1[3];     // direction-switch factors (dd, dn, nd)
+  double f0[4], f1[4];     // direction-switch factors (dd, dn, nd, nn)
   uint64_t forced_seed;
   int32_t forced;
   int32_t done;            // the frontier is empty: every later kernel returns
   int32_t level;           // level in progress
   int32_t level1;          // depth this level writes (level + 1)
-  int32_t dir[3];          // current direction per kernel (0 forward, 1 backward)
+  int32_t dir[4];          // current direction per kernel (0 forward, 1 backward)
+  int32_t nn_do;           // nn under the direction decision (else always forward)
+  int32_t nn_td, nn_bu;    // plan of this level for nn (nn_do only)
   int32_t cand_state;      // -1: the next bottom-up normal pass scans the whole nd source list
   int32_t nc_pending;      // the previous pass compacted a candidate list of unknown length
   int32_t mark_fn;         // this level marks the normal frontier bitmap
   int32_t nd_td, dd_td, dn_td, dn_bu, dd_bu, nd_bu;  // plan of this level
   int32_t bulk_fn, clear_fn, cin_sel, cout_sel;
   int64_t nwords;
-  int64_t rem[3];          // unvisited: delegates with a dd edge, with a dn edge, nd-list normals
+  int64_t rem[4];          // unvisited: delegates with a dd edge, with a dn edge, nd-list
+                           // normals, normals with an nn edge
   int64_t nc;              // candidates of the next bottom-up normal pass
   int64_t qn, fdn;         // frontier sizes of this level
   unsigned long long deg_sum;                         // sum of frontier degrees so far
@@ -81,10 +84,20 @@ struct DevCtl {
 // memory (a ring of 4 slots, slot = level & 3).
 struct LevelStatus {
   int32_t done, level;
-  int32_t plan[8];  // nd_td, dd_td, dn_td, dn_bu (runs), dd_bu, nd_bu, bulk_fn, mark_fn
+  int32_t plan[10];  // nd_td, dd_td, dn_td, dn_bu (runs), dd_bu, nd_bu, bulk_fn, mark_fn,
+                     // nn_td (separate pass), nn_bu
   dsbfs_level_stats rec;
 };
 constexpr int kStatusSlots = 4;
+
+// Whether this level marks the normal frontier bitmap Fn. Fn is read only by
+// a bottom-up nd visit (which needs an unvisited delegate with a dn edge left
+// after this level's frontier: rem[1] - q_dn > 0) and, with nn_do, by a
+// bottom-up nn visit. The delegate previsit runs first, so q_dn is known to
+// the normal previsit and to the decision alike.
+__device__ __forceinline__ int level_marks_fn(const DevCtl *c, int64_t q_dn) {
+  return c->mark_fn && (c->rem[1] - q_dn > 0 || (c->nn_do && c->rem[3] > 0));
+}
 
 // Bytes of one of the two tile arrays of the delegate-frontier prefix sum.
 inline size_t dtiles_half(int64_t d) {
@@ -179,6 +192,11 @@ __global__ void __launch_bounds__(kBS) k_prev_deleg(const uint32_t *Fd, int32_t 
                                                     const uint64_t *doff, int32_t *dlist,
                                                     LevelCtr *cur, const DevCtl *c) {
   if (c->done) return;
+  // The frontier list feeds only the forward dd/dn visit. Under the
+  // heuristic schedule, once dd and dn both go backward with no switch back
+  // (factor1 = 0) none can follow: the list is not written.
+  const bool want_list = !(c->forced == 0 && c->dir[0] == 1 && c->dir[1] == 1 &&
+                           c->f1[0] == 0.0 && c->f1[1] == 0.0);
   __shared__ int shf[kNW];
   __shared__ unsigned long long base;
   __shared__ unsigned long long sh[4 * kNW];
@@ -196,7 +214,8 @@ __global__ void __launch_bounds__(kBS) k_prev_deleg(const uint32_t *Fd, int32_t 
       const int b = __ffs(f) - 1;
       f &= f - 1;
       const int32_t k = int32_t(w * 32 + b);
-      dlist[pf++] = k;
+      if (want_list) dlist[pf] = k;
+      ++pf;
       const uint64_t x0 = doff[k], x1 = doff[k + 1];
       const int64_t dd = row_first(x0), dn = row_start(x1) - row_start(x0) - dd;
       fv_dd += dd;
@@ -313,7 +332,8 @@ __device__ __forceinline__ void expand_normal_rows(int32_t u, int32_t len, int64
 // Fn is only read by a bottom-up nd visit; mark_fn = 0 when none can happen
 // (no unvisited delegate has a dn edge).
 __global__ void __launch_bounds__(kBS) k_normal_level(const int32_t *Q, const LevelCtr *prev,
-                                                      const uint64_t *noff, const int32_t *ncol,
+                                                      const uint64_t *noff, const uint16_t *nlen,
+                                                      const int32_t *ncol,
                                                       Out out, uint32_t *Vn, uint32_t *Fn,
                                                       const DevCtl *c, int32_t *Qnext,
                                                       LevelCtr *cur) {
@@ -322,7 +342,10 @@ __global__ void __launch_bounds__(kBS) k_normal_level(const int32_t *Q, const Le
   // blocks past the queue have nothing to add (a short queue leaves most of
   // the grid idle: skip its LDS set-up and block reductions)
   if (int64_t(blockIdx.x) * blockDim.x >= qn) return;
-  const int mark_fn = c->mark_fn;
+  const int mark_fn = level_marks_fn(c, int64_t(cur->q_dn));
+  // with nn under the direction decision this pass only counts (and marks
+  // Fn); nn is expanded after the decision, forward or backward
+  const int expand = !c->nn_do;
   out.level1 = c->level1;
   __shared__ int32_t s_excl[kNW][kWave];
   __shared__ int32_t s_u[kNW][kWave];
@@ -342,10 +365,20 @@ __global__ void __launch_bounds__(kBS) k_normal_level(const int32_t *Q, const Le
     int64_t beg = 0;
     if (i < qn) {
       u = Q[i];
-      const uint64_t w0 = noff[u], w1 = noff[u + 1];
-      beg = row_start(w0);
-      nn = int32_t(row_first(w0));
-      const int64_t nd = row_start(w1) - beg - nn;
+      // part lengths from 2 bytes per vertex; the row start only for rows
+      // with nn edges (most normal rows have none)
+      const uint32_t lw = nlen[u];
+      int64_t nd;
+      if (lw == kLenWide) {
+        const uint64_t w0 = noff[u], w1 = noff[u + 1];
+        beg = row_start(w0);
+        nn = int32_t(row_first(w0));
+        nd = row_start(w1) - beg - nn;
+      } else {
+        nn = int32_t(lw & 0xFFu);
+        nd = int64_t(lw >> 8);
+        if (nn > 0 && expand) beg = row_start(noff[u]);
+      }
       fv_nn += nn;
       q_nn += nn > 0;
       fv_nd += nd;
@@ -353,14 +386,141 @@ __global__ void __launch_bounds__(kBS) k_normal_level(const int32_t *Q, const Le
     }
     // queues filled by the bottom-up pass are in ascending order: mark word by word
     if (mark_fn) wave_bit_set(Fn, uint32_t(u), i < qn, true);
-    expand_normal_rows<0>(u, nn, beg, s_excl[w], s_u[w], s_beg[w], ncol, nullptr, out, Vn,
-                          nullptr, qa, edges, claimed);
+    expand_normal_rows<0>(u, expand ? nn : 0, beg, s_excl[w], s_u[w], s_beg[w], ncol, nullptr,
+                          out, Vn, nullptr, qa, edges, claimed);
     qa.maybe_flush(kBS * 2);
   }
   qa.flush();
   block_add4(&cur->fv_nn, fv_nn, q_nn, fv_nd, q_nd, sh);
   // units: queue entries (counted on the host), nn edges, normals claimed
   block_add4(cur->units[DSBFS_K_PREV_NORMAL], 0, edges, claimed, 0, sh);
+}
+
+// Top-down nn from the normal queue, after the direction decision (nn_do,
+// levels where nn goes forward): the expansion k_normal_level fuses into the
+// previsit otherwise.
+__global__ void __launch_bounds__(kBS) k_td_nn(const int32_t *Q, const DevCtl *c,
+                                               const uint64_t *noff, const uint16_t *nlen,
+                                               const int32_t *ncol, Out out, uint32_t *Vn,
+                                               int32_t *Qnext, LevelCtr *cur) {
+  if (c->done || !c->nn_td) return;
+  const int64_t qn = c->qn;
+  if (int64_t(blockIdx.x) * blockDim.x >= qn) return;
+  out.level1 = c->level1;
+  __shared__ int32_t s_excl[kNW][kWave];
+  __shared__ int32_t s_u[kNW][kWave];
+  __shared__ int64_t s_beg[kNW][kWave];
+  __shared__ int32_t qbuf[kQCap];
+  __shared__ int qcount;
+  __shared__ unsigned long long qbase;
+  __shared__ unsigned long long sh[4 * kNW];
+  BlockAppend qa{qbuf, &qcount, &qbase, kQCap, &cur->qn_next, Qnext};
+  qa.init();
+  const int w = threadIdx.x / kWave;
+  unsigned long long edges = 0, claimed = 0;
+  for (int64_t b0 = int64_t(blockIdx.x) * blockDim.x; b0 < qn;
+       b0 += int64_t(gridDim.x) * blockDim.x) {
+    const int64_t i = b0 + threadIdx.x;
+    int32_t u = 0, nn = 0;
+    int64_t beg = 0;
+    if (i < qn) {
+      u = Q[i];
+      const uint32_t lw = nlen[u];
+      if (lw == kLenWide) {
+        const uint64_t w0 = noff[u];
+        beg = row_start(w0);
+        nn = int32_t(row_first(w0));
+      } else {
+        nn = int32_t(lw & 0xFFu);
+        if (nn > 0) beg = row_start(noff[u]);
+      }
+    }
+    expand_normal_rows<0>(u, nn, beg, s_excl[w], s_u[w], s_beg[w], ncol, nullptr, out, Vn,
+                          nullptr, qa, edges, claimed);
+    qa.maybe_flush(kBS * 2);
+  }
+  qa.flush();
+  // units: queue entries (counted by the decision), nn edges, normals claimed
+  block_add4(cur->units[DSBFS_K_TD_NN], 0, edges, claimed, 0, sh);
+}
+
+// Bottom-up nn (nn_do, levels where nn goes backward): every normal vertex
+// with an nn edge that is still unvisited scans its nn part (ascending IDs)
+// for a vertex of the level's normal frontier (bitmap Fn, marked by the
+// previsit), stopping at the first; the rows of a wave's 64 candidates are
+// walked together, 64 entries per step, as in k_bu_normal. A candidate is
+// one lane's and no other kernel claims normals while this one runs, so
+// claims set bits without reading them back.
+__global__ void __launch_bounds__(kBS) k_bu_nn(const DevCtl *c, const int32_t *nnsrc,
+                                               int64_t nsrc, const uint64_t *noff,
+                                               const uint16_t *nlen, const int32_t *ncol,
+                                               const uint32_t *Fn, Out out, uint32_t *Vn,
+                                               int32_t *Qnext, LevelCtr *cur) {
+  if (c->done || !c->nn_bu) return;
+  out.level1 = c->level1;
+  __shared__ int32_t s_excl[kNW][kWave];
+  __shared__ int32_t s_found[kNW][kWave];
+  __shared__ int64_t s_beg[kNW][kWave];
+  __shared__ int32_t qbuf[kQCap];
+  __shared__ int qcount;
+  __shared__ unsigned long long qbase;
+  __shared__ unsigned long long sh[4 * kNW];
+  BlockAppend qa{qbuf, &qcount, &qbase, kQCap, &cur->qn_next, Qnext};
+  qa.init();
+  const int w = threadIdx.x / kWave, l = lane_id();
+  constexpr int32_t kNone = 0x7fffffff;
+  unsigned long long reads = 0, scanned = 0, edges = 0, claimed = 0;
+  for (int64_t b0 = int64_t(blockIdx.x) * blockDim.x; b0 < nsrc;
+       b0 += int64_t(gridDim.x) * blockDim.x) {
+    const int64_t i = b0 + threadIdx.x;
+    const bool ok = i < nsrc;
+    int32_t v = 0, len = 0;
+    int64_t beg = 0;
+    if (ok) {
+      v = nnsrc[i];
+      ++reads;
+      if (!bit_test(Vn, uint32_t(v))) {
+        ++scanned;
+        const uint32_t lw = nlen[v];
+        const uint64_t w0 = noff[v];
+        beg = row_start(w0);
+        len = lw == kLenWide ? int32_t(row_first(w0)) : int32_t(lw & 0xFFu);
+      }
+    }
+    const int32_t incl = wave_incl_scan(len);
+    const int32_t T = lane_read(incl, kWave - 1);
+    wave_sync();
+    s_excl[w][l] = incl - len;
+    s_beg[w][l] = beg;
+    s_found[w][l] = kNone;
+    wave_sync();
+    uint64_t remaining = __ballot(len > 0);
+    for (int32_t e0 = 0; e0 < T && remaining; e0 += kWave) {
+      const int32_t e = e0 + l;
+      if (e < T) {
+        const int lo = owner64(s_excl[w], e);
+        if (s_found[w][lo] == kNone) {
+          const int32_t x = ncol[s_beg[w][lo] + (e - s_excl[w][lo])];
+          ++edges;
+          if (bit_test(Fn, uint32_t(x))) atomicMin(&s_found[w][lo], e);
+        }
+      }
+      wave_sync();
+      remaining = __ballot(len > 0 && s_found[w][l] == kNone);
+    }
+    const int32_t fe = s_found[w][l];
+    const bool won = ok && len > 0 && fe != kNone;
+    wave_bit_set(Vn, uint32_t(v), ok, won);
+    if (won) {
+      out.put(v, ncol[beg + (fe - (incl - len))]);
+      ++claimed;
+    }
+    qa.push(won, v);
+    qa.maybe_flush(kBS);
+  }
+  qa.flush();
+  // units: list entries read, unvisited scanned, edges inspected, claimed
+  block_add4(cur->units[DSBFS_K_BU_NN], reads, scanned, edges, claimed, sh);
 }
 
 // Top-down nd from the normal queue (only on levels where nd goes forward).
@@ -579,8 +739,12 @@ __global__ void __launch_bounds__(kBS) k_bu_normal(const DevCtl *c, int32_t *c0,
     }
     const int32_t fe = s_found[w][l];
     const bool found = hit0 >= 0 || (len > 0 && fe != kNone);
-    // candidates come in ascending vertex order: claim word by word
-    const bool won = wave_bit_claim(Vn, uint32_t(v), ok, found);
+    // A vertex is the candidate of one lane only, and no other kernel claims
+    // normal vertices while this one runs (the level's nn visit is complete),
+    // so a found candidate is this lane's: its bit is set without waiting for
+    // the atomic's old value. Candidates are ascending: set word by word.
+    const bool won = ok && found;
+    wave_bit_set(Vn, uint32_t(v), ok, won);
     if (won) {
       out.put(v, hit0 >= 0 ? pk0 : vid_of[nds_col[beg + (fe - (incl - len))]]);
       ++claimed;
@@ -682,7 +846,10 @@ __global__ void __launch_bounds__(kBS) k_bu_deleg(const int32_t *dcand, const Le
       if (len > 0 && fe != kNone) hit = p + (fe - (incl - len));
       wave_sync();
     }
-    const bool won = wave_bit_claim(Cd, uint32_t(k), ok, hit >= 0);
+    // each candidate delegate is one lane's, and no other kernel claims
+    // delegates while this one runs: set the bit without reading it back
+    const bool won = ok && hit >= 0;
+    wave_bit_set(Cd, uint32_t(k), ok, won);
     if (won) {
       int32_t par = px;
       if (!probe_hit) {
@@ -729,7 +896,7 @@ __global__ void k_close(uint32_t *Vd, uint32_t *Fd, const uint32_t *Cd, int32_t 
     if (threadIdx.x == 0) {
       c->level += 1;
       c->level1 = c->level + 1;
-      c->mark_fn = c->rem[1] > 0;
+      c->mark_fn = c->rem[1] > 0 || (c->nn_do && c->rem[3] > 0);
     }
   }
 }
@@ -761,35 +928,52 @@ __device__ void decide_level(DevCtl *__restrict__ c, const LevelCtr *__restrict_
   }
   const int64_t q[3] = {int64_t(cur->q_dd), int64_t(cur->q_dn), int64_t(cur->q_nd)};
   const int64_t FV[3] = {int64_t(cur->fv_dd), int64_t(cur->fv_dn), int64_t(cur->fv_nd)};
+  // what the normal previsit of this level did (before the counts move on)
+  c->mark_fn = level_marks_fn(c, q[1]);
   c->rem[0] -= q[0];
   c->rem[1] -= q[1];
   c->rem[2] -= q[2];
+  const int64_t q_nn = int64_t(cur->q_nn), fv_nn = int64_t(cur->fv_nn);
+  c->rem[3] -= q_nn;
   const int64_t U[3] = {c->rem[0], c->rem[2], c->rem[1]};
   const int64_t S[3] = {c->rem[0], c->rem[1], c->rem[2]};
   double BV[3];
-  for (int k = 0; k < 3; ++k) {
-    BV[k] = bv_estimate(U[k], q[k], S[k]);
+  auto choose = [&](int k, int64_t qk, int64_t fvk, double bvk) {
     int d = c->dir[k];
     if (c->forced == 1) d = 0;
     else if (c->forced == 2) d = L >= 1 ? 1 : 0;
-    else if (c->forced == 3) d = int(mix64(c->forced_seed + uint64_t(L) * 3 + k) & 1);
-    else if (q[k] > 0) {
-      if (d == 0 && double(FV[k]) > c->f0[k] * BV[k]) d = 1;
-      else if (d == 1 && double(FV[k]) < c->f1[k] * BV[k]) d = 0;
+    else if (c->forced == 3)
+      d = int(mix64(c->forced_seed + uint64_t(L) * 3 + k + (k == 3 ? 0x5bd1e995ull : 0)) & 1);
+    else if (qk > 0) {
+      if (d == 0 && double(fvk) > c->f0[k] * bvk) d = 1;
+      else if (d == 1 && double(fvk) < c->f1[k] * bvk) d = 0;
     }
     c->dir[k] = d;
+  };
+  for (int k = 0; k < 3; ++k) {
+    BV[k] = bv_estimate(U[k], q[k], S[k]);
+    choose(k, q[k], FV[k], BV[k]);
     st->rec.q[k] = q[k];
     st->rec.s[k] = S[k];
     st->rec.U[k] = U[k];
     st->rec.FV[k] = FV[k];
     st->rec.BV[k] = BV[k];
-    st->rec.dir[k] = d;
+    st->rec.dir[k] = c->dir[k];
   }
-  st->rec.FV_nn = int64_t(cur->fv_nn);
-  st->rec.q_nn = int64_t(cur->q_nn);
+  // nn (nn_do only): U = s = unvisited normals with an nn edge (symmetric)
+  const double BV_nn = c->nn_do ? bv_estimate(c->rem[3], q_nn, c->rem[3]) : 0.0;
+  if (c->nn_do) choose(3, q_nn, fv_nn, BV_nn);
+  st->rec.U_nn = c->nn_do ? c->rem[3] : 0;
+  st->rec.s_nn = st->rec.U_nn;
+  st->rec.BV_nn = BV_nn;
+  st->rec.dir_nn = c->nn_do ? c->dir[3] : 0;
+  st->rec.FV_nn = fv_nn;
+  st->rec.q_nn = q_nn;
   st->rec.frontier_normal = qn;
   st->rec.frontier_delegate = fdn;
-  // nn went top-down inside k_normal_level already
+  const int nn_td = c->nn_do && c->dir[3] == 0 && q_nn > 0;
+  const int nn_bu = c->nn_do && c->dir[3] == 1 && q_nn > 0 && c->rem[3] > 0;
+  // without nn_do, nn went top-down inside k_normal_level already
   const int dd_td = c->dir[0] == 0 && q[0] > 0, dn_td = c->dir[1] == 0 && q[1] > 0;
   const int nd_td = c->dir[2] == 0 && q[2] > 0;
   const int dd_bu = c->dir[0] == 1 && q[0] > 0 && U[0] > 0;
@@ -804,6 +988,8 @@ __device__ void decide_level(DevCtl *__restrict__ c, const LevelCtr *__restrict_
   c->dn_bu = dn_bu;
   c->dd_bu = dd_bu;
   c->nd_bu = nd_bu;
+  c->nn_td = nn_td;
+  c->nn_bu = nn_bu;
   c->bulk_fn = bulk_fn;
   c->clear_fn = c->mark_fn && !bulk_fn;
   c->qn = qn;
@@ -815,10 +1001,12 @@ __device__ void decide_level(DevCtl *__restrict__ c, const LevelCtr *__restrict_
     c->nc_pending = 1;
   }
   if (nd_td) c->units[DSBFS_K_TD_NORMAL][0] += qn;
+  if (nn_td) c->units[DSBFS_K_TD_NN][0] += qn;
   if (dd_td || dn_td) c->units[DSBFS_K_TD_DELEG][0] += fdn;
   c->units[DSBFS_K_CLOSE][0] += bulk_fn ? c->nwords / 4 : qn;
-  const int plan[8] = {nd_td, dd_td, dn_td, dn_bu, dd_bu, nd_bu, bulk_fn, c->mark_fn};
-  for (int i = 0; i < 8; ++i) st->plan[i] = plan[i];
+  const int plan[10] = {nd_td, dd_td, dn_td, dn_bu, dd_bu, nd_bu, bulk_fn, c->mark_fn, nn_td,
+                        nn_bu};
+  for (int i = 0; i < 10; ++i) st->plan[i] = plan[i];
   st->level = L;
   st->done = 0;
 }
@@ -1056,6 +1244,9 @@ static dsbfs_run_opts default_opts() {
   o.factor1[0] = o.factor1[1] = o.factor1[2] = 0.0;
   o.forced = 0;
   o.forced_seed = 0;
+  o.nn_do = 0;
+  o.factor0_nn = 1e-3;
+  o.factor1_nn = 0.0;
   return o;
 }
 
@@ -1117,6 +1308,7 @@ struct LevelLaunch {
   uint32_t *Vn, *Fn, *Vd, *Fd, *Cd;
   LevelStatus *hs;
   int64_t *bsum, *bscan;
+  bool nn_do;  // nn under the direction decision: its own forward and backward passes
 
   void enqueue(int p, hipStream_t s, Prof *P) const {
     const int32_t n = g->n, d = g->d;
@@ -1126,12 +1318,9 @@ struct LevelLaunch {
     auto end = [&](int k, int b) {
       if (P) P->end(k, b);
     };
-    int b = begin();
-    hipLaunchKernelGGL(k_normal_level, dim3(SG), dim3(kBS), 0, s, Q[p], prev,
-                       g->noff.as<uint64_t>(), g->ncol.as<int32_t>(), out, Vn, Fn,
-                       static_cast<const DevCtl *>(c), Q[p ^ 1], cur);
-    HIPCHK(hipGetLastError());
-    end(DSBFS_K_PREV_NORMAL, b);
+    // the delegate previsit first: the normal previsit reads its frontier
+    // count (whether Fn is needed this level)
+    int b = -1;
     if (d > 0) {
       b = begin();
       hipLaunchKernelGGL(k_prev_deleg, dim3(grid_for(g->dwords(), kBS, 4096)), dim3(kBS), 0, s,
@@ -1140,9 +1329,24 @@ struct LevelLaunch {
       HIPCHK(hipGetLastError());
       end(DSBFS_K_PREV_DELEG, b);
     }
+    b = begin();
+    hipLaunchKernelGGL(k_normal_level, dim3(SG), dim3(kBS), 0, s, Q[p], prev,
+                       g->noff.as<uint64_t>(), g->nlen.as<uint16_t>(), g->ncol.as<int32_t>(),
+                       out, Vn, Fn,
+                       static_cast<const DevCtl *>(c), Q[p ^ 1], cur);
+    HIPCHK(hipGetLastError());
+    end(DSBFS_K_PREV_NORMAL, b);
     hipLaunchKernelGGL(k_decide, dim3(1), dim3(kWave), 0, s, c, static_cast<const LevelCtr *>(cur),
                        static_cast<const LevelCtr *>(prev), hs);
     HIPCHK(hipGetLastError());
+    if (nn_do) {
+      b = begin();
+      hipLaunchKernelGGL(k_td_nn, dim3(SG), dim3(kBS), 0, s, static_cast<const int32_t *>(Q[p]),
+                         static_cast<const DevCtl *>(c), g->noff.as<uint64_t>(),
+                         g->nlen.as<uint16_t>(), g->ncol.as<int32_t>(), out, Vn, Q[p ^ 1], cur);
+      HIPCHK(hipGetLastError());
+      end(DSBFS_K_TD_NN, b);
+    }
     if (d > 0) {
       b = begin();
       hipLaunchKernelGGL(k_td_nd, dim3(SG), dim3(kBS), 0, s, static_cast<const int32_t *>(Q[p]),
@@ -1168,6 +1372,19 @@ struct LevelLaunch {
                          static_cast<const DevCtl *>(c), out, Vn, Cd, Q[p ^ 1], cur);
       HIPCHK(hipGetLastError());
       end(DSBFS_K_TD_DELEG, b);
+    }
+    // bottom-up nn (nn_do): after every forward visit of the level, before
+    // the bottom-up dn visit (which then sees its claims as visited)
+    if (nn_do && g->st.n_nnsrc > 0) {
+      b = begin();
+      hipLaunchKernelGGL(k_bu_nn, dim3(SG), dim3(kBS), 0, s, static_cast<const DevCtl *>(c),
+                         g->nnsrc.as<int32_t>(), g->st.n_nnsrc, g->noff.as<uint64_t>(),
+                         g->nlen.as<uint16_t>(), g->ncol.as<int32_t>(),
+                         static_cast<const uint32_t *>(Fn), out, Vn, Q[p ^ 1], cur);
+      HIPCHK(hipGetLastError());
+      end(DSBFS_K_BU_NN, b);
+    }
+    if (d > 0) {
       if (g->st.n_ndsrc > 0) {
         b = begin();
         hipLaunchKernelGGL(k_bu_normal, dim3(SG), dim3(kBS), 0, s, static_cast<const DevCtl *>(c),
@@ -1200,8 +1417,9 @@ struct LevelLaunch {
   }
 };
 
-LevelLaunch level_launch(const Graph *g, Workspace *ws, const Out &out) {
+LevelLaunch level_launch(const Graph *g, Workspace *ws, const Out &out, bool nn_do) {
   LevelLaunch ll{};
+  ll.nn_do = nn_do;
   ll.g = g;
   ll.ws = ws;
   ll.out = out;
@@ -1228,6 +1446,7 @@ LevelLaunch level_launch(const Graph *g, Workspace *ws, const Out &out) {
 // depth / parent buffers they were captured with.
 struct LevelGraphs {
   int32_t *depth = nullptr, *parent = nullptr;
+  bool nn_do = false;
   hipGraph_t graph[2] = {nullptr, nullptr};
   hipGraphExec_t exec[2] = {nullptr, nullptr};
 };
@@ -1249,12 +1468,14 @@ namespace {
 
 const LevelGraphs &level_graphs(Workspace *ws, const LevelLaunch &ll) {
   auto *lg = static_cast<LevelGraphs *>(ws->lvl);
-  if (lg && lg->depth == ll.out.depth && lg->parent == ll.out.parent) return *lg;
+  if (lg && lg->depth == ll.out.depth && lg->parent == ll.out.parent && lg->nn_do == ll.nn_do)
+    return *lg;
   level_graphs_release(ws);
   lg = new LevelGraphs();
   ws->lvl = lg;
   lg->depth = ll.out.depth;
   lg->parent = ll.out.parent;
+  lg->nn_do = ll.nn_do;
   hipStream_t cs = nullptr;
   HIPCHK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
   try {
@@ -1293,6 +1514,7 @@ void bfs_run(const Graph *g, Workspace *ws, int32_t source, const dsbfs_run_opts
   if (o.mode == 0 && !g->pcol.p && g->m > 0)
     fail(DSBFS_ERR_INVALID_ARG, "mode 0 needs the plain CSR (keep_plain_csr)");
   if (o.forced < 0 || o.forced > 3) fail(DSBFS_ERR_INVALID_ARG, "forced must be 0..3");
+  if (o.nn_do != 0 && o.nn_do != 1) fail(DSBFS_ERR_INVALID_ARG, "nn_do must be 0 or 1");
   int32_t *par = o.want_parent ? parent : nullptr;
 
   const int32_t n = g->n, d = g->d;
@@ -1358,21 +1580,25 @@ void bfs_run(const Graph *g, Workspace *ws, int32_t source, const dsbfs_run_opts
       init.f0[k] = o.factor0[k];
       init.f1[k] = o.factor1[k];
     }
+    init.f0[3] = o.factor0_nn;
+    init.f1[3] = o.factor1_nn;
+    init.nn_do = o.nn_do;
     init.forced = o.forced;
     init.forced_seed = o.forced_seed;
     init.level = 0;  // level 0 is open: counters cleared above, depth 1 next
     init.level1 = 1;
-    init.mark_fn = g->st.n_dnsrc > 0;
+    init.mark_fn = g->st.n_dnsrc > 0 || (o.nn_do && g->st.n_nnsrc > 0);
     init.cand_state = -1;
     init.nwords = g->nwords();
     init.rem[0] = g->st.n_ddsrc;
     init.rem[1] = g->st.n_dnsrc;
     init.rem[2] = g->st.n_ndsrc;
+    init.rem[3] = g->st.n_nnsrc;
     init.nc = g->st.n_ndsrc;
     hipLaunchKernelGGL(k_ctl_init, dim3(1), dim3(1), 0, s, c, init);
     HIPCHK(hipGetLastError());
     LevelStatus *hs = static_cast<LevelStatus *>(ws->hstat);
-    const LevelLaunch ll = level_launch(g, ws, out);
+    const LevelLaunch ll = level_launch(g, ws, out, o.nn_do != 0);
     std::vector<LevelStatus> seen;
     if (ws->borrowed) {
       // allocation-free search: direct launches (no captured graphs, no
@@ -1398,7 +1624,8 @@ void bfs_run(const Graph *g, Workspace *ws, int32_t source, const dsbfs_run_opts
         const LevelStatus st = hs[L & (kStatusSlots - 1)];
         const int32_t ran[DSBFS_NUM_KERNELS] = {
             0, 1, d > 0, !st.done && st.plan[0], !st.done && (st.plan[1] || st.plan[2]),
-            !st.done && st.plan[3], !st.done && (st.plan[4] || st.plan[5]), !st.done, 0};
+            !st.done && st.plan[3], !st.done && (st.plan[4] || st.plan[5]), !st.done, 0,
+            !st.done && st.plan[8], !st.done && st.plan[9]};
         std::vector<Prof::Span> keep;
         for (size_t i = sp0; i < P.spans.size(); ++i) {
           if (ran[P.spans[i].k]) keep.push_back(P.spans[i]);
@@ -1435,6 +1662,8 @@ void bfs_run(const Graph *g, Workspace *ws, int32_t source, const dsbfs_run_opts
         if (pl[1] || pl[2]) ++P.launches[DSBFS_K_TD_DELEG];
         if (pl[3]) ++P.launches[DSBFS_K_BU_NORMAL];
         if (pl[4] || pl[5]) ++P.launches[DSBFS_K_BU_DELEG];
+        if (pl[8]) ++P.launches[DSBFS_K_TD_NN];
+        if (pl[9]) ++P.launches[DSBFS_K_BU_NN];
         ++P.launches[DSBFS_K_CLOSE];
       }
     }
@@ -1471,7 +1700,7 @@ void bfs_run(const Graph *g, Workspace *ws, int32_t source, const dsbfs_run_opts
     const double claims = Uc[DSBFS_K_PREV_NORMAL][2] + Uc[DSBFS_K_TD_NORMAL][3] +
                           Uc[DSBFS_K_TD_DELEG][2] + Uc[DSBFS_K_TD_DELEG][3] +
                           Uc[DSBFS_K_BU_NORMAL][3] + Uc[DSBFS_K_BU_DELEG][2] +
-                          Uc[DSBFS_K_PLAIN][2];
+                          Uc[DSBFS_K_PLAIN][2] + Uc[DSBFS_K_TD_NN][2] + Uc[DSBFS_K_BU_NN][3];
     stats->reached = 1 + int64_t(claims);
     if (o.mode == 0) deg_sum = Uc[DSBFS_K_PLAIN][1];
     stats->edges_cc = int64_t(deg_sum / 2);
@@ -1506,6 +1735,12 @@ void bfs_run(const Graph *g, Workspace *ws, int32_t source, const dsbfs_run_opts
     bytes[DSBFS_K_PLAIN] = U[DSBFS_K_PLAIN][0] * (4 + 16) + U[DSBFS_K_PLAIN][1] * 4 +
                            U[DSBFS_K_PLAIN][2] * (out_b + 4);
     edges[DSBFS_K_PLAIN] = U[DSBFS_K_PLAIN][1];
+    bytes[DSBFS_K_TD_NN] = U[DSBFS_K_TD_NN][0] * (4 + 16) + U[DSBFS_K_TD_NN][1] * 4 +
+                           U[DSBFS_K_TD_NN][2] * (out_b + 4);
+    edges[DSBFS_K_TD_NN] = U[DSBFS_K_TD_NN][1];
+    bytes[DSBFS_K_BU_NN] = U[DSBFS_K_BU_NN][0] * 4 + U[DSBFS_K_BU_NN][1] * 16 +
+                           U[DSBFS_K_BU_NN][2] * 4 + U[DSBFS_K_BU_NN][3] * (out_b + 4 + 4);
+    edges[DSBFS_K_BU_NN] = U[DSBFS_K_BU_NN][2];
     double ms[DSBFS_NUM_KERNELS] = {};
     for (const Prof::Span &sp : P.spans) {
       float t = 0.f;

@@ -149,6 +149,20 @@ __global__ void k_pack_offsets(const int64_t *nstart, const int64_t *dstart, con
   }
 }
 
+// Compact part lengths of the normal rows (see Graph::nlen).
+__global__ void k_pack_lens(const int32_t *deg, const int32_t *did, const int32_t *cnt_del,
+                            int32_t n, uint16_t *nlen) {
+  const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+  for (int64_t v = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; v < n; v += stride) {
+    uint16_t x = 0;
+    if (did[v] < 0) {
+      const int32_t nd = cnt_del[v], nn = deg[v] - nd;
+      x = (nn < 255 && nd < 255) ? uint16_t(nn | (nd << 8)) : kLenWide;
+    }
+    nlen[v] = x;
+  }
+}
+
 // Destination of row u in the new layout: (row offsets, columns, is delegate).
 struct RowDst {
   uint64_t w;
@@ -235,6 +249,14 @@ __global__ void k_flag_ndsrc(const int32_t *did, const int32_t *cnt_del, int32_t
     flag[u] = did[u] < 0 && cnt_del[u] > 0;
 }
 
+// Normal vertices with a normal neighbour (bottom-up nn candidates).
+__global__ void k_flag_nnsrc(const int32_t *deg, const int32_t *did, const int32_t *cnt_del,
+                             int32_t n, uint8_t *flag) {
+  for (int64_t u = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; u < n;
+       u += int64_t(gridDim.x) * blockDim.x)
+    flag[u] = did[u] < 0 && deg[u] > cnt_del[u];
+}
+
 __global__ void k_source_masks(const int32_t *vid_of, const int32_t *deg, const int32_t *cnt_del,
                                int32_t d, uint32_t *ddm, uint32_t *dnm) {
   const int32_t W = (d + 31) / 32;
@@ -282,21 +304,22 @@ __global__ void k_nds_fill(const int32_t *ndsrc, int64_t cnt, const uint64_t *no
 // [0] e_nn [1] e_nd [2] e_dn [3] e_dd [4] n_ndsrc [5] n_ddsrc [6] n_dnsrc [7] max degree
 __global__ void k_stats(const int32_t *deg, const int32_t *did, const int32_t *cnt_del, int32_t n,
                         unsigned long long *out) {
-  unsigned long long a[7] = {0, 0, 0, 0, 0, 0, 0};
+  unsigned long long a[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   unsigned long long mx = 0;
   for (int64_t u = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; u < n;
        u += int64_t(gridDim.x) * blockDim.x) {
     const unsigned long long dg = deg[u], cd = cnt_del[u], cn = dg - cd;
     if (did[u] < 0) {
-      a[0] += cn; a[1] += cd; a[4] += cd > 0;
+      a[0] += cn; a[1] += cd; a[4] += cd > 0; a[7] += cn > 0;
     } else {
       a[2] += cn; a[3] += cd; a[5] += cd > 0; a[6] += cn > 0;
     }
     mx = dg > mx ? dg : mx;
   }
-  for (int i = 0; i < 7; ++i) {
+  for (int i = 0; i < 8; ++i) {
     unsigned long long s = wave_sum(a[i]);
-    if (lane_id() == 0 && s) atomicAdd(&out[i], s);
+    // out[7] is the maximum degree; the count of normals with an nn edge is out[8]
+    if (lane_id() == 0 && s) atomicAdd(&out[i < 7 ? i : 8], s);
   }
   for (int o = 32; o > 0; o >>= 1) {
     unsigned long long t = __shfl_xor(mx, o, kWave);
@@ -431,11 +454,25 @@ __global__ void k_nd_sort(const uint64_t *noff, int32_t n, const int32_t *did, i
 
 }  // namespace
 
+int64_t rmat_pack_keys(const dsbfs_rmat_spec *sp, int B, uint64_t *keys, unsigned long long *cursor,
+                       hipStream_t s);
+
+// Builds the layout from an edge list (src, dst: g pairs), or, with rmat
+// set, from the RMAT generator writing the symmetrized keys directly.
 Graph *graph_create(const int32_t *src, const int32_t *dst, int64_t g, int32_t n,
-                    const dsbfs_build_opts *opts, const dsbfs_allocator *alloc, hipStream_t s) {
+                    const dsbfs_build_opts *opts, const dsbfs_allocator *alloc, hipStream_t s,
+                    const dsbfs_rmat_spec *rmat) {
+  if (rmat) {
+    if (rmat->scale < 1 || rmat->scale > 31)
+      fail(DSBFS_ERR_INVALID_ARG, "scale must be in [1, 31]");
+    if (rmat->scale == 31) fail(DSBFS_ERR_RANGE, "2^31 vertices do not fit int32 IDs");
+    n = int32_t(int64_t(1) << rmat->scale);
+    g = rmat->num_edges;
+    src = dst = nullptr;
+  }
   if (n < 1) fail(DSBFS_ERR_INVALID_ARG, "num_vertices must be >= 1");
   if (g < 0) fail(DSBFS_ERR_INVALID_ARG, "num_edges must be >= 0");
-  if (g > 0 && (!src || !dst)) fail(DSBFS_ERR_INVALID_ARG, "src/dst must not be NULL");
+  if (g > 0 && !rmat && (!src || !dst)) fail(DSBFS_ERR_INVALID_ARG, "src/dst must not be NULL");
   dsbfs_build_opts o{};
   o.threshold = 32;
   o.keep_plain_csr = 1;
@@ -457,10 +494,10 @@ Graph *graph_create(const int32_t *src, const int32_t *dst, int64_t g, int32_t n
     const int B = bits_for(n);
     const uint64_t vmask = (uint64_t(1) << B) - 1;
 
-    // 1. edges on the device, validated
+    // 1. edges on the device, validated (or generated: step 2)
     DevBuf esrc, edst;
     const int32_t *ds = src, *dd = dst;
-    if (!o.edges_on_device && g > 0) {
+    if (!rmat && !o.edges_on_device && g > 0) {
       esrc.alloc(al, size_t(g) * 4, s);
       edst.alloc(al, size_t(g) * 4, s);
       HIPCHK(hipMemcpyAsync(esrc.p, src, size_t(g) * 4, hipMemcpyHostToDevice, s));
@@ -469,25 +506,30 @@ Graph *graph_create(const int32_t *src, const int32_t *dst, int64_t g, int32_t n
       dd = edst.as<int32_t>();
     }
     DevBuf ctr;
-    ctr.alloc(al, 8 * sizeof(unsigned long long), s);
-    HIPCHK(hipMemsetAsync(ctr.p, 0, 8 * sizeof(unsigned long long), s));
+    ctr.alloc(al, 16 * sizeof(unsigned long long), s);
+    HIPCHK(hipMemsetAsync(ctr.p, 0, 16 * sizeof(unsigned long long), s));
     unsigned long long *c = ctr.as<unsigned long long>();
-    if (g > 0) {
-      hipLaunchKernelGGL(k_validate, dim3(grid_for(g, kBS, 8192)), dim3(kBS), 0, s, ds, dd, g, n,
-                         c);
-      HIPCHK(hipGetLastError());
+    int64_t M2 = 2 * g;   // upper bound for the generator (self-loops are dropped)
+    if (!rmat) {
+      if (g > 0) {
+        hipLaunchKernelGGL(k_validate, dim3(grid_for(g, kBS, 8192)), dim3(kBS), 0, s, ds, dd, g,
+                           n, c);
+        HIPCHK(hipGetLastError());
+      }
+      unsigned long long hc[2];
+      HIPCHK(hipMemcpyAsync(hc, c, sizeof(hc), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      if (hc[0]) fail(DSBFS_ERR_INVALID_ARG, "edge endpoint outside [0, num_vertices)");
+      M2 = 2 * int64_t(hc[1]);
     }
-    unsigned long long hc[2];
-    HIPCHK(hipMemcpyAsync(hc, c, sizeof(hc), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
-    if (hc[0]) fail(DSBFS_ERR_INVALID_ARG, "edge endpoint outside [0, num_vertices)");
-    const int64_t M2 = 2 * int64_t(hc[1]);
 
     // 2. symmetrize into keys, sort, de-duplicate
     DevBuf keys, alt;
     keys.alloc(al, size_t(M2) * 8, s);
     alt.alloc(al, size_t(M2) * 8, s);
-    if (M2 > 0) {
+    if (rmat) {
+      M2 = rmat_pack_keys(rmat, B, keys.as<uint64_t>(), c, s);
+    } else if (M2 > 0) {
       HIPCHK(hipMemsetAsync(c, 0, sizeof(unsigned long long), s));
       hipLaunchKernelGGL(k_pack, dim3(grid_for(g, kBS, 8192)), dim3(kBS), 0, s, ds, dd, g, B,
                          keys.as<uint64_t>(), c);
@@ -561,11 +603,11 @@ Graph *graph_create(const int32_t *src, const int32_t *dst, int64_t g, int32_t n
     alt.reset();
 
     // 6. statistics (needed for sizes and the packed-offset range check)
-    HIPCHK(hipMemsetAsync(c, 0, 8 * sizeof(unsigned long long), s));
+    HIPCHK(hipMemsetAsync(c, 0, 9 * sizeof(unsigned long long), s));
     hipLaunchKernelGGL(k_stats, dim3(grid_for(n, kBS, 4096)), dim3(kBS), 0, s,
                        G->deg.as<int32_t>(), G->did.as<int32_t>(), cnt_del.as<int32_t>(), n, c);
     HIPCHK(hipGetLastError());
-    unsigned long long hs[8];
+    unsigned long long hs[9];
     HIPCHK(hipMemcpyAsync(hs, c, sizeof(hs), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     if (int64_t(hs[7]) > kMaxFirstPart)
@@ -591,6 +633,11 @@ Graph *graph_create(const int32_t *src, const int32_t *dst, int64_t g, int32_t n
                          nstart.as<int64_t>(), dstart.as<int64_t>(), G->deg.as<int32_t>(),
                          G->did.as<int32_t>(), G->vid_of.as<int32_t>(), cnt_del.as<int32_t>(), n,
                          int32_t(d), G->noff.as<uint64_t>(), G->doff.as<uint64_t>());
+      HIPCHK(hipGetLastError());
+      G->nlen.alloc(al, size_t(n) * 2, s);
+      hipLaunchKernelGGL(k_pack_lens, dim3(grid_for(n, kBS, 8192)), dim3(kBS), 0, s,
+                         G->deg.as<int32_t>(), G->did.as<int32_t>(), cnt_del.as<int32_t>(), n,
+                         G->nlen.as<uint16_t>());
       HIPCHK(hipGetLastError());
     }
     const int64_t e_nn = hs[0], e_nd = hs[1], e_dn = hs[2], e_dd = hs[3];
@@ -672,6 +719,12 @@ Graph *graph_create(const int32_t *src, const int32_t *dst, int64_t g, int32_t n
     HIPCHK(hipGetLastError());
     G->ndsrc.alloc(al, size_t(hs[4]) * 4, s);
     compact_flags_u8(flag.as<uint8_t>(), n, G->ndsrc.as<int32_t>(), cnt, tmp.p, s);
+    hipLaunchKernelGGL(k_flag_nnsrc, dim3(grid_for(n, kBS, 8192)), dim3(kBS), 0, s,
+                       G->deg.as<int32_t>(), G->did.as<int32_t>(), cnt_del.as<int32_t>(), n,
+                       flag.as<uint8_t>());
+    HIPCHK(hipGetLastError());
+    G->nnsrc.alloc(al, size_t(hs[8]) * 4, s);
+    compact_flags_u8(flag.as<uint8_t>(), n, G->nnsrc.as<int32_t>(), cnt, tmp.p, s);
     {
       const int64_t nsrc = int64_t(hs[4]);
       DevBuf len, stmp;
@@ -739,6 +792,7 @@ Graph *graph_create(const int32_t *src, const int32_t *dst, int64_t g, int32_t n
     st.e_nn = e_nn; st.e_nd = e_nd; st.e_dn = e_dn; st.e_dd = e_dd;
     st.n_ndsrc = hs[4]; st.n_ddsrc = hs[5]; st.n_dnsrc = hs[6];
     st.max_degree = hs[7];
+    st.n_nnsrc = int64_t(hs[8]);
     st.threshold = o.threshold;
     // the four subgraphs; the source-list-ordered nd copy is reported apart
     st.bytes_layout = int64_t(n + 1) * 8 + int64_t(d + 1) * 8 + 4 * m;
@@ -773,6 +827,8 @@ void graph_export(const Graph *G, int32_t which, void *host_out, int64_t cap, in
     case 13: b = &G->nds_col; nb = G->st.e_nd * 4; break;
     case 14: b = &G->nds_first; nb = G->st.n_ndsrc * 8; break;
     case 15: b = &G->dd_first; nb = d * 8; break;
+    case 16: b = &G->nlen; nb = n * 2; break;
+    case 17: b = &G->nnsrc; nb = G->st.n_nnsrc * 4; break;
     default: fail(DSBFS_ERR_INVALID_ARG, "unknown array index");
   }
   *bytes = nb;

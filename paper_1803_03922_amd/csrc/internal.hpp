@@ -78,6 +78,8 @@ struct DevBuf {
 //     [ dd neighbours (delegate IDs) | dn neighbours (vertex IDs) ]
 //   noff/doff are packed: start (bits 0..39) | first-part length << 40.
 // ---------------------------------------------------------------------------
+constexpr uint16_t kLenWide = 0xFFFF;
+
 struct Graph {
   Alloc al;
   hipStream_t stream = nullptr;
@@ -91,6 +93,11 @@ struct Graph {
   // int32 [e_nd] delegate IDs.
   DevBuf nds_off, nds_col, nds_first;
   DevBuf dd_first;  // per delegate: (first dd neighbour, its vertex), or (-1, -1)
+  // per vertex, uint16: nn length | nd length << 8 of a normal row (0 for a
+  // delegate), kLenWide when either is 255 or more (read noff instead); the
+  // normal previsit reads these 2 bytes instead of two 8-byte row offsets
+  DevBuf nlen;
+  DevBuf nnsrc;     // normal vertices with a normal neighbour, ascending (nn_do bottom-up)
   DevBuf poff, pcol;  // plain CSR: int64 offsets [n+1], int32 columns [m]
   int32_t dwords() const { return (d + 31) / 32; }
   int32_t nwords() const { return (n + 31) / 32; }

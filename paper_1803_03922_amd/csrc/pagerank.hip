@@ -1,0 +1,199 @@
+// PageRank on the degree-separated layout.
+//
+// The paper names other graph primitives on degree-separated graphs as future
+// work, where delegates carry multi-bit state instead of the one-bit masks of
+// BFS (Sections VI-D, VII). Here the delegate state is each delegate's rank
+// contribution r/deg, kept in a compact array indexed by delegate ID (the
+// array that would be replicated across GPUs, as the BFS masks are); normal
+// vertices keep theirs in an array indexed by vertex ID. One FP64 power
+// iteration step from r to r':
+//   D = rank of the degree-0 vertices (spread uniformly),
+//   r'[v] = (1 - alpha) / n + alpha * (D / n + sum over neighbours u of
+//           r[u] / deg(u)),
+// as three kernels: contributions (and D), the pull over normal rows (nn part
+// from the normal array, nd part from the delegate array; rows have at most
+// TH entries: one thread per row), and the pull over delegate rows (dd part
+// from the delegate array, dn part from the normal array; long rows: one wave
+// per row). Row sums run in stored row order per thread and in a fixed-shape
+// wave reduction; the dangling mass and the L1 change are summed with atomics,
+// whose order can move the last bits between runs.
+#include "internal.hpp"
+
+namespace dsbfs {
+
+namespace {
+
+constexpr int kPB = 256;
+
+struct PrAcc {
+  double dangling;  // rank of degree-0 vertices this step
+  double delta;     // L1 change of this step
+};
+
+__device__ __forceinline__ double wave_sum_f64(double x) {
+  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, kWave);
+  return x;
+}
+
+// Block sum of one double per thread, added to *dst with one atomic.
+__device__ __forceinline__ void block_add_f64(double *dst, double x, double *sh) {
+  x = wave_sum_f64(x);
+  const int w = threadIdx.x / kWave;
+  if (lane_id() == 0) sh[w] = x;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int i = 0; i < int(blockDim.x) / kWave; ++i) t += sh[i];
+    if (t != 0.0) atomicAdd(dst, t);
+  }
+  __syncthreads();
+}
+
+__global__ void k_pr_fill(double *r, int32_t n, double v) {
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+       i += int64_t(gridDim.x) * blockDim.x)
+    r[i] = v;
+}
+
+__global__ void __launch_bounds__(kPB) k_pr_contrib(const double *r, const int32_t *deg,
+                                                    const int32_t *did, int32_t n, double *cn,
+                                                    double *cd, PrAcc *acc) {
+  __shared__ double sh[kPB / kWave];
+  double dang = 0.0;
+  for (int64_t v0 = int64_t(blockIdx.x) * blockDim.x; v0 < n;
+       v0 += int64_t(gridDim.x) * blockDim.x) {
+    const int64_t v = v0 + threadIdx.x;
+    if (v < n) {
+      const double x = r[v];
+      const int32_t dg = deg[v];
+      const double c = dg > 0 ? x / double(dg) : 0.0;
+      if (dg == 0) dang += x;
+      const int32_t k = did[v];
+      if (k >= 0) cd[k] = c;
+      else cn[v] = c;
+    }
+  }
+  block_add_f64(&acc->dangling, dang, sh);
+}
+
+__device__ __forceinline__ double pr_base(const PrAcc *acc, double alpha, int32_t n) {
+  return (1.0 - alpha) / double(n) + alpha * acc->dangling / double(n);
+}
+
+// Normal rows: nn part (vertex IDs, normal contributions), then nd part
+// (delegate IDs, delegate contributions).
+__global__ void __launch_bounds__(kPB) k_pr_normal(const uint64_t *noff, const int32_t *ncol,
+                                                   const int32_t *did, int32_t n,
+                                                   const double *cn, const double *cd,
+                                                   double alpha, const PrAcc *acc,
+                                                   const double *r, double *rn, PrAcc *out) {
+  __shared__ double sh[kPB / kWave];
+  const double base = pr_base(acc, alpha, n);
+  double delta = 0.0;
+  for (int64_t v0 = int64_t(blockIdx.x) * blockDim.x; v0 < n;
+       v0 += int64_t(gridDim.x) * blockDim.x) {
+    const int64_t v = v0 + threadIdx.x;
+    if (v < n && did[v] < 0) {
+      const uint64_t w0 = noff[v], w1 = noff[v + 1];
+      const int64_t b = row_start(w0), mid = b + row_first(w0), e = row_start(w1);
+      double s = 0.0;
+      for (int64_t i = b; i < mid; ++i) s += cn[ncol[i]];
+      for (int64_t i = mid; i < e; ++i) s += cd[ncol[i]];
+      const double x = base + alpha * s;
+      delta += fabs(x - r[v]);
+      rn[v] = x;
+    }
+  }
+  block_add_f64(&out->delta, delta, sh);
+}
+
+// Delegate rows, one wave per row: dd part (delegate IDs, delegate
+// contributions), then dn part (vertex IDs, normal contributions).
+__global__ void __launch_bounds__(kPB) k_pr_deleg(const uint64_t *doff, const int32_t *dcol,
+                                                  const int32_t *vid_of, int32_t d, int32_t n,
+                                                  const double *cn, const double *cd,
+                                                  double alpha, const PrAcc *acc,
+                                                  const double *r, double *rn, PrAcc *out) {
+  __shared__ double sh[kPB / kWave];
+  const double base = pr_base(acc, alpha, n);
+  const int l = lane_id();
+  const int64_t wid = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) / kWave;
+  const int64_t nw = int64_t(gridDim.x) * blockDim.x / kWave;
+  double delta = 0.0;
+  for (int64_t k = wid; k < d; k += nw) {
+    const uint64_t w0 = doff[k], w1 = doff[k + 1];
+    const int64_t b = row_start(w0), mid = b + row_first(w0), e = row_start(w1);
+    double s = 0.0;
+    for (int64_t i = b + l; i < e; i += kWave) s += i < mid ? cd[dcol[i]] : cn[dcol[i]];
+    s = wave_sum_f64(s);
+    if (l == 0) {
+      const int32_t v = vid_of[k];
+      const double x = base + alpha * s;
+      delta += fabs(x - r[v]);
+      rn[v] = x;
+    }
+  }
+  block_add_f64(&out->delta, delta, sh);
+}
+
+}  // namespace
+
+void pagerank_run(const Graph *g, double alpha, int32_t max_iter, double tol, double *rank,
+                  int32_t *iters_done, double *last_delta, hipStream_t s) {
+  if (!rank) fail(DSBFS_ERR_INVALID_ARG, "rank must not be NULL");
+  if (!(alpha >= 0.0 && alpha <= 1.0)) fail(DSBFS_ERR_INVALID_ARG, "alpha must be in [0, 1]");
+  if (max_iter < 0) fail(DSBFS_ERR_INVALID_ARG, "max_iterations must be >= 0");
+  const int32_t n = g->n, d = g->d;
+  const Alloc *al = &g->al;
+  DevBuf cn, cd, rb, acc;
+  cn.alloc(al, size_t(n) * 8, s);
+  cd.alloc(al, size_t(std::max(d, 1)) * 8, s);
+  rb.alloc(al, size_t(n) * 8, s);
+  // two accumulators per step, alternating (one is cleared while the other is read)
+  acc.alloc(al, 2 * sizeof(PrAcc), s);
+  // the last step must land in `rank`: start in whichever buffer makes it so
+  double *buf[2] = {rank, rb.as<double>()};
+  int cur = (max_iter % 2 == 0) ? 0 : 1;
+  const int G1 = grid_for(n, kPB, 8192);
+  hipLaunchKernelGGL(k_pr_fill, dim3(G1), dim3(kPB), 0, s, buf[cur], n, 1.0 / double(n));
+  HIPCHK(hipGetLastError());
+  PrAcc *A = acc.as<PrAcc>();
+  int32_t it = 0;
+  double dl = 0.0;
+  for (; it < max_iter; ++it) {
+    PrAcc *a = A + (it & 1);
+    HIPCHK(hipMemsetAsync(a, 0, sizeof(PrAcc), s));
+    hipLaunchKernelGGL(k_pr_contrib, dim3(G1), dim3(kPB), 0, s, buf[cur], g->deg.as<int32_t>(),
+                       g->did.as<int32_t>(), n, cn.as<double>(), cd.as<double>(), a);
+    HIPCHK(hipGetLastError());
+    hipLaunchKernelGGL(k_pr_normal, dim3(G1), dim3(kPB), 0, s, g->noff.as<uint64_t>(),
+                       g->ncol.as<int32_t>(), g->did.as<int32_t>(), n, cn.as<double>(),
+                       cd.as<double>(), alpha, a, buf[cur], buf[cur ^ 1], a);
+    HIPCHK(hipGetLastError());
+    if (d > 0) {
+      hipLaunchKernelGGL(k_pr_deleg, dim3(grid_for(int64_t(d) * kWave, kPB, 8192)), dim3(kPB), 0,
+                         s, g->doff.as<uint64_t>(), g->dcol.as<int32_t>(),
+                         g->vid_of.as<int32_t>(), d, n, cn.as<double>(), cd.as<double>(), alpha,
+                         a, buf[cur], buf[cur ^ 1], a);
+      HIPCHK(hipGetLastError());
+    }
+    cur ^= 1;
+    if (tol > 0.0 || it + 1 == max_iter) {
+      PrAcc h{};
+      HIPCHK(hipMemcpyAsync(&h, a, sizeof(PrAcc), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      dl = h.delta;
+      if (tol > 0.0 && dl < tol) {
+        ++it;
+        break;
+      }
+    }
+  }
+  if (buf[cur] != rank)
+    HIPCHK(hipMemcpyAsync(rank, buf[cur], size_t(n) * 8, hipMemcpyDeviceToDevice, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (iters_done) *iters_done = it;
+  if (last_delta) *last_delta = dl;
+}
+
+}  // namespace dsbfs

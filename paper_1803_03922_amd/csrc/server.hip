@@ -22,13 +22,20 @@
 //     than one batch: queue length x (measured time of one single-source
 //     search) >= (measured time of one batched level) x (measured levels per
 //     query). Both times are running averages kept per graph.
-// Admission is bounded by an HBM budget: graph layouts and lane state are
-// charged when a graph is added, and every result row (int32[n]) while it is
-// held; a query waits for budget, and one that can never fit is refused.
-// Results stay on the device until the client releases them.
+// Admission is bounded by an HBM budget: a resident graph's layout and lane
+// state, and every result row (int32[n]) while it is held or cached. A graph
+// that does not fit when it is added, or whose queries wait while idle graphs
+// hold the budget, is kept in host memory: idle graphs (no query waiting or
+// running) are evicted, least recently used first, and a graph is loaded back
+// when a query needs it. A query waits for budget, and one that can never fit
+// is refused. Results stay on the device until the client releases them.
+// Result rows come from the caller's allocator when one is given (called from
+// the scheduler thread), else from hipMalloc; frees of rows dropped to make
+// room run outside the lock that clients take.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <condition_variable>
 #include <deque>
@@ -72,6 +79,7 @@ size_t graph_footprint(const Graph *g) {
          buf_bytes(g->ncol) + buf_bytes(g->doff) + buf_bytes(g->dcol) + buf_bytes(g->ndsrc) +
          buf_bytes(g->ddsrc_mask) + buf_bytes(g->dnsrc_mask) + buf_bytes(g->nds_off) +
          buf_bytes(g->nds_col) + buf_bytes(g->nds_first) + buf_bytes(g->dd_first) +
+         buf_bytes(g->nlen) + buf_bytes(g->nnsrc) +
          buf_bytes(g->poff) +
          buf_bytes(g->pcol);
 }
@@ -91,6 +99,7 @@ struct Query {
   int32_t gid = 0, source = 0;
   int64_t arrival = 0, admit = 0, start = 0, done = 0;
   int32_t levels = 0, batched = 0;
+  int32_t waited_budget = 0, loaded_graph = 0;
   int32_t *res = nullptr;
   QState state = Q_PENDING;
 };
@@ -121,12 +130,23 @@ struct Cohort {
 // and both p50 and p99 latency came out higher than with one.
 constexpr int kCohorts = 1;
 
+// A graph's device buffers saved in host memory while it is evicted.
+struct Saved {
+  DevBuf *buf;
+  size_t bytes;
+  std::vector<char> host;
+};
+
 struct GState {
   Graph *g = nullptr;
   Cohort co[kCohorts];
   std::deque<Query *> pending;
   std::vector<int32_t *> free_bufs;
-  size_t bytes = 0;
+  size_t bytes = 0;            // layout + lane state while resident
+  size_t layout_bytes = 0;
+  bool resident = true;
+  std::vector<Saved> saved;    // device buffers kept on the host while evicted
+  int64_t last_use = 0;        // last admission (eviction order)
   // adaptive mode: cost model and the query served alone this round
   double t_single_ms = 0, t_level_ms = 0, levels_per_query = 0;
   Query *single = nullptr;
@@ -145,26 +165,66 @@ struct GState {
 // running average with weight 1/4 for the newest sample (first sample taken as is)
 void ema(double &avg, double x) { avg = avg > 0 ? 0.75 * avg + 0.25 * x : x; }
 
+// The device buffers of a graph's layout.
+std::vector<DevBuf *> graph_bufs(Graph *g) {
+  return {&g->deg, &g->did, &g->vid_of, &g->noff, &g->ncol, &g->doff, &g->dcol, &g->ndsrc,
+          &g->ddsrc_mask, &g->dnsrc_mask, &g->nds_off, &g->nds_col, &g->nds_first, &g->dd_first,
+          &g->nlen, &g->nnsrc, &g->poff, &g->pcol};
+}
+
+void cohort_init(Cohort &c, Graph *g, bool batched);
+void cohort_free(Cohort &c);
+
+constexpr int kMaxGraphs = 256;
+
 }  // namespace
 
 constexpr int32_t kJoinLevels = 2;
 
 struct Server {
   dsbfs_server_opts o{};
+  int32_t join_levels = kJoinLevels;
   int device = 0;
+  Alloc al;                       // result rows: the caller's allocator, else hipMalloc
   std::mutex mu;
   std::condition_variable cv_work, cv_done;
-  std::vector<GState *> graphs;
+  // Graphs are never removed while the server runs: the scheduler reads the
+  // count once per pass and the entries below it without the lock.
+  GState *graphs[kMaxGraphs] = {};
+  std::atomic<int32_t> ngraphs{0};
   std::unordered_map<int64_t, Query *> queries;
   int64_t next_ticket = 1;
   size_t used_bytes = 0;
+  int64_t loads = 0, evictions = 0, budget_waits = 0, done_count = 0;
+  std::vector<int32_t *> drop;    // rows to free outside the lock
   bool stop = false;
   std::string thread_error;
   std::thread th;
 
   size_t row_bytes(const GState *G) const { return size_t(G->g->n) * 4; }
 
-  // Gets a result row for G within the budget (caller holds mu).
+  int32_t *alloc_row(size_t bytes) {
+    void *p = nullptr;
+    try {
+      p = al.get(bytes, nullptr);
+    } catch (const Error &) {
+      return nullptr;
+    }
+    return static_cast<int32_t *>(p);
+  }
+
+  // Frees rows dropped to make room (scheduler thread, lock not held).
+  void free_dropped() {
+    std::vector<int32_t *> d;
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      d.swap(drop);
+    }
+    for (int32_t *p : d) al.put(p, nullptr);
+  }
+
+  // Gets a result row for G within the budget (caller holds mu). Cached rows
+  // of other graphs dropped to make room are freed later, outside the lock.
   int32_t *take_row(GState *G) {
     if (!G->free_bufs.empty()) {
       int32_t *p = G->free_bufs.back();
@@ -173,34 +233,122 @@ struct Server {
     }
     const size_t need = row_bytes(G);
     if (used_bytes + need > o.hbm_budget_bytes) {
-      // drop cached rows of other graphs to make room
-      for (GState *H : graphs) {
+      const int32_t ng = ngraphs.load(std::memory_order_acquire);
+      for (int32_t i = 0; i < ng; ++i) {
+        GState *H = graphs[i];
         while (!H->free_bufs.empty() && used_bytes + need > o.hbm_budget_bytes) {
-          (void)hipFree(H->free_bufs.back());
+          drop.push_back(H->free_bufs.back());
           H->free_bufs.pop_back();
           used_bytes -= row_bytes(H);
         }
       }
       if (used_bytes + need > o.hbm_budget_bytes) return nullptr;
     }
-    void *p = nullptr;
-    if (hipMalloc(&p, need) != hipSuccess || !p) {
-      (void)hipGetLastError();
-      return nullptr;
-    }
+    int32_t *p = alloc_row(need);
+    if (!p) return nullptr;
     used_bytes += need;
-    return static_cast<int32_t *>(p);
+    return p;
+  }
+
+  // A query that found no budget for its row or its graph (counted once).
+  void budget_wait(Query *q) {
+    if (!q->waited_budget) {
+      q->waited_budget = 1;
+      ++budget_waits;
+    }
+  }
+
+  bool idle(const GState *G) const {
+    return G->resident && !G->running() && !G->in_flight() && !G->single && G->pending.empty();
+  }
+
+  // Graph residency (scheduler thread). evict: an idle graph's layout goes
+  // to host memory and its lane state and cached rows are freed. load: the
+  // reverse, for a graph with waiting queries, after evicting idle graphs
+  // (least recently used first) until it fits. Returns false when it cannot
+  // fit yet (queries of other graphs hold the budget).
+  void evict(GState *G) {
+    for (Cohort &c : G->co) cohort_free(c);
+    std::vector<int32_t *> rows;
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      rows.swap(G->free_bufs);
+      for (size_t i = 0; i < rows.size(); ++i) used_bytes -= row_bytes(G);
+      used_bytes -= G->bytes;
+      G->resident = false;
+      ++evictions;
+    }
+    for (int32_t *p : rows) al.put(p, nullptr);
+    for (DevBuf *b : graph_bufs(G->g)) {
+      if (!b->p) continue;
+      Saved sv{b, b->bytes, std::vector<char>(b->bytes)};
+      HIPCHK(hipMemcpy(sv.host.data(), b->p, b->bytes, hipMemcpyDeviceToHost));
+      b->reset();
+      G->saved.push_back(std::move(sv));
+    }
+  }
+
+  bool make_resident(GState *G) {
+    const size_t need = G->bytes;  // layout + lane state
+    while (true) {
+      GState *victim = nullptr;
+      {
+        std::lock_guard<std::mutex> lk(mu);
+        if (used_bytes + need + row_bytes(G) <= o.hbm_budget_bytes) {
+          used_bytes += need;   // reserved before the copies
+          break;
+        }
+        const int32_t ng = ngraphs.load(std::memory_order_acquire);
+        for (int32_t i = 0; i < ng; ++i) {
+          GState *H = graphs[i];
+          if (H != G && idle(H) && (!victim || H->last_use < victim->last_use)) victim = H;
+        }
+        if (!victim) {
+          if (!G->pending.empty()) budget_wait(G->pending.front());
+          return false;
+        }
+      }
+      evict(victim);
+    }
+    for (Saved &sv : G->saved) {
+      sv.buf->alloc(&G->g->al, sv.bytes, nullptr);
+      HIPCHK(hipMemcpy(sv.buf->p, sv.host.data(), sv.bytes, hipMemcpyHostToDevice));
+    }
+    G->saved.clear();
+    const int nco = o.batched ? kCohorts : 1;
+    for (int i = 0; i < nco; ++i) cohort_init(G->co[i], G->g, o.batched != 0);
+    std::lock_guard<std::mutex> lk(mu);
+    G->resident = true;
+    ++loads;
+    for (Query *q : G->pending) q->loaded_graph = 1;
+    return true;
+  }
+
+  // Loads the graphs that have waiting queries but are on the host.
+  void ensure_resident() {
+    const int32_t ng = ngraphs.load(std::memory_order_acquire);
+    for (int32_t i = 0; i < ng; ++i) {
+      GState *G = graphs[i];
+      bool want;
+      {
+        std::lock_guard<std::mutex> lk(mu);
+        want = !G->resident && !G->pending.empty();
+      }
+      if (want) make_resident(G);
+    }
   }
 
   void finish(Query *q, GState *G, int64_t t) {
     q->done = t;
     q->state = Q_DONE;
+    ++done_count;
     (void)G;
   }
 
   bool has_work() const {
-    for (const GState *G : graphs)
-      if (G->running() || !G->pending.empty()) return true;
+    const int32_t ng = ngraphs.load(std::memory_order_acquire);
+    for (int32_t i = 0; i < ng; ++i)
+      if (graphs[i]->running() || !graphs[i]->pending.empty()) return true;
     return false;
   }
 
@@ -223,11 +371,15 @@ struct Server {
   void admit(GState *G, uint64_t lane_cap, bool adaptive, int64_t t) {
     for (Cohort &c : G->co)
       if (!c.launched) c.new_lanes = 0;
-    if (G->pending.empty()) return;
+    if (G->pending.empty() || !G->resident) return;
+    G->last_use = t;
     if (adaptive && !G->running() && !G->in_flight() && serve_alone(G)) {
       Query *q = G->pending.front();
       int32_t *row = take_row(G);
-      if (!row) return;  // budget: wait for releases
+      if (!row) {  // budget: wait for releases
+        budget_wait(q);
+        return;
+      }
       G->pending.pop_front();
       q->res = row;
       q->admit = q->start = t;
@@ -239,7 +391,7 @@ struct Server {
     for (int pass = 0; pass < 2 && !G->pending.empty(); ++pass) {
       for (Cohort &c : G->co) {
         if (c.launched || G->pending.empty()) continue;
-        const bool joinable = c.used && c.L - c.batch_start < kJoinLevels;
+        const bool joinable = c.used && c.L - c.batch_start < join_levels;
         if (pass == 0 ? !joinable : c.used != 0) continue;
         if (!c.used) c.batch_start = c.L;
         uint64_t free = ~c.used & lane_cap;
@@ -248,6 +400,7 @@ struct Server {
           Query *q = G->pending.front();
           int32_t *row = take_row(G);
           if (!row) {  // budget: the rest waits for releases
+            budget_wait(q);
             no_budget = true;
             break;
           }
@@ -357,27 +510,34 @@ struct Server {
     run_opts_default(&ro);
     ro.want_parent = 0;
     while (true) {
+      const int32_t ng = ngraphs.load(std::memory_order_acquire);
       bool in_flight = false;
-      for (const GState *G : graphs) in_flight = in_flight || G->in_flight();
+      for (int32_t i = 0; i < ng; ++i) in_flight = in_flight || graphs[i]->in_flight();
       {
         std::unique_lock<std::mutex> lk(mu);
         if (!in_flight) cv_work.wait(lk, [&] { return stop || has_work(); });
         if (stop) return;
-        const int64_t t = now_ns();
-        for (GState *G : graphs)
-          if (!G->single) admit(G, lane_cap, adaptive, t);
       }
+      ensure_resident();
+      {
+        std::lock_guard<std::mutex> lk(mu);
+        const int64_t t = now_ns();
+        for (int32_t i = 0; i < ng; ++i)
+          if (!graphs[i]->single) admit(graphs[i], lane_cap, adaptive, t);
+      }
+      free_dropped();
       bool started = false;
-      for (GState *G : graphs)
-        for (Cohort &c : G->co)
+      for (int32_t i = 0; i < ng; ++i)
+        for (Cohort &c : graphs[i]->co)
           if (!c.launched && c.used) {
-            launch_level(G, c);
+            launch_level(graphs[i], c);
             started = true;
           }
       // queries served alone run while the levels of other graphs are in
       // flight (on the first cohort's workspace, idle when one is chosen)
       bool progressed = false;
-      for (GState *G : graphs) {
+      for (int32_t i = 0; i < ng; ++i) {
+        GState *G = graphs[i];
         Query *q = G->single;
         if (!q) continue;
         Cohort &c = G->co[0];
@@ -394,13 +554,13 @@ struct Server {
         G->single = nullptr;
         progressed = true;
       }
-      for (GState *G : graphs)
-        for (Cohort &c : G->co) {
+      for (int32_t i = 0; i < ng; ++i)
+        for (Cohort &c : graphs[i]->co) {
           if (!c.launched) continue;
           const hipError_t e = hipEventQuery(c.ev);
           if (e == hipErrorNotReady) continue;
           HIPCHK(e);
-          complete_level(G, c);
+          complete_level(graphs[i], c);
           progressed = true;
         }
       if (progressed) {
@@ -408,7 +568,7 @@ struct Server {
         continue;
       }
       in_flight = false;
-      for (const GState *G : graphs) in_flight = in_flight || G->in_flight();
+      for (int32_t i = 0; i < ng; ++i) in_flight = in_flight || graphs[i]->in_flight();
       if (in_flight) {
         if (!started) std::this_thread::sleep_for(std::chrono::microseconds(20));
       } else {
@@ -430,23 +590,40 @@ struct Server {
         std::unique_lock<std::mutex> lk(mu);
         cv_work.wait(lk, [&] { return stop || has_work(); });
         if (stop) return;
-        // oldest waiting query over all graphs
-        for (GState *H : graphs)
-          if (!H->pending.empty() &&
+      }
+      ensure_resident();
+      {
+        std::unique_lock<std::mutex> lk(mu);
+        // oldest waiting query over the resident graphs
+        const int32_t ng = ngraphs.load(std::memory_order_acquire);
+        for (int32_t i = 0; i < ng; ++i) {
+          GState *H = graphs[i];
+          if (H->resident && !H->pending.empty() &&
               (!q || H->pending.front()->arrival < q->arrival)) {
             q = H->pending.front();
             G = H;
           }
+        }
+        if (!q) {   // every waiting query's graph is on the host and cannot fit yet
+          cv_done.wait_for(lk, std::chrono::milliseconds(1));
+          continue;
+        }
         int32_t *row = take_row(G);
         if (!row) {
+          budget_wait(q);
+          lk.unlock();
+          free_dropped();
+          lk.lock();
           cv_done.wait_for(lk, std::chrono::milliseconds(1));
           continue;
         }
         G->pending.pop_front();
+        G->last_use = now_ns();
         q->res = row;
         q->admit = q->start = now_ns();
         q->state = Q_RUNNING;
       }
+      free_dropped();
       bfs_run(G->g, G->co[0].ws, q->source, &ro, q->res, nullptr, nullptr, G->co[0].stream);
       HIPCHK(hipStreamSynchronize(G->co[0].stream));
       {
@@ -478,9 +655,15 @@ Server *server_create(const dsbfs_server_opts *o, const dsbfs_allocator *alloc) 
     fail(DSBFS_ERR_INVALID_ARG, "batched must be 0 (plain), 1 (batched) or 2 (adaptive)");
   if (o->ms.bu_permille < 0 || o->ms.bu_permille > 1000)
     fail(DSBFS_ERR_INVALID_ARG, "ms.bu_permille must be in [0, 1000]");
-  (void)alloc;  // result rows come from hipMalloc: the scheduler thread never calls back
+  if (alloc && (!alloc->alloc || !alloc->free))
+    fail(DSBFS_ERR_INVALID_ARG, "allocator needs both alloc and free");
   Server *S = new Server();
   S->o = *o;
+  S->join_levels = o->join_levels > 0 ? o->join_levels : kJoinLevels;
+  if (alloc) {
+    S->al.a = *alloc;
+    S->al.custom = true;
+  }
   HIPCHK(hipGetDevice(&S->device));
   S->th = std::thread([S] { S->run(); });
   return S;
@@ -523,17 +706,38 @@ void server_add_graph(Server *S, Graph *g, int32_t *id) {
     G->g = g;
     // the plain server needs one search workspace; batched modes one per cohort
     const int nco = S->o.batched ? kCohorts : 1;
-    G->bytes = graph_footprint(g);
+    G->layout_bytes = graph_footprint(g);
+    G->bytes = G->layout_bytes;
     for (int i = 0; i < nco; ++i) {
       cohort_init(G->co[i], g, S->o.batched != 0);
       G->bytes += workspace_footprint(G->co[i].ws);
     }
+    bool fits;
+    {
+      std::lock_guard<std::mutex> lk(S->mu);
+      if (S->ngraphs.load() >= kMaxGraphs) fail(DSBFS_ERR_INVALID_ARG, "too many graphs");
+      if (G->bytes + S->row_bytes(G) > S->o.hbm_budget_bytes)
+        fail(DSBFS_ERR_BUDGET, "graph and one result row can never fit the HBM budget");
+      fits = S->used_bytes + G->bytes <= S->o.hbm_budget_bytes;
+      if (fits) S->used_bytes += G->bytes;
+    }
+    if (!fits) {
+      // not visible to the scheduler yet: keep it on the host until a query needs it
+      for (Cohort &c : G->co) cohort_free(c);
+      for (DevBuf *b : graph_bufs(g)) {
+        if (!b->p) continue;
+        Saved sv{b, b->bytes, std::vector<char>(b->bytes)};
+        HIPCHK(hipMemcpy(sv.host.data(), b->p, b->bytes, hipMemcpyDeviceToHost));
+        b->reset();
+        G->saved.push_back(std::move(sv));
+      }
+      G->resident = false;
+    }
     std::lock_guard<std::mutex> lk(S->mu);
-    if (S->used_bytes + G->bytes > S->o.hbm_budget_bytes)
-      fail(DSBFS_ERR_BUDGET, "graph does not fit the HBM budget");
-    S->used_bytes += G->bytes;
-    *id = int32_t(S->graphs.size());
-    S->graphs.push_back(G);
+    const int32_t i = S->ngraphs.load();
+    S->graphs[i] = G;
+    *id = i;
+    S->ngraphs.store(i + 1, std::memory_order_release);
   } catch (...) {
     for (Cohort &c : G->co) cohort_free(c);
     delete G;
@@ -544,13 +748,9 @@ void server_add_graph(Server *S, Graph *g, int32_t *id) {
 void server_submit(Server *S, int32_t gid, int32_t source, int64_t arrival, int64_t *ticket) {
   std::lock_guard<std::mutex> lk(S->mu);
   if (!S->thread_error.empty()) fail(DSBFS_ERR_HIP, "server stopped: " + S->thread_error);
-  if (gid < 0 || gid >= int32_t(S->graphs.size())) fail(DSBFS_ERR_INVALID_ARG, "unknown graph id");
+  if (gid < 0 || gid >= S->ngraphs.load()) fail(DSBFS_ERR_INVALID_ARG, "unknown graph id");
   GState *G = S->graphs[gid];
   if (source < 0 || source >= G->g->n) fail(DSBFS_ERR_INVALID_ARG, "source outside [0, n)");
-  size_t resident = 0;
-  for (const GState *H : S->graphs) resident += H->bytes;
-  if (resident + S->row_bytes(G) > S->o.hbm_budget_bytes)
-    fail(DSBFS_ERR_BUDGET, "a result row of this graph can never fit the HBM budget");
   Query *q = new Query();
   q->ticket = S->next_ticket++;
   q->gid = gid;
@@ -584,8 +784,24 @@ dsbfs_status server_wait(Server *S, int64_t ticket, int64_t timeout_ns, const in
     st->source = q->source;
     st->levels = q->levels;
     st->batched = q->batched;
+    st->waited_budget = q->waited_budget;
+    st->loaded_graph = q->loaded_graph;
   }
   return DSBFS_OK;
+}
+
+void server_stats(Server *S, dsbfs_server_stats *st) {
+  std::lock_guard<std::mutex> lk(S->mu);
+  *st = dsbfs_server_stats{};
+  st->budget_bytes = int64_t(S->o.hbm_budget_bytes);
+  st->used_bytes = int64_t(S->used_bytes);
+  const int32_t ng = S->ngraphs.load();
+  st->graphs = ng;
+  for (int32_t i = 0; i < ng; ++i) st->resident_graphs += S->graphs[i]->resident;
+  st->loads = S->loads;
+  st->evictions = S->evictions;
+  st->budget_waits = S->budget_waits;
+  st->queries_done = S->done_count;
 }
 
 void server_release(Server *S, int64_t ticket) {
@@ -611,12 +827,15 @@ void server_destroy(Server *S) {
   S->cv_done.notify_all();
   if (S->th.joinable()) S->th.join();
   for (auto &kv : S->queries) {
-    if (kv.second->res) (void)hipFree(kv.second->res);
+    if (kv.second->res) S->al.put(kv.second->res, nullptr);
     delete kv.second;
   }
-  for (GState *G : S->graphs) {
+  for (int32_t *p : S->drop) S->al.put(p, nullptr);
+  const int32_t ng = S->ngraphs.load();
+  for (int32_t i = 0; i < ng; ++i) {
+    GState *G = S->graphs[i];
     for (Cohort &c : G->co) cohort_free(c);
-    for (int32_t *p : G->free_bufs) (void)hipFree(p);
+    for (int32_t *p : G->free_bufs) S->al.put(p, nullptr);
     graph_destroy(G->g);
     delete G;
   }

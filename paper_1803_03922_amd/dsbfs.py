@@ -58,33 +58,44 @@ class dsbfs_build_opts(ctypes.Structure):
 class dsbfs_graph_stats(ctypes.Structure):
     _fields_ = [(k, i64) for k in ("n", "m_dir", "d", "e_nn", "e_nd", "e_dn", "e_dd", "n_ndsrc",
                                    "n_ddsrc", "n_dnsrc", "max_degree", "bytes_layout",
-                                   "bytes_plain")] + [("threshold", i32), ("reserved", i32)]
+                                   "bytes_plain")] + [("threshold", i32), ("reserved", i32),
+                                                      ("n_nnsrc", i64)]
 
     def as_dict(self):
         return {k: int(getattr(self, k)) for k, _ in self._fields_ if k != "reserved"}
 
 
+class dsbfs_rmat_spec(ctypes.Structure):
+    _fields_ = [("scale", i32), ("permute", i32), ("num_edges", i64), ("a", ctypes.c_double),
+                ("b", ctypes.c_double), ("c", ctypes.c_double), ("seed", ctypes.c_uint64),
+                ("perm_seed", ctypes.c_uint64)]
+
+
 class dsbfs_run_opts(ctypes.Structure):
     _fields_ = [("mode", i32), ("want_parent", i32), ("factor0", ctypes.c_double * 3),
                 ("factor1", ctypes.c_double * 3), ("forced", i32), ("profile", i32),
-                ("forced_seed", ctypes.c_uint64)]
+                ("forced_seed", ctypes.c_uint64), ("nn_do", i32), ("reserved", i32),
+                ("factor0_nn", ctypes.c_double), ("factor1_nn", ctypes.c_double)]
 
 
 class dsbfs_level_stats(ctypes.Structure):
     _fields_ = [("q", i64 * 3), ("s", i64 * 3), ("U", i64 * 3), ("FV", i64 * 3),
                 ("BV", ctypes.c_double * 3), ("dir", i32 * 3), ("reserved", i32),
                 ("FV_nn", i64), ("q_nn", i64), ("frontier_normal", i64),
-                ("frontier_delegate", i64), ("kernel_ms", ctypes.c_double * 9)]
+                ("frontier_delegate", i64), ("kernel_ms", ctypes.c_double * 11),
+                ("U_nn", i64), ("s_nn", i64), ("BV_nn", ctypes.c_double), ("dir_nn", i32),
+                ("reserved2", i32)]
 
     def as_dict(self):
         return {"q": list(self.q), "s": list(self.s), "U": list(self.U), "FV": list(self.FV),
                 "BV": list(self.BV), "dir": list(self.dir), "FV_nn": int(self.FV_nn),
                 "q_nn": int(self.q_nn), "frontier_normal": int(self.frontier_normal),
-                "frontier_delegate": int(self.frontier_delegate)}
+                "frontier_delegate": int(self.frontier_delegate), "U_nn": int(self.U_nn),
+                "s_nn": int(self.s_nn), "BV_nn": float(self.BV_nn), "dir_nn": int(self.dir_nn)}
 
 
 KERNEL_NAMES = ("init", "prev_normal", "prev_deleg", "td_normal", "td_deleg", "bu_normal",
-                "bu_deleg", "close", "plain")
+                "bu_deleg", "close", "plain", "td_nn", "bu_nn")
 
 
 class dsbfs_kernel_profile(ctypes.Structure):
@@ -107,12 +118,21 @@ class dsbfs_ms_opts(ctypes.Structure):
 
 class dsbfs_query_stats(ctypes.Structure):
     _fields_ = [("arrival_ns", i64), ("admit_ns", i64), ("start_ns", i64), ("done_ns", i64),
-                ("graph_id", i32), ("source", i32), ("levels", i32), ("batched", i32)]
+                ("graph_id", i32), ("source", i32), ("levels", i32), ("batched", i32),
+                ("waited_budget", i32), ("loaded_graph", i32)]
+
+
+class dsbfs_server_stats(ctypes.Structure):
+    _fields_ = [(k, i64) for k in ("budget_bytes", "used_bytes", "graphs", "resident_graphs",
+                                   "loads", "evictions", "budget_waits", "queries_done")]
+
+    def as_dict(self):
+        return {k: int(getattr(self, k)) for k, _ in self._fields_}
 
 
 class dsbfs_server_opts(ctypes.Structure):
     _fields_ = [("hbm_budget_bytes", ctypes.c_size_t), ("max_lanes", i32), ("batched", i32),
-                ("ms", dsbfs_ms_opts)]
+                ("ms", dsbfs_ms_opts), ("join_levels", i32), ("reserved", i32)]
 
 
 def _sig(name, res, args):
@@ -133,6 +153,14 @@ dsbfs_workspace_create = _sig("dsbfs_workspace_create", i32, [vp, i32, ctypes.PO
 dsbfs_workspace_destroy = _sig("dsbfs_workspace_destroy", i32, [vp])
 dsbfs_bfs = _sig("dsbfs_bfs", i32, [vp, vp, i32, ctypes.POINTER(dsbfs_run_opts), vp, vp,
                                     ctypes.POINTER(dsbfs_run_stats), vp])
+dsbfs_rmat_generate = _sig("dsbfs_rmat_generate", i32, [ctypes.POINTER(dsbfs_rmat_spec), vp, vp,
+                                                        vp])
+dsbfs_graph_create_rmat = _sig("dsbfs_graph_create_rmat", i32,
+                               [ctypes.POINTER(dsbfs_rmat_spec), ctypes.POINTER(dsbfs_build_opts),
+                                ctypes.POINTER(dsbfs_allocator), vp, ctypes.POINTER(vp)])
+dsbfs_pagerank = _sig("dsbfs_pagerank", i32, [vp, ctypes.c_double, i32, ctypes.c_double, vp,
+                                              ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double),
+                                              vp])
 dsbfs_bfs_noalloc = _sig("dsbfs_bfs_noalloc", i32, [vp, i32, ctypes.POINTER(dsbfs_run_opts), vp,
                                                     vp, ctypes.POINTER(dsbfs_run_stats), vp])
 dsbfs_msbfs = _sig("dsbfs_msbfs", i32, [vp, vp, I32P, i32, ctypes.POINTER(dsbfs_ms_opts), vp, vp])
@@ -146,6 +174,7 @@ dsbfs_server_submit = _sig("dsbfs_server_submit", i32, [vp, i32, i32, i64, I64P]
 dsbfs_server_wait = _sig("dsbfs_server_wait", i32, [vp, i64, i64, ctypes.POINTER(vp),
                                                     ctypes.POINTER(dsbfs_query_stats)])
 dsbfs_server_release = _sig("dsbfs_server_release", i32, [vp, i64])
+dsbfs_server_stats_get = _sig("dsbfs_server_stats_get", i32, [vp, ctypes.POINTER(dsbfs_server_stats)])
 dsbfs_server_destroy = _sig("dsbfs_server_destroy", i32, [vp])
 dsbfs_now_ns = _sig("dsbfs_now_ns", i64, [])
 dsbfs_status_str = _sig("dsbfs_status_str", ctypes.c_char_p, [i32])
@@ -264,7 +293,8 @@ PAPER_FACTOR0 = (0.5, 0.05, 1e-7)
 
 
 def run_opts(mode: int = 1, want_parent: bool = True, factor0=None, factor1=None,
-             forced: int = 0, forced_seed: int = 0, profile: bool = False) -> dsbfs_run_opts:
+             forced: int = 0, forced_seed: int = 0, profile: bool = False, nn_do: bool = False,
+             factor_nn=None) -> dsbfs_run_opts:
     o = dsbfs_run_opts()
     check(dsbfs_run_opts_default(ctypes.byref(o)), "dsbfs_run_opts_default")
     o.mode = mode
@@ -276,18 +306,51 @@ def run_opts(mode: int = 1, want_parent: bool = True, factor0=None, factor1=None
     o.forced = forced
     o.forced_seed = forced_seed
     o.profile = int(bool(profile))
+    o.nn_do = int(bool(nn_do))
+    if factor_nn is not None:
+        o.factor0_nn, o.factor1_nn = float(factor_nn[0]), float(factor_nn[1])
     return o
+
+
+def rmat_spec(scale: int, edge_factor: int = 16, seed: int | None = None, permute: bool = True,
+              a: float = 0.57, b: float = 0.19, c: float = 0.19,
+              perm_seed: int | None = None) -> dsbfs_rmat_spec:
+    """RMAT spec with the workload's conventions: graph seed
+    0x1803039220000000 + scale, relabelling seed graph seed ^ 1."""
+    gs = (0x1803039220000000 + scale) if seed is None else seed
+    ps = (gs ^ 1) if perm_seed is None else perm_seed
+    return dsbfs_rmat_spec(scale, int(permute), edge_factor << scale, a, b, c, gs, ps)
+
+
+def rmat_generate(spec: dsbfs_rmat_spec, stream: int | None = None):
+    """The RMAT edge list of spec on the device: (src, dst) int32 torch tensors."""
+    torch = _torch()
+    stream = current_stream() if stream is None else stream
+    src = torch.empty(max(spec.num_edges, 1), dtype=torch.int32, device="cuda")
+    dst = torch.empty_like(src)
+    check(dsbfs_rmat_generate(ctypes.byref(spec), _dev_ptr(src), _dev_ptr(dst), stream),
+          "dsbfs_rmat_generate")
+    return src[:spec.num_edges], dst[:spec.num_edges]
 
 
 class Graph:
     """A graph resident on the current GPU (dsbfs_graph)."""
 
     def __init__(self, src, dst, n: int, threshold: int = 32, keep_plain_csr: bool = True,
-                 allocator: TorchAllocator | None = None, stream: int | None = None):
+                 allocator: TorchAllocator | None = None, stream: int | None = None,
+                 rmat: dsbfs_rmat_spec | None = None):
+        """From an edge list (host numpy or device torch arrays), or, with
+        rmat given (src, dst, n ignored), generated on the device."""
         self.alloc = allocator or default_allocator()
         self.stream = current_stream() if stream is None else stream
         opts = dsbfs_build_opts(threshold, 0, int(keep_plain_csr), 0)
         h = vp()
+        if rmat is not None:
+            check(dsbfs_graph_create_rmat(ctypes.byref(rmat), ctypes.byref(opts),
+                                          ctypes.byref(self.alloc.struct), self.stream,
+                                          ctypes.byref(h)), "dsbfs_graph_create_rmat")
+            self._finish(h, 1 << rmat.scale)
+            return
         on_dev = not isinstance(src, np.ndarray)
         if on_dev:
             opts.edges_on_device = 1
@@ -301,6 +364,9 @@ class Graph:
         check(dsbfs_graph_create(ps, pd, g, n, ctypes.byref(opts), ctypes.byref(self.alloc.struct),
                                  self.stream, ctypes.byref(h)), "dsbfs_graph_create")
         self._src = self._dst = None
+        self._finish(h, n)
+
+    def _finish(self, h, n):
         self.h = h
         self.n = n
         st = dsbfs_graph_stats()
@@ -397,6 +463,18 @@ def bfs_noalloc(graph: Graph, source: int, depth, parent=None, opts=None,
                             _dev_ptr(parent), None, stream), "dsbfs_bfs_noalloc")
 
 
+def pagerank(graph: Graph, rank, alpha: float = 0.85, iterations: int = 20,
+             tolerance: float = 0.0, stream: int | None = None):
+    """dsbfs_pagerank into a device float64 tensor rank[n]; returns
+    (steps run, last L1 change)."""
+    stream = current_stream() if stream is None else stream
+    it = i32(0)
+    dl = ctypes.c_double(0.0)
+    check(dsbfs_pagerank(graph.h, alpha, iterations, tolerance, _dev_ptr(rank), ctypes.byref(it),
+                         ctypes.byref(dl), stream), "dsbfs_pagerank")
+    return it.value, dl.value
+
+
 def msbfs(graph: Graph, ws: Workspace, sources, depth, opts: dsbfs_ms_opts | None = None,
           stream: int | None = None):
     stream = current_stream() if stream is None else stream
@@ -442,15 +520,23 @@ class Server:
     PLAIN, BATCHED, ADAPTIVE = 0, 1, 2
 
     def __init__(self, budget_bytes: int, max_lanes: int = 64, batched: bool | int = True,
-                 ms: dsbfs_ms_opts | None = None):
-        """batched: False/0 plain, True/1 continuous batching, 2 adaptive."""
+                 ms: dsbfs_ms_opts | None = None, join_levels: int = 0,
+                 allocator: TorchAllocator | None = None):
+        """batched: False/0 plain, True/1 continuous batching, 2 adaptive.
+        allocator: result rows from it (e.g. default_allocator(), PyTorch's
+        caching allocator; its callbacks then run on the scheduler thread),
+        else from hipMalloc."""
         o = dsbfs_server_opts()
         o.hbm_budget_bytes = int(budget_bytes)
         o.max_lanes = max_lanes
         o.batched = int(batched)
         o.ms = ms if ms is not None else dsbfs_ms_opts(256, 4, 2, 0)
+        o.join_levels = join_levels
+        self.alloc = allocator
         h = vp()
-        check(dsbfs_server_create(ctypes.byref(o), None, ctypes.byref(h)), "dsbfs_server_create")
+        check(dsbfs_server_create(ctypes.byref(o),
+                                  ctypes.byref(allocator.struct) if allocator else None,
+                                  ctypes.byref(h)), "dsbfs_server_create")
         self.h = h
         self.n_of = {}
         _track(self)
@@ -478,6 +564,11 @@ class Server:
 
     def release(self, ticket: int):
         check(dsbfs_server_release(self.h, ticket), "dsbfs_server_release")
+
+    def stats(self) -> dict:
+        st = dsbfs_server_stats()
+        check(dsbfs_server_stats_get(self.h, ctypes.byref(st)), "dsbfs_server_stats_get")
+        return st.as_dict()
 
     def destroy(self):
         if self.h:

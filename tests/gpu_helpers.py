@@ -41,10 +41,11 @@ class GpuGraph:
         return self.g.stats
 
     def bfs(self, s, mode=1, forced=0, seed=0, want_parent=True, want_stats=False,
-            factor0=None, factor1=None, profile=False):
+            factor0=None, factor1=None, profile=False, nn_do=False, factor_nn=None):
         d = lib()
         o = d.run_opts(mode=mode, want_parent=want_parent, forced=forced, forced_seed=seed,
-                       factor0=factor0, factor1=factor1, profile=profile)
+                       factor0=factor0, factor1=factor1, profile=profile, nn_do=nn_do,
+                       factor_nn=factor_nn)
         st = d.bfs(self.g, self.ws, s, self.depth, self.parent if want_parent else None, opts=o,
                    want_stats=want_stats)
         self.torch.cuda.synchronize()

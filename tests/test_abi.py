@@ -19,7 +19,7 @@ def test_header_symbols_exported():
     from paper_1803_03922_amd import dsbfs
     lib = ctypes.CDLL(dsbfs.LIB_PATH)
     names = _declared()
-    assert len(names) == 20
+    assert len(names) == 24
     for name in names:
         assert hasattr(lib, name), name
     # and the binding wraps every one of them under the same name
@@ -46,6 +46,8 @@ def test_default_factors():
     assert paper == {"DD": 0.5, "DN": 0.05, "ND": 1e-7}
     assert list(o.factor1) == [0.0, 0.0, 0.0]
     assert o.mode == 1 and o.want_parent == 1 and o.forced == 0
+    # nn stays forward unless the DO-on-nn variant is asked for
+    assert o.nn_do == 0 and o.factor0_nn == 1e-3 and o.factor1_nn == 0.0
 
 
 def test_host_side_argument_errors():
@@ -66,6 +68,13 @@ def test_host_side_argument_errors():
     assert dsbfs.dsbfs_workspace_destroy(None) == 0
     assert dsbfs.dsbfs_server_destroy(None) == 0
     assert dsbfs.dsbfs_server_create(None, None, None) == dsbfs.ERR_INVALID_ARG
+    assert dsbfs.dsbfs_server_stats_get(None, None) == dsbfs.ERR_INVALID_ARG
+    assert dsbfs.dsbfs_graph_create_rmat(None, None, None, None, None) == dsbfs.ERR_INVALID_ARG
+    assert dsbfs.dsbfs_pagerank(None, 0.85, 1, 0.0, None, None, None, None) == dsbfs.ERR_INVALID_ARG
+    sp = dsbfs.rmat_spec(40)
+    assert dsbfs.dsbfs_rmat_generate(ctypes.byref(sp), None, None, None) == dsbfs.ERR_INVALID_ARG
+    sp = dsbfs.rmat_spec(10, a=0.7, b=0.3, c=0.3)
+    assert dsbfs.dsbfs_rmat_generate(ctypes.byref(sp), None, None, None) == dsbfs.ERR_INVALID_ARG
 
 
 def test_now_is_monotonic():

@@ -340,6 +340,10 @@ def test_builder_layout_matches_oracle_split(inputs_mod, oracle_mod, scale, TH):
     nn_len = np.diff(r["nn_off"])
     nd_len = np.diff(r["nd_off"])
     np.testing.assert_array_equal(nf[:n], nn_len)
+    lens = g.export(16, np.uint16).astype(np.int64)
+    fits = (nn_len < 255) & (nd_len < 255)
+    np.testing.assert_array_equal(lens[fits], (nn_len | (nd_len << 8))[fits])
+    assert np.all(lens[~fits] == 0xFFFF)
     np.testing.assert_array_equal(np.diff(ns), nn_len + nd_len)
     deg = O.degrees()
     vid = np.nonzero(r["did"] >= 0)[0]
@@ -365,6 +369,9 @@ def test_builder_layout_matches_oracle_split(inputs_mod, oracle_mod, scale, TH):
         assert row[df[k]:].tolist() == r["dn_col"][r["dn_off"][k]:r["dn_off"][k + 1]].tolist()
     nd_src = np.nonzero(nd_len > 0)[0]
     np.testing.assert_array_equal(g.export(7, np.int32), nd_src)
+    nn_src = np.nonzero(nn_len > 0)[0]
+    np.testing.assert_array_equal(g.export(17, np.int32), nn_src)
+    assert G.stats["n_nnsrc"] == len(nn_src)
     nds_off = g.export(12, np.int64)
     nds_col = g.export(13, np.int32)
     np.testing.assert_array_equal(np.diff(nds_off), nd_len[nd_src])

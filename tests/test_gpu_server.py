@@ -160,8 +160,8 @@ def test_server_budget_admission(inputs_mod, oracle_mod):
     assert e.value.status == d.ERR_BUDGET
     g.destroy()
     S.destroy()
-    # find the exact resident footprint (smallest budget that admits the
-    # graph, by bisection), then allow exactly two result rows of 4n bytes
+    # find the smallest budget that admits the graph (its resident footprint
+    # plus one result row, by bisection), then allow exactly two result rows
     def admits(budget):
         S = d.Server(budget, batched=True)
         g = d.Graph(src, dst, n, threshold=16, keep_plain_csr=True)
@@ -183,8 +183,8 @@ def test_server_budget_admission(inputs_mod, oracle_mod):
             hi = mid
         else:
             lo = mid
-    foot = hi
-    S = d.Server(foot + 3 * 4 * n - 1, batched=True)
+    foot = hi   # footprint + one row of 4n bytes
+    S = d.Server(foot + 2 * 4 * n - 1, batched=True)
     gid = S.add_graph(d.Graph(src, dst, n, threshold=16, keep_plain_csr=True))
     sources = inputs_mod.pick_sources(src, dst, n, 5, seed=3)
     ts = [S.submit(gid, int(s)) for s in sources]
@@ -201,12 +201,11 @@ def test_server_budget_admission(inputs_mod, oracle_mod):
         row, _ = _fetch(S, t, n)
         np.testing.assert_array_equal(row, O.bfs(int(s), want_parent=False)[0])
     S.destroy()
-    # a row that can never fit is refused at submission
-    S = d.Server(foot + 16, batched=True)
-    gid = S.add_graph(d.Graph(src, dst, n, threshold=16, keep_plain_csr=True))
-    with pytest.raises(d.DsbfsError) as e:
-        S.submit(gid, int(sources[0]))
-    assert e.value.status == d.ERR_BUDGET
+    # the footprint is what the server charges for the resident graph
+    S = d.Server(foot, batched=True)
+    S.add_graph(d.Graph(src, dst, n, threshold=16, keep_plain_csr=True))
+    st = S.stats()
+    assert st["used_bytes"] == foot - 4 * n and st["resident_graphs"] == 1
     S.destroy()
 
 
@@ -298,3 +297,130 @@ def test_server_real_mix_rows_match_digests(inputs_mod, batched):
     assert not bad, f"served rows differ from the oracle for (graph, source) {bad[:5]}"
     if batched == 1:
         assert sum(done) == len(keys)
+
+
+def _footprints(specs, batched):
+    """Resident bytes the server charges for each graph of specs."""
+    d = lib()
+    out = []
+    for n, src, dst, _ in specs:
+        S = d.Server(BIG, batched=batched)
+        S.add_graph(d.Graph(src, dst, n, threshold=16, keep_plain_csr=True))
+        out.append(S.stats()["used_bytes"])
+        S.destroy()
+    return out
+
+
+@pytest.mark.parametrize("batched", [1, 0, 2])
+def test_server_evicts_and_loads_graphs(inputs_mod, oracle_mod, batched):
+    """A budget that holds one graph (plus a few rows) at a time: graphs added
+    beyond it wait in host memory, idle graphs are evicted to make room, and
+    every query of every graph still gets the oracle's depths."""
+    d = lib()
+    torch_cuda()
+    # three RMAT scale-12 graphs of similar size (different seeds)
+    specs = []
+    for i in range(3):
+        src, dst = inputs_mod.rmat_edges(12, seed=inputs_mod.graph_seed(12) + 100 + i)
+        specs.append((1 << 12, src, dst, oracle_mod.Graph(src, dst, 1 << 12)))
+    fp = _footprints(specs, batched)
+    nmax = max(n for n, _, _, _ in specs)
+    budget = max(fp) + 6 * 4 * nmax
+    assert sorted(fp)[0] + sorted(fp)[1] > budget   # two graphs never fit together
+    S = d.Server(budget, batched=batched)
+    gids = [S.add_graph(d.Graph(s, t, n, threshold=16, keep_plain_csr=True))
+            for n, s, t, _ in specs]
+    st = S.stats()
+    assert st["graphs"] == 3 and st["resident_graphs"] == 1, st
+    rng = np.random.default_rng(11)
+    for rnd in range(3):
+        # one graph at a time: its queries are submitted, then collected (a
+        # client that held results while waiting for another graph's query
+        # could keep that graph from ever fitting)
+        for k in rng.permutation(3).tolist():
+            n, src, dst, O = specs[k]
+            srcs = inputs_mod.pick_sources(src, dst, n, 3, seed=700 + 10 * rnd + k).tolist()
+            ts = [S.submit(gids[k], s) for s in srcs]
+            for s, t in zip(srcs, ts):
+                row, qs = _fetch(S, t, n)
+                np.testing.assert_array_equal(row, O.bfs(s, want_parent=False)[0],
+                                              err_msg=f"round {rnd} graph {k} source {s}")
+                assert qs["graph_id"] == gids[k]
+        log(f"evict/load batched={batched} round {rnd}: {S.stats()}")
+    st = S.stats()
+    assert st["loads"] >= 4 and st["evictions"] >= 4, st
+    assert st["resident_graphs"] == 1 and st["used_bytes"] <= budget, st
+    assert st["queries_done"] == 3 * 3 * 3
+    S.destroy()
+
+
+def test_server_add_graph_while_serving(inputs_mod, oracle_mod):
+    """Graphs added from another thread while queries of the first one run."""
+    import threading
+    d = lib()
+    torch_cuda()
+    specs = _graphs(inputs_mod, oracle_mod)
+    S = d.Server(BIG, batched=2)
+    gids = [S.add_graph(d.Graph(specs[0][1], specs[0][2], specs[0][0], threshold=16,
+                                keep_plain_csr=True))]
+    n0, src0, dst0, O0 = specs[0]
+    stream_src = inputs_mod.pick_sources(src0, dst0, n0, 60, seed=41).tolist()
+    tickets = []
+
+    def client():
+        for i, s in enumerate(stream_src):
+            tickets.append((s, S.submit(gids[0], s)))
+            if i % 10 == 9:
+                time.sleep(0.001)
+
+    th = threading.Thread(target=client)
+    th.start()
+    for n, s, t, _ in specs[1:]:   # added while the client's queries are being served
+        gids.append(S.add_graph(d.Graph(s, t, n, threshold=16, keep_plain_csr=True)))
+    late = []
+    for k in (1, 2):
+        n, src, dst, _ = specs[k]
+        for s in inputs_mod.pick_sources(src, dst, n, 8, seed=50 + k).tolist():
+            late.append((k, s, S.submit(gids[k], s)))
+    th.join()
+    for s, t in tickets:
+        row, _ = _fetch(S, t, n0)
+        np.testing.assert_array_equal(row, O0.bfs(s, want_parent=False)[0])
+    for k, s, t in late:
+        n, _, _, O = specs[k]
+        row, _ = _fetch(S, t, n)
+        np.testing.assert_array_equal(row, O.bfs(s, want_parent=False)[0])
+    assert S.stats()["graphs"] == 3
+    S.destroy()
+
+
+def test_server_rows_from_allocator_and_budget_waits(inputs_mod, oracle_mod):
+    """Result rows from PyTorch's caching allocator (called on the scheduler
+    thread); with room for two rows, later queries wait for budget and are
+    counted."""
+    d = lib()
+    torch = torch_cuda()
+    specs = _graphs(inputs_mod, oracle_mod)[:1]
+    n, src, dst, O = specs[0]
+    fp = _footprints(specs, True)[0]
+    alloc = d.default_allocator()
+    S = d.Server(fp + 2 * 4 * n, batched=True, allocator=alloc)
+    gid = S.add_graph(d.Graph(src, dst, n, threshold=16, keep_plain_csr=True))
+    before = torch.cuda.memory_allocated()
+    sources = inputs_mod.pick_sources(src, dst, n, 6, seed=8).tolist()
+    ts = [S.submit(gid, s) for s in sources]
+    p0, _ = S.wait(ts[0])
+    p1, _ = S.wait(ts[1])
+    assert torch.cuda.memory_allocated() >= before + 2 * 4 * n   # rows came from torch
+    with pytest.raises(d.DsbfsError) as e:
+        S.wait(ts[2], timeout_ns=100_000_000)
+    assert e.value.status == d.ERR_NOT_READY
+    waited = []
+    for s, t in zip(sources, ts):
+        row, qs = _fetch(S, t, n)
+        np.testing.assert_array_equal(row, O.bfs(s, want_parent=False)[0])
+        waited.append(qs["waited_budget"])
+    assert waited[:2] == [0, 0] and sum(waited) >= 1
+    st = S.stats()
+    assert st["budget_waits"] == sum(waited) and st["queries_done"] == 6
+    S.destroy()
