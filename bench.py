@@ -255,8 +255,9 @@ def main():
     self_gbs = dk["bytes"] / (dk["ms"] * 1e-3) / 1e9 if dk["ms"] > 0 else 0.0
     unprof_ms = sum(sum(per_source_ms[s]) / len(per_source_ms[s]) for s in msrc)
 
-    def time_factors(f0):
-        o3 = dsbfs.run_opts(want_parent=parent is not None, factor0=f0)
+    def time_factors(f0, nn=None):
+        o3 = dsbfs.run_opts(want_parent=parent is not None, factor0=f0, nn_do=nn is not None,
+                            factor_nn=nn)
         tt, rr = [], []
         for i in range(args.factor_steps):
             s = int(sources[i % len(sources)])
@@ -276,6 +277,13 @@ def main():
                  "default_factor0": base, "default_gteps": gtd, "default_ms_per_search": mssd,
                  "sources": args.factor_steps}
         log(f"paper factors {dsbfs.PAPER_FACTOR0}: {gt} GTEPS; default {base}: {gtd} GTEPS")
+    # the DO-on-nn variant (nn under the direction decision too), per nn factor
+    nn_sweep = []
+    for fnn in ((1e-6, 0.0), (1e-4, 0.0), (1e-3, 0.0), (1e-2, 0.0), (1.0, 0.0)) if mode == 1 else ():
+        gt, mss = time_factors(base, nn=fnn)
+        nn_sweep.append({"factor0_nn": fnn[0], "factor1_nn": fnn[1], "gteps": gt,
+                         "ms_per_search": mss})
+        log(f"nn_do factor0_nn = {fnn[0]:g}: {gt} GTEPS")
     for ki, kname_f in enumerate(("dd", "dn", "nd")):
         for v in fvals if mode == 1 else []:
             f0 = list(base)
@@ -381,7 +389,7 @@ def main():
         "cpu_baseline": cpu,
         "work_model": model,
         "th_sweep": sweep,
-        "factors": {"paper_vs_default": paper, "sweep": fsweep},
+        "factors": {"paper_vs_default": paper, "sweep": fsweep, "nn_do": nn_sweep},
         "configs": configs,
         "batched": batched,
         "served": served,
