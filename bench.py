@@ -39,13 +39,14 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-def measured_traffic(kernel, workload):
+def measured_traffic(kernel, workload, source="bfs.hip"):
     """HBM bytes per launch of `kernel` from a committed rocprofv3 summary in
     profiles/ (FETCH_SIZE + WRITE_SIZE runs, calibrated on a copy kernel), if
-    one exists for this workload and for the current kernel source; else None."""
+    one exists for this workload and for the current text of the kernel's
+    source file (csrc/<source>); else None."""
     import glob
     import hashlib
-    src = os.path.join(ROOT, "paper_1803_03922_amd", "csrc", "bfs.hip")
+    src = os.path.join(ROOT, "paper_1803_03922_amd", "csrc", source)
     h = hashlib.sha256(open(src, "rb").read()).hexdigest()
     for f in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
         for line in open(f):
@@ -138,6 +139,9 @@ def main():
                     help="1: also measure multi-source BFS (RMAT scale --ms-scale, 1024 sources)")
     ap.add_argument("--ms-scale", type=int, default=24)
     ap.add_argument("--ms-sources", type=int, default=1024)
+    ap.add_argument("--ms-single", type=int, default=1,
+                    help="1 = time single-source DOBFS from the same sources beside the "
+                         "multi-source launch; 0 = skip it (profiling runs)")
     ap.add_argument("--served", type=int, default=1,
                     help="1: also measure the query server (5 graphs, 3 Poisson rates)")
     ap.add_argument("--serve-queries", type=int, default=4096)
@@ -145,7 +149,8 @@ def main():
     ap.add_argument("--factor-sweep", default="1e-8,1e-6,1e-4,1e-2,0.05,0.5,2,10",
                     help="comma-separated factor0 values tried for each of dd, dn, nd in turn "
                          "(the other two at their defaults); '' = none")
-    ap.add_argument("--factor-steps", type=int, default=16)
+    ap.add_argument("--factor-steps", type=int, default=16,
+                    help="sources timed per factor setting; 0 = no factor legs")
     ap.add_argument("--factor-grid", default="",
                     help="joint sweep: 'dd values;dn values;nd values', each comma-separated; "
                          "every combination is timed over --factor-steps sources")
@@ -270,7 +275,7 @@ def main():
     fvals = [float(x) for x in args.factor_sweep.split(",") if x.strip()]
     base = list(dsbfs.run_opts().factor0)
     paper = None
-    if mode == 1:
+    if mode == 1 and args.factor_steps > 0:
         gt, mss = time_factors(list(dsbfs.PAPER_FACTOR0))
         gtd, mssd = time_factors(base)
         paper = {"factor0": list(dsbfs.PAPER_FACTOR0), "gteps": gt, "ms_per_search": mss,
@@ -279,13 +284,14 @@ def main():
         log(f"paper factors {dsbfs.PAPER_FACTOR0}: {gt} GTEPS; default {base}: {gtd} GTEPS")
     # the DO-on-nn variant (nn under the direction decision too), per nn factor
     nn_sweep = []
-    for fnn in ((1e-6, 0.0), (1e-4, 0.0), (1e-3, 0.0), (1e-2, 0.0), (1.0, 0.0)) if mode == 1 else ():
+    for fnn in ((1e-6, 0.0), (1e-4, 0.0), (1e-3, 0.0), (1e-2, 0.0), (1.0, 0.0)) \
+            if mode == 1 and args.factor_steps > 0 else ():
         gt, mss = time_factors(base, nn=fnn)
         nn_sweep.append({"factor0_nn": fnn[0], "factor1_nn": fnn[1], "gteps": gt,
                          "ms_per_search": mss})
         log(f"nn_do factor0_nn = {fnn[0]:g}: {gt} GTEPS")
     for ki, kname_f in enumerate(("dd", "dn", "nd")):
-        for v in fvals if mode == 1 else []:
+        for v in fvals if mode == 1 and args.factor_steps > 0 else []:
             f0 = list(base)
             f0[ki] = v
             gt, mss = time_factors(f0)
@@ -324,7 +330,9 @@ def main():
     else:
         roofline.update({"achieved": round(self_gbs, 2), "frac": round(self_gbs / HBM_PEAK_GBS, 5),
                          "bytes_source": "kernels' own work counts (no CPU leg)"})
-    wl = f"RMAT{args.scale} TH{args.threshold} {args.mode} {args.sources}src parents={int(parent is not None)}"
+    # traffic per launch over the same searches as avg_launch_ms: the model
+    # sources (the picker draws in sequence, so the first k of any larger pick)
+    wl = f"RMAT{args.scale} TH{args.threshold} {args.mode} {len(msrc)}src parents={int(parent is not None)}"
     tr = measured_traffic(KERNEL_SYMBOL[dname], wl)
     roofline["traffic"] = None if tr is None else round(tr, 0)
     roofline["traffic_unit"] = "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated)"
@@ -402,6 +410,7 @@ def main():
             "sources_in_tiny_components": tiny,
             "levels_mean": sum(levels) / len(levels),
             "kernel_ms_per_search": {k: round(v["ms"] / len(msrc), 4) for k, v in kern.items()},
+            "kernel_launches_per_search": {k: v["launches"] / len(msrc) for k, v in kern.items()},
             "kernel_self_counted_gbs": {k: round(v["bytes"] / (v["ms"] * 1e-3) / 1e9, 1)
                                         for k, v in kern.items() if v["ms"] > 0},
             "kernel_share_profiled": round(sum(k["ms"] for k in kern.values()) / sum(ptimes), 3),
@@ -673,8 +682,8 @@ def bench_batched(args, torch, dsbfs, inputs):
     ecc = {}
     for s in set(sources.tolist()):
         ecc[s] = dsbfs.bfs(g, ws, s, d1, None, opts=o1, want_stats=True)["edges_cc"]
-    tot_ms, tot_e = 0.0, 0
-    for s in sources.tolist():
+    tot_ms, tot_e = 0.0, sum(ecc[s] for s in sources.tolist())
+    for s in sources.tolist() if args.ms_single else ():
         a = torch.cuda.Event(enable_timing=True)
         b = torch.cuda.Event(enable_timing=True)
         a.record(stream)
@@ -682,19 +691,22 @@ def bench_batched(args, torch, dsbfs, inputs):
         b.record(stream)
         b.synchronize()
         tot_ms += a.elapsed_time(b)
-        tot_e += ecc[s]
     log(f"single-source DOBFS: {tot_ms:.1f} ms total")
     ws.destroy()
     g.destroy()
-    for sh in shapes.values():
+    for name, sh in shapes.items():
         sh["gteps"] = round(tot_e / (sh["launch_ms"] * 1e-3) / 1e9, 2)
-        sh["speedup_vs_single_source"] = round(tot_ms / sh["launch_ms"], 2)
+        sh["speedup_vs_single_source"] = round(tot_ms / sh["launch_ms"], 2) if tot_ms else None
+        o = sh["opts"]
+        wl = (f"RMAT{scale} {k}src lanes={sh['lanes_per_batch']} block={o['block']} "
+              f"bpc={o['blocks_per_cu']} bu={o['bu_permille']}")
+        sh["traffic"] = measured_traffic("k_msbfs", wl, "msbfs.hip")
     if args.cpu_sources > 0:
         cpu_leg_batched(src, dst, n, sources, shapes)
     t = shapes["tuned"]
     out = {"workload": f"RMAT scale {scale}, {k} sources in one persistent graph-captured launch",
            "value": t["gteps"], "unit": "GTEPS (aggregate)", "launch_ms": t["launch_ms"],
-           "plain_gteps": round(tot_e / (tot_ms * 1e-3) / 1e9, 2),
+           "plain_gteps": round(tot_e / (tot_ms * 1e-3) / 1e9, 2) if tot_ms else None,
            "plain_ms_total": round(tot_ms, 2), "speedup": t["speedup_vs_single_source"],
            "shapes": shapes}
     return out

@@ -81,20 +81,36 @@ int main() {
   hipLaunchKernelGGL(fill_calib_kernel, dim3(4096), dim3(256), 0, 0, reinterpret_cast<int4 *>(g),
                      big / sizeof(int4), 2);
   if (check(hipGetLastError(), "fill")) return 1;
+  // each dispatch timed with events on the null stream: the rate of scattered
+  // single-word accesses, the ceiling of a kernel made of them
+  hipEvent_t ev[7];
+  for (auto &e : ev)
+    if (check(hipEventCreate(&e), "hipEventCreate")) return 1;
+  if (check(hipEventRecord(ev[0], 0), "hipEventRecord")) return 1;
   for (int r = 0; r < 3; ++r) {
     hipLaunchKernelGGL(gather_calib_kernel, dim3(grid), dim3(block), 0, 0, g, out, accesses,
                        lines_log2);
     if (check(hipGetLastError(), "gather")) return 1;
+    if (check(hipEventRecord(ev[1 + r], 0), "hipEventRecord")) return 1;
   }
   for (int r = 0; r < 3; ++r) {
     hipLaunchKernelGGL(scatter_calib_kernel, dim3(grid), dim3(block), 0, 0, g, accesses,
                        lines_log2, r);
     if (check(hipGetLastError(), "scatter")) return 1;
+    if (check(hipEventRecord(ev[4 + r], 0), "hipEventRecord")) return 1;
   }
   if (check(hipDeviceSynchronize(), "sync")) return 1;
-  std::printf("gather_calib: 3 dispatches of %zu scattered 4-byte reads (+ %zu bytes written)\n",
-              accesses, size_t(grid) * block * sizeof(int));
-  std::printf("scatter_calib: 3 dispatches of %zu scattered 4-byte writes\n", accesses);
+  float ms[6];
+  for (int r = 0; r < 6; ++r)
+    if (check(hipEventElapsedTime(&ms[r], ev[r], ev[r + 1]), "hipEventElapsedTime")) return 1;
+  std::printf("gather_calib: 3 dispatches of %zu scattered 4-byte reads (+ %zu bytes written); "
+              "ms %.4f %.4f %.4f; last: %.2f G reads/s\n",
+              accesses, size_t(grid) * block * sizeof(int), ms[0], ms[1], ms[2],
+              accesses / (ms[2] * 1e-3) / 1e9);
+  std::printf("scatter_calib: 3 dispatches of %zu scattered 4-byte writes; ms %.4f %.4f %.4f; "
+              "last: %.2f G writes/s\n",
+              accesses, ms[3], ms[4], ms[5], accesses / (ms[5] * 1e-3) / 1e9);
+  for (auto &e : ev) (void)hipEventDestroy(e);
   (void)hipFree(g);
   (void)hipFree(out);
   return 0;
