@@ -127,7 +127,7 @@ def main():
     ap.add_argument("--mode", choices=("do", "plain"), default="do")
     ap.add_argument("--model-sources", type=int, default=16,
                     help="sources of the profiled pass and of the work model (roofline)")
-    ap.add_argument("--cpu-sources", type=int, default=4,
+    ap.add_argument("--cpu-sources", type=int, default=2,
                     help="sources the CPU oracle times one by one on one core (0 = skip the "
                          "CPU leg: no cpu_baseline and no work-model roofline)")
     ap.add_argument("--cpu-threads", type=int, default=16,
@@ -703,6 +703,11 @@ def bench_batched(args, torch, dsbfs, inputs):
         sh["traffic"] = measured_traffic("k_msbfs", wl, "msbfs.hip")
     if args.cpu_sources > 0:
         cpu_leg_batched(src, dst, n, sources, shapes)
+    for sh in shapes.values():
+        if "roofline" in sh:
+            sh["roofline"]["traffic"] = sh.pop("traffic")
+            sh["roofline"]["traffic_unit"] = ("bytes per launch (rocprofv3 FETCH_SIZE + "
+                                              "WRITE_SIZE, calibrated)")
     t = shapes["tuned"]
     out = {"workload": f"RMAT scale {scale}, {k} sources in one persistent graph-captured launch",
            "value": t["gteps"], "unit": "GTEPS (aggregate)", "launch_ms": t["launch_ms"],
