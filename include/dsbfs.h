@@ -238,7 +238,10 @@ dsbfs_status dsbfs_graph_stats_get(const dsbfs_graph *g, dsbfs_graph_stats *out)
  * of every normal row, uint16[n]: nn length | nd length << 8, 0xFFFF when
  * either is 255 or more, 0 for a delegate (read by the normal previsit);
  * 17 the normal vertices with a normal neighbour, ascending, int32[n_nnsrc]
- * (candidates of the bottom-up nn visit when nn_do is set).
+ * (candidates of the bottom-up nn visit when nn_do is set); 18 the start of
+ * each vertex's nn part in array 19, uint32[n]; 19 the nn parts of all
+ * normal rows concatenated in vertex order, int32[e_nn] (what the forward nn
+ * visit reads). 18 and 19 are empty (size 0) when e_nn >= 2^32.
  * Row offsets are packed: bits 0..39 = start of the row, bits 40..63 = length
  * of its first part (nn for normal rows, dd for delegate rows); the row ends
  * at the start of the next row. Normal row v holds nn neighbours (vertex IDs)

@@ -333,7 +333,8 @@ __device__ __forceinline__ void expand_normal_rows(int32_t u, int32_t len, int64
 // (no unvisited delegate has a dn edge).
 __global__ void __launch_bounds__(kBS) k_normal_level(const int32_t *Q, const LevelCtr *prev,
                                                       const uint64_t *noff, const uint16_t *nlen,
-                                                      const int32_t *ncol,
+                                                      const int32_t *ncol, const uint32_t *nnoff,
+                                                      const int32_t *nncol,
                                                       Out out, uint32_t *Vn, uint32_t *Fn,
                                                       const DevCtl *c, int32_t *Qnext,
                                                       LevelCtr *cur) {
@@ -365,19 +366,20 @@ __global__ void __launch_bounds__(kBS) k_normal_level(const int32_t *Q, const Le
     int64_t beg = 0;
     if (i < qn) {
       u = Q[i];
-      // part lengths from 2 bytes per vertex; the row start only for rows
-      // with nn edges (most normal rows have none)
+      // part lengths from 2 bytes per vertex; where the nn part starts only
+      // for rows with nn edges (most normal rows have none), from the compact
+      // nn copy when there is one
       const uint32_t lw = nlen[u];
       int64_t nd;
       if (lw == kLenWide) {
         const uint64_t w0 = noff[u], w1 = noff[u + 1];
-        beg = row_start(w0);
         nn = int32_t(row_first(w0));
-        nd = row_start(w1) - beg - nn;
+        nd = row_start(w1) - row_start(w0) - nn;
+        beg = nnoff ? int64_t(nnoff[u]) : row_start(w0);
       } else {
         nn = int32_t(lw & 0xFFu);
         nd = int64_t(lw >> 8);
-        if (nn > 0 && expand) beg = row_start(noff[u]);
+        if (nn > 0 && expand) beg = nnoff ? int64_t(nnoff[u]) : row_start(noff[u]);
       }
       fv_nn += nn;
       q_nn += nn > 0;
@@ -386,8 +388,8 @@ __global__ void __launch_bounds__(kBS) k_normal_level(const int32_t *Q, const Le
     }
     // queues filled by the bottom-up pass are in ascending order: mark word by word
     if (mark_fn) wave_bit_set(Fn, uint32_t(u), i < qn, true);
-    expand_normal_rows<0>(u, expand ? nn : 0, beg, s_excl[w], s_u[w], s_beg[w], ncol, nullptr,
-                          out, Vn, nullptr, qa, edges, claimed);
+    expand_normal_rows<0>(u, expand ? nn : 0, beg, s_excl[w], s_u[w], s_beg[w],
+                          nnoff ? nncol : ncol, nullptr, out, Vn, nullptr, qa, edges, claimed);
     qa.maybe_flush(kBS * 2);
   }
   qa.flush();
@@ -401,7 +403,8 @@ __global__ void __launch_bounds__(kBS) k_normal_level(const int32_t *Q, const Le
 // previsit otherwise.
 __global__ void __launch_bounds__(kBS) k_td_nn(const int32_t *Q, const DevCtl *c,
                                                const uint64_t *noff, const uint16_t *nlen,
-                                               const int32_t *ncol, Out out, uint32_t *Vn,
+                                               const int32_t *ncol, const uint32_t *nnoff,
+                                               const int32_t *nncol, Out out, uint32_t *Vn,
                                                int32_t *Qnext, LevelCtr *cur) {
   if (c->done || !c->nn_td) return;
   const int64_t qn = c->qn;
@@ -428,15 +431,15 @@ __global__ void __launch_bounds__(kBS) k_td_nn(const int32_t *Q, const DevCtl *c
       const uint32_t lw = nlen[u];
       if (lw == kLenWide) {
         const uint64_t w0 = noff[u];
-        beg = row_start(w0);
         nn = int32_t(row_first(w0));
+        beg = nnoff ? int64_t(nnoff[u]) : row_start(w0);
       } else {
         nn = int32_t(lw & 0xFFu);
-        if (nn > 0) beg = row_start(noff[u]);
+        if (nn > 0) beg = nnoff ? int64_t(nnoff[u]) : row_start(noff[u]);
       }
     }
-    expand_normal_rows<0>(u, nn, beg, s_excl[w], s_u[w], s_beg[w], ncol, nullptr, out, Vn,
-                          nullptr, qa, edges, claimed);
+    expand_normal_rows<0>(u, nn, beg, s_excl[w], s_u[w], s_beg[w], nnoff ? nncol : ncol, nullptr,
+                          out, Vn, nullptr, qa, edges, claimed);
     qa.maybe_flush(kBS * 2);
   }
   qa.flush();
@@ -1332,7 +1335,8 @@ struct LevelLaunch {
     b = begin();
     hipLaunchKernelGGL(k_normal_level, dim3(SG), dim3(kBS), 0, s, Q[p], prev,
                        g->noff.as<uint64_t>(), g->nlen.as<uint16_t>(), g->ncol.as<int32_t>(),
-                       out, Vn, Fn,
+                       static_cast<const uint32_t *>(g->nnoff.as<uint32_t>()),
+                       static_cast<const int32_t *>(g->nncol.as<int32_t>()), out, Vn, Fn,
                        static_cast<const DevCtl *>(c), Q[p ^ 1], cur);
     HIPCHK(hipGetLastError());
     end(DSBFS_K_PREV_NORMAL, b);
@@ -1343,7 +1347,10 @@ struct LevelLaunch {
       b = begin();
       hipLaunchKernelGGL(k_td_nn, dim3(SG), dim3(kBS), 0, s, static_cast<const int32_t *>(Q[p]),
                          static_cast<const DevCtl *>(c), g->noff.as<uint64_t>(),
-                         g->nlen.as<uint16_t>(), g->ncol.as<int32_t>(), out, Vn, Q[p ^ 1], cur);
+                         g->nlen.as<uint16_t>(), g->ncol.as<int32_t>(),
+                         static_cast<const uint32_t *>(g->nnoff.as<uint32_t>()),
+                         static_cast<const int32_t *>(g->nncol.as<int32_t>()), out, Vn, Q[p ^ 1],
+                         cur);
       HIPCHK(hipGetLastError());
       end(DSBFS_K_TD_NN, b);
     }

@@ -163,6 +163,31 @@ __global__ void k_pack_lens(const int32_t *deg, const int32_t *did, const int32_
   }
 }
 
+// nn length of every vertex (0 for a delegate): the part sizes of the
+// compact nn copy.
+__global__ void k_nn_counts(const int32_t *deg, const int32_t *did, const int32_t *cnt_del,
+                            int32_t n, int32_t *cnt) {
+  const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+  for (int64_t v = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; v < n; v += stride)
+    cnt[v] = did[v] < 0 ? deg[v] - cnt_del[v] : 0;
+}
+
+// Copies the nn part of every normal row (its first part) to its place in
+// the compact nn copy and records where it starts.
+__global__ void k_nn_fill(const int64_t *start, const int32_t *cnt, const uint64_t *noff,
+                          const int32_t *ncol, int32_t n, uint32_t *nnoff, int32_t *nncol) {
+  const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+  for (int64_t v = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; v < n; v += stride) {
+    const int64_t o = start[v];
+    nnoff[v] = uint32_t(o);
+    const int32_t c = cnt[v];
+    if (c > 0) {
+      const int64_t b = row_start(noff[v]);
+      for (int32_t j = 0; j < c; ++j) nncol[o + j] = ncol[b + j];
+    }
+  }
+}
+
 // Destination of row u in the new layout: (row offsets, columns, is delegate).
 struct RowDst {
   uint64_t w;
@@ -665,6 +690,28 @@ Graph *graph_create(const int32_t *src, const int32_t *dst, int64_t g, int32_t n
       HIPCHK(hipStreamSynchronize(s));
     }
 
+    // 8a. compact copy of the nn parts (the forward nn visit's rows), while
+    //     its 32-bit starts can address it
+    if (e_nn < (int64_t(1) << 32)) {
+      DevBuf cnt_nn, start, stmp;
+      cnt_nn.alloc(al, size_t(n) * 4, s);
+      start.alloc(al, size_t(n + 1) * 8, s);
+      stmp.alloc(al, scan_tmp_bytes(n), s);
+      hipLaunchKernelGGL(k_nn_counts, dim3(grid_for(n, kBS, 8192)), dim3(kBS), 0, s,
+                         G->deg.as<int32_t>(), G->did.as<int32_t>(), cnt_del.as<int32_t>(), n,
+                         cnt_nn.as<int32_t>());
+      HIPCHK(hipGetLastError());
+      scan_excl_i32_to_i64(cnt_nn.as<int32_t>(), start.as<int64_t>(), n, stmp.p, s);
+      G->nnoff.alloc(al, size_t(n) * 4, s);
+      G->nncol.alloc(al, size_t(std::max<int64_t>(e_nn, 1)) * 4, s);
+      hipLaunchKernelGGL(k_nn_fill, dim3(grid_for(n, kBS, 8192)), dim3(kBS), 0, s,
+                         start.as<int64_t>(), cnt_nn.as<int32_t>(), G->noff.as<uint64_t>(),
+                         G->ncol.as<int32_t>(), n, G->nnoff.as<uint32_t>(),
+                         G->nncol.as<int32_t>());
+      HIPCHK(hipGetLastError());
+      HIPCHK(hipStreamSynchronize(s));
+    }
+
     // 8b. delegate-neighbour parts ordered by neighbour degree, highest first:
     //     bottom-up scans meet frontier hubs early. (Order inside a part is
     //     free; the four subgraphs are unchanged.)
@@ -829,6 +876,8 @@ void graph_export(const Graph *G, int32_t which, void *host_out, int64_t cap, in
     case 15: b = &G->dd_first; nb = d * 8; break;
     case 16: b = &G->nlen; nb = n * 2; break;
     case 17: b = &G->nnsrc; nb = G->st.n_nnsrc * 4; break;
+    case 18: b = &G->nnoff; nb = G->nnoff.p ? n * 4 : 0; break;
+    case 19: b = &G->nncol; nb = G->nncol.p ? G->st.e_nn * 4 : 0; break;
     default: fail(DSBFS_ERR_INVALID_ARG, "unknown array index");
   }
   *bytes = nb;

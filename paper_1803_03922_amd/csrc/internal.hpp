@@ -98,6 +98,13 @@ struct Graph {
   // normal previsit reads these 2 bytes instead of two 8-byte row offsets
   DevBuf nlen;
   DevBuf nnsrc;     // normal vertices with a normal neighbour, ascending (nn_do bottom-up)
+  // nn parts again, concatenated in vertex order (int32 [e_nn] vertex IDs),
+  // and the start of each vertex's part (uint32 [n]): a forward nn visit
+  // reads 4 bytes per frontier vertex and a column array of 4 bytes per nn
+  // edge, where most parts are one or two entries, instead of the 8-byte
+  // packed offset and a line of the full row. Not built (null) when
+  // e_nn >= 2^32; the kernels then read noff and ncol.
+  DevBuf nnoff, nncol;
   DevBuf poff, pcol;  // plain CSR: int64 offsets [n+1], int32 columns [m]
   int32_t dwords() const { return (d + 31) / 32; }
   int32_t nwords() const { return (n + 31) / 32; }

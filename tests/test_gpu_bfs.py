@@ -372,6 +372,10 @@ def test_builder_layout_matches_oracle_split(inputs_mod, oracle_mod, scale, TH):
     nn_src = np.nonzero(nn_len > 0)[0]
     np.testing.assert_array_equal(g.export(17, np.int32), nn_src)
     assert G.stats["n_nnsrc"] == len(nn_src)
+    # the compact nn copy is the oracle's nn subgraph in CSR form: part starts
+    # (32-bit) and the parts concatenated in vertex order
+    np.testing.assert_array_equal(g.export(18, np.uint32).astype(np.int64), r["nn_off"][:n])
+    np.testing.assert_array_equal(g.export(19, np.int32), r["nn_col"])
     nds_off = g.export(12, np.int64)
     nds_col = g.export(13, np.int32)
     np.testing.assert_array_equal(np.diff(nds_off), nd_len[nd_src])
