@@ -360,7 +360,11 @@ dsbfs_status dsbfs_bfs_noalloc(const dsbfs_graph *g, int32_t source, const dsbfs
  * below tolerance (tolerance > 0: one host synchronization per step). rank:
  * device double[n], caller-owned. *iterations_done and *last_delta (host,
  * either may be NULL) receive the steps run and the last L1 change. Scratch
- * (3 n + d doubles) comes from the graph's allocator for the call.
+ * (3 n + 2 d doubles) comes from the graph's allocator for the call. The
+ * first call on a graph also builds a cache kept with the graph until it is
+ * destroyed: the delegates' ranks by descending degree and a copy of the
+ * delegate columns with dd entries as ranks (4 (d + e_dd + e_dn) bytes), so
+ * that dd gathers of the most-connected delegates share cache lines.
  * Synchronizes the stream. Errors: INVALID_ARG (alpha outside [0, 1],
  * negative max_iterations, NULL rank), OUT_OF_MEMORY, HIP.
  */

@@ -5,6 +5,7 @@
 
 #include <cstdint>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -106,6 +107,13 @@ struct Graph {
   // e_nn >= 2^32; the kernels then read noff and ncol.
   DevBuf nnoff, nncol;
   DevBuf poff, pcol;  // plain CSR: int64 offsets [n+1], int32 columns [m]
+  // PageRank's gather-friendly copy, built by its first call and kept with
+  // the graph: pr_rank[k] = rank of delegate k by descending degree (ties by
+  // ID), and pr_col = dcol with every dd entry replaced by that rank, so the
+  // contributions of the most-gathered delegates sit together (int32 [d],
+  // int32 [e_dd + e_dn]).
+  mutable DevBuf pr_rank, pr_col;
+  mutable std::mutex pr_mu;
   int32_t dwords() const { return (d + 31) / 32; }
   int32_t nwords() const { return (n + 31) / 32; }
 };

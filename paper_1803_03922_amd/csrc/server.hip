@@ -80,6 +80,7 @@ size_t graph_footprint(const Graph *g) {
          buf_bytes(g->ddsrc_mask) + buf_bytes(g->dnsrc_mask) + buf_bytes(g->nds_off) +
          buf_bytes(g->nds_col) + buf_bytes(g->nds_first) + buf_bytes(g->dd_first) +
          buf_bytes(g->nlen) + buf_bytes(g->nnsrc) + buf_bytes(g->nnoff) + buf_bytes(g->nncol) +
+         buf_bytes(g->pr_rank) + buf_bytes(g->pr_col) +
          buf_bytes(g->poff) +
          buf_bytes(g->pcol);
 }
@@ -169,7 +170,8 @@ void ema(double &avg, double x) { avg = avg > 0 ? 0.75 * avg + 0.25 * x : x; }
 std::vector<DevBuf *> graph_bufs(Graph *g) {
   return {&g->deg, &g->did, &g->vid_of, &g->noff, &g->ncol, &g->doff, &g->dcol, &g->ndsrc,
           &g->ddsrc_mask, &g->dnsrc_mask, &g->nds_off, &g->nds_col, &g->nds_first, &g->dd_first,
-          &g->nlen, &g->nnsrc, &g->nnoff, &g->nncol, &g->poff, &g->pcol};
+          &g->nlen, &g->nnsrc, &g->nnoff, &g->nncol, &g->pr_rank, &g->pr_col, &g->poff,
+          &g->pcol};
 }
 
 void cohort_init(Cohort &c, Graph *g, bool batched);
