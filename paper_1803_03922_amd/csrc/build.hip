@@ -503,6 +503,8 @@ Graph *graph_create(const int32_t *src, const int32_t *dst, int64_t g, int32_t n
   o.keep_plain_csr = 1;
   if (opts) o = *opts;
   if (o.threshold < 0) fail(DSBFS_ERR_INVALID_ARG, "threshold must be >= 0");
+  if (o.skip_nn_copy != 0 && o.skip_nn_copy != 1)
+    fail(DSBFS_ERR_INVALID_ARG, "skip_nn_copy must be 0 or 1");
   if (g > (int64_t(1) << 38)) fail(DSBFS_ERR_RANGE, "too many edges for the packed offsets");
 
   Graph *G = new Graph();
@@ -692,7 +694,7 @@ Graph *graph_create(const int32_t *src, const int32_t *dst, int64_t g, int32_t n
 
     // 8a. compact copy of the nn parts (the forward nn visit's rows), while
     //     its 32-bit starts can address it
-    if (e_nn < (int64_t(1) << 32)) {
+    if (e_nn < (int64_t(1) << 32) && !o.skip_nn_copy) {
       DevBuf cnt_nn, start, stmp;
       cnt_nn.alloc(al, size_t(n) * 4, s);
       start.alloc(al, size_t(n + 1) * 8, s);

@@ -225,31 +225,63 @@ struct Server {
     for (int32_t *p : d) al.put(p, nullptr);
   }
 
-  // Gets a result row for G within the budget (caller holds mu). Cached rows
-  // of other graphs dropped to make room are freed later, outside the lock.
-  int32_t *take_row(GState *G) {
-    if (!G->free_bufs.empty()) {
-      int32_t *p = G->free_bufs.back();
-      G->free_bufs.pop_back();
-      return p;
-    }
+  // Gets a result row for G within the budget, leaving `keep` bytes of it
+  // free (caller holds mu). A cached row of G is reused (it is charged
+  // already); cached rows of other graphs dropped to make room are freed
+  // later, outside the lock.
+  int32_t *take_row(GState *G, size_t keep) {
     const size_t need = row_bytes(G);
-    if (used_bytes + need > o.hbm_budget_bytes) {
+    const bool cached = !G->free_bufs.empty();
+    const size_t add = cached ? 0 : need;  // what taking the row adds to the charge
+    if (used_bytes + add + keep > o.hbm_budget_bytes) {
       const int32_t ng = ngraphs.load(std::memory_order_acquire);
       for (int32_t i = 0; i < ng; ++i) {
         GState *H = graphs[i];
-        while (!H->free_bufs.empty() && used_bytes + need > o.hbm_budget_bytes) {
+        const size_t spare = (H == G && cached) ? 1 : 0;  // the row about to be reused
+        while (H->free_bufs.size() > spare && used_bytes + add + keep > o.hbm_budget_bytes) {
           drop.push_back(H->free_bufs.back());
           H->free_bufs.pop_back();
           used_bytes -= row_bytes(H);
         }
       }
-      if (used_bytes + need > o.hbm_budget_bytes) return nullptr;
+      if (used_bytes + add + keep > o.hbm_budget_bytes) return nullptr;
+    }
+    if (cached) {
+      int32_t *p = G->free_bufs.back();
+      G->free_bufs.pop_back();
+      return p;
     }
     int32_t *p = alloc_row(need);
     if (!p) return nullptr;
     used_bytes += need;
     return p;
+  }
+
+  // The oldest waiting query over the resident graphs, and the bytes of its
+  // row (caller holds mu). A younger query is admitted only while that row
+  // would still fit: when the budget binds, memory freed by releases then
+  // goes to the oldest query instead of to later arrivals on graphs with
+  // smaller rows, which would otherwise starve it.
+  Query *oldest = nullptr;
+  size_t oldest_bytes = 0;
+  void pick_oldest() {
+    oldest = nullptr;
+    oldest_bytes = 0;
+    const int32_t ng = ngraphs.load(std::memory_order_acquire);
+    for (int32_t i = 0; i < ng; ++i) {
+      GState *H = graphs[i];
+      if (!H->resident || H->pending.empty()) continue;
+      Query *q = H->pending.front();
+      if (!oldest || q->arrival < oldest->arrival) {
+        oldest = q;
+        oldest_bytes = row_bytes(H);
+      }
+    }
+  }
+  size_t keep_for(const Query *q) const { return q == oldest ? 0 : oldest_bytes; }
+  // after admitting q: the next oldest is reserved for
+  void admitted(const Query *q) {
+    if (q == oldest) pick_oldest();
   }
 
   // A query that found no budget for its row or its graph (counted once).
@@ -377,12 +409,13 @@ struct Server {
     G->last_use = t;
     if (adaptive && !G->running() && !G->in_flight() && serve_alone(G)) {
       Query *q = G->pending.front();
-      int32_t *row = take_row(G);
+      int32_t *row = take_row(G, keep_for(q));
       if (!row) {  // budget: wait for releases
         budget_wait(q);
         return;
       }
       G->pending.pop_front();
+      admitted(q);
       q->res = row;
       q->admit = q->start = t;
       q->state = Q_RUNNING;
@@ -400,13 +433,14 @@ struct Server {
         bool no_budget = false;
         while (free && !G->pending.empty()) {
           Query *q = G->pending.front();
-          int32_t *row = take_row(G);
+          int32_t *row = take_row(G, keep_for(q));
           if (!row) {  // budget: the rest waits for releases
             budget_wait(q);
             no_budget = true;
             break;
           }
           G->pending.pop_front();
+          admitted(q);
           const int i = __builtin_ctzll(free);
           free &= free - 1;
           q->res = row;
@@ -524,6 +558,7 @@ struct Server {
       {
         std::lock_guard<std::mutex> lk(mu);
         const int64_t t = now_ns();
+        pick_oldest();
         for (int32_t i = 0; i < ng; ++i)
           if (!graphs[i]->single) admit(graphs[i], lane_cap, adaptive, t);
       }
@@ -610,7 +645,7 @@ struct Server {
           cv_done.wait_for(lk, std::chrono::milliseconds(1));
           continue;
         }
-        int32_t *row = take_row(G);
+        int32_t *row = take_row(G, 0);  // q is the oldest waiting query
         if (!row) {
           budget_wait(q);
           lk.unlock();

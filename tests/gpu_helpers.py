@@ -26,12 +26,13 @@ def log(*a):
 class GpuGraph:
     """A graph on the GPU plus a workspace and output buffers."""
 
-    def __init__(self, src, dst, n, threshold=32, keep_plain=True, lanes=0):
+    def __init__(self, src, dst, n, threshold=32, keep_plain=True, lanes=0, nn_copy=True):
         torch = torch_cuda()
         d = lib()
         self.torch = torch
         self.n = n
-        self.g = d.Graph(src, dst, n, threshold=threshold, keep_plain_csr=keep_plain)
+        self.g = d.Graph(src, dst, n, threshold=threshold, keep_plain_csr=keep_plain,
+                         nn_copy=nn_copy)
         self.ws = d.Workspace(self.g, max_lanes=lanes)
         self.depth = torch.empty(max(n, 1), dtype=torch.int32, device="cuda")
         self.parent = torch.empty(max(n, 1), dtype=torch.int32, device="cuda")

@@ -61,6 +61,9 @@ def test_host_side_argument_errors():
     bo = dsbfs.dsbfs_build_opts(-1, 0, 1, 0)
     st = dsbfs.dsbfs_graph_create(None, None, 0, 10, ctypes.byref(bo), None, None, ctypes.byref(h))
     assert st == dsbfs.ERR_INVALID_ARG and b"threshold" in dsbfs.dsbfs_last_error()
+    bo = dsbfs.dsbfs_build_opts(32, 0, 1, 2)
+    st = dsbfs.dsbfs_graph_create(None, None, 0, 10, ctypes.byref(bo), None, None, ctypes.byref(h))
+    assert st == dsbfs.ERR_INVALID_ARG and b"skip_nn_copy" in dsbfs.dsbfs_last_error()
     assert dsbfs.dsbfs_graph_create(None, None, 0, 1, None, None, None, None) == dsbfs.ERR_INVALID_ARG
     assert dsbfs.dsbfs_bfs(None, None, 0, None, None, None, None, None) == dsbfs.ERR_INVALID_ARG
     assert dsbfs.dsbfs_bfs_noalloc(None, 0, None, None, None, None, None) == dsbfs.ERR_INVALID_ARG

@@ -247,6 +247,24 @@ def test_schedule_and_threshold_invariance(inputs_mod, oracle_mod):
         G.close()
 
 
+@pytest.mark.parametrize("TH", [2, 32, 10**6])
+def test_without_compact_nn_copy(inputs_mod, oracle_mod, TH):
+    """skip_nn_copy = 1: the forward nn visits read the packed offsets and the
+    full rows (the path a graph with e_nn >= 2^32 takes). Depths equal the
+    oracle's and parents pass its invariants under the heuristic schedule,
+    all forward, and with nn under the decision; arrays 18 and 19 are empty."""
+    n, src, dst, O = _rmat(inputs_mod, oracle_mod, 13)
+    G = GpuGraph(src, dst, n, threshold=TH, nn_copy=False)
+    assert len(G.g.export(18, np.uint32)) == 0 and len(G.g.export(19, np.int32)) == 0
+    for s in inputs_mod.pick_sources(src, dst, n, 4, seed=91).tolist():
+        want, _ = O.bfs(s, want_parent=False)
+        for kw in ({}, {"forced": 1}, {"nn_do": True, "factor_nn": (1e-3, 0.0)}):
+            depth, parent, _ = G.bfs(s, **kw)
+            np.testing.assert_array_equal(depth, want, err_msg=f"TH={TH} {kw}")
+            assert O.check(s, depth, parent, None)[0] == 0
+    G.close()
+
+
 @pytest.mark.parametrize("scale,TH", [(12, 8), (14, 16), (16, 32)])
 def test_direction_schedule_matches_oracle_replay(inputs_mod, oracle_mod, scale, TH):
     """Per-level q, s, |U|, FV, BV and the chosen directions equal the oracle's

@@ -424,3 +424,42 @@ def test_server_rows_from_allocator_and_budget_waits(inputs_mod, oracle_mod):
     st = S.stats()
     assert st["budget_waits"] == sum(waited) and st["queries_done"] == 6
     S.destroy()
+
+
+@pytest.mark.parametrize("batched", [1, 2])
+def test_server_budget_serves_oldest_first(inputs_mod, oracle_mod, batched):
+    """When the budget binds, a waiting query keeps its place: with two large
+    results held, a large-graph query X waits for room, and later queries on
+    a small graph, whose rows would fit the room left, are not admitted
+    before X (they would otherwise take every release and starve it). All
+    rows equal the oracle's."""
+    d = lib()
+    specs = _graphs(inputs_mod, oracle_mod)
+    small, large = specs[0], specs[1]            # RMAT 10 and RMAT 12
+    fps = _footprints([small, large], batched)
+    nl, ns = large[0], small[0]
+    S = d.Server(sum(fps) + 2 * 4 * nl + 2 * 4 * ns, batched=batched)
+    gs = S.add_graph(d.Graph(small[1], small[2], ns, threshold=16, keep_plain_csr=True))
+    gl = S.add_graph(d.Graph(large[1], large[2], nl, threshold=16, keep_plain_csr=True))
+    srcl = inputs_mod.pick_sources(large[1], large[2], nl, 3, seed=12).tolist()
+    srcs = inputs_mod.pick_sources(small[1], small[2], ns, 4, seed=13).tolist()
+    held = [S.submit(gl, s) for s in srcl[:2]]
+    for t in held:
+        S.wait(t)                                # done, rows still held
+    x = S.submit(gl, srcl[2])
+    ys = [S.submit(gs, s) for s in srcs]
+    time.sleep(0.05)                             # room for the small rows, none for X's
+    with pytest.raises(d.DsbfsError) as e:
+        S.wait(x, timeout_ns=1_000_000)
+    assert e.value.status == d.ERR_NOT_READY
+    for t, s in zip(held, srcl[:2]):
+        row, _ = _fetch(S, t, nl)
+        np.testing.assert_array_equal(row, large[3].bfs(s, want_parent=False)[0])
+    row, qx = _fetch(S, x, nl)
+    np.testing.assert_array_equal(row, large[3].bfs(srcl[2], want_parent=False)[0])
+    assert qx["waited_budget"] == 1
+    for t, s in zip(ys, srcs):
+        row, qy = _fetch(S, t, ns)
+        np.testing.assert_array_equal(row, small[3].bfs(s, want_parent=False)[0])
+        assert qy["admit_ns"] >= qx["admit_ns"], "a later query was admitted before the waiting one"
+    S.destroy()
