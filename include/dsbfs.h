@@ -68,7 +68,10 @@ typedef struct dsbfs_build_opts {
   int32_t edges_on_device; /* 1: src/dst are device pointers; 0: host pointers */
   int32_t keep_plain_csr;  /* 1: keep the plain CSR too (needed by mode 0 and by
                               multi-source BFS); 0: free it after the split */
-  int32_t reserved;
+  int32_t skip_nn_copy;    /* 0 (default): build the compact copy of the nn
+                              parts that the forward nn visit reads (arrays 18
+                              and 19 of dsbfs_graph_export, 4 n + 8 e_nn bytes);
+                              1: do not, and read the packed offsets and rows */
 } dsbfs_build_opts;
 
 /* Sizes of a built graph. Degrees are counted after symmetrization,

@@ -52,7 +52,7 @@ class dsbfs_allocator(ctypes.Structure):
 
 class dsbfs_build_opts(ctypes.Structure):
     _fields_ = [("threshold", i32), ("edges_on_device", i32), ("keep_plain_csr", i32),
-                ("reserved", i32)]
+                ("skip_nn_copy", i32)]
 
 
 class dsbfs_graph_stats(ctypes.Structure):
@@ -338,12 +338,13 @@ class Graph:
 
     def __init__(self, src, dst, n: int, threshold: int = 32, keep_plain_csr: bool = True,
                  allocator: TorchAllocator | None = None, stream: int | None = None,
-                 rmat: dsbfs_rmat_spec | None = None):
+                 rmat: dsbfs_rmat_spec | None = None, nn_copy: bool = True):
         """From an edge list (host numpy or device torch arrays), or, with
-        rmat given (src, dst, n ignored), generated on the device."""
+        rmat given (src, dst, n ignored), generated on the device. nn_copy =
+        False skips the compact nn copy (skip_nn_copy)."""
         self.alloc = allocator or default_allocator()
         self.stream = current_stream() if stream is None else stream
-        opts = dsbfs_build_opts(threshold, 0, int(keep_plain_csr), 0)
+        opts = dsbfs_build_opts(threshold, 0, int(keep_plain_csr), int(not nn_copy))
         h = vp()
         if rmat is not None:
             check(dsbfs_graph_create_rmat(ctypes.byref(rmat), ctypes.byref(opts),
