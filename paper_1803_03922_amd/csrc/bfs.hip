@@ -140,7 +140,8 @@ __global__ void k_init(int32_t *depth, int32_t *parent, int32_t n, uint32_t *Vn,
 }
 
 // Seeds the source: a delegate enters the delegate frontier mask, a normal
-// vertex the normal queue. prev->qn_next becomes the level-0 queue length.
+// vertex the normal queue. prev's queue tail becomes the level-0 queue
+// length (no bottom-up candidates yet).
 __global__ void k_seed(int32_t s, const int32_t *did, int32_t *depth, int32_t *parent,
                        uint32_t *Vn, uint32_t *Vd, uint32_t *Fd, uint32_t *Cd, int32_t *Q,
                        LevelCtr *prev, int mode) {
@@ -151,13 +152,12 @@ __global__ void k_seed(int32_t s, const int32_t *did, int32_t *depth, int32_t *p
     Vd[k >> 5] |= 1u << (k & 31);
     Fd[k >> 5] |= 1u << (k & 31);
     Cd[k >> 5] |= 1u << (k & 31);
-    prev->qn_next = 0;
+    prev->qn_nc = 0;
   } else {
     Vn[s >> 5] |= 1u << (s & 31);
     Q[0] = s;
-    prev->qn_next = 1;
+    prev->qn_nc = 1;
   }
-  prev->nc_next = 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -339,7 +339,7 @@ __global__ void __launch_bounds__(kBS) k_normal_level(const int32_t *Q, const Le
                                                       const DevCtl *c, int32_t *Qnext,
                                                       LevelCtr *cur) {
   if (c->done) return;
-  const int64_t qn = int64_t(prev->qn_next);
+  const int64_t qn = lc_qn(prev);
   // blocks past the queue have nothing to add (a short queue leaves most of
   // the grid idle: skip its LDS set-up and block reductions)
   if (int64_t(blockIdx.x) * blockDim.x >= qn) return;
@@ -355,7 +355,7 @@ __global__ void __launch_bounds__(kBS) k_normal_level(const int32_t *Q, const Le
   __shared__ int qcount;
   __shared__ unsigned long long qbase;
   __shared__ unsigned long long sh[4 * kNW];
-  BlockAppend qa{qbuf, &qcount, &qbase, kQCap, &cur->qn_next, Qnext};
+  BlockAppend qa{qbuf, &qcount, &qbase, kQCap, &cur->qn_nc, Qnext};
   qa.init();
   const int w = threadIdx.x / kWave;
   unsigned long long fv_nn = 0, q_nn = 0, fv_nd = 0, q_nd = 0, edges = 0, claimed = 0;
@@ -417,7 +417,7 @@ __global__ void __launch_bounds__(kBS) k_td_nn(const int32_t *Q, const DevCtl *c
   __shared__ int qcount;
   __shared__ unsigned long long qbase;
   __shared__ unsigned long long sh[4 * kNW];
-  BlockAppend qa{qbuf, &qcount, &qbase, kQCap, &cur->qn_next, Qnext};
+  BlockAppend qa{qbuf, &qcount, &qbase, kQCap, &cur->qn_nc, Qnext};
   qa.init();
   const int w = threadIdx.x / kWave;
   unsigned long long edges = 0, claimed = 0;
@@ -468,7 +468,7 @@ __global__ void __launch_bounds__(kBS) k_bu_nn(const DevCtl *c, const int32_t *n
   __shared__ int qcount;
   __shared__ unsigned long long qbase;
   __shared__ unsigned long long sh[4 * kNW];
-  BlockAppend qa{qbuf, &qcount, &qbase, kQCap, &cur->qn_next, Qnext};
+  BlockAppend qa{qbuf, &qcount, &qbase, kQCap, &cur->qn_nc, Qnext};
   qa.init();
   const int w = threadIdx.x / kWave, l = lane_id();
   constexpr int32_t kNone = 0x7fffffff;
@@ -589,7 +589,7 @@ __global__ void __launch_bounds__(kBS) k_td_deleg(const int32_t *dlist, const in
   __shared__ int qcount;
   __shared__ unsigned long long qbase;
   __shared__ unsigned long long sh[4 * kNW];
-  BlockAppend qa{qbuf, &qcount, &qbase, kQCap, &cur->qn_next, Qnext};
+  BlockAppend qa{qbuf, &qcount, &qbase, kQCap, &cur->qn_nc, Qnext};
   qa.init();
   const int64_t nd = int64_t(curc->nd_list);
   const int64_t E = dscan[nd];
@@ -672,8 +672,8 @@ __global__ void __launch_bounds__(kBS) k_bu_normal(const DevCtl *c, int32_t *c0,
   __shared__ int qcount, ccount;
   __shared__ unsigned long long qbase, cbase;
   __shared__ unsigned long long sh[4 * kNW];
-  BlockAppend qa{qbuf, &qcount, &qbase, kQCap, &cur->qn_next, Qnext};
-  BlockAppend ca{cbuf, &ccount, &cbase, kQCap, &cur->nc_next, cout};
+  BlockAppend qa{qbuf, &qcount, &qbase, kQCap, &cur->qn_nc, Qnext};
+  BlockAppend ca{cbuf, &ccount, &cbase, kQCap, &cur->qn_nc, cout, 32};
   qa.init();
   ca.init();
   const int w = threadIdx.x / kWave, l = lane_id();
@@ -755,13 +755,9 @@ __global__ void __launch_bounds__(kBS) k_bu_normal(const DevCtl *c, int32_t *c0,
     qa.push(won, v);
     ca.push(ok && !visited && !found, pos);
     __syncthreads();
-    if (qcount > kQCap - kBS || ccount > kQCap - kBS) {
-      qa.flush();
-      ca.flush();
-    }
+    if (qcount > kQCap - kBS || ccount > kQCap - kBS) flush_pair(qa, ca);
   }
-  qa.flush();
-  ca.flush();
+  flush_pair(qa, ca);
   // units: list entries read, unvisited scanned, edges inspected, claimed
   block_add4(cur->units[DSBFS_K_BU_NORMAL], reads, scanned, edges, claimed, sh);
 }
@@ -913,14 +909,14 @@ __global__ void k_ctl_init(DevCtl *c, DevCtl init) { *c = init; }
 __device__ void decide_level(DevCtl *__restrict__ c, const LevelCtr *__restrict__ cur,
                              const LevelCtr *__restrict__ prev, LevelStatus *st) {
   const int32_t L = c->level;
-  const int64_t qn = int64_t(prev->qn_next), fdn = int64_t(cur->nd_list);
+  const int64_t qn = lc_qn(prev), fdn = int64_t(cur->nd_list);
   c->units[DSBFS_K_PREV_NORMAL][0] += qn;
   c->units[DSBFS_K_PREV_DELEG][0] += fdn;
   c->deg_sum += cur->fv_nn + cur->fv_nd + cur->fv_dd + cur->fv_dn;
   if (c->nc_pending) {
     // length of the candidate list the previous bottom-up normal pass compacted
-    c->nc = int64_t(prev->nc_next);
-    c->units[DSBFS_K_BU_NORMAL][4] += prev->nc_next;
+    c->nc = lc_nc(prev);
+    c->units[DSBFS_K_BU_NORMAL][4] += lc_nc(prev);
     c->nc_pending = 0;
   }
   if (qn == 0 && fdn == 0) {
@@ -1134,7 +1130,7 @@ constexpr int kRun = 4;
 
 __global__ void k_plain_len(const int32_t *Q, const LevelCtr *prev, const int64_t *poff,
                             int32_t *len) {
-  const int64_t qn = int64_t(prev->qn_next);
+  const int64_t qn = lc_qn(prev);
   for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < qn;
        i += int64_t(gridDim.x) * blockDim.x) {
     const int32_t u = Q[i];
@@ -1150,9 +1146,9 @@ __global__ void __launch_bounds__(kBS) k_plain_expand(const int32_t *Q, const Le
   __shared__ int qcount;
   __shared__ unsigned long long qbase;
   __shared__ unsigned long long sh[4 * kNW];
-  BlockAppend qa{qbuf, &qcount, &qbase, kQCap, &cur->qn_next, Qnext};
+  BlockAppend qa{qbuf, &qcount, &qbase, kQCap, &cur->qn_nc, Qnext};
   qa.init();
-  const int64_t qn = int64_t(prev->qn_next);
+  const int64_t qn = lc_qn(prev);
   const int64_t E = scan[qn];
   const int64_t nruns = (E + kRun - 1) / kRun;
   unsigned long long claimed = 0;
@@ -1560,7 +1556,7 @@ void bfs_run(const Graph *g, Workspace *ws, int32_t source, const dsbfs_run_opts
       HIPCHK(hipMemcpyAsync(h, prev, sizeof(LevelCtr), hipMemcpyDeviceToHost, s));
       HIPCHK(hipStreamSynchronize(s));
       P.add_level(*h);
-      const int64_t qn = int64_t(h->qn_next);
+      const int64_t qn = lc_qn(h);
       if (qn == 0) break;
       HIPCHK(hipMemsetAsync(cur, 0, sizeof(LevelCtr), s));
       out.level1 = L + 1;

@@ -121,8 +121,11 @@ struct Graph {
 // Per-level counters of a single-source search (device; accumulated with
 // wave-aggregated atomics). Two copies alternate between levels.
 struct LevelCtr {
-  unsigned long long qn_next;   // tail of the next normal queue (queue length of the next level)
-  unsigned long long nc_next;   // tail of the next bottom-up normal candidate list
+  // Tails of the next normal queue (bits 0..31: the queue length of the next
+  // level) and of the next bottom-up normal candidate list (bits 32..63), in
+  // one word: the bottom-up normal pass appends to both and reserves both
+  // with one atomic. Neither count reaches 2^31, so no carry crosses.
+  unsigned long long qn_nc;
   unsigned long long nd_list;   // frontier delegates of this level (length of dlist)
   unsigned long long nd_cand;   // unvisited delegates with a dd or dn edge (length of dcand)
   unsigned long long fv_nn, q_nn, fv_nd, q_nd;  // normal previsit
@@ -130,6 +133,11 @@ struct LevelCtr {
   // Work units per kernel (index DSBFS_K_*), slot meanings in bfs.hip.
   unsigned long long units[DSBFS_NUM_KERNELS][4];
 };
+
+__host__ __device__ inline int64_t lc_qn(const LevelCtr *c) {
+  return int64_t(c->qn_nc & 0xffffffffull);
+}
+__host__ __device__ inline int64_t lc_nc(const LevelCtr *c) { return int64_t(c->qn_nc >> 32); }
 
 // Scratch of one search at a time (single-source and multi-source).
 struct Workspace {
@@ -372,6 +380,12 @@ struct BlockAppend {
   int cap;
   unsigned long long *gcount;
   int32_t *gout;
+  int shift = 0;  // the 32-bit half of *gcount that counts this list (0 or 32)
+
+  // Reserves n entries of the list: the old count of its half of *gcount.
+  __device__ unsigned long long reserve(unsigned long long n) const {
+    return (atomicAdd(gcount, n << shift) >> shift) & 0xffffffffull;
+  }
 
   __device__ void init() {
     if (threadIdx.x == 0) *count = 0;
@@ -387,8 +401,14 @@ struct BlockAppend {
     const int pos = p + int(lanes_below(m));
     const bool over = want && pos >= cap;
     if (want && !over) buf[pos] = v;
-    const int64_t gp = wave_append(over, gcount);
-    if (over) gout[gp] = v;
+    const uint64_t mo = __ballot(over);
+    if (mo) {
+      const int lo = __ffsll(static_cast<long long>(mo)) - 1;
+      unsigned long long b = 0;
+      if (lane_id() == lo) b = reserve(__popcll(mo));
+      b = lane_read(b, lo);
+      if (over) gout[b + lanes_below(mo)] = v;
+    }
   }
   // Block-uniform: writes the buffer out if it holds more than cap - margin.
   __device__ void maybe_flush(int margin) {
@@ -399,7 +419,7 @@ struct BlockAppend {
   __device__ void flush() {
     __syncthreads();
     const int c = min(*count, cap);
-    if (threadIdx.x == 0) *base = c ? atomicAdd(gcount, (unsigned long long)c) : 0ull;
+    if (threadIdx.x == 0) *base = c ? reserve((unsigned long long)c) : 0ull;
     __syncthreads();
     const unsigned long long b = *base;
     for (int i = threadIdx.x; i < c; i += blockDim.x) gout[b + i] = buf[i];
@@ -408,6 +428,31 @@ struct BlockAppend {
     __syncthreads();
   }
 };
+
+// Writes out two append buffers that count in the two halves of one word
+// (q: bits 0..31, c: bits 32..63) with a single atomic (block-uniform).
+__device__ inline void flush_pair(BlockAppend &q, BlockAppend &c) {
+  __syncthreads();
+  const int nq = min(*q.count, q.cap), nc = min(*c.count, c.cap);
+  if (threadIdx.x == 0) {
+    unsigned long long b = 0;
+    if (nq || nc)
+      b = atomicAdd(q.gcount, (static_cast<unsigned long long>(nc) << 32) |
+                                  static_cast<unsigned long long>(nq));
+    *q.base = b & 0xffffffffull;
+    *c.base = b >> 32;
+  }
+  __syncthreads();
+  const unsigned long long bq = *q.base, bc = *c.base;
+  for (int i = threadIdx.x; i < nq; i += blockDim.x) q.gout[bq + i] = q.buf[i];
+  for (int i = threadIdx.x; i < nc; i += blockDim.x) c.gout[bc + i] = c.buf[i];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    *q.count = 0;
+    *c.count = 0;
+  }
+  __syncthreads();
+}
 
 // Sums four per-thread counts over the block and adds them to dst[0..3] with
 // one global atomic each (block-uniform call; sh holds 4 * waves entries).
