@@ -150,6 +150,8 @@ def main():
     ap.add_argument("--factor-sweep", default="1e-8,1e-6,1e-4,1e-2,0.05,0.5,2,10",
                     help="comma-separated factor0 values tried for each of dd, dn, nd in turn "
                          "(the other two at their defaults); '' = none")
+    ap.add_argument("--depth-only", type=int, default=1,
+                    help="1 = also time the sources without the parent output; 0 = skip")
     ap.add_argument("--factor-steps", type=int, default=16,
                     help="sources timed per factor setting; 0 = no factor legs")
     ap.add_argument("--factor-grid", default="",
@@ -288,7 +290,7 @@ def main():
     # the same searches without the parent output (depths only, as the paper's
     # search produces), one pass over all sources
     depth_only = None
-    if parent is not None:
+    if parent is not None and args.depth_only:
         o_np = dsbfs.run_opts(mode=mode, want_parent=False)
         timed(g, ws, int(sources[0]), o_np)   # untimed: captures the depth-only level graphs
         tt, rr = [], []
