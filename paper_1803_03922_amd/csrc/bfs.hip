@@ -1640,16 +1640,18 @@ void bfs_run(const Graph *g, Workspace *ws, int32_t source, const dsbfs_run_opts
         seen.push_back(st);
       }
     } else {
-      // one captured graph per level; the host stays two levels ahead and
-      // stops once a finished level reports an empty frontier (the levels
-      // already queued behind it return at once)
+      // one captured graph per level; the host stays one level ahead and
+      // stops once a finished level reports an empty frontier (the level
+      // already queued behind it returns at once). One level ahead hides the
+      // host's wait and launch behind the level in flight; two would add a
+      // second graph of no-op kernels at the end of every search.
       const LevelGraphs &lg = level_graphs(ws, ll);
       for (int32_t L = 0;; ++L) {
         HIPCHK(hipGraphLaunch(lg.exec[L & 1], s));
         HIPCHK(hipEventRecord(ws->lev_ev[L % 3], s));
-        if (L >= 2) {
-          HIPCHK(hipEventSynchronize(ws->lev_ev[(L - 2) % 3]));
-          const LevelStatus &st = hs[(L - 2) & (kStatusSlots - 1)];
+        if (L >= 1) {
+          HIPCHK(hipEventSynchronize(ws->lev_ev[(L - 1) % 3]));
+          const LevelStatus &st = hs[(L - 1) & (kStatusSlots - 1)];
           if (st.done) break;
           seen.push_back(st);
         }
