@@ -1309,7 +1309,10 @@ struct LevelLaunch {
   int64_t *bsum, *bscan;
   bool nn_do;  // nn under the direction decision: its own forward and backward passes
 
-  void enqueue(int p, hipStream_t s, Prof *P) const {
+  // skip: kernels left out because they cannot have work (captured level
+  // variants): bit 0 the forward nd visit, bit 1 the forward dd/dn visit and
+  // its prefix sum. Direct launches pass 0.
+  void enqueue(int p, hipStream_t s, Prof *P, int skip = 0) const {
     const int32_t n = g->n, d = g->d;
     LevelCtr *cur = ctr + p, *prev = ctr + (p ^ 1);
     const int SG = stride_grid();
@@ -1350,13 +1353,15 @@ struct LevelLaunch {
       HIPCHK(hipGetLastError());
       end(DSBFS_K_TD_NN, b);
     }
-    if (d > 0) {
+    if (d > 0 && !(skip & 1)) {
       b = begin();
       hipLaunchKernelGGL(k_td_nd, dim3(SG), dim3(kBS), 0, s, static_cast<const int32_t *>(Q[p]),
                          static_cast<const DevCtl *>(c), g->noff.as<uint64_t>(),
                          g->ncol.as<int32_t>(), g->vid_of.as<int32_t>(), out, Cd, cur);
       HIPCHK(hipGetLastError());
       end(DSBFS_K_TD_NORMAL, b);
+    }
+    if (d > 0 && !(skip & 2)) {
       b = begin();
       const unsigned nb = unsigned((int64_t(d) + kScanTile - 1) / kScanTile);
       hipLaunchKernelGGL(k_dscan_reduce, dim3(nb), dim3(kBS), 0, s,
@@ -1445,13 +1450,15 @@ LevelLaunch level_launch(const Graph *g, Workspace *ws, const Out &out, bool nn_
   return ll;
 }
 
-// Two captured level graphs per workspace (one per queue parity), for the
-// depth / parent buffers they were captured with.
+// Captured level graphs per workspace, for the depth / parent buffers they
+// were captured with: one per queue parity and skip variant (see
+// LevelLaunch::enqueue), each captured when first needed.
+constexpr int kLevelVariants = 4;
 struct LevelGraphs {
   int32_t *depth = nullptr, *parent = nullptr;
   bool nn_do = false;
-  hipGraph_t graph[2] = {nullptr, nullptr};
-  hipGraphExec_t exec[2] = {nullptr, nullptr};
+  hipGraph_t graph[kLevelVariants][2] = {};
+  hipGraphExec_t exec[kLevelVariants][2] = {};
 };
 
 }  // namespace
@@ -1459,17 +1466,20 @@ struct LevelGraphs {
 void level_graphs_release(Workspace *ws) {
   auto *lg = static_cast<LevelGraphs *>(ws->lvl);
   if (!lg) return;
-  for (int i = 0; i < 2; ++i) {
-    if (lg->exec[i]) (void)hipGraphExecDestroy(lg->exec[i]);
-    if (lg->graph[i]) (void)hipGraphDestroy(lg->graph[i]);
-  }
+  for (int v = 0; v < kLevelVariants; ++v)
+    for (int i = 0; i < 2; ++i) {
+      if (lg->exec[v][i]) (void)hipGraphExecDestroy(lg->exec[v][i]);
+      if (lg->graph[v][i]) (void)hipGraphDestroy(lg->graph[v][i]);
+    }
   delete lg;
   ws->lvl = nullptr;
 }
 
 namespace {
 
-const LevelGraphs &level_graphs(Workspace *ws, const LevelLaunch &ll) {
+// The level graphs of this workspace for ll's buffers (recaptured when they
+// change); variant v of parity p is captured on first use.
+LevelGraphs &level_graphs(Workspace *ws, const LevelLaunch &ll) {
   auto *lg = static_cast<LevelGraphs *>(ws->lvl);
   if (lg && lg->depth == ll.out.depth && lg->parent == ll.out.parent && lg->nn_do == ll.nn_do)
     return *lg;
@@ -1479,29 +1489,32 @@ const LevelGraphs &level_graphs(Workspace *ws, const LevelLaunch &ll) {
   lg->depth = ll.out.depth;
   lg->parent = ll.out.parent;
   lg->nn_do = ll.nn_do;
+  return *lg;
+}
+
+hipGraphExec_t level_exec(Workspace *ws, LevelGraphs &lg, const LevelLaunch &ll, int v, int p) {
+  if (lg.exec[v][p]) return lg.exec[v][p];
   hipStream_t cs = nullptr;
   HIPCHK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
   try {
-    for (int p = 0; p < 2; ++p) {
-      HIPCHK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-      try {
-        ll.enqueue(p, cs, nullptr);
-      } catch (...) {
-        hipGraph_t gr = nullptr;
-        (void)hipStreamEndCapture(cs, &gr);
-        if (gr) (void)hipGraphDestroy(gr);
-        throw;
-      }
-      HIPCHK(hipStreamEndCapture(cs, &lg->graph[p]));
-      HIPCHK(hipGraphInstantiate(&lg->exec[p], lg->graph[p], nullptr, nullptr, 0));
+    HIPCHK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    try {
+      ll.enqueue(p, cs, nullptr, v);
+    } catch (...) {
+      hipGraph_t gr = nullptr;
+      (void)hipStreamEndCapture(cs, &gr);
+      if (gr) (void)hipGraphDestroy(gr);
+      throw;
     }
+    HIPCHK(hipStreamEndCapture(cs, &lg.graph[v][p]));
+    HIPCHK(hipGraphInstantiate(&lg.exec[v][p], lg.graph[v][p], nullptr, nullptr, 0));
   } catch (...) {
     (void)hipStreamDestroy(cs);
     level_graphs_release(ws);
     throw;
   }
   (void)hipStreamDestroy(cs);
-  return *lg;
+  return lg.exec[v][p];
 }
 
 }  // namespace
@@ -1645,15 +1658,26 @@ void bfs_run(const Graph *g, Workspace *ws, int32_t source, const dsbfs_run_opts
       // already queued behind it returns at once). One level ahead hides the
       // host's wait and launch behind the level in flight; two would add a
       // second graph of no-op kernels at the end of every search.
-      const LevelGraphs &lg = level_graphs(ws, ll);
+      //
+      // Under the heuristic schedule with factor1 = 0 a subgraph that went
+      // backward never switches back (FV < 0 * BV never holds), so once the
+      // host has seen it backward, the level it launches next leaves out
+      // that subgraph's forward kernels, which could only return at once.
+      LevelGraphs &lg = level_graphs(ws, ll);
+      const bool monotone = o.forced == 0 && o.factor1[0] == 0.0 && o.factor1[1] == 0.0 &&
+                            o.factor1[2] == 0.0;
+      int variant = 0;
       for (int32_t L = 0;; ++L) {
-        HIPCHK(hipGraphLaunch(lg.exec[L & 1], s));
+        HIPCHK(hipGraphLaunch(level_exec(ws, lg, ll, variant, L & 1), s));
         HIPCHK(hipEventRecord(ws->lev_ev[L % 3], s));
         if (L >= 1) {
           HIPCHK(hipEventSynchronize(ws->lev_ev[(L - 1) % 3]));
           const LevelStatus &st = hs[(L - 1) & (kStatusSlots - 1)];
           if (st.done) break;
           seen.push_back(st);
+          if (monotone)
+            variant = (st.rec.dir[2] == 1 ? 1 : 0) |
+                      (st.rec.dir[0] == 1 && st.rec.dir[1] == 1 ? 2 : 0);
         }
       }
     }
