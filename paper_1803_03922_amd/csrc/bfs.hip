@@ -1393,7 +1393,7 @@ struct LevelLaunch {
       end(DSBFS_K_BU_NN, b);
     }
     if (d > 0) {
-      if (g->st.n_ndsrc > 0) {
+      if (g->st.n_ndsrc > 0 && !(skip & 4)) {
         b = begin();
         hipLaunchKernelGGL(k_bu_normal, dim3(SG), dim3(kBS), 0, s, static_cast<const DevCtl *>(c),
                            C[0], C[1], g->ndsrc.as<int32_t>(), g->nds_off.as<int64_t>(),
@@ -1403,6 +1403,7 @@ struct LevelLaunch {
         HIPCHK(hipGetLastError());
         end(DSBFS_K_BU_NORMAL, b);
       }
+      if (!(skip & 8)) {
       b = begin();
       hipLaunchKernelGGL(k_dcand, dim3(grid_for(g->dwords(), kBS, 4096)), dim3(kBS), 0, s,
                          static_cast<const uint32_t *>(Cd), g->ddsrc_mask.as<uint32_t>(),
@@ -1415,6 +1416,7 @@ struct LevelLaunch {
                          g->vid_of.as<int32_t>(), static_cast<const DevCtl *>(c), out, Cd, cur);
       HIPCHK(hipGetLastError());
       end(DSBFS_K_BU_DELEG, b);
+      }
     }
     b = begin();
     hipLaunchKernelGGL(k_close, dim3(grid_for(std::max<int64_t>(n, g->dwords()), kBS, 4096)),
@@ -1453,7 +1455,7 @@ LevelLaunch level_launch(const Graph *g, Workspace *ws, const Out &out, bool nn_
 // Captured level graphs per workspace, for the depth / parent buffers they
 // were captured with: one per queue parity and skip variant (see
 // LevelLaunch::enqueue), each captured when first needed.
-constexpr int kLevelVariants = 4;
+constexpr int kLevelVariants = 16;
 struct LevelGraphs {
   int32_t *depth = nullptr, *parent = nullptr;
   bool nn_do = false;
@@ -1659,10 +1661,13 @@ void bfs_run(const Graph *g, Workspace *ws, int32_t source, const dsbfs_run_opts
       // host's wait and launch behind the level in flight; two would add a
       // second graph of no-op kernels at the end of every search.
       //
-      // Under the heuristic schedule with factor1 = 0 a subgraph that went
-      // backward never switches back (FV < 0 * BV never holds), so once the
-      // host has seen it backward, the level it launches next leaves out
-      // that subgraph's forward kernels, which could only return at once.
+      // The level the host launches next leaves out kernels that cannot have
+      // work, from the latest status it has seen (two levels earlier):
+      // - under the heuristic schedule with factor1 = 0 a subgraph that went
+      //   backward never switches back (FV < 0 * BV never holds), so its
+      //   forward kernels could only return at once;
+      // - the counts U of unvisited vertices a bottom-up visit scans never
+      //   grow, and a bottom-up visit needs U > 0 (any schedule).
       LevelGraphs &lg = level_graphs(ws, ll);
       const bool monotone = o.forced == 0 && o.factor1[0] == 0.0 && o.factor1[1] == 0.0 &&
                             o.factor1[2] == 0.0;
@@ -1675,9 +1680,10 @@ void bfs_run(const Graph *g, Workspace *ws, int32_t source, const dsbfs_run_opts
           const LevelStatus &st = hs[(L - 1) & (kStatusSlots - 1)];
           if (st.done) break;
           seen.push_back(st);
+          variant = (st.rec.U[1] == 0 ? 4 : 0) | (st.rec.U[0] == 0 && st.rec.U[2] == 0 ? 8 : 0);
           if (monotone)
-            variant = (st.rec.dir[2] == 1 ? 1 : 0) |
-                      (st.rec.dir[0] == 1 && st.rec.dir[1] == 1 ? 2 : 0);
+            variant |= (st.rec.dir[2] == 1 ? 1 : 0) |
+                       (st.rec.dir[0] == 1 && st.rec.dir[1] == 1 ? 2 : 0);
         }
       }
     }
