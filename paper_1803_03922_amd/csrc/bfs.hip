@@ -1459,6 +1459,7 @@ constexpr int kLevelVariants = 16;
 struct LevelGraphs {
   int32_t *depth = nullptr, *parent = nullptr;
   bool nn_do = false;
+  int64_t searches = 0;  // searches run on these graphs
   hipGraph_t graph[kLevelVariants][2] = {};
   hipGraphExec_t exec[kLevelVariants][2] = {};
 };
@@ -1668,7 +1669,12 @@ void bfs_run(const Graph *g, Workspace *ws, int32_t source, const dsbfs_run_opts
       //   forward kernels could only return at once;
       // - the counts U of unvisited vertices a bottom-up visit scans never
       //   grow, and a bottom-up visit needs U > 0 (any schedule).
+      //
+      // Variants run only on graphs kept from an earlier search: a caller
+      // that passes new output buffers on every call (the query server's
+      // result rows) would otherwise capture several graphs per search.
       LevelGraphs &lg = level_graphs(ws, ll);
+      const bool variants = lg.searches > 0;
       const bool monotone = o.forced == 0 && o.factor1[0] == 0.0 && o.factor1[1] == 0.0 &&
                             o.factor1[2] == 0.0;
       int variant = 0;
@@ -1680,12 +1686,14 @@ void bfs_run(const Graph *g, Workspace *ws, int32_t source, const dsbfs_run_opts
           const LevelStatus &st = hs[(L - 1) & (kStatusSlots - 1)];
           if (st.done) break;
           seen.push_back(st);
+          if (!variants) continue;
           variant = (st.rec.U[1] == 0 ? 4 : 0) | (st.rec.U[0] == 0 && st.rec.U[2] == 0 ? 8 : 0);
           if (monotone)
             variant |= (st.rec.dir[2] == 1 ? 1 : 0) |
                        (st.rec.dir[0] == 1 && st.rec.dir[1] == 1 ? 2 : 0);
         }
       }
+      ++lg.searches;
     }
     for (const LevelStatus &st : seen) {
       rec.push_back(st.rec);
