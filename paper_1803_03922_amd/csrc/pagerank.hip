@@ -153,7 +153,16 @@ __global__ void __launch_bounds__(kPB) k_pr_normal(const uint64_t *noff, const i
 }
 
 // Delegate rows, one wave per row: dd part (delegate ranks, contributions by
-// rank), then dn part (vertex IDs, normal contributions).
+// rank), then dn part (vertex IDs, normal contributions). Each lane takes the
+// row's entries l, l + 64, l + 128, ... in that order. Rows longer than a wave
+// go eight entries per lane at a time: eight column loads, then eight
+// gathers, then the eight additions, so eight gathers are in flight per lane
+// instead of one and the sum is the same. A slot past the row end loads the
+// row's last entry again (no branch, so no wait between the loads) and adds
+// +0.0, which leaves the non-negative partial sum unchanged. Eight costs 80
+// VGPRs (6 waves per SIMD) and still beats four at 64 (8 waves per SIMD).
+constexpr int kPrUnroll = 8;
+
 __global__ void __launch_bounds__(kPB) k_pr_deleg(const uint64_t *doff, const int32_t *pcol,
                                                   const int32_t *vid_of, int32_t d, int32_t n,
                                                   const double *cn, const double *cdr,
@@ -169,9 +178,27 @@ __global__ void __launch_bounds__(kPB) k_pr_deleg(const uint64_t *doff, const in
     const uint64_t w0 = doff[k], w1 = doff[k + 1];
     const int64_t b = row_start(w0), mid = b + row_first(w0), e = row_start(w1);
     double s = 0.0;
-    for (int64_t i = b + l; i < e; i += kWave) {
-      const int32_t c = __builtin_nontemporal_load(pcol + i);
-      s += i < mid ? cdr[c] : cn[c];
+    if (e - b <= kWave) {
+      const int64_t i = b + l;
+      if (i < e) s = (i < mid ? cdr : cn)[__builtin_nontemporal_load(pcol + i)];
+    } else {
+      for (int64_t i0 = b + l; i0 < e; i0 += kPrUnroll * kWave) {
+        int32_t c[kPrUnroll];
+        double x[kPrUnroll];
+#pragma unroll
+        for (int u = 0; u < kPrUnroll; ++u) {
+          const int64_t j = i0 + int64_t(u) * kWave;
+          c[u] = __builtin_nontemporal_load(pcol + (j < e ? j : e - 1));
+        }
+#pragma unroll
+        for (int u = 0; u < kPrUnroll; ++u) {
+          const int64_t j = i0 + int64_t(u) * kWave;
+          const double v = ((j < e ? j : e - 1) < mid ? cdr : cn)[c[u]];
+          x[u] = j < e ? v : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < kPrUnroll; ++u) s += x[u];
+      }
     }
     s = wave_sum_f64(s);
     if (l == 0) {

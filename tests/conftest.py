@@ -10,6 +10,9 @@ if ROOT not in sys.path:
 
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU")
+    # progress lines of long tests reach the terminal under output capture too
+    import gpu_helpers
+    gpu_helpers.CAPTURE_MANAGER = config.pluginmanager.getplugin("capturemanager")
 
 
 @pytest.fixture(scope="session")

@@ -18,9 +18,20 @@ def lib():
     return dsbfs
 
 
+# pytest's capture manager, set by conftest.py: log() suspends capture so that
+# a long test's progress lines appear while it runs, also under -q
+CAPTURE_MANAGER = None
+
+
 def log(*a):
-    print(*a, flush=True)
-    sys.stdout.flush()
+    cm = CAPTURE_MANAGER
+    if cm is not None:
+        with cm.global_and_fixture_disabled():
+            print(*a, flush=True)
+            sys.stdout.flush()
+    else:
+        print(*a, flush=True)
+        sys.stdout.flush()
 
 
 class GpuGraph:
