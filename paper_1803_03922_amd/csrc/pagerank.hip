@@ -126,7 +126,12 @@ __device__ __forceinline__ double pr_base(const PrAcc *acc, double alpha, int32_
 }
 
 // Normal rows: nn part (vertex IDs, normal contributions), then nd part
-// (delegate IDs, delegate contributions).
+// (delegate IDs, delegate contributions). A thread sums its row in stored
+// order, four entries at a time: four column loads, then four gathers, then
+// the four additions. Slots past the row end re-load its last entry and add
+// +0.0 (the partial sum is non-negative), as in the delegate pull.
+constexpr int kPrRowUnroll = 4;
+
 __global__ void __launch_bounds__(kPB) k_pr_normal(const uint64_t *noff, const int32_t *ncol,
                                                    const int32_t *did, int32_t n,
                                                    const double *cn, const double *cd,
@@ -142,8 +147,20 @@ __global__ void __launch_bounds__(kPB) k_pr_normal(const uint64_t *noff, const i
       const uint64_t w0 = noff[v], w1 = noff[v + 1];
       const int64_t b = row_start(w0), mid = b + row_first(w0), e = row_start(w1);
       double s = 0.0;
-      for (int64_t i = b; i < mid; ++i) s += cn[ncol[i]];
-      for (int64_t i = mid; i < e; ++i) s += cd[ncol[i]];
+      for (int64_t i0 = b; i0 < e; i0 += kPrRowUnroll) {
+        int32_t c[kPrRowUnroll];
+        double y[kPrRowUnroll];
+#pragma unroll
+        for (int u = 0; u < kPrRowUnroll; ++u) c[u] = ncol[i0 + u < e ? i0 + u : e - 1];
+#pragma unroll
+        for (int u = 0; u < kPrRowUnroll; ++u) {
+          const int64_t j = i0 + u;
+          const double g = ((j < e ? j : e - 1) < mid ? cn : cd)[c[u]];
+          y[u] = j < e ? g : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < kPrRowUnroll; ++u) s += y[u];
+      }
       const double x = base + alpha * s;
       delta += fabs(x - r[v]);
       rn[v] = x;
