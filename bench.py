@@ -11,10 +11,15 @@ value = harmonic mean over the timed steps of GTEPS(s) = m_cc(s) / t(s), with
 m_cc(s) the undirected simple edges of the source's component and t(s) the
 HIP-event time of the call on its stream.
 
-Also reported: the roofline of the dominant kernel (algorithmic bytes from
-the kernels' own work counts / their HIP-event time), the CPU oracle timed on
-one host core on a bounded sample of the same workload, and (with --batched /
---served) the multi-source and served forms.
+Also reported: the roofline of the dominant kernel (the oracle work model's
+bytes for the profiled searches / the kernel's HIP-event time, with the
+kernels' own byte counts beside it, and the measured HBM traffic per launch
+from the committed rocprofv3 summary while the kernel's source is unchanged),
+the CPU oracle timed on one host core on a bounded sample of the same
+workload, the threshold and factor sweeps, the depth-only form, RMAT 16 and
+22, and, unless switched off (0), the multi-source (--batched), served
+(--served), PageRank (--pagerank-steps) and device-generated RMAT 28
+(--big-scale) legs.
 
     python bench.py [--steps K] [--warmup W] [--scale S] [--threshold TH]
 """
